@@ -1,0 +1,185 @@
+/*
+ * pa.h -- C ABI of an MI355X (gfx950) library for population annealing (PA)
+ * of the two-dimensional q-state Potts model.
+ *
+ * Method: Barash, Weigel, Shchur, Janke, "Exploring first-order phase
+ * transitions with population annealing", arXiv:1704.01888.
+ *   Sec. 2, steps 1-5 : the PA loop (initial population, resampling with the
+ *                       relative Boltzmann weights, theta Metropolis rounds,
+ *                       population averages, next temperature);
+ *   Sec. 2, eq. (1)   : Poisson copy numbers, R_i = sum_j r_j;
+ *   Sec. 2, eq. (2)   : free-energy estimator -beta_i F = ln Z_beta0 + sum ln Q_m;
+ *   Sec. 3, eq. (3)   : H = -sum_<ij> delta(s_i, s_j), J = 1, periodic L x L;
+ *   Sec. 3, eq. (4)   : population averages;
+ *   Sec. 5, eq. (6)   : ground-state initial population (heating runs);
+ *   Sec. 6, eq. (7)-(8): ln Z at beta -> infinity = ln q - beta E_0, E_0 = -2N.
+ *
+ * Conventions fixed by this library where the paper leaves a choice open
+ * (all of them are also implemented, independently, by the CPU oracle):
+ *   - spins are uint8 in 0..q-1, replica-major, row-major (site n = y*L + x);
+ *   - random words: Philox4x32-10 keyed by (seed low 32 bits, seed high 32
+ *     bits); the counter is (index within unit, slot, step, domain << 28 |
+ *     sub-index), so every random number is a pure function of logical
+ *     indices and never of threads, tiles or launches;
+ *   - one Metropolis round = one checkerboard sweep: colour 0 ((x+y) even)
+ *     then colour 1; proposal uniform over the q-1 other states; acceptance
+ *     iff dE <= 0 or w < floor(2^32 exp(-beta dE));
+ *   - Poisson resampling is drawn as R_i ~ Pois(R) (from the plan) followed by
+ *     R_i multinomial draws with integer weights round(2^Kb exp(-|dbeta| d_j)),
+ *     d_j = |E_j - E_ref|; this is the same joint law as eq. (1) because the
+ *     Poisson means add up to R;
+ *   - the new population is stored in ancestor order.
+ *
+ * Memory ownership: device memory belongs to the caller.  The library only
+ * sub-allocates inside the workspace d_ws (device pointer, at least
+ * pa_plan_info.workspace_bytes bytes, 256-byte aligned), which must stay
+ * valid until pa_run_finish returns.  All host pointers passed in are read
+ * during the call only; result buffers are caller-owned host memory.
+ * "stream" is a hipStream_t (NULL = the null stream); all device work of a
+ * run is ordered on it.
+ *
+ * Errors: every call returns pa_status; nothing throws across the ABI.
+ * pa_last_error() gives a thread-local message for the last failure.
+ * A device error (PA_ERR_DEVICE) leaves the run unusable; finish it.
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PA_OK = 0,
+    PA_ERR_INVALID = -1,   /* bad argument or description                          */
+    PA_ERR_NOMEM = -2,     /* workspace smaller than pa_plan_info.workspace_bytes  */
+    PA_ERR_DEVICE = -3,    /* HIP error or failed device-side consistency check    */
+    PA_ERR_CAPACITY = -4,  /* the Poisson schedule drew R_i = 0 or R_i > 2^31      */
+    PA_ERR_UNSUPPORTED = -5 /* valid for the method, outside this device path     */
+} pa_status;
+
+typedef enum { PA_RESAMPLE_POISSON = 0, PA_RESAMPLE_MULTINOMIAL = 1, PA_RESAMPLE_NONE = 2 } pa_resample;
+typedef enum { PA_INIT_RANDOM = 0, PA_INIT_GROUND = 1 } pa_init;
+
+/* Output selection bits for pa_run_desc.outputs. */
+enum {
+    PA_OUT_HIST = 1,   /* per-step energy histograms, [K][2N+1]           */
+    PA_OUT_FINAL = 4   /* final population, energies and last ancestors  */
+};
+
+/* A PA run (Sec. 2): lattice L x L periodic (Sec. 3), q states, target
+ * population R, inverse temperatures beta[0..K-1], theta sweeps per step. */
+typedef struct {
+    uint32_t L;          /* lattice side; this device path needs L % 4 == 0, 4 <= L <= 256 */
+    uint32_t q;          /* 2 <= q <= 255                                               */
+    uint64_t R;          /* 1 <= R <= 2^31                                              */
+    uint32_t K;          /* number of temperatures, K >= 1                              */
+    const double *beta;  /* [K] host array, finite and >= 0; random init needs beta[0] == 0 */
+    uint32_t theta;      /* Metropolis sweeps per step, < 2^27                          */
+    uint64_t seed;       /* Philox key                                                  */
+    int32_t resample;    /* pa_resample                                                 */
+    int32_t init;        /* pa_init                                                     */
+    uint32_t outputs;    /* PA_OUT_* bits                                               */
+} pa_run_desc;
+
+/* Kernel kinds, for the optional per-kernel timing of pa_result. */
+enum {
+    PA_KERNEL_INIT = 0,     /* initial population + energies (step 1)         */
+    PA_KERNEL_SWEEP = 1,    /* gather + theta sweeps + energies (eq. (1), step 3) */
+    PA_KERNEL_STATS = 2,    /* sums, E_ref, ln Q (eq. (2), (4))              */
+    PA_KERNEL_WEIGHTS = 3,  /* weights + inclusive scan (step 2)             */
+    PA_KERNEL_SAMPLE = 4,   /* multinomial draws (step 2)                    */
+    PA_KERNEL_SLOTMAP = 5,  /* copy numbers -> ancestors (eq. (1))           */
+    PA_KERNEL_KINDS = 6
+};
+
+/* Host result buffers, caller-allocated; arrays of length K unless noted. */
+typedef struct {
+    uint64_t *R_i;           /* population size after each step                    */
+    int64_t  *E_sum;         /* exact integer sum of the energies                  */
+    double   *E_mean;        /* eq. (4): E_sum / R_i                               */
+    double   *lnQ;           /* ln Q_i of Sec. 2 step 2; lnQ[0] = 0                */
+    double   *minus_beta_F;  /* eq. (2) with ln Z_beta0 (N ln q, or eq. (7)-(8))   */
+    uint32_t *hist;          /* [K][2N+1], h[b] = #{j: E_j = b - 2N}; NULL unless PA_OUT_HIST */
+    uint8_t  *final_spins;   /* [R_{K-1}][N]; NULL unless PA_OUT_FINAL              */
+    int32_t  *final_E;       /* [R_{K-1}];     NULL unless PA_OUT_FINAL              */
+    uint32_t *last_anc;      /* [R_{K-1}] ancestors of the last resampling (identity if K == 1) */
+    double   *kernel_ms;     /* [PA_KERNEL_KINDS] summed HIP-event time per kernel kind, or NULL;
+                                filled only when profiling is on (pa_ctx_set_profiling) */
+    uint64_t *kernel_launches; /* [PA_KERNEL_KINDS] launches per kind, or NULL          */
+} pa_result;
+
+typedef struct {
+    uint64_t R_cap;            /* largest population of the run                     */
+    uint64_t R_final;          /* R_{K-1}                                           */
+    uint64_t workspace_bytes;  /* device bytes pa_run / pa_run_begin need            */
+    uint32_t Kb;               /* weight precision: 63 - ceil(log2 R_cap)           */
+    uint32_t n_tables;         /* distinct |beta_i - beta_{i-1}| values             */
+} pa_plan_info;
+
+typedef struct pa_ctx pa_ctx;          /* device handle                           */
+typedef struct pa_run_state pa_run_state; /* one run in flight                     */
+
+/* Plan a run on the host (no device work): validates the description, draws
+ * the population schedule (Sec. 2 eq. (1), see the header comment) and sizes
+ * the workspace. */
+pa_status pa_plan(const pa_run_desc *desc, pa_plan_info *info);
+
+/* The plan's integer tables, for checking against an independent
+ * implementation: T[K][4] Metropolis thresholds floor(2^32 exp(-beta_i dE)),
+ * dE = 1..4 (Sec. 2 step 3); R_sched[K] population sizes (R_sched[0] = R).
+ * Either pointer may be NULL. */
+pa_status pa_plan_tables(const pa_run_desc *desc, uint64_t *T, uint64_t *R_sched);
+
+/* Integer resampling weights W[d] = round(2^Kb exp(-|dbeta| d)), d = 0..2N, as
+ * the library builds them; returns the table length D (first zero) in *D. */
+pa_status pa_weight_table(double abs_dbeta, uint32_t Kb, uint32_t N, uint64_t *W, uint32_t *D);
+
+/* Device handle on HIP device `device`. */
+pa_status pa_ctx_create(int device, pa_ctx **out);
+void pa_ctx_destroy(pa_ctx *ctx);
+/* Bracket every kernel launch of later runs with HIP events on the run's
+ * stream and report the summed durations in pa_result.kernel_ms. */
+pa_status pa_ctx_set_profiling(pa_ctx *ctx, int enable);
+
+/* Whole run, steps 1-5 of Sec. 2, enqueued on `stream`; returns when the
+ * results are in `out`. */
+pa_status pa_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes,
+                 void *stream, pa_result *out);
+
+/* Stepwise form of pa_run.
+ * pa_run_begin: plan, upload tables, create the initial population (step 0).
+ * pa_run_advance: enqueue the next n steps (resampling + theta sweeps + stats).
+ * pa_run_sync: wait for the enqueued work.
+ * pa_run_read: synchronous copy of the current population (any pointer NULL
+ *   to skip): spins[R_cur][N], E[R_cur], anc[R_cur] (ancestors of the last
+ *   resampling), counts[R_prev] (copy numbers of the last resampling).
+ * pa_run_load: replace the current population by host spins[R_cur][N] at step
+ *   `step` with -beta F value minus_beta_F (resume from a checkpoint).
+ * pa_run_read_slots: see below.
+ * pa_run_finish: wait, copy the per-step results into `out` (may be NULL) and
+ *   release the run. */
+pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes,
+                       void *stream, pa_run_state **out);
+pa_status pa_run_advance(pa_run_state *run, uint32_t n_steps);
+pa_status pa_run_sync(pa_run_state *run);
+pa_status pa_run_read(pa_run_state *run, uint32_t *step, uint64_t *R_cur, uint64_t *R_prev,
+                      uint8_t *spins, int32_t *E, uint32_t *anc, uint32_t *counts);
+pa_status pa_run_load(pa_run_state *run, uint32_t step, uint64_t R_cur, const uint8_t *spins,
+                      double minus_beta_F);
+/* Synchronous copy of n selected replicas: from the current population
+ * (previous == 0) or from the population before the last step (previous == 1,
+ * valid until the next pa_run_advance).  spins_out is [n][N]. */
+pa_status pa_run_read_slots(pa_run_state *run, int previous, const uint32_t *slots, uint32_t n,
+                            uint8_t *spins_out);
+pa_status pa_run_finish(pa_run_state *run, pa_result *out);
+
+const char *pa_status_str(pa_status s);
+const char *pa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

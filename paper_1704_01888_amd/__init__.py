@@ -1,0 +1,301 @@
+"""Population annealing of the 2D q-state Potts model on MI355X (gfx950).
+
+Python binding of the C ABI in ``include/pa.h`` (libpa.so).  Argument
+marshalling only: every step of the method runs in the library's HIP kernels.
+PyTorch provides device memory (the workspace) and the stream.
+
+Method: Barash, Weigel, Shchur, Janke, arXiv:1704.01888, Sec. 2-3.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpa.so")
+
+PA_OK, PA_ERR_INVALID, PA_ERR_NOMEM, PA_ERR_DEVICE, PA_ERR_CAPACITY, PA_ERR_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5
+RESAMPLE_POISSON, RESAMPLE_MULTINOMIAL, RESAMPLE_NONE = 0, 1, 2
+INIT_RANDOM, INIT_GROUND = 0, 1
+OUT_HIST, OUT_FINAL = 1, 4
+KERNEL_NAMES = ("init", "sweep", "stats", "weights_scan", "sample", "slotmap")
+
+EXPORTS = [
+    "pa_plan", "pa_plan_tables", "pa_weight_table", "pa_ctx_create", "pa_ctx_destroy",
+    "pa_ctx_set_profiling",
+    "pa_run", "pa_run_begin", "pa_run_advance", "pa_run_sync", "pa_run_read", "pa_run_load",
+    "pa_run_read_slots", "pa_run_finish", "pa_status_str", "pa_last_error",
+]
+
+
+class PAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class RunDesc(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_uint32), ("q", ctypes.c_uint32), ("R", ctypes.c_uint64),
+        ("K", ctypes.c_uint32), ("beta", ctypes.POINTER(ctypes.c_double)),
+        ("theta", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+        ("resample", ctypes.c_int32), ("init", ctypes.c_int32), ("outputs", ctypes.c_uint32),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("R_i", ctypes.c_void_p), ("E_sum", ctypes.c_void_p), ("E_mean", ctypes.c_void_p),
+        ("lnQ", ctypes.c_void_p), ("minus_beta_F", ctypes.c_void_p), ("hist", ctypes.c_void_p),
+        ("final_spins", ctypes.c_void_p), ("final_E", ctypes.c_void_p),
+        ("last_anc", ctypes.c_void_p), ("kernel_ms", ctypes.c_void_p),
+        ("kernel_launches", ctypes.c_void_p),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("R_cap", ctypes.c_uint64), ("R_final", ctypes.c_uint64),
+        ("workspace_bytes", ctypes.c_uint64), ("Kb", ctypes.c_uint32),
+        ("n_tables", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpa.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1704_01888_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32, dbl = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32,
+                              ctypes.c_double)
+    P = ctypes.POINTER
+    L.pa_plan.argtypes = [P(RunDesc), P(PlanInfo)]
+    L.pa_plan_tables.argtypes = [P(RunDesc), vp, vp]
+    L.pa_weight_table.argtypes = [dbl, u32, u32, vp, vp]
+    L.pa_ctx_create.argtypes = [ctypes.c_int, P(vp)]
+    L.pa_ctx_destroy.argtypes = [vp]
+    L.pa_ctx_destroy.restype = None
+    L.pa_ctx_set_profiling.argtypes = [vp, ctypes.c_int]
+    L.pa_ctx_set_profiling.restype = i32
+    L.pa_run.argtypes = [vp, P(RunDesc), vp, u64, vp, P(Result)]
+    L.pa_run_begin.argtypes = [vp, P(RunDesc), vp, u64, vp, P(vp)]
+    L.pa_run_advance.argtypes = [vp, u32]
+    L.pa_run_sync.argtypes = [vp]
+    L.pa_run_read.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.pa_run_load.argtypes = [vp, u32, u64, vp, dbl]
+    L.pa_run_finish.argtypes = [vp, P(Result)]
+    L.pa_run_read_slots.argtypes = [vp, ctypes.c_int, vp, u32, vp]
+    L.pa_status_str.argtypes = [i32]
+    L.pa_status_str.restype = ctypes.c_char_p
+    L.pa_last_error.argtypes = []
+    L.pa_last_error.restype = ctypes.c_char_p
+    for name in ("pa_plan", "pa_plan_tables", "pa_weight_table", "pa_ctx_create", "pa_run",
+                 "pa_run_begin", "pa_run_advance", "pa_run_sync", "pa_run_read", "pa_run_load",
+                 "pa_run_read_slots", "pa_run_finish"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != PA_OK:
+        raise PAError(status, lib().pa_last_error().decode())
+
+
+def _ptr(a) -> int:
+    return a.ctypes.data if a is not None else None
+
+
+class Desc:
+    """A run description (fields of ``pa_run_desc``)."""
+
+    def __init__(self, L, q, R, beta, theta, seed, resample=RESAMPLE_POISSON, init=INIT_RANDOM,
+                 outputs=0):
+        self.L, self.q, self.R = int(L), int(q), int(R)
+        self.beta = np.ascontiguousarray(beta, dtype=np.float64)
+        self.K = len(self.beta)
+        self.theta, self.seed = int(theta), int(seed)
+        self.resample, self.init, self.outputs = int(resample), int(init), int(outputs)
+
+    @property
+    def N(self):
+        return self.L * self.L
+
+    def c(self) -> RunDesc:
+        d = RunDesc()
+        d.L, d.q, d.R, d.K = self.L, self.q, self.R, self.K
+        d.beta = self.beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.theta, d.seed = self.theta, self.seed
+        d.resample, d.init, d.outputs = self.resample, self.init, self.outputs
+        return d
+
+
+def pa_plan(desc: Desc) -> PlanInfo:
+    info = PlanInfo()
+    _check(lib().pa_plan(ctypes.byref(desc.c()), ctypes.byref(info)))
+    return info
+
+
+def pa_plan_tables(desc: Desc):
+    T = np.zeros((desc.K, 4), dtype=np.uint64)
+    R_sched = np.zeros(desc.K, dtype=np.uint64)
+    _check(lib().pa_plan_tables(ctypes.byref(desc.c()), _ptr(T), _ptr(R_sched)))
+    return T, R_sched
+
+
+def pa_weight_table(abs_dbeta: float, Kb: int, N: int):
+    W = np.zeros(2 * N + 1, dtype=np.uint64)
+    D = ctypes.c_uint32(0)
+    _check(lib().pa_weight_table(float(abs_dbeta), int(Kb), int(N), _ptr(W), ctypes.byref(D)))
+    return W, int(D.value)
+
+
+class Context:
+    """A device handle (``pa_ctx``) on torch's current HIP device."""
+
+    def __init__(self, device: int | None = None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible to torch")
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        _check(lib().pa_ctx_create(self.device, ctypes.byref(h)))
+        self.handle = h
+
+    def set_profiling(self, on: bool):
+        _check(lib().pa_ctx_set_profiling(self.handle, 1 if on else 0))
+
+    def close(self):
+        if self.handle:
+            lib().pa_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _workspace(nbytes: int, device: int):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=f"cuda:{device}")
+
+
+def _stream_ptr():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _alloc_result(desc: Desc, info: PlanInfo):
+    K, N = desc.K, desc.N
+    out = {
+        "R_i": np.zeros(K, np.uint64), "E_sum": np.zeros(K, np.int64),
+        "E_mean": np.zeros(K), "lnQ": np.zeros(K), "minus_beta_F": np.zeros(K),
+    }
+    res = Result()
+    for k in ("R_i", "E_sum", "E_mean", "lnQ", "minus_beta_F"):
+        setattr(res, k, _ptr(out[k]))
+    if desc.outputs & OUT_HIST:
+        out["hist"] = np.zeros((K, 2 * N + 1), np.uint32)
+        res.hist = _ptr(out["hist"])
+    if desc.outputs & OUT_FINAL:
+        RF = int(info.R_final)
+        out["final_spins"] = np.zeros((RF, N), np.uint8)
+        out["final_E"] = np.zeros(RF, np.int32)
+        out["last_anc"] = np.zeros(RF, np.uint32)
+        res.final_spins = _ptr(out["final_spins"])
+        res.final_E = _ptr(out["final_E"])
+        res.last_anc = _ptr(out["last_anc"])
+    out["kernel_ms"] = np.zeros(len(KERNEL_NAMES))
+    out["kernel_launches"] = np.zeros(len(KERNEL_NAMES), np.uint64)
+    res.kernel_ms = _ptr(out["kernel_ms"])
+    res.kernel_launches = _ptr(out["kernel_launches"])
+    return out, res
+
+
+def pa_run(ctx: Context, desc: Desc, workspace=None):
+    """Whole run on the current torch stream; returns a dict of numpy arrays."""
+    info = pa_plan(desc)
+    ws = workspace if workspace is not None else _workspace(info.workspace_bytes, ctx.device)
+    out, res = _alloc_result(desc, info)
+    _check(lib().pa_run(ctx.handle, ctypes.byref(desc.c()), ctypes.c_void_p(ws.data_ptr()),
+                        ws.numel(), _stream_ptr(), ctypes.byref(res)))
+    return out
+
+
+class Run:
+    """Stepwise run (pa_run_begin / advance / read / load / finish)."""
+
+    def __init__(self, ctx: Context, desc: Desc, workspace=None):
+        self.desc = desc
+        self.info = pa_plan(desc)
+        self.ws = workspace if workspace is not None else _workspace(self.info.workspace_bytes,
+                                                                     ctx.device)
+        h = ctypes.c_void_p()
+        _check(lib().pa_run_begin(ctx.handle, ctypes.byref(desc.c()),
+                                  ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                  _stream_ptr(), ctypes.byref(h)))
+        self.handle = h
+
+    def advance(self, n: int = 1):
+        _check(lib().pa_run_advance(self.handle, int(n)))
+
+    def sync(self):
+        _check(lib().pa_run_sync(self.handle))
+
+    def read(self, spins=True, E=True, anc=True, counts=True):
+        step = ctypes.c_uint32()
+        R_cur, R_prev = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().pa_run_read(self.handle, ctypes.byref(step), ctypes.byref(R_cur),
+                                 ctypes.byref(R_prev), None, None, None, None))
+        rc, rp, N = int(R_cur.value), int(R_prev.value), self.desc.N
+        out = {"step": int(step.value), "R_cur": rc, "R_prev": rp}
+        bufs = {}
+        if spins:
+            bufs["spins"] = np.zeros((rc, N), np.uint8)
+        if E:
+            bufs["E"] = np.zeros(rc, np.int32)
+        if anc:
+            bufs["anc"] = np.zeros(rc, np.uint32)
+        if counts:
+            bufs["counts"] = np.zeros(rp, np.uint32)
+        _check(lib().pa_run_read(self.handle, None, None, None, _ptr(bufs.get("spins")),
+                                 _ptr(bufs.get("E")), _ptr(bufs.get("anc")),
+                                 _ptr(bufs.get("counts"))))
+        out.update(bufs)
+        return out
+
+    def load(self, step: int, spins: np.ndarray, minus_beta_F: float):
+        s = np.ascontiguousarray(spins, dtype=np.uint8)
+        _check(lib().pa_run_load(self.handle, int(step), int(s.shape[0]), _ptr(s),
+                                 float(minus_beta_F)))
+
+    def read_slots(self, slots, previous=False):
+        sl = np.ascontiguousarray(slots, dtype=np.uint32)
+        out = np.zeros((len(sl), self.desc.N), np.uint8)
+        _check(lib().pa_run_read_slots(self.handle, 1 if previous else 0, _ptr(sl), len(sl),
+                                       _ptr(out)))
+        return out
+
+    def finish(self):
+        out, res = _alloc_result(self.desc, self.info)
+        h, self.handle = self.handle, None
+        _check(lib().pa_run_finish(h, ctypes.byref(res)))
+        return out
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                lib().pa_run_finish(self.handle, None)
+            except Exception:
+                pass

@@ -1,0 +1,89 @@
+// pa_device.h -- launch interface between the host runtime (pa_host.cpp) and
+// the gfx950 kernels (pa_kernels.hip).  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pa {
+
+enum SweepMode : uint32_t { SWEEP_UPDATE = 0, SWEEP_INIT_RANDOM = 1, SWEEP_INIT_GROUND = 2 };
+
+// Philox domain tags (counter word 3, bits 28..31).
+enum : uint32_t { DOM_INIT = 0, DOM_SWEEP = 1, DOM_RESAMPLE = 2, DOM_PLAN = 3, DOM_GROUND = 4 };
+
+struct SweepArgs {
+    const uint8_t *old_pop;   // [R_prev][N] (UPDATE mode)
+    const uint32_t *anc;      // [R_new] ancestors, or nullptr for the identity
+    uint8_t *new_pop;         // [R_new][N]
+    int32_t *E_out;           // [R_new]
+    uint32_t *hist;           // [2N+1], accumulated with atomics
+    uint64_t T[4];            // thresholds for dE = 1..4 (<= 2^32)
+    uint32_t L, q, N;
+    uint32_t R_new;
+    uint32_t step;            // Philox counter word 2
+    uint32_t theta;
+    uint32_t mode;            // SweepMode
+    uint32_t key0, key1;      // Philox key
+    uint32_t G_log2;          // log2 of lanes per replica (2..6)
+    uint32_t waves_per_block;
+};
+
+struct StatsArgs {
+    const uint32_t *hist;     // [2N+1] population at step i
+    uint32_t *zero_next;      // histogram buffer to clear for step i+1, or nullptr
+    uint32_t nbins;           // 2N+1
+    int32_t two_n;
+    uint64_t R_i;
+    uint32_t step;            // i
+    uint32_t has_next;        // i + 1 < K
+    double dbeta_next;        // beta_{i+1} - beta_i
+    const double *w64_next;   // [2N+1] exp(-|dbeta_next| d)
+    int64_t *E_sum;           // [K]
+    double *E_mean;           // [K]
+    uint64_t *count;          // [K]   sum of the histogram (consistency check)
+    double *lnQ;              // [K]
+    double *mbF;              // [K]   -beta F
+    int32_t *E_ref;           // [K]   reference energy used by step i+1
+};
+
+struct WeightsArgs {
+    const int32_t *E;         // [R_prev]
+    const int32_t *E_ref;     // device scalar
+    const uint64_t *W;        // [D] fixed-point weights
+    uint32_t D;
+    uint64_t R_prev;
+    uint64_t *C;              // [R_prev] inclusive prefix sums
+};
+
+struct SampleArgs {
+    const uint64_t *C;        // [R_prev]
+    uint64_t R_prev;
+    uint64_t n_new;
+    uint32_t step;
+    uint32_t key0, key1;
+    uint32_t *r;              // [R_prev] copy counts (pre-zeroed)
+};
+
+struct SlotmapArgs {
+    uint32_t *r;              // [R_prev] copy counts, cleared on exit
+    uint64_t R_prev;
+    uint32_t *anc;            // [anc_cap]
+    uint64_t anc_cap;         // capacity of anc (writes beyond it are dropped)
+    uint32_t *counts_last;    // [R_prev] copy of the counts, or nullptr
+};
+
+hipError_t launch_sweep(const SweepArgs &a, hipStream_t s);
+hipError_t launch_stats(const StatsArgs &a, hipStream_t s);
+hipError_t launch_weights_scan(const WeightsArgs &a, hipStream_t s);
+hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
+hipError_t launch_slotmap(const SlotmapArgs &a, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+
+// Lanes per replica and waves per block chosen for a lattice side L.
+void sweep_shape(uint32_t L, uint32_t *G_log2, uint32_t *waves_per_block);
+size_t sweep_lds_bytes(uint32_t N, uint32_t G_log2, uint32_t waves_per_block);
+// Largest dynamic LDS a workgroup may use on the current device.
+size_t max_lds_per_block(int device);
+
+}  // namespace pa

@@ -1,0 +1,673 @@
+// pa_host.cpp -- host side of the population-annealing library: validation,
+// plan (population schedule, Metropolis thresholds, resampling weight tables),
+// workspace layout, the per-step launch sequence, and the C ABI of pa.h.
+//
+// The plan implements, on the host, the parts of Sec. 2 of arXiv:1704.01888
+// whose arithmetic must be bit-identical everywhere: the population sizes
+// R_i (eq. (1), drawn as R_i ~ Pois(R)), the integer acceptance thresholds of
+// the Metropolis rounds (step 3) and the integer resampling weights (step 2).
+#include "pa.h"
+#include "pa_device.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pa_status fail(pa_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 on the host (Salmon et al., SC'11), for the plan stream.
+// ---------------------------------------------------------------------------
+void philox_host(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)p1;
+        c[3] = (uint32_t)p0;
+        c[0] = n0;
+        c[2] = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Poisson(lambda) by inversion of u in [0,1): the support is visited in the
+// order m, m+1, m-1, m+2, m-2, ... from the mode m = floor(lambda), with the
+// pmf carried by its ratios from p(m) = exp(-lambda + m ln lambda - lgamma(m+1)).
+uint64_t poisson_inversion(double lambda, double u) {
+    const double m = std::floor(lambda);
+    const double pm = std::exp(-lambda + m * std::log(lambda) - std::lgamma(m + 1.0));
+    double acc = pm;
+    if (u < acc) return (uint64_t)m;
+    double hi = m, lo = m, phi = pm, plo = pm;
+    for (;;) {
+        hi = hi + 1.0;
+        phi = phi * lambda / hi;
+        acc = acc + phi;
+        if (u < acc) return (uint64_t)hi;
+        if (lo > 0.0) {
+            plo = plo * lo / lambda;
+            lo = lo - 1.0;
+            acc = acc + plo;
+            if (u < acc) return (uint64_t)lo;
+        }
+        if (phi == 0.0 && (lo == 0.0 || plo == 0.0)) return (uint64_t)hi;
+    }
+}
+
+uint32_t weight_table(double abs_dbeta, uint32_t Kb, uint32_t N, uint64_t *W) {
+    const uint32_t nb = 2 * N + 1;
+    uint32_t D = nb;
+    for (uint32_t d = 0; d < nb; ++d) {
+        const double x = abs_dbeta * (double)d;
+        W[d] = (uint64_t)std::nearbyint(std::ldexp(std::exp(-x), (int)Kb));
+        if (W[d] == 0 && D == nb) D = d;
+    }
+    for (uint32_t d = D; d < nb; ++d) W[d] = 0;
+    return D;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Plan {
+    pa_run_desc desc;
+    std::vector<double> beta;
+    uint32_t N = 0, nbins = 0;
+    std::vector<uint64_t> R_sched;
+    uint64_t R_cap = 0;
+    uint32_t Kb = 0;
+    std::vector<uint64_t> T;              // [K][4]
+    std::vector<double> dbeta;            // [K], dbeta[0] = 0
+    std::vector<uint32_t> table_of_step;  // [K]
+    std::vector<uint64_t> W;              // [n_tables][nbins]
+    std::vector<uint32_t> D;              // [n_tables]
+    std::vector<double> w64;              // [n_tables][nbins]
+    uint32_t n_tables = 0;
+    bool hist_all = false;
+    // workspace layout
+    size_t off_pop[2], off_E, off_C, off_r, off_anc, off_counts, off_hist, off_Esum, off_Emean,
+        off_count, off_lnQ, off_mbF, off_Eref, off_W, off_w64, total;
+};
+
+pa_status validate(const pa_run_desc *d) {
+    if (!d) return fail(PA_ERR_INVALID, "null run description");
+    if (d->L < 2 || (d->L & 1u)) return fail(PA_ERR_INVALID, "L must be even and >= 2");
+    if (d->q < 2 || d->q > 255) return fail(PA_ERR_INVALID, "q must be in [2, 255]");
+    if (d->R < 1 || d->R > (1ull << 31)) return fail(PA_ERR_INVALID, "R must be in [1, 2^31]");
+    if (d->K < 1 || !d->beta) return fail(PA_ERR_INVALID, "K must be >= 1 with a beta array");
+    if (d->theta >= (1u << 27)) return fail(PA_ERR_INVALID, "theta must be < 2^27");
+    if (d->resample < 0 || d->resample > 2) return fail(PA_ERR_INVALID, "bad resample mode");
+    if (d->init < 0 || d->init > 1) return fail(PA_ERR_INVALID, "bad init mode");
+    for (uint32_t i = 0; i < d->K; ++i)
+        if (!std::isfinite(d->beta[i]) || d->beta[i] < 0.0)
+            return fail(PA_ERR_INVALID, "beta must be finite and >= 0");
+    if (d->init == PA_INIT_RANDOM && d->beta[0] != 0.0)
+        return fail(PA_ERR_INVALID, "a random initial population needs beta[0] == 0");
+    if ((d->L & 3u) || d->L < 4 || d->L > 256)
+        return fail(PA_ERR_UNSUPPORTED, "this device path needs L % 4 == 0 and 4 <= L <= 256");
+    return PA_OK;
+}
+
+pa_status build_plan(const pa_run_desc *d, Plan &p, bool tables) {
+    pa_status st = validate(d);
+    if (st) return st;
+    p.desc = *d;
+    p.beta.assign(d->beta, d->beta + d->K);
+    p.desc.beta = p.beta.data();
+    p.N = d->L * d->L;
+    p.nbins = 2 * p.N + 1;
+    const uint32_t K = d->K;
+
+    // Population sizes (eq. (1) through R_i ~ Pois(R)); one uniform per step
+    // from Philox(0, 0, i, PLAN << 28).
+    p.R_sched.assign(K, d->R);
+    uint64_t cap = d->R;
+    const uint32_t k0 = (uint32_t)(d->seed & 0xffffffffu), k1 = (uint32_t)(d->seed >> 32);
+    for (uint32_t i = 1; i < K; ++i) {
+        uint64_t n = d->R;
+        if (d->resample == PA_RESAMPLE_POISSON) {
+            uint32_t c[4] = {0u, 0u, i, (uint32_t)pa::DOM_PLAN << 28};
+            philox_host(c, k0, k1);
+            const uint64_t x = ((uint64_t)c[1] << 32) | (uint64_t)c[0];
+            const double u = std::ldexp((double)(x >> 11), -53);
+            n = poisson_inversion((double)d->R, u);
+            if (n == 0 || n > (1ull << 31))
+                return fail(PA_ERR_CAPACITY, "Poisson schedule drew an empty or oversized population");
+        }
+        p.R_sched[i] = n;
+        if (n > cap) cap = n;
+    }
+    p.R_cap = cap;
+    uint32_t lg = 0;
+    while ((1ull << lg) < cap) ++lg;
+    p.Kb = 63u - lg;
+
+    // Metropolis thresholds floor(2^32 exp(-beta_i dE)), dE = 1..4.
+    p.T.assign((size_t)K * 4, 0);
+    for (uint32_t i = 0; i < K; ++i)
+        for (uint32_t dE = 1; dE <= 4; ++dE) {
+            const double x = p.beta[i] * (double)dE;
+            p.T[(size_t)i * 4 + dE - 1] = (uint64_t)std::floor(std::ldexp(std::exp(-x), 32));
+        }
+
+    // One weight table per distinct |beta_i - beta_{i-1}|.
+    p.dbeta.assign(K, 0.0);
+    p.table_of_step.assign(K, 0);
+    std::unordered_map<uint64_t, uint32_t> seen;
+    std::vector<double> abs_list;
+    for (uint32_t i = 1; i < K; ++i) {
+        p.dbeta[i] = p.beta[i] - p.beta[i - 1];
+        const double a = std::fabs(p.dbeta[i]);
+        uint64_t bits;
+        std::memcpy(&bits, &a, sizeof bits);
+        auto it = seen.find(bits);
+        if (it == seen.end()) {
+            const uint32_t id = (uint32_t)abs_list.size();
+            seen.emplace(bits, id);
+            abs_list.push_back(a);
+            p.table_of_step[i] = id;
+        } else {
+            p.table_of_step[i] = it->second;
+        }
+    }
+    if (abs_list.empty()) abs_list.push_back(0.0);
+    p.n_tables = (uint32_t)abs_list.size();
+    if (tables) {
+        p.W.assign((size_t)p.n_tables * p.nbins, 0);
+        p.D.assign(p.n_tables, 0);
+        p.w64.assign((size_t)p.n_tables * p.nbins, 0.0);
+        for (uint32_t t = 0; t < p.n_tables; ++t) {
+            p.D[t] = weight_table(abs_list[t], p.Kb, p.N, p.W.data() + (size_t)t * p.nbins);
+            for (uint32_t dd = 0; dd < p.nbins; ++dd)
+                p.w64[(size_t)t * p.nbins + dd] = std::exp(-(abs_list[t] * (double)dd));
+        }
+    }
+
+    // Workspace layout.
+    p.hist_all = (d->outputs & PA_OUT_HIST) != 0;
+    size_t o = 0;
+    const size_t popb = align256((size_t)p.R_cap * p.N);
+    p.off_pop[0] = o; o += popb;
+    p.off_pop[1] = o; o += popb;
+    p.off_E = o; o += align256(4 * p.R_cap);
+    p.off_C = o; o += align256(8 * p.R_cap);
+    p.off_r = o; o += align256(4 * p.R_cap);
+    p.off_anc = o; o += align256(4 * p.R_cap);
+    p.off_counts = o; o += align256(4 * p.R_cap);
+    p.off_hist = o; o += align256((size_t)4 * p.nbins * (p.hist_all ? K : 2));
+    p.off_Esum = o; o += align256(8 * (size_t)K);
+    p.off_Emean = o; o += align256(8 * (size_t)K);
+    p.off_count = o; o += align256(8 * (size_t)K);
+    p.off_lnQ = o; o += align256(8 * (size_t)K);
+    p.off_mbF = o; o += align256(8 * (size_t)K);
+    p.off_Eref = o; o += align256(4 * (size_t)K);
+    p.off_W = o; o += align256((size_t)8 * p.nbins * p.n_tables);
+    p.off_w64 = o; o += align256((size_t)8 * p.nbins * p.n_tables);
+    p.total = o;
+    return PA_OK;
+}
+
+}  // namespace
+
+struct pa_ctx {
+    int device;
+    int profiling;
+};
+
+struct pa_run_state {
+    pa_ctx *ctx;
+    Plan plan;
+    uint8_t *ws;
+    hipStream_t stream;
+    uint32_t step;       // current step (population at beta_step)
+    int cur;             // pop buffer holding the current population
+    uint64_t R_cur, R_prev;
+    uint32_t G_log2, wpb;
+    double mbF0;
+    uint32_t first_step;  // step of the initial or loaded population
+    uint64_t R_first;
+    bool broken;
+    struct Timed { int kind; hipEvent_t a, b; };
+    std::vector<Timed> timed;
+    template <typename T> T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
+};
+
+namespace {
+
+pa_status hip_check(pa_run_state *r, hipError_t e, const char *what) {
+    if (e == hipSuccess) return PA_OK;
+    if (r) r->broken = true;
+    return fail(PA_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Launch through `fn`, bracketed by HIP events on the run's stream when the
+// context profiles.
+template <typename F>
+pa_status timed_launch(pa_run_state *r, int kind, const char *what, F fn) {
+    hipEvent_t a = nullptr, b = nullptr;
+    const bool prof = r->ctx && r->ctx->profiling;
+    if (prof) {
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+            return fail(PA_ERR_DEVICE, "hipEventCreate");
+        hipEventRecord(a, r->stream);
+    }
+    pa_status st = hip_check(r, fn(), what);
+    if (prof) {
+        hipEventRecord(b, r->stream);
+        r->timed.push_back({kind, a, b});
+    }
+    return st;
+}
+
+void release_events(pa_run_state *r, double *ms, uint64_t *count) {
+    if (ms) for (int k = 0; k < PA_KERNEL_KINDS; ++k) ms[k] = 0.0;
+    if (count) for (int k = 0; k < PA_KERNEL_KINDS; ++k) count[k] = 0;
+    for (auto &t : r->timed) {
+        float e = 0.f;
+        if (ms && hipEventElapsedTime(&e, t.a, t.b) == hipSuccess) ms[t.kind] += e;
+        if (count) count[t.kind] += 1;
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    r->timed.clear();
+}
+
+uint32_t *hist_of(pa_run_state *r, uint32_t i) {
+    const Plan &p = r->plan;
+    const size_t slot = p.hist_all ? i : (i & 1u);
+    return r->at<uint32_t>(p.off_hist) + slot * p.nbins;
+}
+
+pa_status launch_stats_for(pa_run_state *r, uint32_t i) {
+    const Plan &p = r->plan;
+    pa::StatsArgs s{};
+    s.hist = hist_of(r, i);
+    s.zero_next = (!p.hist_all && i + 1 < p.desc.K) ? hist_of(r, i + 1) : nullptr;
+    s.nbins = p.nbins;
+    s.two_n = (int32_t)(2 * p.N);
+    s.R_i = r->R_cur;
+    s.step = i;
+    s.has_next = (i + 1 < p.desc.K) ? 1u : 0u;
+    s.dbeta_next = s.has_next ? p.dbeta[i + 1] : 0.0;
+    s.w64_next = r->at<double>(p.off_w64) +
+                 (size_t)(s.has_next ? p.table_of_step[i + 1] : 0) * p.nbins;
+    s.E_sum = r->at<int64_t>(p.off_Esum);
+    s.E_mean = r->at<double>(p.off_Emean);
+    s.count = r->at<uint64_t>(p.off_count);
+    s.lnQ = r->at<double>(p.off_lnQ);
+    s.mbF = r->at<double>(p.off_mbF);
+    s.E_ref = r->at<int32_t>(p.off_Eref);
+    return timed_launch(r, PA_KERNEL_STATS, "stats kernel", [&] { return pa::launch_stats(s, r->stream); });
+}
+
+pa::SweepArgs sweep_args(pa_run_state *r, uint32_t i, uint32_t mode, const uint8_t *old_pop,
+                         const uint32_t *anc, uint8_t *new_pop, uint32_t theta) {
+    const Plan &p = r->plan;
+    pa::SweepArgs a{};
+    a.old_pop = old_pop;
+    a.anc = anc;
+    a.new_pop = new_pop;
+    a.E_out = r->at<int32_t>(p.off_E);
+    a.hist = hist_of(r, i);
+    for (int d = 0; d < 4; ++d) a.T[d] = p.T[(size_t)i * 4 + d];
+    a.L = p.desc.L;
+    a.q = p.desc.q;
+    a.N = p.N;
+    a.R_new = (uint32_t)r->R_cur;
+    a.step = i;
+    a.theta = theta;
+    a.mode = mode;
+    a.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
+    a.key1 = (uint32_t)(p.desc.seed >> 32);
+    a.G_log2 = r->G_log2;
+    a.waves_per_block = r->wpb;
+    return a;
+}
+
+pa_status do_step(pa_run_state *r) {
+    const Plan &p = r->plan;
+    const uint32_t i = r->step + 1;
+    const uint64_t R_prev = r->R_cur, R_new = p.R_sched[i];
+    pa_status st;
+    const uint32_t *anc = nullptr;
+    if (p.desc.resample != PA_RESAMPLE_NONE) {
+        const uint32_t tab = p.table_of_step[i];
+        pa::WeightsArgs w{};
+        w.E = r->at<int32_t>(p.off_E);
+        w.E_ref = r->at<int32_t>(p.off_Eref) + i;
+        w.W = r->at<uint64_t>(p.off_W) + (size_t)tab * p.nbins;
+        w.D = p.D[tab];
+        w.R_prev = R_prev;
+        w.C = r->at<uint64_t>(p.off_C);
+        if ((st = timed_launch(r, PA_KERNEL_WEIGHTS, "weights kernel",
+                               [&] { return pa::launch_weights_scan(w, r->stream); })))
+            return st;
+        pa::SampleArgs s{};
+        s.C = w.C;
+        s.R_prev = R_prev;
+        s.n_new = R_new;
+        s.step = i;
+        s.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
+        s.key1 = (uint32_t)(p.desc.seed >> 32);
+        s.r = r->at<uint32_t>(p.off_r);
+        if ((st = timed_launch(r, PA_KERNEL_SAMPLE, "sample kernel",
+                               [&] { return pa::launch_sample(s, r->stream); })))
+            return st;
+        pa::SlotmapArgs m{};
+        m.r = s.r;
+        m.R_prev = R_prev;
+        m.anc = r->at<uint32_t>(p.off_anc);
+        m.anc_cap = p.R_cap;
+        m.counts_last = r->at<uint32_t>(p.off_counts);
+        if ((st = timed_launch(r, PA_KERNEL_SLOTMAP, "slotmap kernel",
+                               [&] { return pa::launch_slotmap(m, r->stream); })))
+            return st;
+        anc = m.anc;
+    } else if (R_new != R_prev) {
+        return fail(PA_ERR_INVALID, "resampling off needs a constant population");
+    }
+    r->R_prev = R_prev;
+    r->R_cur = R_new;
+    const uint8_t *old_pop = r->at<uint8_t>(p.off_pop[r->cur]);
+    uint8_t *new_pop = r->at<uint8_t>(p.off_pop[1 - r->cur]);
+    pa::SweepArgs a = sweep_args(r, i, pa::SWEEP_UPDATE, old_pop, anc, new_pop, p.desc.theta);
+    if ((st = timed_launch(r, PA_KERNEL_SWEEP, "sweep kernel", [&] { return pa::launch_sweep(a, r->stream); })))
+        return st;
+    r->cur = 1 - r->cur;
+    r->step = i;
+    return launch_stats_for(r, i);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pa_status_str(pa_status s) {
+    switch (s) {
+        case PA_OK: return "ok";
+        case PA_ERR_INVALID: return "invalid argument";
+        case PA_ERR_NOMEM: return "workspace too small";
+        case PA_ERR_DEVICE: return "device error";
+        case PA_ERR_CAPACITY: return "population capacity";
+        case PA_ERR_UNSUPPORTED: return "unsupported on this device path";
+    }
+    return "unknown status";
+}
+
+const char *pa_last_error(void) { return g_last_error.c_str(); }
+
+pa_status pa_plan(const pa_run_desc *desc, pa_plan_info *info) {
+    if (!info) return fail(PA_ERR_INVALID, "null plan info");
+    Plan p;
+    pa_status st = build_plan(desc, p, false);
+    if (st) return st;
+    info->R_cap = p.R_cap;
+    info->R_final = p.R_sched.back();
+    info->workspace_bytes = p.total;
+    info->Kb = p.Kb;
+    info->n_tables = p.n_tables;
+    return PA_OK;
+}
+
+pa_status pa_plan_tables(const pa_run_desc *desc, uint64_t *T, uint64_t *R_sched) {
+    Plan p;
+    pa_status st = build_plan(desc, p, false);
+    if (st) return st;
+    if (T) std::memcpy(T, p.T.data(), sizeof(uint64_t) * p.T.size());
+    if (R_sched) std::memcpy(R_sched, p.R_sched.data(), sizeof(uint64_t) * p.R_sched.size());
+    return PA_OK;
+}
+
+pa_status pa_weight_table(double abs_dbeta, uint32_t Kb, uint32_t N, uint64_t *W, uint32_t *D) {
+    if (!W || !D || Kb > 63 || !(abs_dbeta >= 0.0)) return fail(PA_ERR_INVALID, "bad weight table request");
+    *D = weight_table(abs_dbeta, Kb, N, W);
+    return PA_OK;
+}
+
+pa_status pa_ctx_create(int device, pa_ctx **out) {
+    if (!out) return fail(PA_ERR_INVALID, "null output");
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || device < 0 || device >= n)
+        return fail(PA_ERR_DEVICE, "no such HIP device");
+    pa_ctx *c = new (std::nothrow) pa_ctx;
+    if (!c) return fail(PA_ERR_NOMEM, "out of host memory");
+    c->device = device;
+    c->profiling = 0;
+    *out = c;
+    return PA_OK;
+}
+
+void pa_ctx_destroy(pa_ctx *ctx) { delete ctx; }
+
+pa_status pa_ctx_set_profiling(pa_ctx *ctx, int enable) {
+    if (!ctx) return fail(PA_ERR_INVALID, "null context");
+    ctx->profiling = enable ? 1 : 0;
+    return PA_OK;
+}
+
+pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes,
+                       void *stream, pa_run_state **out) {
+    if (!ctx || !out) return fail(PA_ERR_INVALID, "null context or output");
+    pa_run_state *r = new (std::nothrow) pa_run_state;
+    if (!r) return fail(PA_ERR_NOMEM, "out of host memory");
+    pa_status st = build_plan(desc, r->plan, true);
+    if (st) { delete r; return st; }
+    const Plan &p = r->plan;
+    if (!d_ws || ws_bytes < p.total || ((uintptr_t)d_ws & 255u)) {
+        delete r;
+        return fail(PA_ERR_NOMEM, "workspace missing, unaligned or smaller than pa_plan's workspace_bytes");
+    }
+    r->ctx = ctx;
+    r->ws = static_cast<uint8_t *>(d_ws);
+    r->stream = static_cast<hipStream_t>(stream);
+    r->step = 0;
+    r->cur = 0;
+    r->R_cur = p.desc.R;
+    r->R_prev = p.desc.R;
+    r->first_step = 0;
+    r->R_first = p.desc.R;
+    r->broken = false;
+    pa::sweep_shape(p.desc.L, &r->G_log2, &r->wpb);
+    if (pa::sweep_lds_bytes(p.N, r->G_log2, r->wpb) > pa::max_lds_per_block(ctx->device)) {
+        delete r;
+        return fail(PA_ERR_UNSUPPORTED, "lattice does not fit the LDS of one workgroup on this device");
+    }
+    if ((st = hip_check(r, hipSetDevice(ctx->device), "hipSetDevice"))) { delete r; return st; }
+
+    // Tables and initial state.
+    hipStream_t s = r->stream;
+    if ((st = hip_check(r, hipMemcpyAsync(r->ws + p.off_W, p.W.data(), 8 * p.W.size(),
+                                          hipMemcpyHostToDevice, s), "upload W")) ||
+        (st = hip_check(r, hipMemcpyAsync(r->ws + p.off_w64, p.w64.data(), 8 * p.w64.size(),
+                                          hipMemcpyHostToDevice, s), "upload w64"))) {
+        delete r; return st;
+    }
+    const size_t hist_words = (size_t)p.nbins * (p.hist_all ? p.desc.K : 2);
+    if ((st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_hist), hist_words, 0u, s), "fill")) ||
+        (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_r), p.R_cap, 0u, s), "fill")) ||
+        (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_lnQ), 2 * (size_t)p.desc.K, 0u, s), "fill"))) {
+        delete r; return st;
+    }
+    // ln Z at beta_0: N ln q (Z = q^N at beta = 0, Sec. 6) or, for ground
+    // states, ln q + 2N beta_0 (eq. (7)-(8), E_0 = -2N).
+    r->mbF0 = (p.desc.init == PA_INIT_GROUND)
+                  ? std::log((double)p.desc.q) + 2.0 * (double)p.N * p.beta[0]
+                  : (double)p.N * std::log((double)p.desc.q);
+    if ((st = hip_check(r, hipMemcpyAsync(r->ws + p.off_mbF, &r->mbF0, 8, hipMemcpyHostToDevice, s), "upload"))) {
+        delete r; return st;
+    }
+    const uint32_t mode = p.desc.init == PA_INIT_GROUND ? pa::SWEEP_INIT_GROUND : pa::SWEEP_INIT_RANDOM;
+    pa::SweepArgs a = sweep_args(r, 0, mode, nullptr, nullptr, r->at<uint8_t>(p.off_pop[0]), 0);
+    if ((st = timed_launch(r, PA_KERNEL_INIT, "init kernel", [&] { return pa::launch_sweep(a, s); })) ||
+        (st = launch_stats_for(r, 0))) {
+        release_events(r, nullptr, nullptr);
+        delete r; return st;
+    }
+    // The uploads read host memory owned by the run; make sure they are done.
+    if ((st = hip_check(r, hipStreamSynchronize(s), "sync"))) { delete r; return st; }
+    *out = r;
+    return PA_OK;
+}
+
+pa_status pa_run_advance(pa_run_state *r, uint32_t n_steps) {
+    if (!r) return fail(PA_ERR_INVALID, "null run");
+    if (r->broken) return fail(PA_ERR_DEVICE, "run is unusable after a device error");
+    if ((uint64_t)r->step + n_steps > (uint64_t)r->plan.desc.K - 1)
+        return fail(PA_ERR_INVALID, "advancing past the last temperature");
+    for (uint32_t n = 0; n < n_steps; ++n) {
+        pa_status st = do_step(r);
+        if (st) return st;
+    }
+    return PA_OK;
+}
+
+pa_status pa_run_sync(pa_run_state *r) {
+    if (!r) return fail(PA_ERR_INVALID, "null run");
+    return hip_check(r, hipStreamSynchronize(r->stream), "sync");
+}
+
+pa_status pa_run_read(pa_run_state *r, uint32_t *step, uint64_t *R_cur, uint64_t *R_prev,
+                      uint8_t *spins, int32_t *E, uint32_t *anc, uint32_t *counts) {
+    if (!r) return fail(PA_ERR_INVALID, "null run");
+    pa_status st = hip_check(r, hipStreamSynchronize(r->stream), "sync");
+    if (st) return st;
+    const Plan &p = r->plan;
+    if (step) *step = r->step;
+    if (R_cur) *R_cur = r->R_cur;
+    if (R_prev) *R_prev = r->R_prev;
+    struct { void *dst; size_t off, bytes; } cp[4] = {
+        {spins, p.off_pop[r->cur], (size_t)r->R_cur * p.N},
+        {E, p.off_E, 4 * (size_t)r->R_cur},
+        {anc, p.off_anc, 4 * (size_t)r->R_cur},
+        {counts, p.off_counts, 4 * (size_t)r->R_prev},
+    };
+    for (auto &c : cp) {
+        if (!c.dst) continue;
+        if ((st = hip_check(r, hipMemcpy(c.dst, r->ws + c.off, c.bytes, hipMemcpyDeviceToHost), "read")))
+            return st;
+    }
+    return PA_OK;
+}
+
+pa_status pa_run_load(pa_run_state *r, uint32_t step, uint64_t R_cur, const uint8_t *spins,
+                      double minus_beta_F) {
+    if (!r || !spins) return fail(PA_ERR_INVALID, "null run or spins");
+    const Plan &p = r->plan;
+    if (step >= p.desc.K || R_cur < 1 || R_cur > p.R_cap)
+        return fail(PA_ERR_INVALID, "step or population size out of range");
+    pa_status st;
+    hipStream_t s = r->stream;
+    r->step = step;
+    r->R_cur = R_cur;
+    r->R_prev = R_cur;
+    r->first_step = step;
+    r->R_first = R_cur;
+    // Upload into the idle buffer, then recompute E and the histogram with a
+    // sweep of zero rounds into the other buffer.
+    const int idle = 1 - r->cur;
+    if ((st = hip_check(r, hipMemcpyAsync(r->ws + p.off_pop[idle], spins, (size_t)R_cur * p.N,
+                                          hipMemcpyHostToDevice, s), "upload spins")))
+        return st;
+    r->mbF0 = minus_beta_F;
+    if ((st = hip_check(r, hipMemcpyAsync(r->at<double>(p.off_mbF) + step, &r->mbF0, 8,
+                                          hipMemcpyHostToDevice, s), "upload")))
+        return st;
+    if ((st = hip_check(r, pa::launch_fill_u32(hist_of(r, step), p.nbins, 0u, s), "fill")))
+        return st;
+    pa::SweepArgs a = sweep_args(r, step, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[idle]), nullptr,
+                                 r->at<uint8_t>(p.off_pop[r->cur]), 0);
+    if ((st = hip_check(r, pa::launch_sweep(a, s), "load kernel"))) return st;
+    if ((st = launch_stats_for(r, step))) return st;
+    return hip_check(r, hipStreamSynchronize(s), "sync");
+}
+
+pa_status pa_run_read_slots(pa_run_state *r, int previous, const uint32_t *slots, uint32_t n,
+                            uint8_t *spins_out) {
+    if (!r || (n && (!slots || !spins_out))) return fail(PA_ERR_INVALID, "null argument");
+    pa_status st = hip_check(r, hipStreamSynchronize(r->stream), "sync");
+    if (st) return st;
+    const Plan &p = r->plan;
+    const uint64_t R = previous ? r->R_prev : r->R_cur;
+    const size_t off = p.off_pop[previous ? 1 - r->cur : r->cur];
+    for (uint32_t j = 0; j < n; ++j) {
+        if (slots[j] >= R) return fail(PA_ERR_INVALID, "slot out of range");
+        if ((st = hip_check(r, hipMemcpy(spins_out + (size_t)j * p.N, r->ws + off + (size_t)slots[j] * p.N,
+                                         p.N, hipMemcpyDeviceToHost), "read")))
+            return st;
+    }
+    return PA_OK;
+}
+
+pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
+    if (!r) return fail(PA_ERR_INVALID, "null run");
+    pa_status st = hip_check(r, hipStreamSynchronize(r->stream), "sync");
+    const Plan &p = r->plan;
+    const uint32_t K = p.desc.K;
+    if (!st && out) {
+        std::vector<uint64_t> count(K);
+        if (!st) st = hip_check(r, hipMemcpy(count.data(), r->ws + p.off_count, 8 * (size_t)K, hipMemcpyDeviceToHost), "read");
+        for (uint32_t i = r->first_step; !st && i <= r->step; ++i)
+            if (count[i] != (i == r->first_step ? r->R_first : p.R_sched[i]))
+                st = fail(PA_ERR_DEVICE, "population histogram does not add up to R_i");
+        if (!st && out->R_i) {
+            for (uint32_t i = 0; i < K; ++i) out->R_i[i] = p.R_sched[i];
+            out->R_i[r->first_step] = r->R_first;
+        }
+        struct { void *dst; size_t off, bytes; } cp[6] = {
+            {out->E_sum, p.off_Esum, 8 * (size_t)K},
+            {out->E_mean, p.off_Emean, 8 * (size_t)K},
+            {out->lnQ, p.off_lnQ, 8 * (size_t)K},
+            {out->minus_beta_F, p.off_mbF, 8 * (size_t)K},
+            {p.hist_all ? out->hist : nullptr, p.off_hist, 4 * (size_t)K * p.nbins},
+            {nullptr, 0, 0},
+        };
+        for (auto &c : cp) {
+            if (st || !c.dst) continue;
+            st = hip_check(r, hipMemcpy(c.dst, r->ws + c.off, c.bytes, hipMemcpyDeviceToHost), "read");
+        }
+        if (!st && out->lnQ) out->lnQ[0] = 0.0;
+        if (!st && (out->kernel_ms || out->kernel_launches))
+            release_events(r, out->kernel_ms, out->kernel_launches);
+        if (!st && (p.desc.outputs & PA_OUT_FINAL)) {
+            if (out->final_spins)
+                st = hip_check(r, hipMemcpy(out->final_spins, r->ws + p.off_pop[r->cur], (size_t)r->R_cur * p.N, hipMemcpyDeviceToHost), "read");
+            if (!st && out->final_E)
+                st = hip_check(r, hipMemcpy(out->final_E, r->ws + p.off_E, 4 * (size_t)r->R_cur, hipMemcpyDeviceToHost), "read");
+            if (!st && out->last_anc) {
+                if (r->step == 0 || p.desc.resample == PA_RESAMPLE_NONE) {
+                    for (uint64_t k = 0; k < r->R_cur; ++k) out->last_anc[k] = (uint32_t)k;
+                } else {
+                    st = hip_check(r, hipMemcpy(out->last_anc, r->ws + p.off_anc, 4 * (size_t)r->R_cur, hipMemcpyDeviceToHost), "read");
+                }
+            }
+        }
+    }
+    release_events(r, nullptr, nullptr);
+    delete r;
+    return st;
+}
+
+pa_status pa_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes, void *stream,
+                 pa_result *out) {
+    pa_run_state *r = nullptr;
+    pa_status st = pa_run_begin(ctx, desc, d_ws, ws_bytes, stream, &r);
+    if (st) return st;
+    st = pa_run_advance(r, desc->K - 1);
+    pa_status st2 = pa_run_finish(r, out);
+    return st ? st : st2;
+}
+
+}  // extern "C"
