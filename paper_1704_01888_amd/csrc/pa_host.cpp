@@ -261,11 +261,11 @@ pa_status timed_launch(pa_run_state *r, int kind, const char *what, F fn) {
     if (prof) {
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
             return fail(PA_ERR_DEVICE, "hipEventCreate");
-        hipEventRecord(a, r->stream);
+        (void)hipEventRecord(a, r->stream);
     }
     pa_status st = hip_check(r, fn(), what);
     if (prof) {
-        hipEventRecord(b, r->stream);
+        (void)hipEventRecord(b, r->stream);
         r->timed.push_back({kind, a, b});
     }
     return st;
@@ -278,8 +278,8 @@ void release_events(pa_run_state *r, double *ms, uint64_t *count) {
         float e = 0.f;
         if (ms && hipEventElapsedTime(&e, t.a, t.b) == hipSuccess) ms[t.kind] += e;
         if (count) count[t.kind] += 1;
-        hipEventDestroy(t.a);
-        hipEventDestroy(t.b);
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
     }
     r->timed.clear();
 }

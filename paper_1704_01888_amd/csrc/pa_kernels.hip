@@ -25,26 +25,52 @@ constexpr uint32_t PHILOX_M1 = 0xCD9E8D57u;
 constexpr uint32_t PHILOX_W0 = 0x9E3779B9u;
 constexpr uint32_t PHILOX_W1 = 0xBB67AE85u;
 
-// Philox4x32-10 (Salmon et al., SC'11), all in registers.
-__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                        uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)PHILOX_M0 * c0;
+// Philox4x32-10 (Salmon et al., SC'11), all in registers.  The two xors of
+// each output word are one three-input bitop (truth table 0x96 = a ^ b ^ c).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// Rounds 2..10 of Philox after a first round whose product M0 * c0 is given.
+__device__ __forceinline__ uint4 philox_from(uint64_t p0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                             uint32_t k0, uint32_t k1) {
+    {
         const uint64_t p1 = (uint64_t)PHILOX_M1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
-        c0 = n0;
+        uint32_t c0 = n0;
         c2 = n2;
         k0 += PHILOX_W0;
         k1 += PHILOX_W1;
+#pragma unroll
+        for (int r = 1; r < 10; ++r) {
+            const uint64_t q0 = (uint64_t)PHILOX_M0 * c0;
+            const uint64_t q1 = (uint64_t)PHILOX_M1 * c2;
+            const uint32_t m0 = xor3((uint32_t)(q1 >> 32), c1, k0);
+            const uint32_t m2 = xor3((uint32_t)(q0 >> 32), c3, k1);
+            c1 = (uint32_t)q1;
+            c3 = (uint32_t)q0;
+            c0 = m0;
+            c2 = m2;
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        return make_uint4(c0, c1, c2, c3);
     }
-    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+    return philox_from((uint64_t)PHILOX_M0 * c0, c1, c2, c3, k0, k1);
 }
 
 __device__ __forceinline__ uint32_t mulhi32(uint32_t w, uint32_t n) { return __umulhi(w, n); }
+
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+    return __builtin_amdgcn_perm(hi, lo, sel);   // byte sel 0-3 from lo, 4-7 from hi
+}
 
 // Number of equal bytes between two words.
 __device__ __forceinline__ uint32_t eq_bytes(uint32_t a, uint32_t b) {
@@ -53,17 +79,127 @@ __device__ __forceinline__ uint32_t eq_bytes(uint32_t a, uint32_t b) {
     return 4u - __popc(nz);
 }
 
-// Metropolis update of one site (Sec. 2 step 3 with the proposal and
-// acceptance arithmetic of the header comment of pa.h).
-__device__ __forceinline__ uint32_t update_site(uint32_t s, uint32_t l, uint32_t r, uint32_t u,
-                                                uint32_t d, uint32_t w_prop, uint32_t w_acc,
-                                                uint32_t qm1, const uint64_t *Ttab) {
+// Acceptance thresholds in LDS, indexed by dE + 4.  Entries for dE <= 0 accept
+// always.  T64: the exact 64-bit form "w < T" with T <= 2^32; otherwise the
+// 32-bit form "w <= T - 1", valid when every T >= 1 (the host checks).
+template <bool T64>
+struct Thresholds {
+    const void *tab;
+    __device__ __forceinline__ bool accept(uint32_t idx, uint32_t w) const {
+        if (T64) return static_cast<const uint64_t *>(tab)[idx] > (uint64_t)w;
+        return w <= static_cast<const uint32_t *>(tab)[idx];
+    }
+};
+
+// Metropolis update of one site (Sec. 2 step 3; proposal and acceptance as in
+// the header comment of pa.h).  sb = current spin in all four bytes, n = the
+// four neighbours, one per byte.  Returns the new spin in all four bytes.
+// With q <= 128 every byte of n ^ sb has bit 7 clear, so adding 0x7F to each
+// byte never carries into the next one and bit 7 of the sum marks a differing
+// byte; for larger q the low seven bits are masked first.
+template <bool QSMALL, bool T64>
+__device__ __forceinline__ uint32_t site_update(uint32_t sb, uint32_t n, uint32_t w_prop,
+                                                uint32_t w_acc, uint32_t qm1,
+                                                const Thresholds<T64> &thr) {
+    const uint32_t s = sb & 0xFFu;
     const uint32_t rr = mulhi32(w_prop, qm1);
     const uint32_t sp = rr + (rr >= s ? 1u : 0u);
-    const int dE = (int)(l == s) + (int)(r == s) + (int)(u == s) + (int)(d == s)
-                 - (int)(l == sp) - (int)(r == sp) - (int)(u == sp) - (int)(d == sp);
-    const uint64_t T = Ttab[dE + 4];
-    return (T > (uint64_t)w_acc) ? sp : s;
+    const uint32_t spb = perm(0u, sp, 0u);                 // broadcast byte 0
+    const uint32_t xa = n ^ sb, xb = n ^ spb;
+    uint32_t eq_a, ne_b;
+    if (QSMALL) {
+        eq_a = ~(xa + 0x7F7F7F7Fu) & 0x80808080u;
+        ne_b = (xb + 0x7F7F7F7Fu) & 0x80808080u;
+    } else {
+        eq_a = ~(((xa & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | xa) & 0x80808080u;
+        ne_b = (((xb & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | xb) & 0x80808080u;
+    }
+    // #equal(current) + #unequal(proposed) = 4 + dE
+    uint32_t idx = __popc(ne_b) + __popc(eq_a);
+    asm volatile("" : "+v"(idx));   // keep the index one add (no re-association)
+    return thr.accept(idx, w_acc) ? spb : sb;
+}
+
+// Per-parity constants of a pair update (see update_pair).
+struct PairSel {
+    uint32_t selH, selV, sel0, sel1, mask;
+    PairSel() = default;
+    __device__ __forceinline__ explicit PairSel(uint32_t par) {
+        const uint32_t pb = par * 0x01010101u;
+        selH = par ? 0x04020200u : 0x03010107u;
+        selV = 0x06020400u + pb;
+        sel0 = pb;
+        sel1 = pb + 0x02020202u;
+        mask = 0x00FF00FFu << (par << 3);
+    }
+};
+
+// Update of the two colour-c sites x0 = xb + par and x0 + 2 held in the row
+// dword D0 (bytes xb..xb+3).  Dx is the dword left of D0 (par = 0) or right of
+// it (par = 1); U and Dn are the dwords above and below.
+template <bool QSMALL, bool T64>
+__device__ __forceinline__ uint32_t update_pair(uint32_t D0, uint32_t Dx, uint32_t U, uint32_t Dn,
+                                                const PairSel &ps, uint4 w, uint32_t qm1,
+                                                const Thresholds<T64> &thr) {
+    const uint32_t H = perm(Dx, D0, ps.selH);            // x0-1, x0+1, x0+1, x0+3
+    const uint32_t V = perm(Dn, U, ps.selV);             // up0, down0, up1, down1
+    const uint32_t n0 = perm(V, H, 0x05040100u);
+    const uint32_t n1 = perm(V, H, 0x07060302u);
+    const uint32_t sb0 = perm(0u, D0, ps.sel0);
+    const uint32_t sb1 = perm(0u, D0, ps.sel1);
+    const uint32_t t0 = site_update<QSMALL, T64>(sb0, n0, w.x, w.y, qm1, thr);
+    const uint32_t t1 = site_update<QSMALL, T64>(sb1, n1, w.z, w.w, qm1, thr);
+    const uint32_t X = perm(t1, t0, 0x05040100u);         // s0', s0', s1', s1'
+    return (X & ps.mask) | (D0 & ~ps.mask);
+}
+
+// Philox for the sweep counter (p, k, step, c3) with k, step, c3 and the key
+// wave-uniform: the first two rounds are half scalar.  P0 = M0 * p.
+struct SweepKey {
+    uint32_t n0, n1, c3k1, k0[10], k1[10];
+};
+
+__device__ __forceinline__ SweepKey sweep_key(uint32_t k, uint32_t step, uint32_t c3, uint32_t key0,
+                                              uint32_t key1) {
+    SweepKey s;
+    uint32_t a0 = key0, a1 = key1;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        s.k0[r] = a0;
+        s.k1[r] = a1;
+        a0 += PHILOX_W0;
+        a1 += PHILOX_W1;
+    }
+    const uint64_t p1 = (uint64_t)PHILOX_M1 * step;
+    s.n0 = (uint32_t)(p1 >> 32) ^ k ^ key0;
+    s.n1 = (uint32_t)p1;
+    s.c3k1 = c3 ^ key1;
+    return s;
+}
+
+__device__ __forceinline__ uint4 philox_sweep(uint64_t P0, const SweepKey &s) {
+    // round 1
+    const uint32_t a2 = (uint32_t)(P0 >> 32) ^ s.c3k1;
+    const uint32_t a3 = (uint32_t)P0;
+    // round 2: M0 * n0 is uniform
+    const uint64_t q0 = (uint64_t)PHILOX_M0 * s.n0;
+    const uint64_t q1 = (uint64_t)PHILOX_M1 * a2;
+    uint32_t c0 = (uint32_t)(q1 >> 32) ^ (s.n1 ^ s.k0[1]);
+    uint32_t c1 = (uint32_t)q1;
+    uint32_t c2 = a3 ^ ((uint32_t)(q0 >> 32) ^ s.k1[1]);
+    uint32_t c3 = (uint32_t)q0;
+#pragma unroll
+    for (int r = 2; r < 10; ++r) {
+        const uint64_t r0 = (uint64_t)PHILOX_M0 * c0;
+        const uint64_t r1 = (uint64_t)PHILOX_M1 * c2;
+        const uint32_t m0 = xor3((uint32_t)(r1 >> 32), c1, s.k0[r]);
+        const uint32_t m2 = xor3((uint32_t)(r0 >> 32), c3, s.k1[r]);
+        c1 = (uint32_t)r1;
+        c3 = (uint32_t)r0;
+        c0 = m0;
+        c2 = m2;
+    }
+    return make_uint4(c0, c1, c2, c3);
 }
 
 __device__ __forceinline__ void wave_fence() {
@@ -71,14 +207,120 @@ __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Replica layout in LDS: rows -1 .. L of L bytes each; row r at byte (r+1)*L.
+// Rows -1 and L are copies of rows L-1 and 0 (periodic halo), kept current by
+// the lanes that update rows L-1 and 0.
+//
+// Fixed L (a power of two): lane g of the replica's G lanes owns dword column
+// xd = g mod L/4 and rows y0 + j*RS (y0 = g div L/4, RS = G / (L/4)), so all
+// its addresses are the base plus compile-time offsets and its parity per
+// unrolled slot is fixed.
+template <uint32_t LT, bool QSMALL>
+__device__ __forceinline__ void sweeps_fixed(uint32_t *lds32, uint32_t g, uint32_t k,
+                                             const SweepArgs &a, const Thresholds<false> &thr,
+                                             uint32_t theta) {
+    constexpr uint32_t L = LT, N = L * L, P = N / 4, DPR = L / 4;
+    constexpr uint32_t G = P < 64 ? P : 64;
+    constexpr uint32_t PPL = P / G, RS = G / DPR;
+    constexpr uint32_t UNR = PPL >= 2 ? 2 : 1;
+    static_assert(G % DPR == 0 && P % G == 0 && PPL % UNR == 0, "shape");
+    const uint32_t xd = g % DPR, y0 = g / DPR;
+    const int32_t dl = xd == 0 ? (int32_t)(DPR - 1) : -1;
+    const int32_t dr = xd == DPR - 1 ? -(int32_t)(DPR - 1) : 1;
+    const uint32_t base = (y0 + 1) * DPR + xd;
+    const uint64_t mg = (uint64_t)PHILOX_M0 * g;                    // M0 * first pair
+    constexpr uint64_t MSTEP = (uint64_t)PHILOX_M0 * G;              // M0 * pair stride
+    const uint32_t qm1 = a.q - 1u;
+    const bool top = y0 == 0, bottom = y0 + (PPL - 1) * RS == L - 1;
+    for (uint32_t t = 0; t < theta; ++t) {
+        for (uint32_t c = 0; c < 2u; ++c) {
+            const SweepKey key = sweep_key(k, a.step, (DOM_SWEEP << 28) | (t << 1) | c, a.key0, a.key1);
+            // parity of unrolled slot u (j is a multiple of UNR, and RS * UNR is even
+            // unless PPL == 1)
+            PairSel ps[UNR];
+            int32_t dx[UNR];
+#pragma unroll
+            for (uint32_t u = 0; u < UNR; ++u) {
+                const uint32_t par = (y0 + u * RS + c) & 1u;
+                ps[u] = PairSel(par);
+                dx[u] = par ? dr : dl;
+            }
+            uint64_t P0 = mg;
+            for (uint32_t j = 0; j < PPL; j += UNR) {
+                uint32_t idx[UNR], D0[UNR], Dx[UNR], U[UNR], Dn[UNR];
+                uint4 w[UNR];
+#pragma unroll
+                for (uint32_t u = 0; u < UNR; ++u) {
+                    idx[u] = base + (j + u) * RS * DPR;
+                    D0[u] = lds32[idx[u]];
+                    Dx[u] = lds32[idx[u] + dx[u]];
+                    U[u] = lds32[idx[u] - DPR];
+                    Dn[u] = lds32[idx[u] + DPR];
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < UNR; ++u) w[u] = philox_sweep(P0 + u * MSTEP, key);
+                P0 += UNR * MSTEP;
+#pragma unroll
+                for (uint32_t u = 0; u < UNR; ++u) {
+                    const uint32_t nw = update_pair<QSMALL, false>(D0[u], Dx[u], U[u], Dn[u], ps[u],
+                                                                   w[u], qm1, thr);
+                    lds32[idx[u]] = nw;
+                    if (j + u == 0 && top) lds32[idx[u] + L * DPR] = nw;
+                    if (j + u == PPL - 1 && bottom) lds32[idx[u] - L * DPR] = nw;
+                }
+            }
+            wave_fence();
+        }
+    }
+}
+
+// Any L divisible by 4: pairs visited with an incremental (row, column) walk.
+template <bool QSMALL, bool T64>
+__device__ __forceinline__ void sweeps_any(uint32_t *lds32, uint32_t g, uint32_t G, uint32_t k,
+                                           const SweepArgs &a, const Thresholds<T64> &thr,
+                                           uint32_t theta) {
+    const uint32_t L = a.L, N = a.N, H = L >> 1, P = N >> 2, DPR = L >> 2;
+    const uint32_t step2G = 2u * G;
+    const uint32_t dy = step2G / H, dj = step2G % H;
+    const uint32_t qm1 = a.q - 1u;
+    for (uint32_t t = 0; t < theta; ++t) {
+        for (uint32_t c = 0; c < 2u; ++c) {
+            const SweepKey key = sweep_key(k, a.step, (DOM_SWEEP << 28) | (t << 1) | c, a.key0, a.key1);
+            uint32_t y = (2u * g) / H, j0 = (2u * g) % H;
+            for (uint32_t p = g; p < P; p += G) {
+                const uint32_t par = (y + c) & 1u;
+                const uint32_t xd = j0 >> 1;                       // dword column
+                const uint32_t idx = (y + 1) * DPR + xd;
+                const uint32_t xo = par ? (xd == DPR - 1 ? idx - (DPR - 1) : idx + 1)
+                                        : (xd == 0 ? idx + (DPR - 1) : idx - 1);
+                const uint32_t D0 = lds32[idx], Dx = lds32[xo];
+                const uint32_t U = lds32[idx - DPR], Dn = lds32[idx + DPR];
+                const uint4 w = philox_sweep((uint64_t)PHILOX_M0 * p, key);
+                const uint32_t nw = update_pair<QSMALL, T64>(D0, Dx, U, Dn, PairSel(par), w, qm1, thr);
+                lds32[idx] = nw;
+                if (y == 0) lds32[idx + L * DPR] = nw;
+                if (y == L - 1) lds32[idx - L * DPR] = nw;
+                j0 += dj;
+                if (j0 >= H) { j0 -= H; ++y; }
+                y += dy;
+            }
+            wave_fence();
+        }
+    }
+}
+
+template <uint32_t LT, bool QSMALL, bool T64>
 __global__ void __launch_bounds__(256) k_sweep(SweepArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
-    uint64_t *Ttab = reinterpret_cast<uint64_t *>(smem);          // [9], index dE + 4
+    // thresholds indexed by dE + 4
     if (threadIdx.x < 9) {
         const int dE = (int)threadIdx.x - 4;
-        Ttab[threadIdx.x] = dE <= 0 ? (1ull << 32) : a.T[dE - 1];
+        const uint64_t T = dE <= 0 ? (1ull << 32) : a.T[dE - 1];
+        if (T64) reinterpret_cast<uint64_t *>(smem)[threadIdx.x] = T;
+        else reinterpret_cast<uint32_t *>(smem)[threadIdx.x] = (uint32_t)(T - 1u);
     }
     __syncthreads();
+    const Thresholds<T64> thr{smem};
 
     const uint32_t G_log2 = a.G_log2;
     const uint32_t G = 1u << G_log2;
@@ -91,88 +333,52 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a) {
     const uint64_t first_in_wave = (uint64_t)blockIdx.x * a.waves_per_block * rpw + wave * rpw;
     if (first_in_wave >= a.R_new) return;                        // whole wave idle
     const bool live = k64 < a.R_new;
-    const uint32_t k = (uint32_t)k64;
+    const uint32_t k = rpw == 1 ? __builtin_amdgcn_readfirstlane((uint32_t)k64) : (uint32_t)k64;
 
-    const uint32_t L = a.L, N = a.N;
-    uint8_t *rep_lds = smem + 128 + (size_t)rep * N;
+    const uint32_t L = a.L, N = a.N, DPR = L >> 2;
+    uint8_t *rep_lds = smem + 128 + (size_t)rep * (N + 2 * L);
     uint32_t *lds32 = reinterpret_cast<uint32_t *>(rep_lds);
+    uint32_t *rows32 = lds32 + DPR;                              // row 0
 
     // ---- load or create the replica in LDS -----------------------------
     if (a.mode == SWEEP_UPDATE) {
         const uint32_t src = live ? (a.anc ? a.anc[k] : k) : 0u;
         const uint4 *gsrc = reinterpret_cast<const uint4 *>(a.old_pop + (size_t)src * N);
-        uint4 *ldst = reinterpret_cast<uint4 *>(rep_lds);
+        uint4 *ldst = reinterpret_cast<uint4 *>(rep_lds + L);
         for (uint32_t o = g; o < N / 16u; o += G) ldst[o] = live ? gsrc[o] : make_uint4(0, 0, 0, 0);
     } else if (a.mode == SWEEP_INIT_RANDOM) {
         // Site n takes word n mod 4 of Philox(n / 4, k, 0, INIT).
         for (uint32_t dd = g; dd < N / 4u; dd += G) {
             const uint4 w = philox(dd, k, 0u, DOM_INIT << 28, a.key0, a.key1);
-            lds32[dd] = mulhi32(w.x, a.q) | (mulhi32(w.y, a.q) << 8) | (mulhi32(w.z, a.q) << 16) |
-                        (mulhi32(w.w, a.q) << 24);
+            rows32[dd] = mulhi32(w.x, a.q) | (mulhi32(w.y, a.q) << 8) | (mulhi32(w.z, a.q) << 16) |
+                         (mulhi32(w.w, a.q) << 24);
         }
     } else {
         // eq. (6): all spins alpha, alpha uniform over the q states.
         const uint4 w = philox(0u, k, 0u, DOM_GROUND << 28, a.key0, a.key1);
         const uint32_t alpha = mulhi32(w.x, a.q) * 0x01010101u;
-        for (uint32_t dd = g; dd < N / 4u; dd += G) lds32[dd] = alpha;
+        for (uint32_t dd = g; dd < N / 4u; dd += G) rows32[dd] = alpha;
+    }
+    wave_fence();
+    for (uint32_t dd = g; dd < DPR; dd += G) {                   // periodic halo rows
+        lds32[dd] = rows32[(L - 1) * DPR + dd];
+        lds32[(L + 1) * DPR + dd] = rows32[dd];
     }
     wave_fence();
 
     // ---- theta checkerboard sweeps --------------------------------------
     const uint32_t theta = (a.mode == SWEEP_UPDATE) ? a.theta : 0u;
-    const uint32_t H = L >> 1;                 // colour-c sites per row
-    const uint32_t P = N >> 2;                 // pairs per half-sweep
-    const uint32_t step2G = 2u * G;
-    const uint32_t dy = step2G / H, dj = step2G % H;
-    const uint32_t qm1 = a.q - 1u;
-    for (uint32_t t = 0; t < theta; ++t) {
-        for (uint32_t c = 0; c < 2u; ++c) {
-            const uint32_t c3 = (DOM_SWEEP << 28) | (t << 1) | c;
-            uint32_t y = (2u * g) / H, j0 = (2u * g) % H;
-            for (uint32_t p = g; p < P; p += G) {
-                const uint32_t par = (y + c) & 1u;
-                const uint32_t xb = 2u * j0;                       // dword column, x0 = xb + par
-                const uint32_t rowY = y * L;
-                const uint32_t rowU = (y == 0 ? L - 1u : y - 1u) * L;
-                const uint32_t rowD = (y == L - 1u ? 0u : y + 1u) * L;
-                const uint32_t xo = par ? (xb + 4u == L ? 0u : xb + 4u) : (xb == 0u ? L - 4u : xb - 4u);
-                const uint32_t D0 = lds32[(rowY + xb) >> 2];
-                const uint32_t Dx = lds32[(rowY + xo) >> 2];
-                const uint32_t U = lds32[(rowU + xb) >> 2];
-                const uint32_t Dn = lds32[(rowD + xb) >> 2];
-
-                // bytes x0-1, x0, x0+1, x1 = x0+2 in lo; x1+1 in b4
-                const uint32_t lo = par ? D0 : __builtin_amdgcn_alignbyte(D0, Dx, 3);
-                const uint32_t b4 = par ? (Dx & 0xFFu) : (D0 >> 24);
-                const uint32_t sh = par << 3;
-                const uint32_t Us = U >> sh, Ds = Dn >> sh;
-
-                const uint4 w = philox(p, k, a.step, c3, a.key0, a.key1);
-                const uint32_t s0 = update_site((lo >> 8) & 0xFFu, lo & 0xFFu, (lo >> 16) & 0xFFu,
-                                                Us & 0xFFu, Ds & 0xFFu, w.x, w.y, qm1, Ttab);
-                const uint32_t s1 = update_site(lo >> 24, (lo >> 16) & 0xFFu, b4,
-                                                (Us >> 16) & 0xFFu, (Ds >> 16) & 0xFFu, w.z, w.w,
-                                                qm1, Ttab);
-                const uint32_t mask = 0x00FF00FFu << sh;
-                const uint32_t val = (s0 | (s1 << 16)) << sh;
-                lds32[(rowY + xb) >> 2] = (D0 & ~mask) | val;
-
-                j0 += dj;
-                if (j0 >= H) { j0 -= H; ++y; }
-                y += dy;
-            }
-            wave_fence();
-        }
-    }
+    if constexpr (LT != 0) sweeps_fixed<LT, QSMALL>(lds32, g, k, a, thr, theta);
+    else sweeps_any<QSMALL, T64>(lds32, g, G, k, a, thr, theta);
 
     // ---- energy (eq. (3)), histogram, store ------------------------------
-    const uint32_t dpr = L >> 2;               // dwords per row
     uint32_t bonds = 0;
     for (uint32_t dd = g; dd < N / 4u; dd += G) {
-        const uint32_t y = dd / dpr, xb = (dd - y * dpr) * 4u;
-        const uint32_t D = lds32[dd];
-        const uint32_t Dr = lds32[(y * L + (xb + 4u == L ? 0u : xb + 4u)) >> 2];
-        const uint32_t Dd = lds32[((y == L - 1u ? 0u : y + 1u) * L + xb) >> 2];
+        const uint32_t xd = dd % DPR;
+        const uint32_t idx = DPR + dd;
+        const uint32_t D = lds32[idx];
+        const uint32_t Dr = lds32[xd == DPR - 1 ? idx - (DPR - 1) : idx + 1];
+        const uint32_t Dd = lds32[idx + DPR];
         const uint32_t right = __builtin_amdgcn_alignbyte(Dr, D, 1);
         bonds += eq_bytes(D, right) + eq_bytes(D, Dd);
     }
@@ -184,7 +390,7 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a) {
             atomicAdd(&a.hist[(uint32_t)(E + 2 * (int32_t)N)], 1u);
         }
         uint4 *gdst = reinterpret_cast<uint4 *>(a.new_pop + (size_t)k * N);
-        const uint4 *lsrc = reinterpret_cast<const uint4 *>(rep_lds);
+        const uint4 *lsrc = reinterpret_cast<const uint4 *>(rep_lds + L);
         for (uint32_t o = g; o < N / 16u; o += G) gdst[o] = lsrc[o];
     }
 }
@@ -378,12 +584,14 @@ void sweep_shape(uint32_t L, uint32_t *G_log2, uint32_t *waves_per_block) {
     const uint32_t N = L * L;
     const uint32_t rpw = 64u >> gl;
     uint32_t wpb = 4;
-    while (wpb > 1 && (size_t)wpb * rpw * N > 32768u) wpb >>= 1;
+    while (wpb > 1 && (size_t)wpb * rpw * (N + 2 * L) > 32768u) wpb >>= 1;
     *waves_per_block = wpb;
 }
 
 size_t sweep_lds_bytes(uint32_t N, uint32_t G_log2, uint32_t waves_per_block) {
-    return 128u + (size_t)waves_per_block * (64u >> G_log2) * N;
+    uint32_t L = 0;
+    while (L * L < N) ++L;
+    return 128u + (size_t)waves_per_block * (64u >> G_log2) * (N + 2 * L);
 }
 
 size_t max_lds_per_block(int device) {
@@ -399,12 +607,25 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t s) {
     const uint64_t blocks = (a.R_new + per_block - 1) / per_block;
     if (blocks == 0) return hipSuccess;
     const size_t lds = sweep_lds_bytes(a.N, a.G_log2, a.waves_per_block);
+    // The 32-bit threshold form needs every T >= 1 (T decreases with dE).
+    const bool t64 = a.T[3] == 0;
+    const bool qs = a.q <= 128;
+    void (*kern)(SweepArgs) = qs ? (t64 ? k_sweep<0, true, true> : k_sweep<0, true, false>)
+                                 : (t64 ? k_sweep<0, false, true> : k_sweep<0, false, false>);
+    if (!t64) {
+#define PA_FIXED(LV) case LV: kern = qs ? k_sweep<LV, true, false> : k_sweep<LV, false, false>; break;
+        switch (a.L) {
+            PA_FIXED(4) PA_FIXED(8) PA_FIXED(16) PA_FIXED(32) PA_FIXED(64) PA_FIXED(128) PA_FIXED(256)
+            default: break;
+        }
+#undef PA_FIXED
+    }
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_sweep, dim3((uint32_t)blocks), dim3(64u * a.waves_per_block), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3((uint32_t)blocks), dim3(64u * a.waves_per_block), lds, s, a);
     return hipGetLastError();
 }
 
