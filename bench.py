@@ -29,19 +29,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Potts spin-flip attempts/ns on 1 MI355X (batched vs plain), p99 run latency"
 
-# MI355X 32-bit VALU issue peak: the fp32 vector rate 157.3 TFLOP/s is one FMA
-# (2 flops) per lane-op, i.e. 78.6e12 full-rate lane-ops/s = 256 CUs x 128
-# lanes/clock x 2.4 GHz (a dependent-free xor stream measures 75.7e12/s).
-VALU_PEAK_LANE_OPS = 256 * 128 * 2.4e9
+# VALU issue peak of MI355X for the instructions the sweep is made of:
+# 256 CUs x 64 lanes/clock x 2.4 GHz = 39.3e12 lane-ops/s.  Measured on the
+# device with dependent-free streams of one instruction kind: v_perm_b32,
+# v_bitop3_b32, v_bcnt_u32_b32, v_add3_u32, v_cmp + v_cndmask issue at
+# 36.7-38.3e12/s; v_mad_u64_u32 at 33.6e12/s (1.17 slots); v_mul_hi_u32 at
+# 20.8e12/s (1.9 slots).  (Plain VOP2 xor issues at twice the peak, 75e12/s;
+# the fp32 vector rate 157.3 TFLOP/s counts packed FMA.)
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
-# Issue slots per spin-flip attempt the sweep's arithmetic needs (see the
-# design notes): half a Philox4x32-10 block (10 rounds x 2 wide 32x32->64
-# multiplies and 2 three-input xors, per 2 attempts -> 10 multiplies, 10 xors),
-# one 32x32 high multiply for the proposal, 8 equality tests accumulated into
-# dE (16 ops), proposal fix-up (2), threshold lookup, compare and select (3).
-# A wide multiply costs MUL_SLOTS issue slots (quarter rate).
-MUL_SLOTS = 4
-OPS_PER_ATTEMPT = 11 * MUL_SLOTS + 10 + 16 + 2 + 3
+# Issue slots per spin-flip attempt of the sweep kernel (32x32 instance), from
+# its AMD assembly: the inner block updates 4 pairs (8 attempts) with 295 VALU
+# instructions, 73 of them v_mad_u64_u32 (Philox and the proposal), i.e. 36.9
+# instructions (9.1 wide multiplies) per attempt; the SQ_INSTS_VALU counter
+# agrees (38.6 per attempt including the gather/energy epilogue).  Weighted:
+# (36.9 - 9.1) + 9.1 * 1.17 = 38.5 slots.
+INSTR_PER_ATTEMPT = 295 / 8
+MAD_PER_ATTEMPT = 73 / 8
+MAD_SLOTS = 1.17
+OPS_PER_ATTEMPT = (INSTR_PER_ATTEMPT - MAD_PER_ATTEMPT) + MAD_PER_ATTEMPT * MAD_SLOTS
+
+# HBM bytes per k_sweep launch on this workload, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by 2.00 and 1.00, the factors a plain 256 MiB copy gives):
+# (7568.2 * 2 + 20781.1) KiB; profiles/k_sweep_32x32_q10_R20000.md.  The
+# algorithmic bytes are 2 * R * N = 41 MB (gather + store); repeated ancestors
+# are served from cache.
+SWEEP_TRAFFIC_BYTES = (7568.2 * 2.0 + 20781.1) * 1024
 
 WORKLOAD = dict(L=32, q=10, R=20000, K=401, beta_max=1.6, theta=10, seed=2)
 
@@ -107,26 +120,28 @@ def main():
         pa.pa_run(ctx, desc, workspace=ws)
     torch.cuda.synchronize()
 
-    ctx.set_profiling(True)
     total_att = 0.0
-    kernel_ms = np.zeros(len(pa.KERNEL_NAMES))
-    kernel_n = np.zeros(len(pa.KERNEL_NAMES))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out = pa.pa_run(ctx, desc, workspace=ws)
         total_att += attempts_of(out["R_i"], desc.theta, N)
-        kernel_ms += out["kernel_ms"]
-        kernel_n += out["kernel_launches"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ctx.set_profiling(False)
-
     value = total_att / dt / 1e9
+
+    # One more run, outside the timed region, with every kernel bracketed by
+    # HIP events on the run's stream: per-kernel durations.
+    ctx.set_profiling(True)
+    prof = pa.pa_run(ctx, desc, workspace=ws)
+    ctx.set_profiling(False)
+    kernel_ms = prof["kernel_ms"]
+    kernel_n = prof["kernel_launches"]
+    prof_att = attempts_of(prof["R_i"], desc.theta, N)
     sweep = pa.KERNEL_NAMES.index("sweep")
     sweep_s = kernel_ms[sweep] / 1e3
     sweep_avg_ms = kernel_ms[sweep] / max(kernel_n[sweep], 1)
-    sweep_rate = total_att / sweep_s if sweep_s > 0 else 0.0   # attempts/s inside the sweep kernel
+    sweep_rate = prof_att / sweep_s if sweep_s > 0 else 0.0   # attempts/s inside the sweep kernel
     achieved = sweep_rate * OPS_PER_ATTEMPT / 1e12
     peak = VALU_PEAK_LANE_OPS / 1e12
     result = {
@@ -156,12 +171,12 @@ def main():
             "peak": peak,
             "unit": "T lane-ops/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": SWEEP_TRAFFIC_BYTES,
             "ops_per_attempt": OPS_PER_ATTEMPT,
             "sweep_attempts_per_ns": sweep_rate / 1e9,
             "sweep_avg_launch_ms": sweep_avg_ms,
         },
-        "kernel_ms_per_run": {k: float(v) / args.steps for k, v in zip(pa.KERNEL_NAMES, kernel_ms)},
+        "kernel_ms_per_run": {k: float(v) for k, v in zip(pa.KERNEL_NAMES, kernel_ms)},
     }
     if args.cpu_steps > 0:
         result["cpu_baseline"] = cpu_baseline(args.cpu_steps)

@@ -86,13 +86,11 @@ typedef struct {
 
 /* Kernel kinds, for the optional per-kernel timing of pa_result. */
 enum {
-    PA_KERNEL_INIT = 0,     /* initial population + energies (step 1)         */
-    PA_KERNEL_SWEEP = 1,    /* gather + theta sweeps + energies (eq. (1), step 3) */
-    PA_KERNEL_STATS = 2,    /* sums, E_ref, ln Q (eq. (2), (4))              */
-    PA_KERNEL_WEIGHTS = 3,  /* weights + inclusive scan (step 2)             */
-    PA_KERNEL_SAMPLE = 4,   /* multinomial draws (step 2)                    */
-    PA_KERNEL_SLOTMAP = 5,  /* copy numbers -> ancestors (eq. (1))           */
-    PA_KERNEL_KINDS = 6
+    PA_KERNEL_INIT = 0,     /* initial population + energies (step 1)               */
+    PA_KERNEL_SWEEP = 1,    /* gather + theta sweeps + energies (eq. (1), step 3)   */
+    PA_KERNEL_POST = 2,     /* sums, E_ref, ln Q (eq. (2), (4)) + weight scan (step 2) */
+    PA_KERNEL_RESAMPLE = 3, /* multinomial draws + copy numbers -> ancestors (eq. (1)) */
+    PA_KERNEL_KINDS = 4
 };
 
 /* Host result buffers, caller-allocated; arrays of length K unless noted. */

@@ -21,7 +21,7 @@ PA_OK, PA_ERR_INVALID, PA_ERR_NOMEM, PA_ERR_DEVICE, PA_ERR_CAPACITY, PA_ERR_UNSU
 RESAMPLE_POISSON, RESAMPLE_MULTINOMIAL, RESAMPLE_NONE = 0, 1, 2
 INIT_RANDOM, INIT_GROUND = 0, 1
 OUT_HIST, OUT_FINAL = 1, 4
-KERNEL_NAMES = ("init", "sweep", "stats", "weights_scan", "sample", "slotmap")
+KERNEL_NAMES = ("init", "sweep", "post", "resample")
 
 EXPORTS = [
     "pa_plan", "pa_plan_tables", "pa_weight_table", "pa_ctx_create", "pa_ctx_destroy",

@@ -29,7 +29,8 @@ struct SweepArgs {
     uint32_t waves_per_block;
 };
 
-struct StatsArgs {
+struct PostArgs {
+    // population statistics of step i
     const uint32_t *hist;     // [2N+1] population at step i
     uint32_t *zero_next;      // histogram buffer to clear for step i+1, or nullptr
     uint32_t nbins;           // 2N+1
@@ -45,15 +46,12 @@ struct StatsArgs {
     double *lnQ;              // [K]
     double *mbF;              // [K]   -beta F
     int32_t *E_ref;           // [K]   reference energy used by step i+1
-};
-
-struct WeightsArgs {
-    const int32_t *E;         // [R_prev]
-    const int32_t *E_ref;     // device scalar
-    const uint64_t *W;        // [D] fixed-point weights
+    // weights of the resampling to step i+1
+    uint32_t do_weights;
+    const int32_t *E;         // [R_i] energies of the population at step i
+    const uint64_t *W;        // [D] fixed-point weights of step i+1
     uint32_t D;
-    uint64_t R_prev;
-    uint64_t *C;              // [R_prev] inclusive prefix sums
+    uint64_t *C;              // [R_i] inclusive prefix sums
 };
 
 struct SampleArgs {
@@ -70,14 +68,13 @@ struct SlotmapArgs {
     uint64_t R_prev;
     uint32_t *anc;            // [anc_cap]
     uint64_t anc_cap;         // capacity of anc (writes beyond it are dropped)
-    uint32_t *counts_last;    // [R_prev] copy of the counts, or nullptr
+    uint32_t *counts_last;    // [R_prev] copy of the counts
 };
 
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t s);
-hipError_t launch_stats(const StatsArgs &a, hipStream_t s);
-hipError_t launch_weights_scan(const WeightsArgs &a, hipStream_t s);
-hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
-hipError_t launch_slotmap(const SlotmapArgs &a, hipStream_t s);
+hipError_t launch_post(const PostArgs &a, hipStream_t s);
+// multinomial draws (k_sample), then count scan + slot map (k_countfill)
+hipError_t launch_resample(const SampleArgs &a, const SlotmapArgs &m, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 
 // Lanes per replica and waves per block chosen for a lattice side L.

@@ -290,9 +290,10 @@ uint32_t *hist_of(pa_run_state *r, uint32_t i) {
     return r->at<uint32_t>(p.off_hist) + slot * p.nbins;
 }
 
-pa_status launch_stats_for(pa_run_state *r, uint32_t i) {
+// Statistics of step i, ln Q_{i+1}, and the weights of the resampling to i+1.
+pa_status launch_post_for(pa_run_state *r, uint32_t i) {
     const Plan &p = r->plan;
-    pa::StatsArgs s{};
+    pa::PostArgs s{};
     s.hist = hist_of(r, i);
     s.zero_next = (!p.hist_all && i + 1 < p.desc.K) ? hist_of(r, i + 1) : nullptr;
     s.nbins = p.nbins;
@@ -301,15 +302,20 @@ pa_status launch_stats_for(pa_run_state *r, uint32_t i) {
     s.step = i;
     s.has_next = (i + 1 < p.desc.K) ? 1u : 0u;
     s.dbeta_next = s.has_next ? p.dbeta[i + 1] : 0.0;
-    s.w64_next = r->at<double>(p.off_w64) +
-                 (size_t)(s.has_next ? p.table_of_step[i + 1] : 0) * p.nbins;
+    const uint32_t tab = s.has_next ? p.table_of_step[i + 1] : 0;
+    s.w64_next = r->at<double>(p.off_w64) + (size_t)tab * p.nbins;
     s.E_sum = r->at<int64_t>(p.off_Esum);
     s.E_mean = r->at<double>(p.off_Emean);
     s.count = r->at<uint64_t>(p.off_count);
     s.lnQ = r->at<double>(p.off_lnQ);
     s.mbF = r->at<double>(p.off_mbF);
     s.E_ref = r->at<int32_t>(p.off_Eref);
-    return timed_launch(r, PA_KERNEL_STATS, "stats kernel", [&] { return pa::launch_stats(s, r->stream); });
+    s.do_weights = (s.has_next && p.desc.resample != PA_RESAMPLE_NONE) ? 1u : 0u;
+    s.E = r->at<int32_t>(p.off_E);
+    s.W = r->at<uint64_t>(p.off_W) + (size_t)tab * p.nbins;
+    s.D = p.D.empty() ? 0u : p.D[tab];
+    s.C = r->at<uint64_t>(p.off_C);
+    return timed_launch(r, PA_KERNEL_POST, "post kernel", [&] { return pa::launch_post(s, r->stream); });
 }
 
 pa::SweepArgs sweep_args(pa_run_state *r, uint32_t i, uint32_t mode, const uint8_t *old_pop,
@@ -343,36 +349,24 @@ pa_status do_step(pa_run_state *r) {
     pa_status st;
     const uint32_t *anc = nullptr;
     if (p.desc.resample != PA_RESAMPLE_NONE) {
-        const uint32_t tab = p.table_of_step[i];
-        pa::WeightsArgs w{};
-        w.E = r->at<int32_t>(p.off_E);
-        w.E_ref = r->at<int32_t>(p.off_Eref) + i;
-        w.W = r->at<uint64_t>(p.off_W) + (size_t)tab * p.nbins;
-        w.D = p.D[tab];
-        w.R_prev = R_prev;
-        w.C = r->at<uint64_t>(p.off_C);
-        if ((st = timed_launch(r, PA_KERNEL_WEIGHTS, "weights kernel",
-                               [&] { return pa::launch_weights_scan(w, r->stream); })))
-            return st;
+        // C (inclusive weight scan over the step i-1 population) was written
+        // by the post kernel of step i-1.
         pa::SampleArgs s{};
-        s.C = w.C;
+        s.C = r->at<uint64_t>(p.off_C);
         s.R_prev = R_prev;
         s.n_new = R_new;
         s.step = i;
         s.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
         s.key1 = (uint32_t)(p.desc.seed >> 32);
         s.r = r->at<uint32_t>(p.off_r);
-        if ((st = timed_launch(r, PA_KERNEL_SAMPLE, "sample kernel",
-                               [&] { return pa::launch_sample(s, r->stream); })))
-            return st;
         pa::SlotmapArgs m{};
         m.r = s.r;
         m.R_prev = R_prev;
         m.anc = r->at<uint32_t>(p.off_anc);
         m.anc_cap = p.R_cap;
         m.counts_last = r->at<uint32_t>(p.off_counts);
-        if ((st = timed_launch(r, PA_KERNEL_SLOTMAP, "slotmap kernel",
-                               [&] { return pa::launch_slotmap(m, r->stream); })))
+        if ((st = timed_launch(r, PA_KERNEL_RESAMPLE, "resample kernel",
+                               [&] { return pa::launch_resample(s, m, r->stream); })))
             return st;
         anc = m.anc;
     } else if (R_new != R_prev) {
@@ -387,7 +381,7 @@ pa_status do_step(pa_run_state *r) {
         return st;
     r->cur = 1 - r->cur;
     r->step = i;
-    return launch_stats_for(r, i);
+    return launch_post_for(r, i);
 }
 
 }  // namespace
@@ -512,7 +506,7 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
     const uint32_t mode = p.desc.init == PA_INIT_GROUND ? pa::SWEEP_INIT_GROUND : pa::SWEEP_INIT_RANDOM;
     pa::SweepArgs a = sweep_args(r, 0, mode, nullptr, nullptr, r->at<uint8_t>(p.off_pop[0]), 0);
     if ((st = timed_launch(r, PA_KERNEL_INIT, "init kernel", [&] { return pa::launch_sweep(a, s); })) ||
-        (st = launch_stats_for(r, 0))) {
+        (st = launch_post_for(r, 0))) {
         release_events(r, nullptr, nullptr);
         delete r; return st;
     }
@@ -590,7 +584,7 @@ pa_status pa_run_load(pa_run_state *r, uint32_t step, uint64_t R_cur, const uint
     pa::SweepArgs a = sweep_args(r, step, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[idle]), nullptr,
                                  r->at<uint8_t>(p.off_pop[r->cur]), 0);
     if ((st = hip_check(r, pa::launch_sweep(a, s), "load kernel"))) return st;
-    if ((st = launch_stats_for(r, step))) return st;
+    if ((st = launch_post_for(r, step))) return st;
     return hip_check(r, hipStreamSynchronize(s), "sync");
 }
 

@@ -5,11 +5,11 @@
 //                    gather of each new replica from its ancestor (eq. (1)) plus
 //                    theta checkerboard Metropolis sweeps (step 3) held in LDS,
 //                    then the energy of eq. (3) and the population histogram.
-//   k_stats        : population sums for eq. (4), the reference energy and
-//                    ln Q of step 2 / eq. (2) in FP64 (one workgroup).
-//   k_weights_scan : integer weights W(|E_j - E_ref|) and their inclusive scan.
+//   k_post         : population sums for eq. (4), the reference energy and
+//                    ln Q of step 2 / eq. (2) in FP64, then the integer weights
+//                    W(|E_j - E_ref|) of the next resampling and their scan.
 //   k_sample       : the multinomial draws of the resampling step.
-//   k_slotmap      : exclusive scan of the copy numbers -> ancestor of each new slot.
+//   k_countfill    : exclusive scan of the copy numbers -> ancestor of each new slot.
 //
 // One replica lives inside one wavefront (G = 4..64 lanes of it), so the two
 // half-sweeps of a sweep need no workgroup barrier: LDS operations of a wave
@@ -68,6 +68,15 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
 
 __device__ __forceinline__ uint32_t mulhi32(uint32_t w, uint32_t n) { return __umulhi(w, n); }
 
+// floor(w * n / 2^32) through the full 32x32->64 multiply: v_mad_u64_u32
+// issues at about twice the rate of v_mul_hi_u32 on gfx950, but the compiler
+// picks the latter when only the high half is used.
+__device__ __forceinline__ uint32_t mulhi32_wide(uint32_t w, uint32_t n) {
+    uint64_t prod, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(prod), "=s"(carry) : "v"(w), "s"(n));
+    return (uint32_t)(prod >> 32);
+}
+
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
     return __builtin_amdgcn_perm(hi, lo, sel);   // byte sel 0-3 from lo, 4-7 from hi
 }
@@ -102,7 +111,7 @@ __device__ __forceinline__ uint32_t site_update(uint32_t sb, uint32_t n, uint32_
                                                 uint32_t w_acc, uint32_t qm1,
                                                 const Thresholds<T64> &thr) {
     const uint32_t s = sb & 0xFFu;
-    const uint32_t rr = mulhi32(w_prop, qm1);
+    const uint32_t rr = mulhi32_wide(w_prop, qm1);
     const uint32_t sp = rr + (rr >= s ? 1u : 0u);
     const uint32_t spb = perm(0u, sp, 0u);                 // broadcast byte 0
     const uint32_t xa = n ^ sb, xb = n ^ spb;
@@ -404,52 +413,60 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// Exclusive scan of one value per thread over a 1024-thread block; returns the
-// exclusive prefix and writes the total to *total.
+// Exclusive scan of one value per thread over the block; *total receives the
+// block sum.  scratch holds blockDim/64 + 1 entries.
 template <typename T>
-__device__ T block_exclusive_scan(T v, T *scratch /*[16]*/, T *total) {
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+__device__ __forceinline__ T block_exclusive_scan(T v, T *scratch, T *total) {
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     T incl = v;
+#pragma unroll
     for (uint32_t off = 1; off < 64; off <<= 1) {
-        T n = __shfl_up(incl, off, 64);
+        const T n = __shfl_up(incl, off, 64);
         if (lane >= off) incl += n;
     }
     if (lane == 63) scratch[wave] = incl;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        T run = 0;
-        for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) {
-            T s = scratch[w];
-            scratch[w] = run;
-            run += s;
+    if (wave == 0) {
+        T w = lane < nw ? scratch[lane] : T(0);
+        T wi = w;
+#pragma unroll
+        for (uint32_t off = 1; off < 16; off <<= 1) {
+            const T n = __shfl_up(wi, off, 64);
+            if (lane >= off) wi += n;
         }
-        scratch[16] = run;
+        if (lane < nw) scratch[lane] = wi - w;
+        if (lane == nw - 1) scratch[nw] = wi;
     }
     __syncthreads();
-    T res = scratch[wave] + incl - v;
-    *total = scratch[16];
+    const T res = scratch[wave] + incl - v;
+    *total = scratch[nw];
     __syncthreads();
     return res;
 }
 
+constexpr uint32_t TILE_V = 32;  // elements per thread per tile in the one-workgroup weight scan
+constexpr uint32_t FILL_V = 16;  // elements per thread per tile in the count scan + slot map
+
 // ---------------------------------------------------------------------------
-// k_stats: eq. (4) sums and ln Q_{i+1} of Sec. 2 step 2 from the histogram.
+// k_post(i): population sums of eq. (4) and ln Q_{i+1} of Sec. 2 step 2 /
+// eq. (2) from the energy histogram of step i, then (if resampling follows)
+// the integer weights W(|E_j - E_ref|) of step i+1 and their inclusive scan C.
+// One workgroup; histogram bins and energies are read with coalesced loads.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_stats(StatsArgs a) {
+__global__ void __launch_bounds__(1024) k_post(PostArgs a) {
     __shared__ int64_t s_esum[16];
     __shared__ uint64_t s_cnt[16];
     __shared__ int32_t s_min[16], s_max[16];
     __shared__ double s_w[16];
     __shared__ int32_t s_ref;
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    __shared__ uint64_t scratch[17];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nw = blockDim.x >> 6;
     const uint32_t nb = a.nbins;
-    const uint32_t chunk = (nb + blockDim.x - 1) / blockDim.x;
-    const uint32_t b0 = tid * chunk, b1 = min(nb, b0 + chunk);
 
     int64_t esum = 0;
     uint64_t cnt = 0;
     int32_t bmin = 0x7fffffff, bmax = -1;
-    for (uint32_t b = b0; b < b1; ++b) {
+    for (uint32_t b = tid; b < nb; b += blockDim.x) {
         const uint32_t h = a.hist[b];
         if (h) {
             esum += (int64_t)h * ((int32_t)b - a.two_n);
@@ -468,7 +485,7 @@ __global__ void __launch_bounds__(1024) k_stats(StatsArgs a) {
     __syncthreads();
     if (tid == 0) {
         int64_t E = 0; uint64_t C = 0; int32_t mn = 0x7fffffff, mx = -1;
-        for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) {
+        for (uint32_t w = 0; w < nw; ++w) {
             E += s_esum[w]; C += s_cnt[w]; mn = min(mn, s_min[w]); mx = max(mx, s_max[w]);
         }
         a.E_sum[a.step] = E;
@@ -478,23 +495,20 @@ __global__ void __launch_bounds__(1024) k_stats(StatsArgs a) {
         if (a.has_next) a.E_ref[a.step + 1] = s_ref;
     }
     __syncthreads();
+    const int32_t ref = s_ref;
 
     if (a.has_next) {
-        const int32_t ref = s_ref;
         double acc = 0.0;
-        for (uint32_t b = b0; b < b1; ++b) {
+        for (uint32_t b = tid; b < nb; b += blockDim.x) {
             const uint32_t h = a.hist[b];
-            if (h) {
-                const int32_t dd = abs((int32_t)b - a.two_n - ref);
-                acc += (double)h * a.w64_next[dd];
-            }
+            if (h) acc += (double)h * a.w64_next[abs((int32_t)b - a.two_n - ref)];
         }
         acc = wave_sum(acc);
         if (lane == 0) s_w[wave] = acc;
         __syncthreads();
         if (tid == 0) {
             double S = 0.0;
-            for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) S += s_w[w];
+            for (uint32_t w = 0; w < nw; ++w) S += s_w[w];
             const double lnq = -a.dbeta_next * (double)ref + log(S) - log((double)a.R_i);
             a.lnQ[a.step + 1] = lnq;
             a.mbF[a.step + 1] = a.mbF[a.step] + lnq;
@@ -502,34 +516,108 @@ __global__ void __launch_bounds__(1024) k_stats(StatsArgs a) {
     }
     if (a.zero_next)
         for (uint32_t b = tid; b < nb; b += blockDim.x) a.zero_next[b] = 0u;
-}
 
-// ---------------------------------------------------------------------------
-// k_weights_scan: C_j = sum_{j' <= j} W(|E_j' - E_ref|)  (one workgroup).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t weight_of(const WeightsArgs &a, int32_t ref, uint64_t j) {
-    const uint32_t dd = (uint32_t)abs(a.E[j] - ref);
-    return dd < a.D ? a.W[dd] : 0ull;
-}
-
-__global__ void __launch_bounds__(1024) k_weights_scan(WeightsArgs a) {
-    __shared__ uint64_t scratch[17];
-    const int32_t ref = *a.E_ref;
-    const uint64_t n = a.R_prev;
-    const uint64_t chunk = (n + blockDim.x - 1) / blockDim.x;
-    const uint64_t j0 = (uint64_t)threadIdx.x * chunk, j1 = min(n, j0 + chunk);
-    uint64_t local = 0;
-    for (uint64_t j = j0; j < j1; ++j) local += weight_of(a, ref, j);
-    uint64_t total;
-    uint64_t run = block_exclusive_scan<uint64_t>(local, scratch, &total);
-    for (uint64_t j = j0; j < j1; ++j) {
-        run += weight_of(a, ref, j);
-        a.C[j] = run;
+    if (!a.do_weights) return;
+    // C_j = sum_{j' <= j} W(|E_j' - E_ref|), tiles of blockDim * TILE_V elements
+    const uint64_t n = a.R_i;
+    uint64_t carry = 0;
+    for (uint64_t base = 0; base < n; base += (uint64_t)blockDim.x * TILE_V) {
+        const uint64_t j0 = base + (uint64_t)tid * TILE_V;
+        int32_t e[TILE_V];
+        if (j0 + TILE_V <= n) {
+            const int4 *src = reinterpret_cast<const int4 *>(a.E + j0);
+#pragma unroll
+            for (uint32_t v = 0; v < TILE_V / 4; ++v) {
+                const int4 x = src[v];
+                e[4 * v] = x.x; e[4 * v + 1] = x.y; e[4 * v + 2] = x.z; e[4 * v + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (uint32_t v = 0; v < TILE_V; ++v) e[v] = j0 + v < n ? a.E[j0 + v] : ref + (int32_t)a.D;
+        }
+        uint64_t w[TILE_V];
+        uint64_t local = 0;
+#pragma unroll
+        for (uint32_t v = 0; v < TILE_V; ++v) {
+            const uint32_t dd = (uint32_t)abs(e[v] - ref);
+            w[v] = dd < a.D ? a.W[dd] : 0ull;
+            local += w[v];
+        }
+        uint64_t total;
+        uint64_t run = carry + block_exclusive_scan<uint64_t>(local, scratch, &total);
+#pragma unroll
+        for (uint32_t v = 0; v < TILE_V; ++v) {
+            run += w[v];
+            w[v] = run;
+        }
+        if (j0 + TILE_V <= n) {
+            ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(a.C + j0);
+#pragma unroll
+            for (uint32_t v = 0; v < TILE_V; v += 2) dst[v / 2] = make_ulonglong2(w[v], w[v + 1]);
+        } else {
+#pragma unroll
+            for (uint32_t v = 0; v < TILE_V; ++v)
+                if (j0 + v < n) a.C[j0 + v] = w[v];
+        }
+        carry += total;
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_sample: draw kk picks the first j with C_j > floor(x_kk * S / 2^64).
+// Count scan and slot map: o = exclusive scan of the copy numbers r;
+// anc[o_j + c] = j for c < r_j (new population in ancestor order, eq. (1));
+// r is cleared for the next step.  Run by one whole workgroup.
+// ---------------------------------------------------------------------------
+__device__ void countfill_block(const SlotmapArgs &a, uint64_t *scratch) {
+    const uint32_t tid = threadIdx.x;
+    const uint64_t n = a.R_prev;
+    uint64_t carry = 0;
+    for (uint64_t base = 0; base < n; base += (uint64_t)blockDim.x * FILL_V) {
+        const uint64_t j0 = base + (uint64_t)tid * FILL_V;
+        uint32_t r[FILL_V];
+        const bool full = j0 + FILL_V <= n;
+        if (full) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(a.r + j0);
+#pragma unroll
+            for (uint32_t v = 0; v < FILL_V / 4; ++v) {
+                const uint4 x = src[v];
+                r[4 * v] = x.x; r[4 * v + 1] = x.y; r[4 * v + 2] = x.z; r[4 * v + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (uint32_t v = 0; v < FILL_V; ++v) r[v] = j0 + v < n ? a.r[j0 + v] : 0u;
+        }
+        uint64_t local = 0;
+#pragma unroll
+        for (uint32_t v = 0; v < FILL_V; ++v) local += r[v];
+        uint64_t total;
+        uint64_t o = carry + block_exclusive_scan<uint64_t>(local, scratch, &total);
+#pragma unroll
+        for (uint32_t v = 0; v < FILL_V; ++v) {
+            for (uint32_t c = 0; c < r[v]; ++c)
+                if (o + c < a.anc_cap) a.anc[o + c] = (uint32_t)(j0 + v);
+            o += r[v];
+        }
+        if (full) {
+            uint4 *cnt = reinterpret_cast<uint4 *>(a.counts_last + j0);
+            uint4 *rz = reinterpret_cast<uint4 *>(a.r + j0);
+#pragma unroll
+            for (uint32_t v = 0; v < FILL_V / 4; ++v) {
+                cnt[v] = make_uint4(r[4 * v], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
+                rz[v] = make_uint4(0, 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (uint32_t v = 0; v < FILL_V; ++v)
+                if (j0 + v < n) { a.counts_last[j0 + v] = r[v]; a.r[j0 + v] = 0u; }
+        }
+        carry += total;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_sample: draw kk picks the first j with C_j > floor(x_kk * S / 2^64) and
+// counts it in r_j.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
     const uint64_t kk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -546,26 +634,9 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
     atomicAdd(&a.r[lo], 1u);
 }
 
-// ---------------------------------------------------------------------------
-// k_slotmap: anc[o_j + c] = j for c < r_j, o = exclusive scan of r (one workgroup).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_slotmap(SlotmapArgs a) {
+__global__ void __launch_bounds__(1024) k_countfill(SlotmapArgs m) {
     __shared__ uint64_t scratch[17];
-    const uint64_t n = a.R_prev;
-    const uint64_t chunk = (n + blockDim.x - 1) / blockDim.x;
-    const uint64_t j0 = (uint64_t)threadIdx.x * chunk, j1 = min(n, j0 + chunk);
-    uint64_t local = 0;
-    for (uint64_t j = j0; j < j1; ++j) local += a.r[j];
-    uint64_t total;
-    uint64_t o = block_exclusive_scan<uint64_t>(local, scratch, &total);
-    for (uint64_t j = j0; j < j1; ++j) {
-        const uint32_t rj = a.r[j];
-        for (uint32_t c = 0; c < rj; ++c)
-            if (o + c < a.anc_cap) a.anc[o + c] = (uint32_t)j;
-        o += rj;
-        if (a.counts_last) a.counts_last[j] = rj;
-        a.r[j] = 0u;
-    }
+    countfill_block(m, scratch);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
@@ -629,25 +700,15 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_stats(const StatsArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, s, a);
+hipError_t launch_post(const PostArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_post, dim3(1), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_weights_scan(const WeightsArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_weights_scan, dim3(1), dim3(1024), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_sample(const SampleArgs &a, hipStream_t s) {
+hipError_t launch_resample(const SampleArgs &a, const SlotmapArgs &m, hipStream_t s) {
     const uint64_t blocks = (a.n_new + 255) / 256;
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sample, dim3((uint32_t)blocks), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_slotmap(const SlotmapArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_slotmap, dim3(1), dim3(1024), 0, s, a);
+    if (blocks) hipLaunchKernelGGL(k_sample, dim3((uint32_t)blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_countfill, dim3(1), dim3(1024), 0, s, m);
     return hipGetLastError();
 }
 
