@@ -71,6 +71,36 @@ def attempts_of(R_i, theta, N):
     return float(theta) * float(N) * float(np.asarray(R_i[1:], dtype=np.float64).sum())
 
 
+def batched_vs_plain(pa, torch, ctx, runs, reps=1):
+    """The same runs as separate pa_run calls and as one pa_run_batch."""
+    descs = [pa.Desc(**r) for r in runs]
+    att = sum(float(r["theta"]) * r["L"] ** 2 * float(np.sum(pa.pa_plan_tables(d)[1][1:]))
+              for r, d in zip(runs, descs))
+    ws_b = torch.empty(pa.pa_plan_batch(descs), dtype=torch.uint8, device="cuda:0")
+    ws_p = torch.empty(max(pa.pa_plan(d).workspace_bytes for d in descs), dtype=torch.uint8,
+                       device="cuda:0")
+    for d in descs[:2]:
+        pa.pa_run(ctx, d, workspace=ws_p)
+    pa.pa_run_batch(ctx, descs, workspace=ws_b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for d in descs:
+            pa.pa_run(ctx, d, workspace=ws_p)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pa.pa_run_batch(ctx, descs, workspace=ws_b)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    del ws_b, ws_p
+    return {"runs": len(runs), "attempts": att,
+            "plain_attempts_per_ns": att / t_plain / 1e9, "plain_ms": t_plain * 1e3,
+            "batched_attempts_per_ns": att / t_batch / 1e9, "batched_ms": t_batch * 1e3,
+            "speedup": t_plain / t_batch}
+
+
 def cpu_baseline(n_steps: int):
     """The oracle on the host cores: the same workload cut to its first
     n_steps temperature steps."""
@@ -95,6 +125,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain lines")
     ap.add_argument("--cpu-steps", type=int, default=12,
                     help="temperature steps of the oracle's CPU-baseline sample (0 = skip)")
     args = ap.parse_args()
@@ -178,6 +209,14 @@ def main():
         },
         "kernel_ms_per_run": {k: float(v) for k, v in zip(pa.KERNEL_NAMES, kernel_ms)},
     }
+    if not args.no_batched:
+        from paper_1704_01888_amd import workloads
+        result["batched"] = {
+            "20 runs of 8x8 q=8 R=1000, 200 steps, theta=10, multinomial":
+                batched_vs_plain(pa, torch, ctx, workloads.small_runs(20), reps=3),
+            "20 runs L in {16..64}, q in {5..20}, R in [1e4,1e5], 300 steps, theta=10, Poisson":
+                batched_vs_plain(pa, torch, ctx, workloads.mixed_runs(20), reps=1),
+        }
     if args.cpu_steps > 0:
         result["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(result), flush=True)

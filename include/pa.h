@@ -174,6 +174,15 @@ pa_status pa_run_read_slots(pa_run_state *run, int previous, const uint32_t *slo
                             uint8_t *spins_out);
 pa_status pa_run_finish(pa_run_state *run, pa_result *out);
 
+/* Batched runs: n independent PA runs (any mix of L, q, R, K, theta, seeds,
+ * resampling and init modes) advanced together, one set of segmented launches
+ * per global step g for every run with K > g.  Results are identical to n
+ * separate pa_run calls.  pa_plan_batch gives the workspace size (the runs'
+ * workspaces plus the per-step descriptor tables); outs[n] as in pa_run. */
+pa_status pa_plan_batch(const pa_run_desc *descs, uint32_t n, uint64_t *workspace_bytes);
+pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_t n, void *d_ws,
+                       uint64_t ws_bytes, void *stream, pa_result *outs);
+
 const char *pa_status_str(pa_status s);
 const char *pa_last_error(void);
 

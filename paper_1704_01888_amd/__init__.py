@@ -28,6 +28,7 @@ EXPORTS = [
     "pa_ctx_set_profiling",
     "pa_run", "pa_run_begin", "pa_run_advance", "pa_run_sync", "pa_run_read", "pa_run_load",
     "pa_run_read_slots", "pa_run_finish", "pa_status_str", "pa_last_error",
+    "pa_plan_batch", "pa_run_batch",
 ]
 
 
@@ -94,13 +95,15 @@ def lib() -> ctypes.CDLL:
     L.pa_run_load.argtypes = [vp, u32, u64, vp, dbl]
     L.pa_run_finish.argtypes = [vp, P(Result)]
     L.pa_run_read_slots.argtypes = [vp, ctypes.c_int, vp, u32, vp]
+    L.pa_plan_batch.argtypes = [P(RunDesc), u32, P(u64)]
+    L.pa_run_batch.argtypes = [vp, P(RunDesc), u32, vp, u64, vp, P(Result)]
     L.pa_status_str.argtypes = [i32]
     L.pa_status_str.restype = ctypes.c_char_p
     L.pa_last_error.argtypes = []
     L.pa_last_error.restype = ctypes.c_char_p
     for name in ("pa_plan", "pa_plan_tables", "pa_weight_table", "pa_ctx_create", "pa_run",
                  "pa_run_begin", "pa_run_advance", "pa_run_sync", "pa_run_read", "pa_run_load",
-                 "pa_run_read_slots", "pa_run_finish"):
+                 "pa_run_read_slots", "pa_run_finish", "pa_plan_batch", "pa_run_batch"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -299,3 +302,32 @@ class Run:
                 lib().pa_run_finish(self.handle, None)
             except Exception:
                 pass
+
+
+def _desc_array(descs):
+    arr = (RunDesc * len(descs))()
+    for i, d in enumerate(descs):
+        arr[i] = d.c()
+    return arr
+
+
+def pa_plan_batch(descs) -> int:
+    n = ctypes.c_uint64(0)
+    arr = _desc_array(descs)
+    _check(lib().pa_plan_batch(arr, len(descs), ctypes.byref(n)))
+    return int(n.value)
+
+
+def pa_run_batch(ctx: Context, descs, workspace=None):
+    """Several independent runs advanced together; returns one result dict per run."""
+    ws_bytes = pa_plan_batch(descs)
+    ws = workspace if workspace is not None else _workspace(ws_bytes, ctx.device)
+    outs, ress = [], (Result * len(descs))()
+    for i, d in enumerate(descs):
+        o, r = _alloc_result(d, pa_plan(d))
+        outs.append(o)
+        ress[i] = r
+    arr = _desc_array(descs)
+    _check(lib().pa_run_batch(ctx.handle, arr, len(descs), ctypes.c_void_p(ws.data_ptr()),
+                              ws.numel(), _stream_ptr(), ress))
+    return outs

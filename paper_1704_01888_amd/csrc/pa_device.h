@@ -77,6 +77,15 @@ hipError_t launch_post(const PostArgs &a, hipStream_t s);
 hipError_t launch_resample(const SampleArgs &a, const SlotmapArgs &m, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 
+// Batched forms: several runs per launch.  Sweep launches group runs of one
+// kernel class (sweep_class); `start` [n+1] gives each run's first workgroup.
+uint32_t sweep_class(uint32_t L, uint32_t q, bool t64);
+hipError_t launch_sweep_batch(uint32_t cls, const SweepArgs *runs, const uint32_t *start, uint32_t n,
+                              uint32_t blocks, uint32_t threads, size_t lds, hipStream_t s);
+hipError_t launch_post_batch(const PostArgs *runs, uint32_t n, hipStream_t s);
+hipError_t launch_resample_batch(const SampleArgs *sruns, const uint32_t *start, uint32_t n,
+                                 uint32_t blocks, const SlotmapArgs *mruns, hipStream_t s);
+
 // Lanes per replica and waves per block chosen for a lattice side L.
 void sweep_shape(uint32_t L, uint32_t *G_log2, uint32_t *waves_per_block);
 size_t sweep_lds_bytes(uint32_t N, uint32_t G_log2, uint32_t waves_per_block);

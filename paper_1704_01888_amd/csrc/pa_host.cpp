@@ -9,6 +9,7 @@
 #include "pa.h"
 #include "pa_device.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -652,6 +653,260 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
     release_events(r, nullptr, nullptr);
     delete r;
     return st;
+}
+
+// ---------------------------------------------------------------------------
+// Batched runs: every run keeps its own workspace region and plan; per global
+// step g one set of segmented launches advances every run with K > g.  All
+// sizes are known from the plans, so the per-step descriptor tables are built
+// once on the host and uploaded once.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchLayout {
+    std::vector<Plan> plans;
+    std::vector<size_t> run_off;   // byte offset of each run's region
+    size_t desc_off = 0;           // descriptor tables
+    size_t desc_bytes = 0;
+    size_t total = 0;
+    uint32_t max_K = 0;
+};
+
+pa_status batch_layout(const pa_run_desc *descs, uint32_t n, BatchLayout &b, bool tables) {
+    if (!descs || n == 0) return fail(PA_ERR_INVALID, "empty batch");
+    b.plans.resize(n);
+    b.run_off.resize(n);
+    size_t o = 0;
+    b.max_K = 0;
+    for (uint32_t r = 0; r < n; ++r) {
+        pa_status st = build_plan(&descs[r], b.plans[r], tables);
+        if (st) return st;
+        b.run_off[r] = o;
+        o += align256(b.plans[r].total);
+        if (descs[r].K > b.max_K) b.max_K = descs[r].K;
+    }
+    // descriptor tables: per global step, sample / slot map / sweep / post
+    // records of the active runs (upper bound: every run active every step)
+    const size_t per_step = align256(n * sizeof(pa::SampleArgs)) + align256((n + 1) * 4) +
+                            align256(n * sizeof(pa::SlotmapArgs)) +
+                            align256(n * sizeof(pa::SweepArgs)) + align256(2 * (n + 1) * 4 + 4 * n) +
+                            align256(n * sizeof(pa::PostArgs));
+    b.desc_off = o;
+    b.desc_bytes = per_step * (b.max_K > 1 ? b.max_K - 1 : 1);
+    o += b.desc_bytes;
+    b.total = o;
+    return PA_OK;
+}
+
+struct StepLaunch {
+    // offsets into the descriptor region
+    size_t sample_off, sample_start_off, slot_off, sweep_off, sweep_start_off, post_off;
+    uint32_t n_res, sample_blocks, n_post;
+    struct Group { uint32_t cls, first, count, blocks, threads; size_t lds; };
+    std::vector<Group> groups;
+};
+
+}  // namespace
+
+extern "C" pa_status pa_plan_batch(const pa_run_desc *descs, uint32_t n, uint64_t *workspace_bytes) {
+    if (!workspace_bytes) return fail(PA_ERR_INVALID, "null output");
+    BatchLayout b;
+    pa_status st = batch_layout(descs, n, b, false);
+    if (st) return st;
+    *workspace_bytes = b.total;
+    return PA_OK;
+}
+
+extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_t n, void *d_ws,
+                                  uint64_t ws_bytes, void *stream, pa_result *outs) {
+    if (!ctx) return fail(PA_ERR_INVALID, "null context");
+    BatchLayout b;
+    pa_status st = batch_layout(descs, n, b, false);
+    if (st) return st;
+    if (!d_ws || ws_bytes < b.total || ((uintptr_t)d_ws & 255u))
+        return fail(PA_ERR_NOMEM, "workspace missing, unaligned or smaller than pa_plan_batch's size");
+    uint8_t *ws = static_cast<uint8_t *>(d_ws);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    // Initial populations (step 0) of every run.
+    std::vector<pa_run_state *> runs(n, nullptr);
+    auto cleanup = [&](pa_status code) {
+        for (auto *r : runs)
+            if (r) pa_run_finish(r, nullptr);
+        return code;
+    };
+    for (uint32_t r = 0; r < n; ++r) {
+        st = pa_run_begin(ctx, &descs[r], ws + b.run_off[r], align256(b.plans[r].total), stream, &runs[r]);
+        if (st) {
+            const std::string msg = g_last_error;
+            cleanup(st);
+            return fail(st, "run " + std::to_string(r) + ": " + msg);
+        }
+    }
+
+    // Descriptor tables for every global step.
+    std::vector<uint8_t> blob(b.desc_bytes, 0);
+    std::vector<StepLaunch> steps;
+    size_t cursor = 0;
+    auto take = [&](size_t bytes) { size_t at = cursor; cursor += align256(bytes); return at; };
+    for (uint32_t g = 1; g < b.max_K; ++g) {
+        StepLaunch L{};
+        std::vector<pa::SampleArgs> sa;
+        std::vector<uint32_t> sstart;
+        std::vector<pa::SlotmapArgs> sm;
+        std::vector<pa::PostArgs> po;
+        struct SW { uint32_t cls, blocks, threads; size_t lds; pa::SweepArgs a; };
+        std::vector<SW> sw;
+        uint32_t sblocks = 0;
+        for (uint32_t ri = 0; ri < n; ++ri) {
+            pa_run_state *r = runs[ri];
+            const Plan &p = r->plan;
+            if (g >= p.desc.K) continue;
+            const uint64_t R_prev = p.R_sched[g - 1], R_new = p.R_sched[g];
+            const uint32_t prev_buf = (g - 1) & 1u, new_buf = g & 1u;
+            const uint32_t *anc = nullptr;
+            if (p.desc.resample != PA_RESAMPLE_NONE) {
+                pa::SampleArgs a{};
+                a.C = r->at<uint64_t>(p.off_C);
+                a.R_prev = R_prev;
+                a.n_new = R_new;
+                a.step = g;
+                a.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
+                a.key1 = (uint32_t)(p.desc.seed >> 32);
+                a.r = r->at<uint32_t>(p.off_r);
+                sstart.push_back(sblocks);
+                sblocks += (uint32_t)((R_new + 255) / 256);
+                sa.push_back(a);
+                pa::SlotmapArgs m{};
+                m.r = a.r;
+                m.R_prev = R_prev;
+                m.anc = r->at<uint32_t>(p.off_anc);
+                m.anc_cap = p.R_cap;
+                m.counts_last = r->at<uint32_t>(p.off_counts);
+                sm.push_back(m);
+                anc = m.anc;
+            }
+            // sweep
+            r->R_cur = R_new;   // sweep_args reads R_cur
+            pa::SweepArgs a = sweep_args(r, g, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[prev_buf]), anc,
+                                         r->at<uint8_t>(p.off_pop[new_buf]), p.desc.theta);
+            const uint32_t rpw = 64u >> r->G_log2;
+            const uint64_t per_block = (uint64_t)r->wpb * rpw;
+            SW e;
+            e.cls = pa::sweep_class(p.desc.L, p.desc.q, a.T[3] == 0);
+            e.blocks = (uint32_t)((R_new + per_block - 1) / per_block);
+            e.threads = 64u * r->wpb;
+            e.lds = pa::sweep_lds_bytes(p.N, r->G_log2, r->wpb);
+            e.a = a;
+            sw.push_back(e);
+            // post of step g
+            r->R_prev = R_prev;
+            r->R_cur = R_new;
+            r->cur = (int)new_buf;
+            r->step = g;
+            pa::PostArgs pp{};
+            pp.hist = hist_of(r, g);
+            pp.zero_next = (!p.hist_all && g + 1 < p.desc.K) ? hist_of(r, g + 1) : nullptr;
+            pp.nbins = p.nbins;
+            pp.two_n = (int32_t)(2 * p.N);
+            pp.R_i = R_new;
+            pp.step = g;
+            pp.has_next = (g + 1 < p.desc.K) ? 1u : 0u;
+            pp.dbeta_next = pp.has_next ? p.dbeta[g + 1] : 0.0;
+            const uint32_t tab = pp.has_next ? p.table_of_step[g + 1] : 0;
+            pp.w64_next = r->at<double>(p.off_w64) + (size_t)tab * p.nbins;
+            pp.E_sum = r->at<int64_t>(p.off_Esum);
+            pp.E_mean = r->at<double>(p.off_Emean);
+            pp.count = r->at<uint64_t>(p.off_count);
+            pp.lnQ = r->at<double>(p.off_lnQ);
+            pp.mbF = r->at<double>(p.off_mbF);
+            pp.E_ref = r->at<int32_t>(p.off_Eref);
+            pp.do_weights = (pp.has_next && p.desc.resample != PA_RESAMPLE_NONE) ? 1u : 0u;
+            pp.E = r->at<int32_t>(p.off_E);
+            pp.W = r->at<uint64_t>(p.off_W) + (size_t)tab * p.nbins;
+            pp.D = p.D.empty() ? 0u : p.D[tab];
+            pp.C = r->at<uint64_t>(p.off_C);
+            po.push_back(pp);
+        }
+        // sample + slot map
+        L.n_res = (uint32_t)sa.size();
+        L.sample_blocks = sblocks;
+        sstart.push_back(sblocks);
+        L.sample_off = take(n * sizeof(pa::SampleArgs));
+        L.sample_start_off = take((n + 1) * 4);
+        L.slot_off = take(n * sizeof(pa::SlotmapArgs));
+        std::memcpy(blob.data() + L.sample_off, sa.data(), sa.size() * sizeof(pa::SampleArgs));
+        std::memcpy(blob.data() + L.sample_start_off, sstart.data(), sstart.size() * 4);
+        std::memcpy(blob.data() + L.slot_off, sm.data(), sm.size() * sizeof(pa::SlotmapArgs));
+        // sweep groups: runs of one kernel class are contiguous in the table
+        std::stable_sort(sw.begin(), sw.end(), [](const SW &x, const SW &y) { return x.cls < y.cls; });
+        L.sweep_off = take(n * sizeof(pa::SweepArgs));
+        L.sweep_start_off = take(2 * (n + 1) * 4 + 4 * n);
+        std::vector<uint32_t> starts;
+        for (size_t k = 0; k < sw.size();) {
+            StepLaunch::Group G{sw[k].cls, (uint32_t)k, 0, 0, sw[k].threads, sw[k].lds};
+            const uint32_t start_index = (uint32_t)starts.size();
+            while (k < sw.size() && sw[k].cls == G.cls) {
+                starts.push_back(G.blocks);
+                G.blocks += sw[k].blocks;
+                ++G.count;
+                ++k;
+            }
+            starts.push_back(G.blocks);
+            G.first = start_index;       // index of this group's first start entry
+            L.groups.push_back(G);
+        }
+        for (size_t k = 0; k < sw.size(); ++k)
+            std::memcpy(blob.data() + L.sweep_off + k * sizeof(pa::SweepArgs), &sw[k].a, sizeof(pa::SweepArgs));
+        std::memcpy(blob.data() + L.sweep_start_off, starts.data(), starts.size() * 4);
+        // post
+        L.n_post = (uint32_t)po.size();
+        L.post_off = take(n * sizeof(pa::PostArgs));
+        std::memcpy(blob.data() + L.post_off, po.data(), po.size() * sizeof(pa::PostArgs));
+        steps.push_back(std::move(L));
+    }
+    if (cursor > b.desc_bytes) return cleanup(fail(PA_ERR_DEVICE, "descriptor table overflow"));
+    uint8_t *dtab = ws + b.desc_off;
+    if (!blob.empty() &&
+        (st = hip_check(nullptr, hipMemcpyAsync(dtab, blob.data(), blob.size(), hipMemcpyHostToDevice, s),
+                        "upload descriptors")))
+        return cleanup(st);
+
+    // The launch sequence.
+    for (const StepLaunch &L : steps) {
+        if (L.n_res &&
+            (st = hip_check(nullptr, pa::launch_resample_batch(
+                                         reinterpret_cast<const pa::SampleArgs *>(dtab + L.sample_off),
+                                         reinterpret_cast<const uint32_t *>(dtab + L.sample_start_off), L.n_res,
+                                         L.sample_blocks,
+                                         reinterpret_cast<const pa::SlotmapArgs *>(dtab + L.slot_off), s),
+                            "batched resample")))
+            return cleanup(st);
+        uint32_t run_index = 0;
+        for (const auto &G : L.groups) {
+            if ((st = hip_check(nullptr, pa::launch_sweep_batch(
+                                             G.cls,
+                                             reinterpret_cast<const pa::SweepArgs *>(dtab + L.sweep_off) + run_index,
+                                             reinterpret_cast<const uint32_t *>(dtab + L.sweep_start_off) + G.first,
+                                             G.count, G.blocks, G.threads, G.lds, s),
+                                "batched sweep")))
+                return cleanup(st);
+            run_index += G.count;
+        }
+        if ((st = hip_check(nullptr, pa::launch_post_batch(
+                                         reinterpret_cast<const pa::PostArgs *>(dtab + L.post_off), L.n_post, s),
+                            "batched post")))
+            return cleanup(st);
+    }
+    // Blob must outlive the async upload.
+    if ((st = hip_check(nullptr, hipStreamSynchronize(s), "sync"))) return cleanup(st);
+    pa_status first = PA_OK;
+    for (uint32_t r = 0; r < n; ++r) {
+        pa_status sr = pa_run_finish(runs[r], outs ? &outs[r] : nullptr);
+        runs[r] = nullptr;
+        if (sr && !first) first = sr;
+    }
+    return first;
 }
 
 pa_status pa_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes, void *stream,

@@ -318,8 +318,10 @@ __device__ __forceinline__ void sweeps_any(uint32_t *lds32, uint32_t g, uint32_t
     }
 }
 
+// One workgroup `block` of the sweep launch of one run (a): gather or create
+// its replicas in LDS, theta sweeps, energies, histogram, store.
 template <uint32_t LT, bool QSMALL, bool T64>
-__global__ void __launch_bounds__(256) k_sweep(SweepArgs a) {
+__device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     extern __shared__ __align__(16) uint8_t smem[];
     // thresholds indexed by dE + 4
     if (threadIdx.x < 9) {
@@ -338,8 +340,8 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a) {
     const uint32_t g = lane & (G - 1u);
     const uint32_t rpw = 64u >> G_log2;                          // replicas per wave
     const uint32_t rep = wave * rpw + (lane >> G_log2);          // replica within block
-    const uint64_t k64 = (uint64_t)blockIdx.x * a.waves_per_block * rpw + rep;
-    const uint64_t first_in_wave = (uint64_t)blockIdx.x * a.waves_per_block * rpw + wave * rpw;
+    const uint64_t k64 = (uint64_t)block * a.waves_per_block * rpw + rep;
+    const uint64_t first_in_wave = (uint64_t)block * a.waves_per_block * rpw + wave * rpw;
     if (first_in_wave >= a.R_new) return;                        // whole wave idle
     const bool live = k64 < a.R_new;
     const uint32_t k = rpw == 1 ? __builtin_amdgcn_readfirstlane((uint32_t)k64) : (uint32_t)k64;
@@ -404,6 +406,31 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs a) {
     }
 }
 
+template <uint32_t LT, bool QSMALL, bool T64>
+__global__ void __launch_bounds__(256) k_sweep(SweepArgs a) {
+    sweep_body<LT, QSMALL, T64>(a, blockIdx.x);
+}
+
+// Index of the segment holding `block`: start[r] <= block < start[r + 1].
+__device__ __forceinline__ uint32_t segment_of(const uint32_t *start, uint32_t n, uint32_t block) {
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= block) lo = mid; else hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Batched form: the workgroups of several runs' sweep launches (same lattice
+// class) in one launch; run r owns workgroups start[r] .. start[r+1]-1.
+template <uint32_t LT, bool QSMALL, bool T64>
+__global__ void __launch_bounds__(256) k_sweep_batch(const SweepArgs *runs, const uint32_t *start,
+                                                     uint32_t n) {
+    const uint32_t r = segment_of(start, n, blockIdx.x);
+    const SweepArgs a = runs[r];
+    sweep_body<LT, QSMALL, T64>(a, blockIdx.x - start[r]);
+}
+
 // ---------------------------------------------------------------------------
 // Workgroup helpers (1024 threads = 16 waves).
 // ---------------------------------------------------------------------------
@@ -453,7 +480,7 @@ constexpr uint32_t FILL_V = 16;  // elements per thread per tile in the count sc
 // the integer weights W(|E_j - E_ref|) of step i+1 and their inclusive scan C.
 // One workgroup; histogram bins and energies are read with coalesced loads.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_post(PostArgs a) {
+__device__ __forceinline__ void post_body(const PostArgs &a) {
     __shared__ int64_t s_esum[16];
     __shared__ uint64_t s_cnt[16];
     __shared__ int32_t s_min[16], s_max[16];
@@ -563,6 +590,14 @@ __global__ void __launch_bounds__(1024) k_post(PostArgs a) {
     }
 }
 
+__global__ void __launch_bounds__(1024) k_post(PostArgs a) { post_body(a); }
+
+// Batched form: workgroup r handles run r.
+__global__ void __launch_bounds__(1024) k_post_batch(const PostArgs *runs) {
+    const PostArgs a = runs[blockIdx.x];
+    post_body(a);
+}
+
 // ---------------------------------------------------------------------------
 // Count scan and slot map: o = exclusive scan of the copy numbers r;
 // anc[o_j + c] = j for c < r_j (new population in ancestor order, eq. (1));
@@ -619,8 +654,7 @@ __device__ void countfill_block(const SlotmapArgs &a, uint64_t *scratch) {
 // k_sample: draw kk picks the first j with C_j > floor(x_kk * S / 2^64) and
 // counts it in r_j.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
-    const uint64_t kk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sample_one(const SampleArgs &a, uint64_t kk) {
     if (kk >= a.n_new) return;
     const uint64_t S = a.C[a.R_prev - 1];
     const uint4 w = philox((uint32_t)kk, 0u, a.step, DOM_RESAMPLE << 28, a.key0, a.key1);
@@ -634,8 +668,27 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
     atomicAdd(&a.r[lo], 1u);
 }
 
+__global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
+    sample_one(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Batched form: run r owns workgroups start[r] .. start[r+1]-1.
+__global__ void __launch_bounds__(256) k_sample_batch(const SampleArgs *runs, const uint32_t *start,
+                                                      uint32_t n) {
+    const uint32_t r = segment_of(start, n, blockIdx.x);
+    const SampleArgs a = runs[r];
+    sample_one(a, (uint64_t)(blockIdx.x - start[r]) * blockDim.x + threadIdx.x);
+}
+
 __global__ void __launch_bounds__(1024) k_countfill(SlotmapArgs m) {
     __shared__ uint64_t scratch[17];
+    countfill_block(m, scratch);
+}
+
+// Batched form: workgroup r handles run r.
+__global__ void __launch_bounds__(1024) k_countfill_batch(const SlotmapArgs *runs) {
+    __shared__ uint64_t scratch[17];
+    const SlotmapArgs m = runs[blockIdx.x];
     countfill_block(m, scratch);
 }
 
@@ -709,6 +762,50 @@ hipError_t launch_resample(const SampleArgs &a, const SlotmapArgs &m, hipStream_
     const uint64_t blocks = (a.n_new + 255) / 256;
     if (blocks) hipLaunchKernelGGL(k_sample, dim3((uint32_t)blocks), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_countfill, dim3(1), dim3(1024), 0, s, m);
+    return hipGetLastError();
+}
+
+uint32_t sweep_class(uint32_t L, uint32_t q, bool t64) {
+    return (L << 2) | ((q <= 128) ? 2u : 0u) | (t64 ? 1u : 0u);
+}
+
+static void *sweep_batch_kernel(uint32_t cls) {
+    const uint32_t lt = cls >> 2;   // L; sizes without a fixed-shape instance use the generic one
+    const bool qs = (cls & 2u) != 0, t64 = (cls & 1u) != 0;
+    if (t64) return qs ? (void *)k_sweep_batch<0, true, true> : (void *)k_sweep_batch<0, false, true>;
+#define PA_BFIXED(LV) case LV: return qs ? (void *)k_sweep_batch<LV, true, false> : (void *)k_sweep_batch<LV, false, false>;
+    switch (lt) {
+        PA_BFIXED(4) PA_BFIXED(8) PA_BFIXED(16) PA_BFIXED(32) PA_BFIXED(64) PA_BFIXED(128) PA_BFIXED(256)
+        default: break;
+    }
+#undef PA_BFIXED
+    return qs ? (void *)k_sweep_batch<0, true, false> : (void *)k_sweep_batch<0, false, false>;
+}
+
+hipError_t launch_sweep_batch(uint32_t cls, const SweepArgs *runs, const uint32_t *start, uint32_t n,
+                              uint32_t blocks, uint32_t threads, size_t lds, hipStream_t s) {
+    if (blocks == 0 || n == 0) return hipSuccess;
+    void *kern = sweep_batch_kernel(cls);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((void (*)(const SweepArgs *, const uint32_t *, uint32_t))kern, dim3(blocks),
+                       dim3(threads), lds, s, runs, start, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_post_batch(const PostArgs *runs, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_post_batch, dim3(n), dim3(1024), 0, s, runs);
+    return hipGetLastError();
+}
+
+hipError_t launch_resample_batch(const SampleArgs *sruns, const uint32_t *start, uint32_t n,
+                                 uint32_t blocks, const SlotmapArgs *mruns, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (blocks) hipLaunchKernelGGL(k_sample_batch, dim3(blocks), dim3(256), 0, s, sruns, start, n);
+    hipLaunchKernelGGL(k_countfill_batch, dim3(n), dim3(1024), 0, s, mruns);
     return hipGetLastError();
 }
 

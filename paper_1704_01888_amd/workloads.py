@@ -1,0 +1,45 @@
+"""Seeded synthetic run descriptions (input generation only).
+
+The paper's workloads are random initial populations annealed along a
+temperature protocol (Sec. 2); there is no dataset.  These helpers produce the
+run descriptions used by the benchmark and the tests: lattice side, q,
+population size, the inverse-temperature array beta_i = beta_max * i / n
+(computed once in double precision, never by repeated addition), sweeps per
+step and seed.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def linear_betas(beta_max: float, n_steps: int) -> np.ndarray:
+    return np.array([beta_max * i / n_steps for i in range(n_steps + 1)], dtype=np.float64)
+
+
+def beta_t(q: int) -> float:
+    """Transition point of the 2D q-state Potts model, ln(1 + sqrt q) (Sec. 3)."""
+    return math.log(1.0 + math.sqrt(q))
+
+
+def small_runs(n_runs: int = 20, seed0: int = 1):
+    """n_runs runs of 8x8, q=8, R=1000, 200 equal steps to beta = 1.6, theta = 10,
+    multinomial resampling, seeds seed0, seed0+1, ... (dicts of desc fields)."""
+    return [dict(L=8, q=8, R=1000, beta=linear_betas(1.6, 200), theta=10, seed=seed0 + r,
+                 resample=1) for r in range(n_runs)]
+
+
+def mixed_runs(n_runs: int = 20, rng_seed: int = 3, n_steps: int = 300, theta: int = 10):
+    """n_runs independent runs with L in {16,24,32,48,64}, q in {5,6,8,10,20},
+    R uniform in [1e4, 1e5], each annealed to 1.1 ln(1 + sqrt q) in n_steps
+    equal steps, theta sweeps, Poisson resampling, seed 3000 + r."""
+    rng = np.random.default_rng(rng_seed)
+    runs = []
+    for r in range(n_runs):
+        L = int(rng.choice([16, 24, 32, 48, 64]))
+        q = int(rng.choice([5, 6, 8, 10, 20]))
+        R = int(rng.integers(10_000, 100_001))
+        runs.append(dict(L=L, q=q, R=R, beta=linear_betas(1.1 * beta_t(q), n_steps), theta=theta,
+                         seed=3000 + r, resample=0))
+    return runs

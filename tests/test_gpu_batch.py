@@ -1,0 +1,60 @@
+"""Batched runs (pa_run_batch) against separate runs and the oracle: every
+output of every run bit-identical (FP64 estimators within 1e-12)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1704_01888_amd as pa
+from paper_1704_01888_amd.workloads import linear_betas
+
+pytestmark = pytest.mark.gpu
+
+KEYS_EXACT = ("R_i", "E_sum", "E_mean", "hist", "final_spins", "final_E", "last_anc")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = pa.Context(0)
+    yield c
+    c.close()
+
+
+def _same(a, b):
+    for k in KEYS_EXACT:
+        if k in a and k in b:
+            assert (a[k] == b[k]).all(), k
+    np.testing.assert_allclose(a["minus_beta_F"], b["minus_beta_F"], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(a["lnQ"], b["lnQ"], rtol=1e-12, atol=1e-13)
+
+
+MIXED = [
+    dict(L=8, q=8, R=300, beta=linear_betas(1.6, 20), theta=3, seed=1, resample=1),
+    dict(L=16, q=10, R=700, beta=linear_betas(1.4, 12), theta=2, seed=2, resample=0),
+    dict(L=12, q=5, R=250, beta=linear_betas(1.2, 25), theta=2, seed=3, resample=0),
+    dict(L=4, q=3, R=333, beta=linear_betas(1.5, 7), theta=4, seed=4, resample=2),
+    dict(L=24, q=20, R=129, beta=linear_betas(1.9, 9), theta=1, seed=5, resample=0),
+    dict(L=32, q=6, R=200, beta=linear_betas(3.0, 10)[::-1].copy(), theta=2, seed=6, resample=0, init=1),
+    dict(L=8, q=200, R=100, beta=linear_betas(2.0, 15), theta=2, seed=7, resample=1),
+    dict(L=64, q=8, R=40, beta=np.array([0.0]), theta=2, seed=8, resample=0),
+]
+
+
+def test_batch_equals_separate_runs_and_oracle(ctx):
+    descs = [pa.Desc(outputs=pa.OUT_HIST | pa.OUT_FINAL, **c) for c in MIXED]
+    print(f"\nbatch of {len(descs)} runs", flush=True)
+    got = pa.pa_run_batch(ctx, descs)
+    for c, d, g in zip(MIXED, descs, got):
+        single = pa.pa_run(ctx, d)
+        _same(g, single)
+        want = oracle.run(oracle.Desc(**c), hist=True, final=True)
+        _same(g, want)
+
+
+def test_batch_of_identical_shapes_differs_only_by_seed(ctx):
+    cfg = [dict(L=16, q=8, R=500, beta=linear_betas(1.3, 15), theta=3, seed=100 + r, resample=1)
+           for r in range(6)]
+    descs = [pa.Desc(outputs=pa.OUT_FINAL, **c) for c in cfg]
+    got = pa.pa_run_batch(ctx, descs)
+    for d, g in zip(descs, got):
+        _same(g, pa.pa_run(ctx, d))
+    assert not (got[0]["final_spins"] == got[1]["final_spins"]).all()
