@@ -57,7 +57,10 @@ typedef enum {
     PA_ERR_NOMEM = -2,     /* workspace smaller than pa_plan_info.workspace_bytes  */
     PA_ERR_DEVICE = -3,    /* HIP error or failed device-side consistency check    */
     PA_ERR_CAPACITY = -4,  /* the Poisson schedule drew R_i = 0 or R_i > 2^31      */
-    PA_ERR_UNSUPPORTED = -5 /* valid for the method, outside this device path     */
+    PA_ERR_UNSUPPORTED = -5, /* valid for the method, outside this device path    */
+    PA_ERR_BUSY = -6,      /* a server already runs on this context                */
+    PA_ERR_CANCELLED = -7, /* request cancelled (pa_serve_cancel / pa_serve_stop)  */
+    PA_ERR_TIMEOUT = -8    /* pa_serve_wait timed out; the request is still live   */
 } pa_status;
 
 typedef enum { PA_RESAMPLE_POISSON = 0, PA_RESAMPLE_MULTINOMIAL = 1, PA_RESAMPLE_NONE = 2 } pa_resample;
@@ -182,6 +185,31 @@ pa_status pa_run_finish(pa_run_state *run, pa_result *out);
 pa_status pa_plan_batch(const pa_run_desc *descs, uint32_t n, uint64_t *workspace_bytes);
 pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_t n, void *d_ws,
                        uint64_t ws_bytes, void *stream, pa_result *outs);
+
+/* Serving: continuous batching of PA runs.  pa_serve_start runs a scheduler
+ * thread on the context; it owns the caller's device arena (d_arena,
+ * 256-byte aligned, valid until pa_serve_stop returns) and the stream.
+ * Requests (pa_serve_submit; the description is copied, the result buffers are
+ * the caller's and must stay valid until pa_serve_wait returns) wait in arrival
+ * order and are admitted as soon as a run slot is free (max_slots) and their
+ * workspace (pa_plan_info.workspace_bytes) fits the free arena, first fit; a
+ * request that does not fit yet lets later ones pass.  Admitted runs stay
+ * device-resident and advance together with the batched launches, several
+ * steps per scheduling round; finished runs release slot and memory at once.
+ * Every run's results equal those of pa_run for the same description.
+ * pa_serve_wait blocks until the ticket finishes (timeout_us < 0: no limit),
+ * fills the timing (microseconds since pa_serve_start) and consumes the
+ * ticket.  pa_serve_cancel marks a ticket: a queued request is dropped, a
+ * running one is released at the next round; its wait returns
+ * PA_ERR_CANCELLED.  pa_serve_stop lets admitted runs finish, cancels queued
+ * ones and joins the thread.  Submit, wait and cancel are thread-safe. */
+typedef struct { double arrival_us, admit_us, done_us; uint64_t attempts; } pa_timing;
+pa_status pa_serve_start(pa_ctx *ctx, void *d_arena, uint64_t arena_bytes, uint32_t max_slots,
+                         void *stream);
+pa_status pa_serve_submit(pa_ctx *ctx, const pa_run_desc *desc, pa_result *out, uint64_t *ticket);
+pa_status pa_serve_wait(pa_ctx *ctx, uint64_t ticket, int64_t timeout_us, pa_timing *timing);
+pa_status pa_serve_cancel(pa_ctx *ctx, uint64_t ticket);
+pa_status pa_serve_stop(pa_ctx *ctx);
 
 const char *pa_status_str(pa_status s);
 const char *pa_last_error(void);

@@ -29,7 +29,9 @@ EXPORTS = [
     "pa_run", "pa_run_begin", "pa_run_advance", "pa_run_sync", "pa_run_read", "pa_run_load",
     "pa_run_read_slots", "pa_run_finish", "pa_status_str", "pa_last_error",
     "pa_plan_batch", "pa_run_batch",
+    "pa_serve_start", "pa_serve_submit", "pa_serve_wait", "pa_serve_cancel", "pa_serve_stop",
 ]
+PA_ERR_BUSY, PA_ERR_CANCELLED, PA_ERR_TIMEOUT = -6, -7, -8
 
 
 class PAError(RuntimeError):
@@ -55,6 +57,11 @@ class Result(ctypes.Structure):
         ("last_anc", ctypes.c_void_p), ("kernel_ms", ctypes.c_void_p),
         ("kernel_launches", ctypes.c_void_p),
     ]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("arrival_us", ctypes.c_double), ("admit_us", ctypes.c_double),
+                ("done_us", ctypes.c_double), ("attempts", ctypes.c_uint64)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -97,13 +104,20 @@ def lib() -> ctypes.CDLL:
     L.pa_run_read_slots.argtypes = [vp, ctypes.c_int, vp, u32, vp]
     L.pa_plan_batch.argtypes = [P(RunDesc), u32, P(u64)]
     L.pa_run_batch.argtypes = [vp, P(RunDesc), u32, vp, u64, vp, P(Result)]
+    L.pa_serve_start.argtypes = [vp, vp, u64, u32, vp]
+    L.pa_serve_submit.argtypes = [vp, P(RunDesc), P(Result), P(u64)]
+    L.pa_serve_wait.argtypes = [vp, u64, ctypes.c_int64, P(Timing)]
+    L.pa_serve_cancel.argtypes = [vp, u64]
+    L.pa_serve_stop.argtypes = [vp]
     L.pa_status_str.argtypes = [i32]
     L.pa_status_str.restype = ctypes.c_char_p
     L.pa_last_error.argtypes = []
     L.pa_last_error.restype = ctypes.c_char_p
     for name in ("pa_plan", "pa_plan_tables", "pa_weight_table", "pa_ctx_create", "pa_run",
                  "pa_run_begin", "pa_run_advance", "pa_run_sync", "pa_run_read", "pa_run_load",
-                 "pa_run_read_slots", "pa_run_finish", "pa_plan_batch", "pa_run_batch"):
+                 "pa_run_read_slots", "pa_run_finish", "pa_plan_batch", "pa_run_batch",
+                 "pa_serve_start", "pa_serve_submit", "pa_serve_wait", "pa_serve_cancel",
+                 "pa_serve_stop"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -331,3 +345,48 @@ def pa_run_batch(ctx: Context, descs, workspace=None):
     _check(lib().pa_run_batch(ctx.handle, arr, len(descs), ctypes.c_void_p(ws.data_ptr()),
                               ws.numel(), _stream_ptr(), ress))
     return outs
+
+
+class Server:
+    """Continuous-batching server (pa_serve_*) on a context and a device arena."""
+
+    def __init__(self, ctx: Context, arena_bytes: int, max_slots: int, arena=None):
+        self.ctx = ctx
+        self.arena = arena if arena is not None else _workspace(arena_bytes, ctx.device)
+        self._live = {}
+        _check(lib().pa_serve_start(ctx.handle, ctypes.c_void_p(self.arena.data_ptr()),
+                                    self.arena.numel(), int(max_slots), _stream_ptr()))
+        self.running = True
+
+    def submit(self, desc: Desc) -> int:
+        out, res = _alloc_result(desc, pa_plan(desc))
+        t = ctypes.c_uint64(0)
+        _check(lib().pa_serve_submit(self.ctx.handle, ctypes.byref(desc.c()), ctypes.byref(res),
+                                     ctypes.byref(t)))
+        self._live[int(t.value)] = (out, res, desc)
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        """Returns (result dict, timing dict); raises PAError on failure."""
+        tm = Timing()
+        st = lib().pa_serve_wait(self.ctx.handle, int(ticket), int(timeout_us), ctypes.byref(tm))
+        if st == PA_ERR_TIMEOUT:
+            raise PAError(st, lib().pa_last_error().decode())
+        out, res, desc = self._live.pop(int(ticket))
+        _check(st)
+        return out, {"arrival_us": tm.arrival_us, "admit_us": tm.admit_us, "done_us": tm.done_us,
+                     "attempts": int(tm.attempts)}
+
+    def cancel(self, ticket: int):
+        _check(lib().pa_serve_cancel(self.ctx.handle, int(ticket)))
+
+    def stop(self):
+        if self.running:
+            _check(lib().pa_serve_stop(self.ctx.handle))
+            self.running = False
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

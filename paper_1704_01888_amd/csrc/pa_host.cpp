@@ -10,7 +10,14 @@
 #include "pa_device.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
 #include <cstring>
 #include <new>
 #include <string>
@@ -222,9 +229,12 @@ pa_status build_plan(const pa_run_desc *d, Plan &p, bool tables) {
 
 }  // namespace
 
+struct Server;
+
 struct pa_ctx {
     int device;
     int profiling;
+    Server *server;
 };
 
 struct pa_run_state {
@@ -397,6 +407,9 @@ const char *pa_status_str(pa_status s) {
         case PA_ERR_DEVICE: return "device error";
         case PA_ERR_CAPACITY: return "population capacity";
         case PA_ERR_UNSUPPORTED: return "unsupported on this device path";
+        case PA_ERR_BUSY: return "busy";
+        case PA_ERR_CANCELLED: return "cancelled";
+        case PA_ERR_TIMEOUT: return "timed out";
     }
     return "unknown status";
 }
@@ -441,11 +454,16 @@ pa_status pa_ctx_create(int device, pa_ctx **out) {
     if (!c) return fail(PA_ERR_NOMEM, "out of host memory");
     c->device = device;
     c->profiling = 0;
+    c->server = nullptr;
     *out = c;
     return PA_OK;
 }
 
-void pa_ctx_destroy(pa_ctx *ctx) { delete ctx; }
+void pa_ctx_destroy(pa_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->server) pa_serve_stop(ctx);
+    delete ctx;
+}
 
 pa_status pa_ctx_set_profiling(pa_ctx *ctx, int enable) {
     if (!ctx) return fail(PA_ERR_INVALID, "null context");
@@ -656,62 +674,197 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
 }
 
 // ---------------------------------------------------------------------------
-// Batched runs: every run keeps its own workspace region and plan; per global
-// step g one set of segmented launches advances every run with K > g.  All
-// sizes are known from the plans, so the per-step descriptor tables are built
-// once on the host and uploaded once.
+// Several runs per launch (batched runs and the serving loop): every run keeps
+// its own workspace region and plan; one "global step" advances each listed
+// run by one temperature step with segmented launches (one sampling launch
+// over all runs' draws, one count-scan workgroup per run, one sweep launch per
+// kernel class, one post workgroup per run).  The descriptor records are built
+// on the host and uploaded before the launches.
 // ---------------------------------------------------------------------------
 namespace {
 
-struct BatchLayout {
-    std::vector<Plan> plans;
-    std::vector<size_t> run_off;   // byte offset of each run's region
-    size_t desc_off = 0;           // descriptor tables
-    size_t desc_bytes = 0;
-    size_t total = 0;
-    uint32_t max_K = 0;
-};
-
-pa_status batch_layout(const pa_run_desc *descs, uint32_t n, BatchLayout &b, bool tables) {
-    if (!descs || n == 0) return fail(PA_ERR_INVALID, "empty batch");
-    b.plans.resize(n);
-    b.run_off.resize(n);
-    size_t o = 0;
-    b.max_K = 0;
-    for (uint32_t r = 0; r < n; ++r) {
-        pa_status st = build_plan(&descs[r], b.plans[r], tables);
-        if (st) return st;
-        b.run_off[r] = o;
-        o += align256(b.plans[r].total);
-        if (descs[r].K > b.max_K) b.max_K = descs[r].K;
-    }
-    // descriptor tables: per global step, sample / slot map / sweep / post
-    // records of the active runs (upper bound: every run active every step)
-    const size_t per_step = align256(n * sizeof(pa::SampleArgs)) + align256((n + 1) * 4) +
-                            align256(n * sizeof(pa::SlotmapArgs)) +
-                            align256(n * sizeof(pa::SweepArgs)) + align256(2 * (n + 1) * 4 + 4 * n) +
-                            align256(n * sizeof(pa::PostArgs));
-    b.desc_off = o;
-    b.desc_bytes = per_step * (b.max_K > 1 ? b.max_K - 1 : 1);
-    o += b.desc_bytes;
-    b.total = o;
-    return PA_OK;
+size_t step_desc_bytes(size_t n) {
+    return align256(n * sizeof(pa::SampleArgs)) + align256((n + 1) * 4) +
+           align256(n * sizeof(pa::SlotmapArgs)) + align256(n * sizeof(pa::SweepArgs)) +
+           align256(2 * (n + 1) * 4 + 4 * n) + align256(n * sizeof(pa::PostArgs));
 }
 
 struct StepLaunch {
-    // offsets into the descriptor region
     size_t sample_off, sample_start_off, slot_off, sweep_off, sweep_start_off, post_off;
     uint32_t n_res, sample_blocks, n_post;
     struct Group { uint32_t cls, first, count, blocks, threads; size_t lds; };
     std::vector<Group> groups;
 };
 
+// Advance the host state of every run in `active` (each with step < K-1) by one
+// step and write the step's descriptor records at blob + cursor.
+StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uint8_t> &blob,
+                      size_t &cursor) {
+    const size_t n = active.size();
+    StepLaunch L{};
+    std::vector<pa::SampleArgs> sa;
+    std::vector<uint32_t> sstart;
+    std::vector<pa::SlotmapArgs> sm;
+    std::vector<pa::PostArgs> po;
+    struct SW { uint32_t cls, blocks, threads; size_t lds; pa::SweepArgs a; };
+    std::vector<SW> sw;
+    uint32_t sblocks = 0;
+    for (pa_run_state *r : active) {
+        const Plan &p = r->plan;
+        const uint32_t g = r->step + 1;
+        const uint64_t R_prev = r->R_cur, R_new = p.R_sched[g];
+        const int prev_buf = r->cur, new_buf = 1 - r->cur;
+        const uint32_t *anc = nullptr;
+        if (p.desc.resample != PA_RESAMPLE_NONE) {
+            pa::SampleArgs a{};
+            a.C = r->at<uint64_t>(p.off_C);
+            a.R_prev = R_prev;
+            a.n_new = R_new;
+            a.step = g;
+            a.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
+            a.key1 = (uint32_t)(p.desc.seed >> 32);
+            a.r = r->at<uint32_t>(p.off_r);
+            sstart.push_back(sblocks);
+            sblocks += (uint32_t)((R_new + 255) / 256);
+            sa.push_back(a);
+            pa::SlotmapArgs m{};
+            m.r = a.r;
+            m.R_prev = R_prev;
+            m.anc = r->at<uint32_t>(p.off_anc);
+            m.anc_cap = p.R_cap;
+            m.counts_last = r->at<uint32_t>(p.off_counts);
+            sm.push_back(m);
+            anc = m.anc;
+        }
+        r->R_prev = R_prev;
+        r->R_cur = R_new;
+        pa::SweepArgs a = sweep_args(r, g, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[prev_buf]), anc,
+                                     r->at<uint8_t>(p.off_pop[new_buf]), p.desc.theta);
+        const uint64_t per_block = (uint64_t)r->wpb * (64u >> r->G_log2);
+        SW e;
+        e.cls = pa::sweep_class(p.desc.L, p.desc.q, a.T[3] == 0);
+        e.blocks = (uint32_t)((R_new + per_block - 1) / per_block);
+        e.threads = 64u * r->wpb;
+        e.lds = pa::sweep_lds_bytes(p.N, r->G_log2, r->wpb);
+        e.a = a;
+        sw.push_back(e);
+        r->cur = new_buf;
+        r->step = g;
+        pa::PostArgs pp{};
+        pp.hist = hist_of(r, g);
+        pp.zero_next = (!p.hist_all && g + 1 < p.desc.K) ? hist_of(r, g + 1) : nullptr;
+        pp.nbins = p.nbins;
+        pp.two_n = (int32_t)(2 * p.N);
+        pp.R_i = R_new;
+        pp.step = g;
+        pp.has_next = (g + 1 < p.desc.K) ? 1u : 0u;
+        pp.dbeta_next = pp.has_next ? p.dbeta[g + 1] : 0.0;
+        const uint32_t tab = pp.has_next ? p.table_of_step[g + 1] : 0;
+        pp.w64_next = r->at<double>(p.off_w64) + (size_t)tab * p.nbins;
+        pp.E_sum = r->at<int64_t>(p.off_Esum);
+        pp.E_mean = r->at<double>(p.off_Emean);
+        pp.count = r->at<uint64_t>(p.off_count);
+        pp.lnQ = r->at<double>(p.off_lnQ);
+        pp.mbF = r->at<double>(p.off_mbF);
+        pp.E_ref = r->at<int32_t>(p.off_Eref);
+        pp.do_weights = (pp.has_next && p.desc.resample != PA_RESAMPLE_NONE) ? 1u : 0u;
+        pp.E = r->at<int32_t>(p.off_E);
+        pp.W = r->at<uint64_t>(p.off_W) + (size_t)tab * p.nbins;
+        pp.D = p.D.empty() ? 0u : p.D[tab];
+        pp.C = r->at<uint64_t>(p.off_C);
+        po.push_back(pp);
+    }
+    auto take = [&](size_t bytes) { size_t at = cursor; cursor += align256(bytes); return at; };
+    if (blob.size() < cursor + step_desc_bytes(n)) blob.resize(cursor + step_desc_bytes(n), 0);
+    L.n_res = (uint32_t)sa.size();
+    L.sample_blocks = sblocks;
+    sstart.push_back(sblocks);
+    L.sample_off = take(n * sizeof(pa::SampleArgs));
+    L.sample_start_off = take((n + 1) * 4);
+    L.slot_off = take(n * sizeof(pa::SlotmapArgs));
+    std::memcpy(blob.data() + L.sample_off, sa.data(), sa.size() * sizeof(pa::SampleArgs));
+    std::memcpy(blob.data() + L.sample_start_off, sstart.data(), sstart.size() * 4);
+    std::memcpy(blob.data() + L.slot_off, sm.data(), sm.size() * sizeof(pa::SlotmapArgs));
+    // sweep groups: runs of one kernel class contiguous in the table
+    std::stable_sort(sw.begin(), sw.end(), [](const SW &x, const SW &y) { return x.cls < y.cls; });
+    L.sweep_off = take(n * sizeof(pa::SweepArgs));
+    L.sweep_start_off = take(2 * (n + 1) * 4 + 4 * n);
+    std::vector<uint32_t> starts;
+    for (size_t k = 0; k < sw.size();) {
+        StepLaunch::Group G{sw[k].cls, (uint32_t)starts.size(), 0, 0, sw[k].threads, sw[k].lds};
+        while (k < sw.size() && sw[k].cls == G.cls) {
+            starts.push_back(G.blocks);
+            G.blocks += sw[k].blocks;
+            ++G.count;
+            ++k;
+        }
+        starts.push_back(G.blocks);
+        L.groups.push_back(G);
+    }
+    for (size_t k = 0; k < sw.size(); ++k)
+        std::memcpy(blob.data() + L.sweep_off + k * sizeof(pa::SweepArgs), &sw[k].a, sizeof(pa::SweepArgs));
+    std::memcpy(blob.data() + L.sweep_start_off, starts.data(), starts.size() * 4);
+    L.n_post = (uint32_t)po.size();
+    L.post_off = take(n * sizeof(pa::PostArgs));
+    std::memcpy(blob.data() + L.post_off, po.data(), po.size() * sizeof(pa::PostArgs));
+    return L;
+}
+
+pa_status launch_step(const StepLaunch &L, const uint8_t *dtab, hipStream_t s) {
+    pa_status st;
+    if (L.n_res &&
+        (st = hip_check(nullptr, pa::launch_resample_batch(
+                                     reinterpret_cast<const pa::SampleArgs *>(dtab + L.sample_off),
+                                     reinterpret_cast<const uint32_t *>(dtab + L.sample_start_off), L.n_res,
+                                     L.sample_blocks, reinterpret_cast<const pa::SlotmapArgs *>(dtab + L.slot_off), s),
+                        "batched resample")))
+        return st;
+    uint32_t run_index = 0;
+    for (const auto &G : L.groups) {
+        if ((st = hip_check(nullptr, pa::launch_sweep_batch(
+                                         G.cls, reinterpret_cast<const pa::SweepArgs *>(dtab + L.sweep_off) + run_index,
+                                         reinterpret_cast<const uint32_t *>(dtab + L.sweep_start_off) + G.first,
+                                         G.count, G.blocks, G.threads, G.lds, s),
+                            "batched sweep")))
+            return st;
+        run_index += G.count;
+    }
+    return hip_check(nullptr, pa::launch_post_batch(reinterpret_cast<const pa::PostArgs *>(dtab + L.post_off),
+                                                    L.n_post, s),
+                     "batched post");
+}
+
+struct BatchLayout {
+    std::vector<Plan> plans;
+    std::vector<size_t> run_off;
+    size_t desc_off = 0, desc_bytes = 0, total = 0;
+    uint32_t max_K = 0;
+};
+
+pa_status batch_layout(const pa_run_desc *descs, uint32_t n, BatchLayout &b) {
+    if (!descs || n == 0) return fail(PA_ERR_INVALID, "empty batch");
+    b.plans.resize(n);
+    b.run_off.resize(n);
+    size_t o = 0;
+    for (uint32_t r = 0; r < n; ++r) {
+        pa_status st = build_plan(&descs[r], b.plans[r], false);
+        if (st) return fail(st, "run " + std::to_string(r) + ": " + g_last_error);
+        b.run_off[r] = o;
+        o += align256(b.plans[r].total);
+        b.max_K = std::max(b.max_K, descs[r].K);
+    }
+    b.desc_off = o;
+    b.desc_bytes = step_desc_bytes(n) * (b.max_K > 1 ? b.max_K - 1 : 1);
+    b.total = o + b.desc_bytes;
+    return PA_OK;
+}
+
 }  // namespace
 
 extern "C" pa_status pa_plan_batch(const pa_run_desc *descs, uint32_t n, uint64_t *workspace_bytes) {
     if (!workspace_bytes) return fail(PA_ERR_INVALID, "null output");
     BatchLayout b;
-    pa_status st = batch_layout(descs, n, b, false);
+    pa_status st = batch_layout(descs, n, b);
     if (st) return st;
     *workspace_bytes = b.total;
     return PA_OK;
@@ -721,184 +874,40 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
                                   uint64_t ws_bytes, void *stream, pa_result *outs) {
     if (!ctx) return fail(PA_ERR_INVALID, "null context");
     BatchLayout b;
-    pa_status st = batch_layout(descs, n, b, false);
+    pa_status st = batch_layout(descs, n, b);
     if (st) return st;
     if (!d_ws || ws_bytes < b.total || ((uintptr_t)d_ws & 255u))
         return fail(PA_ERR_NOMEM, "workspace missing, unaligned or smaller than pa_plan_batch's size");
     uint8_t *ws = static_cast<uint8_t *>(d_ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
-
-    // Initial populations (step 0) of every run.
     std::vector<pa_run_state *> runs(n, nullptr);
     auto cleanup = [&](pa_status code) {
+        const std::string msg = g_last_error;
         for (auto *r : runs)
             if (r) pa_run_finish(r, nullptr);
-        return code;
+        return fail(code, msg);
     };
     for (uint32_t r = 0; r < n; ++r) {
         st = pa_run_begin(ctx, &descs[r], ws + b.run_off[r], align256(b.plans[r].total), stream, &runs[r]);
-        if (st) {
-            const std::string msg = g_last_error;
-            cleanup(st);
-            return fail(st, "run " + std::to_string(r) + ": " + msg);
-        }
+        if (st) return cleanup(fail(st, "run " + std::to_string(r) + ": " + g_last_error));
     }
-
-    // Descriptor tables for every global step.
-    std::vector<uint8_t> blob(b.desc_bytes, 0);
+    // Every global step's records, built up front (all sizes are in the plans).
+    std::vector<uint8_t> blob;
     std::vector<StepLaunch> steps;
     size_t cursor = 0;
-    auto take = [&](size_t bytes) { size_t at = cursor; cursor += align256(bytes); return at; };
     for (uint32_t g = 1; g < b.max_K; ++g) {
-        StepLaunch L{};
-        std::vector<pa::SampleArgs> sa;
-        std::vector<uint32_t> sstart;
-        std::vector<pa::SlotmapArgs> sm;
-        std::vector<pa::PostArgs> po;
-        struct SW { uint32_t cls, blocks, threads; size_t lds; pa::SweepArgs a; };
-        std::vector<SW> sw;
-        uint32_t sblocks = 0;
-        for (uint32_t ri = 0; ri < n; ++ri) {
-            pa_run_state *r = runs[ri];
-            const Plan &p = r->plan;
-            if (g >= p.desc.K) continue;
-            const uint64_t R_prev = p.R_sched[g - 1], R_new = p.R_sched[g];
-            const uint32_t prev_buf = (g - 1) & 1u, new_buf = g & 1u;
-            const uint32_t *anc = nullptr;
-            if (p.desc.resample != PA_RESAMPLE_NONE) {
-                pa::SampleArgs a{};
-                a.C = r->at<uint64_t>(p.off_C);
-                a.R_prev = R_prev;
-                a.n_new = R_new;
-                a.step = g;
-                a.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
-                a.key1 = (uint32_t)(p.desc.seed >> 32);
-                a.r = r->at<uint32_t>(p.off_r);
-                sstart.push_back(sblocks);
-                sblocks += (uint32_t)((R_new + 255) / 256);
-                sa.push_back(a);
-                pa::SlotmapArgs m{};
-                m.r = a.r;
-                m.R_prev = R_prev;
-                m.anc = r->at<uint32_t>(p.off_anc);
-                m.anc_cap = p.R_cap;
-                m.counts_last = r->at<uint32_t>(p.off_counts);
-                sm.push_back(m);
-                anc = m.anc;
-            }
-            // sweep
-            r->R_cur = R_new;   // sweep_args reads R_cur
-            pa::SweepArgs a = sweep_args(r, g, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[prev_buf]), anc,
-                                         r->at<uint8_t>(p.off_pop[new_buf]), p.desc.theta);
-            const uint32_t rpw = 64u >> r->G_log2;
-            const uint64_t per_block = (uint64_t)r->wpb * rpw;
-            SW e;
-            e.cls = pa::sweep_class(p.desc.L, p.desc.q, a.T[3] == 0);
-            e.blocks = (uint32_t)((R_new + per_block - 1) / per_block);
-            e.threads = 64u * r->wpb;
-            e.lds = pa::sweep_lds_bytes(p.N, r->G_log2, r->wpb);
-            e.a = a;
-            sw.push_back(e);
-            // post of step g
-            r->R_prev = R_prev;
-            r->R_cur = R_new;
-            r->cur = (int)new_buf;
-            r->step = g;
-            pa::PostArgs pp{};
-            pp.hist = hist_of(r, g);
-            pp.zero_next = (!p.hist_all && g + 1 < p.desc.K) ? hist_of(r, g + 1) : nullptr;
-            pp.nbins = p.nbins;
-            pp.two_n = (int32_t)(2 * p.N);
-            pp.R_i = R_new;
-            pp.step = g;
-            pp.has_next = (g + 1 < p.desc.K) ? 1u : 0u;
-            pp.dbeta_next = pp.has_next ? p.dbeta[g + 1] : 0.0;
-            const uint32_t tab = pp.has_next ? p.table_of_step[g + 1] : 0;
-            pp.w64_next = r->at<double>(p.off_w64) + (size_t)tab * p.nbins;
-            pp.E_sum = r->at<int64_t>(p.off_Esum);
-            pp.E_mean = r->at<double>(p.off_Emean);
-            pp.count = r->at<uint64_t>(p.off_count);
-            pp.lnQ = r->at<double>(p.off_lnQ);
-            pp.mbF = r->at<double>(p.off_mbF);
-            pp.E_ref = r->at<int32_t>(p.off_Eref);
-            pp.do_weights = (pp.has_next && p.desc.resample != PA_RESAMPLE_NONE) ? 1u : 0u;
-            pp.E = r->at<int32_t>(p.off_E);
-            pp.W = r->at<uint64_t>(p.off_W) + (size_t)tab * p.nbins;
-            pp.D = p.D.empty() ? 0u : p.D[tab];
-            pp.C = r->at<uint64_t>(p.off_C);
-            po.push_back(pp);
-        }
-        // sample + slot map
-        L.n_res = (uint32_t)sa.size();
-        L.sample_blocks = sblocks;
-        sstart.push_back(sblocks);
-        L.sample_off = take(n * sizeof(pa::SampleArgs));
-        L.sample_start_off = take((n + 1) * 4);
-        L.slot_off = take(n * sizeof(pa::SlotmapArgs));
-        std::memcpy(blob.data() + L.sample_off, sa.data(), sa.size() * sizeof(pa::SampleArgs));
-        std::memcpy(blob.data() + L.sample_start_off, sstart.data(), sstart.size() * 4);
-        std::memcpy(blob.data() + L.slot_off, sm.data(), sm.size() * sizeof(pa::SlotmapArgs));
-        // sweep groups: runs of one kernel class are contiguous in the table
-        std::stable_sort(sw.begin(), sw.end(), [](const SW &x, const SW &y) { return x.cls < y.cls; });
-        L.sweep_off = take(n * sizeof(pa::SweepArgs));
-        L.sweep_start_off = take(2 * (n + 1) * 4 + 4 * n);
-        std::vector<uint32_t> starts;
-        for (size_t k = 0; k < sw.size();) {
-            StepLaunch::Group G{sw[k].cls, (uint32_t)k, 0, 0, sw[k].threads, sw[k].lds};
-            const uint32_t start_index = (uint32_t)starts.size();
-            while (k < sw.size() && sw[k].cls == G.cls) {
-                starts.push_back(G.blocks);
-                G.blocks += sw[k].blocks;
-                ++G.count;
-                ++k;
-            }
-            starts.push_back(G.blocks);
-            G.first = start_index;       // index of this group's first start entry
-            L.groups.push_back(G);
-        }
-        for (size_t k = 0; k < sw.size(); ++k)
-            std::memcpy(blob.data() + L.sweep_off + k * sizeof(pa::SweepArgs), &sw[k].a, sizeof(pa::SweepArgs));
-        std::memcpy(blob.data() + L.sweep_start_off, starts.data(), starts.size() * 4);
-        // post
-        L.n_post = (uint32_t)po.size();
-        L.post_off = take(n * sizeof(pa::PostArgs));
-        std::memcpy(blob.data() + L.post_off, po.data(), po.size() * sizeof(pa::PostArgs));
-        steps.push_back(std::move(L));
+        std::vector<pa_run_state *> active;
+        for (auto *r : runs)
+            if (g < r->plan.desc.K) active.push_back(r);
+        steps.push_back(build_step(active, blob, cursor));
     }
     if (cursor > b.desc_bytes) return cleanup(fail(PA_ERR_DEVICE, "descriptor table overflow"));
     uint8_t *dtab = ws + b.desc_off;
-    if (!blob.empty() &&
-        (st = hip_check(nullptr, hipMemcpyAsync(dtab, blob.data(), blob.size(), hipMemcpyHostToDevice, s),
-                        "upload descriptors")))
+    if (cursor && (st = hip_check(nullptr, hipMemcpyAsync(dtab, blob.data(), cursor, hipMemcpyHostToDevice, s),
+                                  "upload descriptors")))
         return cleanup(st);
-
-    // The launch sequence.
-    for (const StepLaunch &L : steps) {
-        if (L.n_res &&
-            (st = hip_check(nullptr, pa::launch_resample_batch(
-                                         reinterpret_cast<const pa::SampleArgs *>(dtab + L.sample_off),
-                                         reinterpret_cast<const uint32_t *>(dtab + L.sample_start_off), L.n_res,
-                                         L.sample_blocks,
-                                         reinterpret_cast<const pa::SlotmapArgs *>(dtab + L.slot_off), s),
-                            "batched resample")))
-            return cleanup(st);
-        uint32_t run_index = 0;
-        for (const auto &G : L.groups) {
-            if ((st = hip_check(nullptr, pa::launch_sweep_batch(
-                                             G.cls,
-                                             reinterpret_cast<const pa::SweepArgs *>(dtab + L.sweep_off) + run_index,
-                                             reinterpret_cast<const uint32_t *>(dtab + L.sweep_start_off) + G.first,
-                                             G.count, G.blocks, G.threads, G.lds, s),
-                                "batched sweep")))
-                return cleanup(st);
-            run_index += G.count;
-        }
-        if ((st = hip_check(nullptr, pa::launch_post_batch(
-                                         reinterpret_cast<const pa::PostArgs *>(dtab + L.post_off), L.n_post, s),
-                            "batched post")))
-            return cleanup(st);
-    }
-    // Blob must outlive the async upload.
+    for (const StepLaunch &L : steps)
+        if ((st = launch_step(L, dtab, s))) return cleanup(st);
     if ((st = hip_check(nullptr, hipStreamSynchronize(s), "sync"))) return cleanup(st);
     pa_status first = PA_OK;
     for (uint32_t r = 0; r < n; ++r) {
@@ -917,6 +926,308 @@ pa_status pa_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_b
     st = pa_run_advance(r, desc->K - 1);
     pa_status st2 = pa_run_finish(r, out);
     return st ? st : st2;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving loop: continuous batching of PA runs inside a caller-provided arena.
+// A scheduler thread admits queued requests whenever a run slot is free and
+// the request's workspace fits the arena (first fit), then advances every
+// admitted run by up to kStepsPerIteration global steps with the batched
+// launches, retires finished runs (results copied into the caller's buffers,
+// memory and slot released) and wakes their waiters.  Populations stay in the
+// arena for the whole run.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr uint32_t kStepsPerIteration = 8;
+
+double now_us() {
+    using namespace std::chrono;
+    return (double)duration_cast<nanoseconds>(steady_clock::now().time_since_epoch()).count() * 1e-3;
+}
+
+// First-fit allocator over [0, size) in 256-byte units, with coalescing.
+class Arena {
+  public:
+    void reset(size_t size) { free_.clear(); if (size) free_[0] = size; }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = align256(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align256(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t largest() const {
+        size_t m = 0;
+        for (auto &kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+
+  private:
+    std::map<size_t, size_t> free_;
+};
+
+enum class ReqState { Queued, Running, Done };
+
+struct Request {
+    uint64_t ticket = 0;
+    pa_run_desc desc{};
+    std::vector<double> beta;
+    pa_result out{};
+    size_t bytes = 0, off = 0;
+    double arrival_us = 0, admit_us = 0, done_us = 0;
+    uint64_t attempts = 0;
+    ReqState state = ReqState::Queued;
+    bool cancel = false;
+    pa_status status = PA_OK;
+    std::string message;
+    pa_run_state *run = nullptr;
+};
+
+}  // namespace
+
+struct Server {
+    pa_ctx *ctx = nullptr;
+    uint8_t *arena = nullptr;
+    size_t desc_bytes = 0;        // descriptor region at the start of the arena
+    size_t run_bytes = 0;         // the rest, for run workspaces
+    uint32_t max_slots = 0;
+    hipStream_t stream = nullptr;
+    double t0 = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Request>> queue;
+    std::map<uint64_t, std::shared_ptr<Request>> tickets;
+    std::vector<std::shared_ptr<Request>> active;
+    Arena alloc;
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    std::thread thread;
+
+    void finish(const std::shared_ptr<Request> &q, pa_status st, const std::string &msg) {
+        q->status = st;
+        q->message = msg;
+        q->done_us = now_us() - t0;
+        q->state = ReqState::Done;
+    }
+
+    void loop() {
+        (void)hipSetDevice(ctx->device);
+        std::vector<uint8_t> blob;
+        for (;;) {
+            std::vector<std::shared_ptr<Request>> admitted;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] { return stopping || !queue.empty() || !active.empty(); });
+                if (stopping && active.empty()) {
+                    for (auto &q : queue) finish(q, PA_ERR_CANCELLED, "server stopped");
+                    queue.clear();
+                    cv_done.notify_all();
+                    return;
+                }
+                // Admission in arrival order; a request that does not fit yet
+                // lets later, smaller ones pass.
+                for (auto it = queue.begin(); it != queue.end();) {
+                    auto q = *it;
+                    if (q->cancel) {
+                        finish(q, PA_ERR_CANCELLED, "cancelled while queued");
+                        it = queue.erase(it);
+                        continue;
+                    }
+                    if (stopping) break;
+                    if (active.size() + admitted.size() >= max_slots) break;
+                    size_t off;
+                    if (!alloc.alloc(q->bytes, &off)) { ++it; continue; }
+                    q->off = off;
+                    q->admit_us = now_us() - t0;
+                    q->state = ReqState::Running;
+                    admitted.push_back(q);
+                    it = queue.erase(it);
+                }
+                cv_done.notify_all();
+            }
+            for (auto &q : admitted) {
+                pa_run_state *run = nullptr;
+                pa_status st = pa_run_begin(ctx, &q->desc, arena + desc_bytes + q->off, align256(q->bytes),
+                                            stream, &run);
+                std::lock_guard<std::mutex> lk(mu);
+                if (st) {
+                    alloc.release(q->off, q->bytes);
+                    finish(q, st, g_last_error);
+                    continue;
+                }
+                q->run = run;
+                active.push_back(q);
+            }
+            // Up to kStepsPerIteration global steps of every active run.
+            std::vector<pa_run_state *> runs;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                for (auto &q : active)
+                    if (!q->cancel) runs.push_back(q->run);
+            }
+            size_t cursor = 0;
+            std::vector<StepLaunch> steps;
+            for (uint32_t k = 0; k < kStepsPerIteration; ++k) {
+                std::vector<pa_run_state *> act;
+                for (auto *r : runs)
+                    if (r->step + 1 < r->plan.desc.K) act.push_back(r);
+                if (act.empty()) break;
+                steps.push_back(build_step(act, blob, cursor));
+            }
+            pa_status st = PA_OK;
+            if (!steps.empty()) {
+                st = hip_check(nullptr, hipMemcpyAsync(arena, blob.data(), cursor, hipMemcpyHostToDevice, stream),
+                               "upload descriptors");
+                for (const auto &L : steps)
+                    if (!st) st = launch_step(L, arena, stream);
+            }
+            if (!st) st = hip_check(nullptr, hipStreamSynchronize(stream), "sync");
+            const std::string msg = st ? g_last_error : std::string();
+            // Retire finished, cancelled or failed runs.
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto it = active.begin(); it != active.end();) {
+                auto q = *it;
+                const bool done = q->run->step + 1 >= q->run->plan.desc.K;
+                if (!(done || q->cancel || st)) { ++it; continue; }
+                pa_status fs;
+                if (st) {
+                    pa_run_finish(q->run, nullptr);
+                    fs = st;
+                } else if (q->cancel) {
+                    pa_run_finish(q->run, nullptr);
+                    fs = PA_ERR_CANCELLED;
+                } else {
+                    fs = pa_run_finish(q->run, &q->out);
+                }
+                q->run = nullptr;
+                alloc.release(q->off, q->bytes);
+                finish(q, fs, fs ? (st ? msg : (q->cancel ? "cancelled while running" : g_last_error)) : "");
+                it = active.erase(it);
+            }
+            cv_done.notify_all();
+        }
+    }
+};
+
+extern "C" {
+
+pa_status pa_serve_start(pa_ctx *ctx, void *d_arena, uint64_t arena_bytes, uint32_t max_slots, void *stream) {
+    if (!ctx || !d_arena || max_slots == 0 || ((uintptr_t)d_arena & 255u))
+        return fail(PA_ERR_INVALID, "bad serving arguments");
+    if (ctx->server) return fail(PA_ERR_BUSY, "a server is already running on this context");
+    Server *sv = new (std::nothrow) Server;
+    if (!sv) return fail(PA_ERR_NOMEM, "out of host memory");
+    sv->ctx = ctx;
+    sv->arena = static_cast<uint8_t *>(d_arena);
+    sv->max_slots = max_slots;
+    sv->desc_bytes = align256(step_desc_bytes(max_slots) * kStepsPerIteration);
+    if (arena_bytes <= sv->desc_bytes) { delete sv; return fail(PA_ERR_NOMEM, "arena too small"); }
+    sv->run_bytes = (arena_bytes - sv->desc_bytes) & ~size_t(255);
+    sv->alloc.reset(sv->run_bytes);
+    sv->stream = static_cast<hipStream_t>(stream);
+    sv->t0 = now_us();
+    ctx->server = sv;
+    sv->thread = std::thread([sv] { sv->loop(); });
+    return PA_OK;
+}
+
+pa_status pa_serve_submit(pa_ctx *ctx, const pa_run_desc *desc, pa_result *out, uint64_t *ticket) {
+    if (!ctx || !ctx->server || !desc || !ticket) return fail(PA_ERR_INVALID, "no server or null argument");
+    Server *sv = ctx->server;
+    auto q = std::make_shared<Request>();
+    Plan p;
+    pa_status st = build_plan(desc, p, false);
+    if (st) return st;
+    if (align256(p.total) > sv->run_bytes)
+        return fail(PA_ERR_NOMEM, "the run's workspace exceeds the serving arena");
+    q->desc = *desc;
+    q->beta.assign(desc->beta, desc->beta + desc->K);
+    q->desc.beta = q->beta.data();
+    if (out) q->out = *out;
+    q->bytes = p.total;
+    double att = 0;
+    for (uint32_t i = 1; i < desc->K; ++i) att += (double)desc->theta * p.N * (double)p.R_sched[i];
+    q->attempts = (uint64_t)att;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stopping) return fail(PA_ERR_CANCELLED, "server stopping");
+    q->ticket = sv->next_ticket++;
+    q->arrival_us = now_us() - sv->t0;
+    sv->tickets[q->ticket] = q;
+    sv->queue.push_back(q);
+    *ticket = q->ticket;
+    sv->cv_work.notify_one();
+    return PA_OK;
+}
+
+pa_status pa_serve_wait(pa_ctx *ctx, uint64_t ticket, int64_t timeout_us, pa_timing *timing) {
+    if (!ctx || !ctx->server) return fail(PA_ERR_INVALID, "no server");
+    Server *sv = ctx->server;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->tickets.find(ticket);
+    if (it == sv->tickets.end()) return fail(PA_ERR_INVALID, "unknown ticket");
+    auto q = it->second;
+    auto ready = [&] { return q->state == ReqState::Done; };
+    if (timeout_us < 0) sv->cv_done.wait(lk, ready);
+    else if (!sv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
+        return fail(PA_ERR_TIMEOUT, "request not finished");
+    if (timing) {
+        timing->arrival_us = q->arrival_us;
+        timing->admit_us = q->admit_us;
+        timing->done_us = q->done_us;
+        timing->attempts = q->attempts;
+    }
+    sv->tickets.erase(it);
+    if (q->status) return fail(q->status, q->message);
+    return PA_OK;
+}
+
+pa_status pa_serve_cancel(pa_ctx *ctx, uint64_t ticket) {
+    if (!ctx || !ctx->server) return fail(PA_ERR_INVALID, "no server");
+    Server *sv = ctx->server;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->tickets.find(ticket);
+    if (it == sv->tickets.end()) return fail(PA_ERR_INVALID, "unknown ticket");
+    it->second->cancel = true;
+    sv->cv_work.notify_one();
+    return PA_OK;
+}
+
+pa_status pa_serve_stop(pa_ctx *ctx) {
+    if (!ctx || !ctx->server) return fail(PA_ERR_INVALID, "no server");
+    Server *sv = ctx->server;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stopping = true;
+        sv->cv_work.notify_one();
+    }
+    sv->thread.join();
+    ctx->server = nullptr;
+    delete sv;
+    return PA_OK;
 }
 
 }  // extern "C"
