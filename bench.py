@@ -101,6 +101,50 @@ def batched_vs_plain(pa, torch, ctx, runs, reps=1):
             "speedup": t_plain / t_batch}
 
 
+def serving(pa, torch, ctx, n_requests, capacity_attempts_per_ns, rho=0.8,
+            arena_bytes=24 << 30, max_slots=16):
+    """The first n_requests of the 500-request stream, arriving as a Poisson
+    process at rho x capacity / mean request attempts; p50/p99 latency."""
+    import threading
+    from paper_1704_01888_amd import workloads
+    reqs = workloads.serving_requests(500)[:n_requests]
+    descs = [pa.Desc(**r) for r in reqs]
+    atts = [float(r["theta"]) * r["L"] ** 2 * float(np.sum(pa.pa_plan_tables(d)[1][1:]))
+            for r, d in zip(reqs, descs)]
+    mean_att = float(np.mean(atts))
+    rate = rho * capacity_attempts_per_ns * 1e9 / mean_att          # requests per second
+    arrivals = workloads.poisson_arrivals(n_requests, rate)
+    sv = pa.Server(ctx, arena_bytes=arena_bytes, max_slots=max_slots)
+    tickets = [None] * n_requests
+    lat = [None] * n_requests
+    t0 = time.perf_counter()
+
+    def submitter():
+        for i, d in enumerate(descs):
+            delay = arrivals[i] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = sv.submit(d)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    for i in range(n_requests):
+        while tickets[i] is None:
+            time.sleep(0.0005)
+        _, tm = sv.wait(tickets[i])
+        lat[i] = (tm["done_us"] - tm["arrival_us"]) * 1e-3
+    th.join()
+    makespan = time.perf_counter() - t0
+    sv.stop()
+    lat = np.array(lat)
+    return {"requests": n_requests, "offered_load": rho, "arrival_rate_per_s": rate,
+            "attempts": float(sum(atts)), "attempts_per_ns": sum(atts) / makespan / 1e9,
+            "latency_ms_p50": float(np.percentile(lat, 50)),
+            "latency_ms_p99": float(np.percentile(lat, 99)),
+            "latency_ms_max": float(lat.max()), "makespan_s": makespan,
+            "arena_GB": arena_bytes / 2**30, "max_slots": max_slots}
+
+
 def cpu_baseline(n_steps: int):
     """The oracle on the host cores: the same workload cut to its first
     n_steps temperature steps."""
@@ -126,6 +170,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain lines")
+    ap.add_argument("--serve-requests", type=int, default=32,
+                    help="requests of the serving line (0 = skip)")
     ap.add_argument("--cpu-steps", type=int, default=12,
                     help="temperature steps of the oracle's CPU-baseline sample (0 = skip)")
     args = ap.parse_args()
@@ -217,6 +263,11 @@ def main():
             "20 runs L in {16..64}, q in {5..20}, R in [1e4,1e5], 300 steps, theta=10, Poisson":
                 batched_vs_plain(pa, torch, ctx, workloads.mixed_runs(20), reps=1),
         }
+    if args.serve_requests > 0:
+        mixed = result.get("batched", {}).get(
+            "20 runs L in {16..64}, q in {5..20}, R in [1e4,1e5], 300 steps, theta=10, Poisson")
+        capacity = mixed["batched_attempts_per_ns"] if mixed else value
+        result["serving"] = serving(pa, torch, ctx, args.serve_requests, capacity)
     if args.cpu_steps > 0:
         result["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(result), flush=True)

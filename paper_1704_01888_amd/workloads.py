@@ -43,3 +43,25 @@ def mixed_runs(n_runs: int = 20, rng_seed: int = 3, n_steps: int = 300, theta: i
         runs.append(dict(L=L, q=q, R=R, beta=linear_betas(1.1 * beta_t(q), n_steps), theta=theta,
                          seed=3000 + r, resample=0))
     return runs
+
+
+def serving_requests(n_requests: int = 500, rng_seed: int = 5, theta: int = 10):
+    """Request stream: L in {16,32,64,128}, q in {5,6,8,10,20}, R = round(10^U(3,5)),
+    200..500 equal steps to 1.1 ln(1 + sqrt q), theta sweeps, Poisson resampling,
+    seed 5000 + k (dicts of desc fields, in arrival order)."""
+    rng = np.random.default_rng(rng_seed)
+    reqs = []
+    for k in range(n_requests):
+        L = int(rng.choice([16, 32, 64, 128]))
+        q = int(rng.choice([5, 6, 8, 10, 20]))
+        R = int(round(10 ** rng.uniform(3.0, 5.0)))
+        n_steps = int(rng.integers(200, 501))
+        reqs.append(dict(L=L, q=q, R=R, beta=linear_betas(1.1 * beta_t(q), n_steps), theta=theta,
+                         seed=5000 + k, resample=0))
+    return reqs
+
+
+def poisson_arrivals(n: int, rate_per_s: float, rng_seed: int = 55) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(rng_seed)
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=n))
