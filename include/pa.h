@@ -145,6 +145,21 @@ void pa_ctx_destroy(pa_ctx *ctx);
  * stream and report the summed durations in pa_result.kernel_ms. */
 pa_status pa_ctx_set_profiling(pa_ctx *ctx, int enable);
 
+/* Sweep kernel shape.  For L a power of two the sweep kernel exists for two
+ * lane counts per replica (fewer than a wave: several replicas per wave; more
+ * than a wave: one replica per workgroup); results do not depend on the
+ * choice.  pa_ctx_get_lanes reports the lanes later runs will use and the
+ * candidates; pa_ctx_set_lanes picks one (0 = default) for later runs.
+ * pa_autotune times every candidate on a synthetic population of about 64 MB
+ * (K = 3, theta = 4) in the caller's workspace (at least pa_plan's size for
+ * it; 256 MB is enough for every L), keeps the fastest in the context and
+ * returns it with its sweep rate. */
+pa_status pa_ctx_set_lanes(pa_ctx *ctx, uint32_t L, uint32_t lanes);
+pa_status pa_ctx_get_lanes(pa_ctx *ctx, uint32_t L, uint32_t *lanes, uint32_t *candidates /*[2]*/,
+                           uint32_t *n_candidates);
+pa_status pa_autotune(pa_ctx *ctx, uint32_t L, uint32_t q, void *d_ws, uint64_t ws_bytes, void *stream,
+                      uint32_t *best_lanes, double *best_attempts_per_ns);
+
 /* Whole run, steps 1-5 of Sec. 2, enqueued on `stream`; returns when the
  * results are in `out`. */
 pa_status pa_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes,

@@ -25,7 +25,7 @@ KERNEL_NAMES = ("init", "sweep", "post", "resample")
 
 EXPORTS = [
     "pa_plan", "pa_plan_tables", "pa_weight_table", "pa_ctx_create", "pa_ctx_destroy",
-    "pa_ctx_set_profiling",
+    "pa_ctx_set_profiling", "pa_ctx_set_lanes", "pa_ctx_get_lanes", "pa_autotune",
     "pa_run", "pa_run_begin", "pa_run_advance", "pa_run_sync", "pa_run_read", "pa_run_load",
     "pa_run_read_slots", "pa_run_finish", "pa_status_str", "pa_last_error",
     "pa_plan_batch", "pa_run_batch",
@@ -94,6 +94,12 @@ def lib() -> ctypes.CDLL:
     L.pa_ctx_destroy.restype = None
     L.pa_ctx_set_profiling.argtypes = [vp, ctypes.c_int]
     L.pa_ctx_set_profiling.restype = i32
+    L.pa_ctx_set_lanes.argtypes = [vp, u32, u32]
+    L.pa_ctx_set_lanes.restype = i32
+    L.pa_ctx_get_lanes.argtypes = [vp, u32, vp, vp, vp]
+    L.pa_ctx_get_lanes.restype = i32
+    L.pa_autotune.argtypes = [vp, u32, u32, vp, u64, vp, vp, vp]
+    L.pa_autotune.restype = i32
     L.pa_run.argtypes = [vp, P(RunDesc), vp, u64, vp, P(Result)]
     L.pa_run_begin.argtypes = [vp, P(RunDesc), vp, u64, vp, P(vp)]
     L.pa_run_advance.argtypes = [vp, u32]
@@ -187,6 +193,26 @@ class Context:
         h = ctypes.c_void_p()
         _check(lib().pa_ctx_create(self.device, ctypes.byref(h)))
         self.handle = h
+
+    def set_lanes(self, L: int, lanes: int):
+        _check(lib().pa_ctx_set_lanes(self.handle, int(L), int(lanes)))
+
+    def get_lanes(self, L: int):
+        """(lanes in use, candidate list) for lattice side L."""
+        cur = np.zeros(1, np.uint32)
+        cand = np.zeros(2, np.uint32)
+        n = np.zeros(1, np.uint32)
+        _check(lib().pa_ctx_get_lanes(self.handle, int(L), _ptr(cur), _ptr(cand), _ptr(n)))
+        return int(cur[0]), [int(x) for x in cand[: int(n[0])]]
+
+    def autotune(self, L: int, q: int, workspace=None):
+        """Time the lane candidates for (L, q); keep and return the fastest."""
+        ws = workspace if workspace is not None else _workspace(256 << 20, self.device)
+        best = np.zeros(1, np.uint32)
+        rate = np.zeros(1, np.float64)
+        _check(lib().pa_autotune(self.handle, int(L), int(q), ctypes.c_void_p(ws.data_ptr()),
+                                 ws.numel(), _stream_ptr(), _ptr(best), _ptr(rate)))
+        return int(best[0]), float(rate[0])
 
     def set_profiling(self, on: bool):
         _check(lib().pa_ctx_set_profiling(self.handle, 1 if on else 0))

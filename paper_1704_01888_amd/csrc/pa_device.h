@@ -79,15 +79,19 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 
 // Batched forms: several runs per launch.  Sweep launches group runs of one
 // kernel class (sweep_class); `start` [n+1] gives each run's first workgroup.
-uint32_t sweep_class(uint32_t L, uint32_t q, bool t64);
+uint32_t sweep_class(uint32_t L, uint32_t q, bool t64, uint32_t G_log2);
+void *sweep_kernel(uint32_t cls, bool batch);
 hipError_t launch_sweep_batch(uint32_t cls, const SweepArgs *runs, const uint32_t *start, uint32_t n,
                               uint32_t blocks, uint32_t threads, size_t lds, hipStream_t s);
 hipError_t launch_post_batch(const PostArgs *runs, uint32_t n, hipStream_t s);
 hipError_t launch_resample_batch(const SampleArgs *sruns, const uint32_t *start, uint32_t n,
                                  uint32_t blocks, const SlotmapArgs *mruns, hipStream_t s);
 
-// Lanes per replica and waves per block chosen for a lattice side L.
-void sweep_shape(uint32_t L, uint32_t *G_log2, uint32_t *waves_per_block);
+// Lanes-per-replica candidates for L (0 if L has no fixed-shape kernel).
+uint32_t lane_candidates(uint32_t L, uint32_t *out /*[2]*/);
+// Lanes per replica (log2) and waves per block for a lattice side L; `lanes`
+// selects a candidate (anything else: the default).
+void sweep_shape(uint32_t L, uint32_t lanes, uint32_t *G_log2, uint32_t *waves_per_block);
 size_t sweep_lds_bytes(uint32_t N, uint32_t G_log2, uint32_t waves_per_block);
 // Largest dynamic LDS a workgroup may use on the current device.
 size_t max_lds_per_block(int device);

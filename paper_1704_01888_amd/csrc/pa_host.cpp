@@ -234,8 +234,15 @@ struct Server;
 struct pa_ctx {
     int device;
     int profiling;
+    uint32_t lanes[7];   // chosen lanes per replica for L = 4, 8, ..., 256 (0 = default)
     Server *server;
 };
+
+static uint32_t ctx_lanes(const pa_ctx *c, uint32_t L) {
+    for (int i = 0; i < 7; ++i)
+        if (L == (4u << i)) return c ? c->lanes[i] : 0u;
+    return 0;
+}
 
 struct pa_run_state {
     pa_ctx *ctx;
@@ -454,6 +461,7 @@ pa_status pa_ctx_create(int device, pa_ctx **out) {
     if (!c) return fail(PA_ERR_NOMEM, "out of host memory");
     c->device = device;
     c->profiling = 0;
+    for (auto &x : c->lanes) x = 0;
     c->server = nullptr;
     *out = c;
     return PA_OK;
@@ -468,6 +476,79 @@ void pa_ctx_destroy(pa_ctx *ctx) {
 pa_status pa_ctx_set_profiling(pa_ctx *ctx, int enable) {
     if (!ctx) return fail(PA_ERR_INVALID, "null context");
     ctx->profiling = enable ? 1 : 0;
+    return PA_OK;
+}
+
+pa_status pa_ctx_set_lanes(pa_ctx *ctx, uint32_t L, uint32_t lanes) {
+    if (!ctx) return fail(PA_ERR_INVALID, "null context");
+    uint32_t cand[2];
+    const uint32_t n = pa::lane_candidates(L, cand);
+    if (n == 0) return fail(PA_ERR_INVALID, "no lane choices for this lattice side");
+    if (lanes != 0 && lanes != cand[0] && !(n > 1 && lanes == cand[1]))
+        return fail(PA_ERR_INVALID, "lanes is not a candidate for this lattice side");
+    for (int i = 0; i < 7; ++i)
+        if (L == (4u << i)) ctx->lanes[i] = lanes;
+    return PA_OK;
+}
+
+pa_status pa_ctx_get_lanes(pa_ctx *ctx, uint32_t L, uint32_t *lanes, uint32_t *candidates,
+                           uint32_t *n_candidates) {
+    if (!ctx) return fail(PA_ERR_INVALID, "null context");
+    uint32_t cand[2] = {0, 0};
+    const uint32_t n = pa::lane_candidates(L, cand);
+    uint32_t gl, wpb;
+    pa::sweep_shape(L, ctx_lanes(ctx, L), &gl, &wpb);
+    if (lanes) *lanes = 1u << gl;
+    if (candidates) { candidates[0] = cand[0]; candidates[1] = cand[1]; }
+    if (n_candidates) *n_candidates = n;
+    return PA_OK;
+}
+
+pa_status pa_autotune(pa_ctx *ctx, uint32_t L, uint32_t q, void *d_ws, uint64_t ws_bytes, void *stream,
+                      uint32_t *best_lanes, double *best_attempts_per_ns) {
+    if (!ctx) return fail(PA_ERR_INVALID, "null context");
+    uint32_t cand[2];
+    const uint32_t n = pa::lane_candidates(L, cand);
+    if (n == 0) return fail(PA_ERR_INVALID, "no lane choices for this lattice side");
+    // A population of about 64 MB of spins (4096 .. 65536 replicas) fills the GPU.
+    const uint64_t N = (uint64_t)L * L;
+    uint64_t R = std::max<uint64_t>(1024, std::min<uint64_t>(65536, (1ull << 26) / N));
+    const double beta[3] = {0.0, 0.5, 1.0};
+    pa_run_desc d{};
+    d.L = L; d.q = q; d.K = 3; d.beta = beta; d.theta = 4; d.seed = 12345;
+    d.resample = PA_RESAMPLE_MULTINOMIAL; d.init = PA_INIT_RANDOM; d.outputs = 0;
+    pa_plan_info info;
+    for (;;) {
+        d.R = R;
+        pa_status st = pa_plan(&d, &info);
+        if (st) return st;
+        if (info.workspace_bytes <= ws_bytes || R <= 64) break;
+        R /= 2;
+    }
+    if (info.workspace_bytes > ws_bytes) return fail(PA_ERR_NOMEM, "workspace too small for tuning");
+    const int saved_prof = ctx->profiling;
+    const uint32_t saved = ctx_lanes(ctx, L);
+    double best = -1.0;
+    uint32_t best_g = cand[0];
+    for (uint32_t c = 0; c < n; ++c) {
+        pa_ctx_set_lanes(ctx, L, cand[c]);
+        pa_result res{};
+        double kms[PA_KERNEL_KINDS];
+        uint64_t kn[PA_KERNEL_KINDS];
+        res.kernel_ms = kms;
+        res.kernel_launches = kn;
+        ctx->profiling = 0;
+        pa_status st = pa_run(ctx, &d, d_ws, ws_bytes, stream, nullptr);   // warm-up
+        ctx->profiling = 1;
+        if (!st) st = pa_run(ctx, &d, d_ws, ws_bytes, stream, &res);
+        ctx->profiling = saved_prof;
+        if (st) { pa_ctx_set_lanes(ctx, L, saved); return st; }
+        const double rate = 4.0 * (double)N * (double)(2 * R) / (kms[PA_KERNEL_SWEEP] * 1e6);
+        if (rate > best) { best = rate; best_g = cand[c]; }
+    }
+    pa_ctx_set_lanes(ctx, L, best_g);
+    if (best_lanes) *best_lanes = best_g;
+    if (best_attempts_per_ns) *best_attempts_per_ns = best;
     return PA_OK;
 }
 
@@ -493,7 +574,7 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
     r->first_step = 0;
     r->R_first = p.desc.R;
     r->broken = false;
-    pa::sweep_shape(p.desc.L, &r->G_log2, &r->wpb);
+    pa::sweep_shape(p.desc.L, ctx_lanes(ctx, p.desc.L), &r->G_log2, &r->wpb);
     if (pa::sweep_lds_bytes(p.N, r->G_log2, r->wpb) > pa::max_lds_per_block(ctx->device)) {
         delete r;
         return fail(PA_ERR_UNSUPPORTED, "lattice does not fit the LDS of one workgroup on this device");
@@ -740,9 +821,9 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
         r->R_cur = R_new;
         pa::SweepArgs a = sweep_args(r, g, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[prev_buf]), anc,
                                      r->at<uint8_t>(p.off_pop[new_buf]), p.desc.theta);
-        const uint64_t per_block = (uint64_t)r->wpb * (64u >> r->G_log2);
+        const uint64_t per_block = (64u * r->wpb) >> r->G_log2;
         SW e;
-        e.cls = pa::sweep_class(p.desc.L, p.desc.q, a.T[3] == 0);
+        e.cls = pa::sweep_class(p.desc.L, p.desc.q, a.T[3] == 0, r->G_log2);
         e.blocks = (uint32_t)((R_new + per_block - 1) / per_block);
         e.threads = 64u * r->wpb;
         e.lds = pa::sweep_lds_bytes(p.N, r->G_log2, r->wpb);

@@ -216,20 +216,32 @@ __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Separates half-sweeps: within one wave LDS operations execute in order, so a
+// compiler fence suffices; a replica spread over several waves needs the
+// workgroup barrier.
+__device__ __forceinline__ void replica_fence(bool multiwave) {
+    if (multiwave) __syncthreads();
+    else wave_fence();
+}
+
+
+
 // Replica layout in LDS: rows -1 .. L of L bytes each; row r at byte (r+1)*L.
 // Rows -1 and L are copies of rows L-1 and 0 (periodic halo), kept current by
 // the lanes that update rows L-1 and 0.
 //
-// Fixed L (a power of two): lane g of the replica's G lanes owns dword column
+// Fixed L (a power of two) and G lanes per replica (a power of two between
+// L/4 and 1024, fewer than a wave for small lattices, several waves for large
+// ones): lane g of the replica's G lanes owns dword column
 // xd = g mod L/4 and rows y0 + j*RS (y0 = g div L/4, RS = G / (L/4)), so all
 // its addresses are the base plus compile-time offsets and its parity per
 // unrolled slot is fixed.
-template <uint32_t LT, bool QSMALL>
+template <uint32_t LT, uint32_t GT, bool QSMALL>
 __device__ __forceinline__ void sweeps_fixed(uint32_t *lds32, uint32_t g, uint32_t k,
                                              const SweepArgs &a, const Thresholds<false> &thr,
                                              uint32_t theta) {
     constexpr uint32_t L = LT, N = L * L, P = N / 4, DPR = L / 4;
-    constexpr uint32_t G = P < 64 ? P : 64;
+    constexpr uint32_t G = GT;
     constexpr uint32_t PPL = P / G, RS = G / DPR;
     constexpr uint32_t UNR = PPL >= 2 ? 2 : 1;
     static_assert(G % DPR == 0 && P % G == 0 && PPL % UNR == 0, "shape");
@@ -278,7 +290,7 @@ __device__ __forceinline__ void sweeps_fixed(uint32_t *lds32, uint32_t g, uint32
                     if (j + u == PPL - 1 && bottom) lds32[idx[u] - L * DPR] = nw;
                 }
             }
-            wave_fence();
+            replica_fence(G > 64);
         }
     }
 }
@@ -313,17 +325,18 @@ __device__ __forceinline__ void sweeps_any(uint32_t *lds32, uint32_t g, uint32_t
                 if (j0 >= H) { j0 -= H; ++y; }
                 y += dy;
             }
-            wave_fence();
+            replica_fence(G > 64);
         }
     }
 }
 
 // One workgroup `block` of the sweep launch of one run (a): gather or create
 // its replicas in LDS, theta sweeps, energies, histogram, store.
-template <uint32_t LT, bool QSMALL, bool T64>
+template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     extern __shared__ __align__(16) uint8_t smem[];
     // thresholds indexed by dE + 4
+    if (threadIdx.x == 32) reinterpret_cast<uint32_t *>(smem)[24] = 0u;   // energy sum (multi-wave)
     if (threadIdx.x < 9) {
         const int dE = (int)threadIdx.x - 4;
         const uint64_t T = dE <= 0 ? (1ull << 32) : a.T[dE - 1];
@@ -334,17 +347,17 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     const Thresholds<T64> thr{smem};
 
     const uint32_t G_log2 = a.G_log2;
-    const uint32_t G = 1u << G_log2;
-    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t G = 1u << G_log2;                             // lanes per replica
+    const bool multiwave = G > 64;
     const uint32_t wave = threadIdx.x >> 6;
-    const uint32_t g = lane & (G - 1u);
-    const uint32_t rpw = 64u >> G_log2;                          // replicas per wave
-    const uint32_t rep = wave * rpw + (lane >> G_log2);          // replica within block
-    const uint64_t k64 = (uint64_t)block * a.waves_per_block * rpw + rep;
-    const uint64_t first_in_wave = (uint64_t)block * a.waves_per_block * rpw + wave * rpw;
-    if (first_in_wave >= a.R_new) return;                        // whole wave idle
+    const uint32_t g = threadIdx.x & (G - 1u);
+    const uint32_t rpb = (64u * a.waves_per_block) >> G_log2;    // replicas per block
+    const uint32_t rep = threadIdx.x >> G_log2;                  // replica within block
+    const uint64_t k64 = (uint64_t)block * rpb + rep;
+    const uint64_t first_in_wave = (uint64_t)block * rpb + ((wave * 64u) >> G_log2);
+    if (first_in_wave >= a.R_new) return;                        // whole wave (replica) idle
     const bool live = k64 < a.R_new;
-    const uint32_t k = rpw == 1 ? __builtin_amdgcn_readfirstlane((uint32_t)k64) : (uint32_t)k64;
+    const uint32_t k = G >= 64 ? __builtin_amdgcn_readfirstlane((uint32_t)k64) : (uint32_t)k64;
 
     const uint32_t L = a.L, N = a.N, DPR = L >> 2;
     uint8_t *rep_lds = smem + 128 + (size_t)rep * (N + 2 * L);
@@ -370,16 +383,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         const uint32_t alpha = mulhi32(w.x, a.q) * 0x01010101u;
         for (uint32_t dd = g; dd < N / 4u; dd += G) rows32[dd] = alpha;
     }
-    wave_fence();
+    replica_fence(multiwave);
     for (uint32_t dd = g; dd < DPR; dd += G) {                   // periodic halo rows
         lds32[dd] = rows32[(L - 1) * DPR + dd];
         lds32[(L + 1) * DPR + dd] = rows32[dd];
     }
-    wave_fence();
+    replica_fence(multiwave);
 
     // ---- theta checkerboard sweeps --------------------------------------
     const uint32_t theta = (a.mode == SWEEP_UPDATE) ? a.theta : 0u;
-    if constexpr (LT != 0) sweeps_fixed<LT, QSMALL>(lds32, g, k, a, thr, theta);
+    if constexpr (LT != 0) sweeps_fixed<LT, GT, QSMALL>(lds32, g, k, a, thr, theta);
     else sweeps_any<QSMALL, T64>(lds32, g, G, k, a, thr, theta);
 
     // ---- energy (eq. (3)), histogram, store ------------------------------
@@ -393,7 +406,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         const uint32_t right = __builtin_amdgcn_alignbyte(Dr, D, 1);
         bonds += eq_bytes(D, right) + eq_bytes(D, Dd);
     }
-    for (uint32_t off = G >> 1; off > 0; off >>= 1) bonds += __shfl_xor(bonds, off, 64);
+    for (uint32_t off = (G < 64 ? G : 64) >> 1; off > 0; off >>= 1) bonds += __shfl_xor(bonds, off, 64);
+    if (multiwave) {
+        uint32_t *sum = reinterpret_cast<uint32_t *>(smem) + 24;
+        if ((threadIdx.x & 63u) == 0) atomicAdd(sum, bonds);
+        __syncthreads();
+        bonds = *sum;
+    }
     if (live) {
         if (g == 0) {
             const int32_t E = -(int32_t)bonds;
@@ -406,9 +425,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     }
 }
 
-template <uint32_t LT, bool QSMALL, bool T64>
-__global__ void __launch_bounds__(256) k_sweep(SweepArgs a) {
-    sweep_body<LT, QSMALL, T64>(a, blockIdx.x);
+template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64>
+__global__ void __launch_bounds__(1024) k_sweep(SweepArgs a) {
+    sweep_body<LT, GT, QSMALL, T64>(a, blockIdx.x);
 }
 
 // Index of the segment holding `block`: start[r] <= block < start[r + 1].
@@ -423,12 +442,12 @@ __device__ __forceinline__ uint32_t segment_of(const uint32_t *start, uint32_t n
 
 // Batched form: the workgroups of several runs' sweep launches (same lattice
 // class) in one launch; run r owns workgroups start[r] .. start[r+1]-1.
-template <uint32_t LT, bool QSMALL, bool T64>
-__global__ void __launch_bounds__(256) k_sweep_batch(const SweepArgs *runs, const uint32_t *start,
-                                                     uint32_t n) {
+template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64>
+__global__ void __launch_bounds__(1024) k_sweep_batch(const SweepArgs *runs, const uint32_t *start,
+                                                      uint32_t n) {
     const uint32_t r = segment_of(start, n, blockIdx.x);
     const SweepArgs a = runs[r];
-    sweep_body<LT, QSMALL, T64>(a, blockIdx.x - start[r]);
+    sweep_body<LT, GT, QSMALL, T64>(a, blockIdx.x - start[r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -700,11 +719,55 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
 
 }  // namespace
 
-void sweep_shape(uint32_t L, uint32_t *G_log2, uint32_t *waves_per_block) {
-    const uint32_t P = (L * L) / 4u;
-    uint32_t gl = 2;
-    while (gl < 6 && (1u << (gl + 1)) <= P) ++gl;
+// Lanes-per-replica candidates of the fixed-shape kernels (first = default,
+// chosen by measurement on MI355X; pa_autotune can pick the other).
+static const uint32_t kLaneChoices[7][2] = {
+    {4, 4},        // L = 4
+    {8, 4},        // L = 8
+    {16, 8},       // L = 16
+    {64, 32},      // L = 32
+    {64, 256},     // L = 64
+    {256, 512},    // L = 128
+    {1024, 512},   // L = 256
+};
+
+static int pow2_index(uint32_t L) {
+    for (int i = 0; i < 7; ++i)
+        if (L == (4u << i)) return i;
+    return -1;
+}
+
+uint32_t lane_candidates(uint32_t L, uint32_t *out) {
+    const int i = pow2_index(L);
+    if (i < 0) return 0;
+    out[0] = kLaneChoices[i][0];
+    if (kLaneChoices[i][1] == kLaneChoices[i][0]) return 1;
+    out[1] = kLaneChoices[i][1];
+    return 2;
+}
+
+void sweep_shape(uint32_t L, uint32_t lanes, uint32_t *G_log2, uint32_t *waves_per_block) {
+    uint32_t G = 0;
+    if (pow2_index(L) >= 0) {
+        uint32_t cand[2];
+        const uint32_t n = lane_candidates(L, cand);
+        G = cand[0];
+        for (uint32_t c = 0; c < n; ++c)
+            if (cand[c] == lanes) G = lanes;
+    } else {
+        // other sizes (generic kernel): two waves per replica from L = 96 on,
+        // four from L = 192; below, the largest power of two <= L*L/4 up to 64
+        if (L >= 192) G = 256;
+        else if (L >= 96) G = 128;
+        else { G = 4; while (G < 64 && 2 * G <= (L * L) / 4u) G *= 2; }
+    }
+    uint32_t gl = 0;
+    while ((1u << gl) < G) ++gl;
     *G_log2 = gl;
+    if (gl > 6) {                      // one replica per workgroup of G/64 waves
+        *waves_per_block = 1u << (gl - 6);
+        return;
+    }
     const uint32_t N = L * L;
     const uint32_t rpw = 64u >> gl;
     uint32_t wpb = 4;
@@ -715,7 +778,7 @@ void sweep_shape(uint32_t L, uint32_t *G_log2, uint32_t *waves_per_block) {
 size_t sweep_lds_bytes(uint32_t N, uint32_t G_log2, uint32_t waves_per_block) {
     uint32_t L = 0;
     while (L * L < N) ++L;
-    return 128u + (size_t)waves_per_block * (64u >> G_log2) * (N + 2 * L);
+    return 128u + (size_t)((64u * waves_per_block) >> G_log2) * (N + 2 * L);
 }
 
 size_t max_lds_per_block(int device) {
@@ -726,30 +789,17 @@ size_t max_lds_per_block(int device) {
 }
 
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t s) {
-    const uint32_t rpw = 64u >> a.G_log2;
-    const uint64_t per_block = (uint64_t)a.waves_per_block * rpw;
+    const uint64_t per_block = (64u * a.waves_per_block) >> a.G_log2;   // replicas per block
     const uint64_t blocks = (a.R_new + per_block - 1) / per_block;
     if (blocks == 0) return hipSuccess;
     const size_t lds = sweep_lds_bytes(a.N, a.G_log2, a.waves_per_block);
-    // The 32-bit threshold form needs every T >= 1 (T decreases with dE).
-    const bool t64 = a.T[3] == 0;
-    const bool qs = a.q <= 128;
-    void (*kern)(SweepArgs) = qs ? (t64 ? k_sweep<0, true, true> : k_sweep<0, true, false>)
-                                 : (t64 ? k_sweep<0, false, true> : k_sweep<0, false, false>);
-    if (!t64) {
-#define PA_FIXED(LV) case LV: kern = qs ? k_sweep<LV, true, false> : k_sweep<LV, false, false>; break;
-        switch (a.L) {
-            PA_FIXED(4) PA_FIXED(8) PA_FIXED(16) PA_FIXED(32) PA_FIXED(64) PA_FIXED(128) PA_FIXED(256)
-            default: break;
-        }
-#undef PA_FIXED
-    }
+    void *kern = sweep_kernel(sweep_class(a.L, a.q, a.T[3] == 0, a.G_log2), false);
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3((uint32_t)blocks), dim3(64u * a.waves_per_block), lds, s, a);
+    hipLaunchKernelGGL((void (*)(SweepArgs))kern, dim3((uint32_t)blocks), dim3(64u * a.waves_per_block), lds,
+                       s, a);
     return hipGetLastError();
 }
 
@@ -765,27 +815,41 @@ hipError_t launch_resample(const SampleArgs &a, const SlotmapArgs &m, hipStream_
     return hipGetLastError();
 }
 
-uint32_t sweep_class(uint32_t L, uint32_t q, bool t64) {
-    return (L << 2) | ((q <= 128) ? 2u : 0u) | (t64 ? 1u : 0u);
+// Kernel class: lattice side, lanes per replica, q <= 128, 64-bit thresholds.
+uint32_t sweep_class(uint32_t L, uint32_t q, bool t64, uint32_t G_log2) {
+    return (L << 8) | (G_log2 << 2) | ((q <= 128) ? 2u : 0u) | (t64 ? 1u : 0u);
 }
 
-static void *sweep_batch_kernel(uint32_t cls) {
-    const uint32_t lt = cls >> 2;   // L; sizes without a fixed-shape instance use the generic one
+// The instance for a class: fixed-shape when L is a power of two with a
+// candidate lane count and the 32-bit threshold form applies, else generic.
+void *sweep_kernel(uint32_t cls, bool batch) {
+    const uint32_t L = cls >> 8, G = 1u << ((cls >> 2) & 63u);
     const bool qs = (cls & 2u) != 0, t64 = (cls & 1u) != 0;
-    if (t64) return qs ? (void *)k_sweep_batch<0, true, true> : (void *)k_sweep_batch<0, false, true>;
-#define PA_BFIXED(LV) case LV: return qs ? (void *)k_sweep_batch<LV, true, false> : (void *)k_sweep_batch<LV, false, false>;
-    switch (lt) {
-        PA_BFIXED(4) PA_BFIXED(8) PA_BFIXED(16) PA_BFIXED(32) PA_BFIXED(64) PA_BFIXED(128) PA_BFIXED(256)
-        default: break;
+#define PA_INST(LV, GV)                                                                       \
+    if (L == LV && G == GV)                                                                   \
+        return batch ? (qs ? (void *)k_sweep_batch<LV, GV, true, false> : (void *)k_sweep_batch<LV, GV, false, false>) \
+                     : (qs ? (void *)k_sweep<LV, GV, true, false> : (void *)k_sweep<LV, GV, false, false>);
+    if (!t64) {
+        PA_INST(4, 4)
+        PA_INST(8, 8) PA_INST(8, 4)
+        PA_INST(16, 16) PA_INST(16, 8)
+        PA_INST(32, 64) PA_INST(32, 32)
+        PA_INST(64, 64) PA_INST(64, 256)
+        PA_INST(128, 256) PA_INST(128, 512)
+        PA_INST(256, 1024) PA_INST(256, 512)
     }
-#undef PA_BFIXED
-    return qs ? (void *)k_sweep_batch<0, true, false> : (void *)k_sweep_batch<0, false, false>;
+#undef PA_INST
+    if (t64)
+        return batch ? (qs ? (void *)k_sweep_batch<0, 0, true, true> : (void *)k_sweep_batch<0, 0, false, true>)
+                     : (qs ? (void *)k_sweep<0, 0, true, true> : (void *)k_sweep<0, 0, false, true>);
+    return batch ? (qs ? (void *)k_sweep_batch<0, 0, true, false> : (void *)k_sweep_batch<0, 0, false, false>)
+                 : (qs ? (void *)k_sweep<0, 0, true, false> : (void *)k_sweep<0, 0, false, false>);
 }
 
 hipError_t launch_sweep_batch(uint32_t cls, const SweepArgs *runs, const uint32_t *start, uint32_t n,
                               uint32_t blocks, uint32_t threads, size_t lds, hipStream_t s) {
     if (blocks == 0 || n == 0) return hipSuccess;
-    void *kern = sweep_batch_kernel(cls);
+    void *kern = sweep_kernel(cls, true);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
