@@ -94,11 +94,22 @@ def batched_vs_plain(pa, torch, ctx, runs, reps=1):
         pa.pa_run_batch(ctx, descs, workspace=ws_b)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
+    # the same batch replayed as a captured HIP graph (captured in the warm-up)
+    ctx.set_graphs(True)
+    pa.pa_run_batch(ctx, descs, workspace=ws_b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pa.pa_run_batch(ctx, descs, workspace=ws_b)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    ctx.set_graphs(False)
     del ws_b, ws_p
     return {"runs": len(runs), "attempts": att,
             "plain_attempts_per_ns": att / t_plain / 1e9, "plain_ms": t_plain * 1e3,
             "batched_attempts_per_ns": att / t_batch / 1e9, "batched_ms": t_batch * 1e3,
-            "speedup": t_plain / t_batch}
+            "graph_attempts_per_ns": att / t_graph / 1e9, "graph_ms": t_graph * 1e3,
+            "speedup": t_plain / min(t_batch, t_graph)}
 
 
 def serving(pa, torch, ctx, n_requests, capacity_attempts_per_ns, rho=0.8,

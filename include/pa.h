@@ -198,6 +198,11 @@ pa_status pa_run_finish(pa_run_state *run, pa_result *out);
  * separate pa_run calls.  pa_plan_batch gives the workspace size (the runs'
  * workspaces plus the per-step descriptor tables); outs[n] as in pa_run. */
 pa_status pa_plan_batch(const pa_run_desc *descs, uint32_t n, uint64_t *workspace_bytes);
+/* With graphs enabled, pa_run_batch records its per-step launch sequence once
+ * as a HIP graph (on a stream of the context, ordered after the caller's
+ * stream by events) and replays it for later calls with the same
+ * descriptions, workspace and kernel shapes (up to 8 cached graphs). */
+pa_status pa_ctx_set_graphs(pa_ctx *ctx, int enable);
 pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_t n, void *d_ws,
                        uint64_t ws_bytes, void *stream, pa_result *outs);
 

@@ -26,6 +26,7 @@ KERNEL_NAMES = ("init", "sweep", "post", "resample")
 EXPORTS = [
     "pa_plan", "pa_plan_tables", "pa_weight_table", "pa_ctx_create", "pa_ctx_destroy",
     "pa_ctx_set_profiling", "pa_ctx_set_lanes", "pa_ctx_get_lanes", "pa_autotune",
+    "pa_ctx_set_graphs",
     "pa_run", "pa_run_begin", "pa_run_advance", "pa_run_sync", "pa_run_read", "pa_run_load",
     "pa_run_read_slots", "pa_run_finish", "pa_status_str", "pa_last_error",
     "pa_plan_batch", "pa_run_batch",
@@ -100,6 +101,8 @@ def lib() -> ctypes.CDLL:
     L.pa_ctx_get_lanes.restype = i32
     L.pa_autotune.argtypes = [vp, u32, u32, vp, u64, vp, vp, vp]
     L.pa_autotune.restype = i32
+    L.pa_ctx_set_graphs.argtypes = [vp, ctypes.c_int]
+    L.pa_ctx_set_graphs.restype = i32
     L.pa_run.argtypes = [vp, P(RunDesc), vp, u64, vp, P(Result)]
     L.pa_run_begin.argtypes = [vp, P(RunDesc), vp, u64, vp, P(vp)]
     L.pa_run_advance.argtypes = [vp, u32]
@@ -213,6 +216,9 @@ class Context:
         _check(lib().pa_autotune(self.handle, int(L), int(q), ctypes.c_void_p(ws.data_ptr()),
                                  ws.numel(), _stream_ptr(), _ptr(best), _ptr(rate)))
         return int(best[0]), float(rate[0])
+
+    def set_graphs(self, on: bool):
+        _check(lib().pa_ctx_set_graphs(self.handle, 1 if on else 0))
 
     def set_profiling(self, on: bool):
         _check(lib().pa_ctx_set_profiling(self.handle, 1 if on else 0))

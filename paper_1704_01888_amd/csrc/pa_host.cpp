@@ -231,11 +231,20 @@ pa_status build_plan(const pa_run_desc *d, Plan &p, bool tables) {
 
 struct Server;
 
+struct GraphCache {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct pa_ctx {
     int device;
     int profiling;
     uint32_t lanes[7];   // chosen lanes per replica for L = 4, 8, ..., 256 (0 = default)
     Server *server;
+    int graphs;          // batched runs replay a captured HIP graph
+    hipStream_t graph_stream;
+    hipEvent_t ev_in, ev_out;
+    std::deque<GraphCache> graph_cache;
 };
 
 static uint32_t ctx_lanes(const pa_ctx *c, uint32_t L) {
@@ -463,6 +472,9 @@ pa_status pa_ctx_create(int device, pa_ctx **out) {
     c->profiling = 0;
     for (auto &x : c->lanes) x = 0;
     c->server = nullptr;
+    c->graphs = 0;
+    c->graph_stream = nullptr;
+    c->ev_in = c->ev_out = nullptr;
     *out = c;
     return PA_OK;
 }
@@ -470,7 +482,24 @@ pa_status pa_ctx_create(int device, pa_ctx **out) {
 void pa_ctx_destroy(pa_ctx *ctx) {
     if (!ctx) return;
     if (ctx->server) pa_serve_stop(ctx);
+    for (auto &g : ctx->graph_cache) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
+    if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+    if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     delete ctx;
+}
+
+pa_status pa_ctx_set_graphs(pa_ctx *ctx, int enable) {
+    if (!ctx) return fail(PA_ERR_INVALID, "null context");
+    if (enable && !ctx->graph_stream) {
+        if (hipSetDevice(ctx->device) != hipSuccess ||
+            hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming) != hipSuccess)
+            return fail(PA_ERR_DEVICE, "cannot create the graph stream");
+    }
+    ctx->graphs = enable ? 1 : 0;
+    return PA_OK;
 }
 
 pa_status pa_ctx_set_profiling(pa_ctx *ctx, int enable) {
@@ -987,8 +1016,46 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
     if (cursor && (st = hip_check(nullptr, hipMemcpyAsync(dtab, blob.data(), cursor, hipMemcpyHostToDevice, s),
                                   "upload descriptors")))
         return cleanup(st);
-    for (const StepLaunch &L : steps)
-        if ((st = launch_step(L, dtab, s))) return cleanup(st);
+    if (ctx->graphs) {
+        // Replay (capturing first if needed) the step sequence as one graph on
+        // the context's stream, ordered after everything on the caller's stream.
+        std::string key((const char *)descs, sizeof(pa_run_desc) * n);
+        for (uint32_t r = 0; r < n; ++r)
+            key.append((const char *)descs[r].beta, sizeof(double) * descs[r].K);
+        key.append((const char *)&d_ws, sizeof d_ws);
+        key.append((const char *)&ws_bytes, sizeof ws_bytes);
+        for (int i = 0; i < 7; ++i) key.append((const char *)&ctx->lanes[i], 4);
+        hipGraphExec_t exec = nullptr;
+        for (auto &g : ctx->graph_cache)
+            if (g.key == key) exec = g.exec;
+        hipStream_t gs = ctx->graph_stream;
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            if ((st = hip_check(nullptr, hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal), "capture")))
+                return cleanup(st);
+            for (const StepLaunch &L : steps)
+                if (!st) st = launch_step(L, dtab, gs);
+            pa_status st2 = hip_check(nullptr, hipStreamEndCapture(gs, &graph), "end capture");
+            if (st || st2) { if (graph) (void)hipGraphDestroy(graph); return cleanup(st ? st : st2); }
+            st = hip_check(nullptr, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
+            (void)hipGraphDestroy(graph);
+            if (st) return cleanup(st);
+            if (ctx->graph_cache.size() >= 8) {
+                (void)hipGraphExecDestroy(ctx->graph_cache.front().exec);
+                ctx->graph_cache.pop_front();
+            }
+            ctx->graph_cache.push_back({key, exec});
+        }
+        if ((st = hip_check(nullptr, hipEventRecord(ctx->ev_in, s), "record")) ||
+            (st = hip_check(nullptr, hipStreamWaitEvent(gs, ctx->ev_in, 0), "wait")) ||
+            (st = hip_check(nullptr, hipGraphLaunch(exec, gs), "graph launch")) ||
+            (st = hip_check(nullptr, hipEventRecord(ctx->ev_out, gs), "record")) ||
+            (st = hip_check(nullptr, hipStreamWaitEvent(s, ctx->ev_out, 0), "wait")))
+            return cleanup(st);
+    } else {
+        for (const StepLaunch &L : steps)
+            if ((st = launch_step(L, dtab, s))) return cleanup(st);
+    }
     if ((st = hip_check(nullptr, hipStreamSynchronize(s), "sync"))) return cleanup(st);
     pa_status first = PA_OK;
     for (uint32_t r = 0; r < n; ++r) {

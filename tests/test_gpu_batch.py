@@ -58,3 +58,23 @@ def test_batch_of_identical_shapes_differs_only_by_seed(ctx):
     for d, g in zip(descs, got):
         _same(g, pa.pa_run(ctx, d))
     assert not (got[0]["final_spins"] == got[1]["final_spins"]).all()
+
+
+def test_graph_replays_equal_eager(ctx):
+    """The captured graph replayed several times (with eager runs and
+    synchronisations in between) gives the eager results every time."""
+    import torch
+    cfg = MIXED[:6]
+    descs = [pa.Desc(outputs=pa.OUT_HIST | pa.OUT_FINAL, **c) for c in cfg]
+    eager = pa.pa_run_batch(ctx, descs)
+    ws = torch.empty(pa.pa_plan_batch(descs), dtype=torch.uint8, device="cuda:0")
+    ctx.set_graphs(True)
+    try:
+        for rep in range(3):
+            got = pa.pa_run_batch(ctx, descs, workspace=ws)
+            for a, b in zip(got, eager):
+                _same(a, b)
+            pa.pa_run(ctx, descs[0])          # eager work between replays
+            torch.cuda.synchronize()
+    finally:
+        ctx.set_graphs(False)
