@@ -28,7 +28,12 @@
  *     R_i multinomial draws with integer weights round(2^Kb exp(-|dbeta| d_j)),
  *     d_j = |E_j - E_ref|; this is the same joint law as eq. (1) because the
  *     Poisson means add up to R;
- *   - the new population is stored in ancestor order.
+ *   - the new population is stored in ancestor order;
+ *   - histogram widths (Sec. 4): bins of bin_e energy levels (bin_m levels of
+ *     M~) counted from E = -2N (M~ = 0); the histogram is taken as the
+ *     piecewise-linear curve through the bin counts (zero beyond both ends),
+ *     and the width is the distance between its outermost crossings of half
+ *     the largest count, converted to e = E/N or m = M/N units.
  *
  * Memory ownership: device memory belongs to the caller.  The library only
  * sub-allocates inside the workspace d_ws (device pointer, at least
@@ -68,8 +73,13 @@ typedef enum { PA_INIT_RANDOM = 0, PA_INIT_GROUND = 1 } pa_init;
 
 /* Output selection bits for pa_run_desc.outputs. */
 enum {
-    PA_OUT_HIST = 1,   /* per-step energy histograms, [K][2N+1]           */
-    PA_OUT_FINAL = 4   /* final population, energies and last ancestors  */
+    PA_OUT_HIST = 1,   /* per-step energy histograms, [K][2N+1] (and, with
+                          PA_OUT_MAG, M~ histograms [K][N+1])              */
+    PA_OUT_MAG = 2,    /* magnetisation, eq. (4)-(5): sum of M~ and M-bar   */
+    PA_OUT_FINAL = 4,  /* final population, energies and last ancestors  */
+    PA_OUT_WIDTHS = 8  /* full width at half maximum of the energy histogram
+                          (and, with PA_OUT_MAG, of the magnetisation
+                          histogram) at every step, Sec. 4              */
 };
 
 /* A PA run (Sec. 2): lattice L x L periodic (Sec. 3), q states, target
@@ -85,6 +95,8 @@ typedef struct {
     int32_t resample;    /* pa_resample                                                 */
     int32_t init;        /* pa_init                                                     */
     uint32_t outputs;    /* PA_OUT_* bits                                               */
+    uint32_t bin_e;      /* PA_OUT_WIDTHS: energy levels per histogram bin (0 means 1)  */
+    uint32_t bin_m;      /* PA_OUT_WIDTHS: M~ levels per histogram bin (0 means 1)      */
 } pa_run_desc;
 
 /* Kernel kinds, for the optional per-kernel timing of pa_result. */
@@ -104,6 +116,12 @@ typedef struct {
     double   *lnQ;           /* ln Q_i of Sec. 2 step 2; lnQ[0] = 0                */
     double   *minus_beta_F;  /* eq. (2) with ln Z_beta0 (N ln q, or eq. (7)-(8))   */
     uint32_t *hist;          /* [K][2N+1], h[b] = #{j: E_j = b - 2N}; NULL unless PA_OUT_HIST */
+    int64_t  *Mt_sum;        /* PA_OUT_MAG: exact sum over the population of M~ (eq. (5)) */
+    double   *M_mean;        /* PA_OUT_MAG: eq. (4)-(5), M-bar = (q Mt_sum - N R_i) / ((q-1) R_i),
+                                one rounding                                         */
+    uint32_t *mhist;         /* [K][N+1], #{j: M~_j = m}; PA_OUT_MAG with PA_OUT_HIST */
+    double   *width_e;       /* PA_OUT_WIDTHS: FWHM of the histogram of e = E/N       */
+    double   *width_m;       /* PA_OUT_WIDTHS with PA_OUT_MAG: FWHM of the histogram of m = M/N */
     uint8_t  *final_spins;   /* [R_{K-1}][N]; NULL unless PA_OUT_FINAL              */
     int32_t  *final_E;       /* [R_{K-1}];     NULL unless PA_OUT_FINAL              */
     uint32_t *last_anc;      /* [R_{K-1}] ancestors of the last resampling (identity if K == 1) */

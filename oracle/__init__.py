@@ -43,6 +43,7 @@ class _Desc(ctypes.Structure):
         ("beta", ctypes.POINTER(ctypes.c_double)),
         ("theta", ctypes.c_uint32), ("seed", ctypes.c_uint64),
         ("resample", ctypes.c_int32), ("init", ctypes.c_int32),
+        ("bin_e", ctypes.c_uint32), ("bin_m", ctypes.c_uint32),
     ]
 
 
@@ -50,7 +51,9 @@ class _Result(ctypes.Structure):
     _fields_ = [
         ("R_i", ctypes.c_void_p), ("E_sum", ctypes.c_void_p), ("E_mean", ctypes.c_void_p),
         ("lnQ", ctypes.c_void_p), ("minus_beta_F", ctypes.c_void_p),
-        ("M_mean", ctypes.c_void_p), ("hist", ctypes.c_void_p),
+        ("M_mean", ctypes.c_void_p), ("Mt_sum", ctypes.c_void_p), ("mhist", ctypes.c_void_p),
+        ("width_e", ctypes.c_void_p), ("width_m", ctypes.c_void_p),
+        ("hist", ctypes.c_void_p),
         ("final_spins", ctypes.c_void_p), ("final_E", ctypes.c_void_p),
         ("last_anc", ctypes.c_void_p), ("n_threads", ctypes.c_int),
     ]
@@ -85,6 +88,8 @@ def lib():
         L.orc_resample.argtypes = [ctypes.POINTER(_Desc), u32, u32, vp, u64, u64, vp, vp, vp]
         L.orc_lnQ.argtypes = [u32, dbl, vp, u64, vp]
         L.orc_lnQ.restype = dbl
+        L.orc_fwhm.argtypes = [vp, u32, u32]
+        L.orc_fwhm.restype = dbl
         L.orc_run.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_Result)]
         L.orc_step.argtypes = [ctypes.POINTER(_Desc), u32, u32, vp, vp, u64, u64, vp, vp, vp]
         _lib = L
@@ -98,12 +103,14 @@ def _ptr(a: np.ndarray) -> int:
 class Desc:
     """Run description (the same fields as the GPU library's run descriptor)."""
 
-    def __init__(self, L, q, R, beta, theta, seed, resample=RESAMPLE_POISSON, init=INIT_RANDOM):
+    def __init__(self, L, q, R, beta, theta, seed, resample=RESAMPLE_POISSON, init=INIT_RANDOM,
+                 bin_e=1, bin_m=1):
         self.L, self.q, self.R = int(L), int(q), int(R)
         self.beta = np.ascontiguousarray(beta, dtype=np.float64)
         self.K = len(self.beta)
         self.theta, self.seed = int(theta), int(seed)
         self.resample, self.init = int(resample), int(init)
+        self.bin_e, self.bin_m = int(bin_e), int(bin_m)
 
     @property
     def N(self):
@@ -114,6 +121,7 @@ class Desc:
         d.L, d.q, d.R, d.K = self.L, self.q, self.R, self.K
         d.beta = self.beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         d.theta, d.seed, d.resample, d.init = self.theta, self.seed, self.resample, self.init
+        d.bin_e, d.bin_m = self.bin_e, self.bin_m
         self._keep = self.beta
         return d
 
@@ -218,7 +226,13 @@ def step(d: Desc, i: int, Kb: int, spins_old: np.ndarray, E_old: np.ndarray, R_n
     return spins_new, E_new, anc
 
 
-def run(d: Desc, hist=False, final=False, magnetisation=False):
+def fwhm(h: np.ndarray, B: int = 1) -> float:
+    """Full width at half maximum of histogram h in bins of B levels (in levels)."""
+    hh = np.ascontiguousarray(h, dtype=np.uint32)
+    return float(lib().orc_fwhm(_ptr(hh), len(hh), int(B)))
+
+
+def run(d: Desc, hist=False, final=False, magnetisation=False, widths=False):
     """Whole PA run; returns a dict of numpy arrays."""
     R_sched, R_cap, Kb = plan(d)
     K, N = d.K, d.N
@@ -231,7 +245,17 @@ def run(d: Desc, hist=False, final=False, magnetisation=False):
         setattr(res, name, _ptr(out[name]))
     if magnetisation:
         out["M_mean"] = np.zeros(K)
+        out["Mt_sum"] = np.zeros(K, dtype=np.int64)
+        out["mhist"] = np.zeros((K, N + 1), dtype=np.uint32)
         res.M_mean = _ptr(out["M_mean"])
+        res.Mt_sum = _ptr(out["Mt_sum"])
+        res.mhist = _ptr(out["mhist"])
+    if widths:
+        out["width_e"] = np.zeros(K)
+        res.width_e = _ptr(out["width_e"])
+        if magnetisation:
+            out["width_m"] = np.zeros(K)
+            res.width_m = _ptr(out["width_m"])
     if hist:
         out["hist"] = np.zeros((K, 2 * N + 1), dtype=np.uint32)
         res.hist = _ptr(out["hist"])

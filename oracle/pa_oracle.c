@@ -440,6 +440,37 @@ int orc_step(const orc_desc *d, uint32_t i, uint32_t Kb, const uint8_t *spins_ol
 }
 
 /* ------------------------------------------------------------------------ */
+/* Histogram width (Sec. 4).                                                 */
+/* ------------------------------------------------------------------------ */
+double orc_fwhm(const uint32_t *h, uint32_t nb, uint32_t B)
+{
+    if (B == 0) B = 1;
+    uint32_t nc = (nb + B - 1) / B;
+    /* c[1..nc] are the bin counts; c[0] = c[nc+1] = 0 stand for the zero
+     * continuation beyond both ends. */
+    double *c = (double *)calloc(nc + 2, sizeof(double));
+    if (!c) return -1.0;
+    for (uint32_t b = 0; b < nb; ++b) c[b / B + 1] += (double)h[b];
+    double H = 0.0;
+    for (uint32_t j = 1; j <= nc; ++j)
+        if (c[j] > H) H = c[j];
+    double width = 0.0;
+    if (H > 0.0) {
+        double half = 0.5 * H;
+        uint32_t jl = 1, jr = nc;
+        while (c[jl] < half) ++jl;     /* first bin at or above H/2 from the left  */
+        while (c[jr] < half) --jr;     /* ... and from the right                   */
+        /* Crossing points on the straight segments into those bins; bin j of
+         * c sits at abscissa j - 1. */
+        double xl = (double)((int64_t)jl - 2) + (half - c[jl - 1]) / (c[jl] - c[jl - 1]);
+        double xr = (double)((int64_t)jr - 1) + (c[jr] - half) / (c[jr] - c[jr + 1]);
+        width = (xr - xl) * (double)B;
+    }
+    free(c);
+    return width;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole run.                                                                */
 /* ------------------------------------------------------------------------ */
 static void observe(const orc_desc *d, uint32_t i, const uint8_t *spins, const int32_t *E,
@@ -452,19 +483,38 @@ static void observe(const orc_desc *d, uint32_t i, const uint8_t *spins, const i
     out->E_sum[i] = sum;
     /* eq. (4): population average. */
     out->E_mean[i] = (double)sum / (double)R_i;
-    if (out->hist) {
-        uint32_t *h = out->hist + (uint64_t)i * (2 * N + 1);
-        memset(h, 0, sizeof(uint32_t) * (2 * N + 1));
-        for (uint64_t k = 0; k < R_i; ++k) h[E[k] + (int32_t)(2 * N)]++;
+    uint32_t *eh = out->hist ? out->hist + (uint64_t)i * (2 * N + 1)
+                             : (uint32_t *)malloc(sizeof(uint32_t) * (2 * N + 1));
+    if (eh) {
+        memset(eh, 0, sizeof(uint32_t) * (2 * N + 1));
+        for (uint64_t k = 0; k < R_i; ++k) eh[E[k] + (int32_t)(2 * N)]++;
+        /* Sec. 4: width of the distribution of e = E/N over the population. */
+        if (out->width_e) out->width_e[i] = orc_fwhm(eh, 2 * N + 1, d->bin_e) / (double)N;
+        if (!out->hist) free(eh);
     }
-    if (out->M_mean) {
-        /* eq. (5): M = (q M~ - N) / (q - 1), averaged as in eq. (4). */
-        double msum = 0.0;
+    if (out->M_mean || out->Mt_sum || out->mhist || out->width_m) {
+        /* eq. (5): M_k = (q M~_k - N) / (q - 1); eq. (4): the population mean
+         * (1/R_i) sum_k M_k = (q sum_k M~_k - N R_i) / ((q - 1) R_i), taken from
+         * the exact integer sum of M~ with one rounding. */
+        int64_t mt_sum = 0;
+        uint32_t *mh = out->mhist ? out->mhist + (uint64_t)i * (N + 1)
+                                  : (uint32_t *)malloc(sizeof(uint32_t) * (N + 1));
+        if (mh) memset(mh, 0, sizeof(uint32_t) * (N + 1));
         for (uint64_t k = 0; k < R_i; ++k) {
             uint32_t mt = orc_mtilde(d->L, d->q, spins + k * N);
-            msum += ((double)d->q * (double)mt - (double)N) / (double)(d->q - 1);
+            mt_sum += mt;
+            if (mh) mh[mt]++;
         }
-        out->M_mean[i] = msum / (double)R_i;
+        if (out->Mt_sum) out->Mt_sum[i] = mt_sum;
+        if (out->M_mean)
+            out->M_mean[i] = ((double)d->q * (double)mt_sum - (double)N * (double)R_i) /
+                             ((double)(d->q - 1) * (double)R_i);
+        /* Sec. 4: width of the distribution of m = M/N; by eq. (5) one level of
+         * M~ is q / ((q - 1) N) in m. */
+        if (out->width_m && mh)
+            out->width_m[i] = (orc_fwhm(mh, N + 1, d->bin_m) * (double)d->q) /
+                              ((double)(d->q - 1) * (double)N);
+        if (!out->mhist) free(mh);
     }
 }
 

@@ -42,6 +42,7 @@ typedef struct {
     uint64_t seed;         /* Philox key = (low 32 bits, high 32 bits)                 */
     int32_t resample;      /* ORC_RESAMPLE_*                                           */
     int32_t init;          /* ORC_INIT_*                                               */
+    uint32_t bin_e, bin_m; /* histogram widths: energy / M~ levels per bin (0 means 1)  */
 } orc_desc;
 
 /* Philox4x32-10 block: out = Philox(ctr, key). */
@@ -72,6 +73,13 @@ int32_t orc_energy(uint32_t L, const uint8_t *s);
 
 /* Magnetisation, eq. (5): returns M~ = max_alpha #{k: s_k = alpha}. */
 uint32_t orc_mtilde(uint32_t L, uint32_t q, const uint8_t *s);
+
+/* Full width at half maximum of a histogram (Sec. 4), in levels: h[0..nb)
+ * grouped into bins of B levels (bin j = levels jB .. jB+B-1), read as the
+ * straight lines through the bin counts at the bin indices, zero beyond both
+ * ends; the width is B times the distance between its outermost crossings of
+ * half the largest count.  Returns 0 for an empty histogram. */
+double orc_fwhm(const uint32_t *h, uint32_t nb, uint32_t B);
 
 /* Initial configuration of slot k (random: uniform spins; ground: all equal). */
 void orc_init_replica(const orc_desc *d, uint64_t k, uint8_t *s);
@@ -106,6 +114,10 @@ typedef struct {
     double   *lnQ;          /* ln Q_i, lnQ[0] = 0                               */
     double   *minus_beta_F; /* eq. (2) with ln Z_{beta_0}                       */
     double   *M_mean;       /* eq. (4)-(5) magnetisation mean, or NULL          */
+    int64_t  *Mt_sum;       /* sum over the population of M~ (eq. (5)), or NULL */
+    uint32_t *mhist;        /* [K][N+1] histogram of M~, or NULL                */
+    double   *width_e;      /* FWHM of the histogram of e = E/N (Sec. 4), or NULL */
+    double   *width_m;      /* FWHM of the histogram of m = M/N (Sec. 4), or NULL */
     uint32_t *hist;         /* [K][2N+1] energy histogram, or NULL              */
     uint8_t  *final_spins;  /* [R_{K-1}][N], or NULL                            */
     int32_t  *final_E;      /* [R_{K-1}], or NULL                               */

@@ -20,7 +20,7 @@ PA_OK, PA_ERR_INVALID, PA_ERR_NOMEM, PA_ERR_DEVICE, PA_ERR_CAPACITY, PA_ERR_UNSU
     0, -1, -2, -3, -4, -5
 RESAMPLE_POISSON, RESAMPLE_MULTINOMIAL, RESAMPLE_NONE = 0, 1, 2
 INIT_RANDOM, INIT_GROUND = 0, 1
-OUT_HIST, OUT_FINAL = 1, 4
+OUT_HIST, OUT_MAG, OUT_FINAL, OUT_WIDTHS = 1, 2, 4, 8
 KERNEL_NAMES = ("init", "sweep", "post", "resample")
 
 EXPORTS = [
@@ -47,6 +47,7 @@ class RunDesc(ctypes.Structure):
         ("K", ctypes.c_uint32), ("beta", ctypes.POINTER(ctypes.c_double)),
         ("theta", ctypes.c_uint32), ("seed", ctypes.c_uint64),
         ("resample", ctypes.c_int32), ("init", ctypes.c_int32), ("outputs", ctypes.c_uint32),
+        ("bin_e", ctypes.c_uint32), ("bin_m", ctypes.c_uint32),
     ]
 
 
@@ -54,6 +55,8 @@ class Result(ctypes.Structure):
     _fields_ = [
         ("R_i", ctypes.c_void_p), ("E_sum", ctypes.c_void_p), ("E_mean", ctypes.c_void_p),
         ("lnQ", ctypes.c_void_p), ("minus_beta_F", ctypes.c_void_p), ("hist", ctypes.c_void_p),
+        ("Mt_sum", ctypes.c_void_p), ("M_mean", ctypes.c_void_p), ("mhist", ctypes.c_void_p),
+        ("width_e", ctypes.c_void_p), ("width_m", ctypes.c_void_p),
         ("final_spins", ctypes.c_void_p), ("final_E", ctypes.c_void_p),
         ("last_anc", ctypes.c_void_p), ("kernel_ms", ctypes.c_void_p),
         ("kernel_launches", ctypes.c_void_p),
@@ -145,12 +148,13 @@ class Desc:
     """A run description (fields of ``pa_run_desc``)."""
 
     def __init__(self, L, q, R, beta, theta, seed, resample=RESAMPLE_POISSON, init=INIT_RANDOM,
-                 outputs=0):
+                 outputs=0, bin_e=1, bin_m=1):
         self.L, self.q, self.R = int(L), int(q), int(R)
         self.beta = np.ascontiguousarray(beta, dtype=np.float64)
         self.K = len(self.beta)
         self.theta, self.seed = int(theta), int(seed)
         self.resample, self.init, self.outputs = int(resample), int(init), int(outputs)
+        self.bin_e, self.bin_m = int(bin_e), int(bin_m)
 
     @property
     def N(self):
@@ -162,6 +166,7 @@ class Desc:
         d.beta = self.beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         d.theta, d.seed = self.theta, self.seed
         d.resample, d.init, d.outputs = self.resample, self.init, self.outputs
+        d.bin_e, d.bin_m = self.bin_e, self.bin_m
         return d
 
 
@@ -257,6 +262,20 @@ def _alloc_result(desc: Desc, info: PlanInfo):
     if desc.outputs & OUT_HIST:
         out["hist"] = np.zeros((K, 2 * N + 1), np.uint32)
         res.hist = _ptr(out["hist"])
+    if desc.outputs & OUT_MAG:
+        out["Mt_sum"] = np.zeros(K, np.int64)
+        out["M_mean"] = np.zeros(K)
+        res.Mt_sum = _ptr(out["Mt_sum"])
+        res.M_mean = _ptr(out["M_mean"])
+        if desc.outputs & OUT_HIST:
+            out["mhist"] = np.zeros((K, N + 1), np.uint32)
+            res.mhist = _ptr(out["mhist"])
+    if desc.outputs & OUT_WIDTHS:
+        out["width_e"] = np.zeros(K)
+        res.width_e = _ptr(out["width_e"])
+        if desc.outputs & OUT_MAG:
+            out["width_m"] = np.zeros(K)
+            res.width_m = _ptr(out["width_m"])
     if desc.outputs & OUT_FINAL:
         RF = int(info.R_final)
         out["final_spins"] = np.zeros((RF, N), np.uint8)

@@ -18,6 +18,7 @@ struct SweepArgs {
     uint8_t *new_pop;         // [R_new][N]
     int32_t *E_out;           // [R_new]
     uint32_t *hist;           // [2N+1], accumulated with atomics
+    uint32_t *mhist;          // [N+1] histogram of M~ (eq. (5)), or nullptr
     uint64_t T[4];            // thresholds for dE = 1..4 (<= 2^32)
     uint32_t L, q, N;
     uint32_t R_new;
@@ -52,6 +53,16 @@ struct PostArgs {
     const uint64_t *W;        // [D] fixed-point weights of step i+1
     uint32_t D;
     uint64_t *C;              // [R_i] inclusive prefix sums
+    // magnetisation (eq. (4)-(5)) and histogram widths of step i
+    const uint32_t *mhist;    // [N+1] histogram of M~ at step i, or nullptr
+    uint32_t *mzero_next;     // M~ histogram buffer to clear for step i+1, or nullptr
+    uint32_t q, N;
+    int64_t *Mt_sum;          // [K]
+    double *M_mean;           // [K]
+    uint32_t widths;          // compute the FWHM of the histograms of step i
+    uint32_t bin_e, bin_m;    // levels per histogram bin (>= 1)
+    double *width_e;          // [K]
+    double *width_m;          // [K] (needs mhist)
 };
 
 struct SampleArgs {

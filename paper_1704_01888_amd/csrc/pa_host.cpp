@@ -103,10 +103,12 @@ struct Plan {
     std::vector<uint32_t> D;              // [n_tables]
     std::vector<double> w64;              // [n_tables][nbins]
     uint32_t n_tables = 0;
-    bool hist_all = false;
+    bool hist_all = false, mag = false, widths = false;
+    uint32_t bin_e = 1, bin_m = 1;
     // workspace layout
     size_t off_pop[2], off_E, off_C, off_r, off_anc, off_counts, off_hist, off_Esum, off_Emean,
-        off_count, off_lnQ, off_mbF, off_Eref, off_W, off_w64, total;
+        off_count, off_lnQ, off_mbF, off_Eref, off_W, off_w64, off_mhist, off_Mtsum, off_Mmean,
+        off_we, off_wm, total;
 };
 
 pa_status validate(const pa_run_desc *d) {
@@ -123,6 +125,10 @@ pa_status validate(const pa_run_desc *d) {
             return fail(PA_ERR_INVALID, "beta must be finite and >= 0");
     if (d->init == PA_INIT_RANDOM && d->beta[0] != 0.0)
         return fail(PA_ERR_INVALID, "a random initial population needs beta[0] == 0");
+    if (d->outputs & ~(uint32_t)(PA_OUT_HIST | PA_OUT_MAG | PA_OUT_FINAL | PA_OUT_WIDTHS))
+        return fail(PA_ERR_INVALID, "unknown output bits");
+    if (d->bin_e > 2 * d->L * d->L + 1 || d->bin_m > d->L * d->L + 1)
+        return fail(PA_ERR_INVALID, "histogram bin wider than the histogram");
     if ((d->L & 3u) || d->L < 4 || d->L > 256)
         return fail(PA_ERR_UNSUPPORTED, "this device path needs L % 4 == 0 and 4 <= L <= 256");
     return PA_OK;
@@ -205,6 +211,10 @@ pa_status build_plan(const pa_run_desc *d, Plan &p, bool tables) {
 
     // Workspace layout.
     p.hist_all = (d->outputs & PA_OUT_HIST) != 0;
+    p.mag = (d->outputs & PA_OUT_MAG) != 0;
+    p.widths = (d->outputs & PA_OUT_WIDTHS) != 0;
+    p.bin_e = d->bin_e ? d->bin_e : 1u;
+    p.bin_m = d->bin_m ? d->bin_m : 1u;
     size_t o = 0;
     const size_t popb = align256((size_t)p.R_cap * p.N);
     p.off_pop[0] = o; o += popb;
@@ -223,6 +233,11 @@ pa_status build_plan(const pa_run_desc *d, Plan &p, bool tables) {
     p.off_Eref = o; o += align256(4 * (size_t)K);
     p.off_W = o; o += align256((size_t)8 * p.nbins * p.n_tables);
     p.off_w64 = o; o += align256((size_t)8 * p.nbins * p.n_tables);
+    p.off_mhist = o; o += p.mag ? align256((size_t)4 * (p.N + 1) * (p.hist_all ? K : 2)) : 0;
+    p.off_Mtsum = o; o += p.mag ? align256(8 * (size_t)K) : 0;
+    p.off_Mmean = o; o += p.mag ? align256(8 * (size_t)K) : 0;
+    p.off_we = o; o += p.widths ? align256(8 * (size_t)K) : 0;
+    p.off_wm = o; o += (p.widths && p.mag) ? align256(8 * (size_t)K) : 0;
     p.total = o;
     return PA_OK;
 }
@@ -317,12 +332,21 @@ uint32_t *hist_of(pa_run_state *r, uint32_t i) {
     return r->at<uint32_t>(p.off_hist) + slot * p.nbins;
 }
 
-// Statistics of step i, ln Q_{i+1}, and the weights of the resampling to i+1.
-pa_status launch_post_for(pa_run_state *r, uint32_t i) {
+uint32_t *mhist_of(pa_run_state *r, uint32_t i) {
+    const Plan &p = r->plan;
+    if (!p.mag) return nullptr;
+    const size_t slot = p.hist_all ? i : (i & 1u);
+    return r->at<uint32_t>(p.off_mhist) + slot * (p.N + 1);
+}
+
+// Post-kernel arguments of step i (population size R_cur): statistics of step
+// i, ln Q_{i+1}, and the weights of the resampling to i+1.
+pa::PostArgs post_args(pa_run_state *r, uint32_t i) {
     const Plan &p = r->plan;
     pa::PostArgs s{};
+    const bool last = i + 1 >= p.desc.K;
     s.hist = hist_of(r, i);
-    s.zero_next = (!p.hist_all && i + 1 < p.desc.K) ? hist_of(r, i + 1) : nullptr;
+    s.zero_next = (!p.hist_all && !last) ? hist_of(r, i + 1) : nullptr;
     s.nbins = p.nbins;
     s.two_n = (int32_t)(2 * p.N);
     s.R_i = r->R_cur;
@@ -342,6 +366,22 @@ pa_status launch_post_for(pa_run_state *r, uint32_t i) {
     s.W = r->at<uint64_t>(p.off_W) + (size_t)tab * p.nbins;
     s.D = p.D.empty() ? 0u : p.D[tab];
     s.C = r->at<uint64_t>(p.off_C);
+    s.mhist = mhist_of(r, i);
+    s.mzero_next = (p.mag && !p.hist_all && !last) ? mhist_of(r, i + 1) : nullptr;
+    s.q = p.desc.q;
+    s.N = p.N;
+    s.Mt_sum = p.mag ? r->at<int64_t>(p.off_Mtsum) : nullptr;
+    s.M_mean = p.mag ? r->at<double>(p.off_Mmean) : nullptr;
+    s.widths = p.widths ? 1u : 0u;
+    s.bin_e = p.bin_e;
+    s.bin_m = p.bin_m;
+    s.width_e = p.widths ? r->at<double>(p.off_we) : nullptr;
+    s.width_m = (p.widths && p.mag) ? r->at<double>(p.off_wm) : nullptr;
+    return s;
+}
+
+pa_status launch_post_for(pa_run_state *r, uint32_t i) {
+    const pa::PostArgs s = post_args(r, i);
     return timed_launch(r, PA_KERNEL_POST, "post kernel", [&] { return pa::launch_post(s, r->stream); });
 }
 
@@ -354,6 +394,7 @@ pa::SweepArgs sweep_args(pa_run_state *r, uint32_t i, uint32_t mode, const uint8
     a.new_pop = new_pop;
     a.E_out = r->at<int32_t>(p.off_E);
     a.hist = hist_of(r, i);
+    a.mhist = mhist_of(r, i);
     for (int d = 0; d < 4; ++d) a.T[d] = p.T[(size_t)i * 4 + d];
     a.L = p.desc.L;
     a.q = p.desc.q;
@@ -619,7 +660,10 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
         delete r; return st;
     }
     const size_t hist_words = (size_t)p.nbins * (p.hist_all ? p.desc.K : 2);
+    const size_t mhist_words = p.mag ? (size_t)(p.N + 1) * (p.hist_all ? p.desc.K : 2) : 0;
     if ((st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_hist), hist_words, 0u, s), "fill")) ||
+        (mhist_words &&
+         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_mhist), mhist_words, 0u, s), "fill"))) ||
         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_r), p.R_cap, 0u, s), "fill")) ||
         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_lnQ), 2 * (size_t)p.desc.K, 0u, s), "fill"))) {
         delete r; return st;
@@ -710,6 +754,8 @@ pa_status pa_run_load(pa_run_state *r, uint32_t step, uint64_t R_cur, const uint
         return st;
     if ((st = hip_check(r, pa::launch_fill_u32(hist_of(r, step), p.nbins, 0u, s), "fill")))
         return st;
+    if (p.mag && (st = hip_check(r, pa::launch_fill_u32(mhist_of(r, step), p.N + 1, 0u, s), "fill")))
+        return st;
     pa::SweepArgs a = sweep_args(r, step, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[idle]), nullptr,
                                  r->at<uint8_t>(p.off_pop[r->cur]), 0);
     if ((st = hip_check(r, pa::launch_sweep(a, s), "load kernel"))) return st;
@@ -749,13 +795,17 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
             for (uint32_t i = 0; i < K; ++i) out->R_i[i] = p.R_sched[i];
             out->R_i[r->first_step] = r->R_first;
         }
-        struct { void *dst; size_t off, bytes; } cp[6] = {
+        struct { void *dst; size_t off, bytes; } cp[] = {
             {out->E_sum, p.off_Esum, 8 * (size_t)K},
             {out->E_mean, p.off_Emean, 8 * (size_t)K},
             {out->lnQ, p.off_lnQ, 8 * (size_t)K},
             {out->minus_beta_F, p.off_mbF, 8 * (size_t)K},
             {p.hist_all ? out->hist : nullptr, p.off_hist, 4 * (size_t)K * p.nbins},
-            {nullptr, 0, 0},
+            {p.mag ? out->Mt_sum : nullptr, p.off_Mtsum, 8 * (size_t)K},
+            {p.mag ? out->M_mean : nullptr, p.off_Mmean, 8 * (size_t)K},
+            {(p.mag && p.hist_all) ? out->mhist : nullptr, p.off_mhist, 4 * (size_t)K * (p.N + 1)},
+            {p.widths ? out->width_e : nullptr, p.off_we, 8 * (size_t)K},
+            {(p.widths && p.mag) ? out->width_m : nullptr, p.off_wm, 8 * (size_t)K},
         };
         for (auto &c : cp) {
             if (st || !c.dst) continue;
@@ -860,29 +910,7 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
         sw.push_back(e);
         r->cur = new_buf;
         r->step = g;
-        pa::PostArgs pp{};
-        pp.hist = hist_of(r, g);
-        pp.zero_next = (!p.hist_all && g + 1 < p.desc.K) ? hist_of(r, g + 1) : nullptr;
-        pp.nbins = p.nbins;
-        pp.two_n = (int32_t)(2 * p.N);
-        pp.R_i = R_new;
-        pp.step = g;
-        pp.has_next = (g + 1 < p.desc.K) ? 1u : 0u;
-        pp.dbeta_next = pp.has_next ? p.dbeta[g + 1] : 0.0;
-        const uint32_t tab = pp.has_next ? p.table_of_step[g + 1] : 0;
-        pp.w64_next = r->at<double>(p.off_w64) + (size_t)tab * p.nbins;
-        pp.E_sum = r->at<int64_t>(p.off_Esum);
-        pp.E_mean = r->at<double>(p.off_Emean);
-        pp.count = r->at<uint64_t>(p.off_count);
-        pp.lnQ = r->at<double>(p.off_lnQ);
-        pp.mbF = r->at<double>(p.off_mbF);
-        pp.E_ref = r->at<int32_t>(p.off_Eref);
-        pp.do_weights = (pp.has_next && p.desc.resample != PA_RESAMPLE_NONE) ? 1u : 0u;
-        pp.E = r->at<int32_t>(p.off_E);
-        pp.W = r->at<uint64_t>(p.off_W) + (size_t)tab * p.nbins;
-        pp.D = p.D.empty() ? 0u : p.D[tab];
-        pp.C = r->at<uint64_t>(p.off_C);
-        po.push_back(pp);
+        po.push_back(post_args(r, g));
     }
     auto take = [&](size_t bytes) { size_t at = cursor; cursor += align256(bytes); return at; };
     if (blob.size() < cursor + step_desc_bytes(n)) blob.resize(cursor + step_desc_bytes(n), 0);

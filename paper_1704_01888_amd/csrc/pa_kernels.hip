@@ -337,6 +337,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     extern __shared__ __align__(16) uint8_t smem[];
     // thresholds indexed by dE + 4
     if (threadIdx.x == 32) reinterpret_cast<uint32_t *>(smem)[24] = 0u;   // energy sum (multi-wave)
+    if (a.mhist && a.G_log2 > 6) {   // per-state counters of a multi-wave replica, after its rows
+        uint32_t *mcnt = reinterpret_cast<uint32_t *>(smem + 128 + a.N + 2 * a.L);
+        for (uint32_t t = threadIdx.x; t < a.q; t += blockDim.x) mcnt[t] = 0u;
+    }
     if (threadIdx.x < 9) {
         const int dE = (int)threadIdx.x - 4;
         const uint64_t T = dE <= 0 ? (1ull << 32) : a.T[dE - 1];
@@ -413,11 +417,29 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         __syncthreads();
         bonds = *sum;
     }
+    // ---- magnetisation (eq. (5)): M~ = the largest number of sites in one state
+    uint32_t mt = 0;
+    if (a.mhist) {
+        uint32_t *mcnt = reinterpret_cast<uint32_t *>(rep_lds + N + 2 * L);   // multi-wave only
+        for (uint32_t st = 0; st < a.q; ++st) {
+            const uint32_t pat = st * 0x01010101u;
+            uint32_t c = 0;
+            for (uint32_t dd = g; dd < N / 4u; dd += G) c += eq_bytes(rows32[dd], pat);
+            for (uint32_t off = (G < 64 ? G : 64) >> 1; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+            if (!multiwave) mt = max(mt, c);
+            else if ((threadIdx.x & 63u) == 0) atomicAdd(&mcnt[st], c);
+        }
+        if (multiwave) {
+            __syncthreads();
+            for (uint32_t st = 0; st < a.q; ++st) mt = max(mt, mcnt[st]);
+        }
+    }
     if (live) {
         if (g == 0) {
             const int32_t E = -(int32_t)bonds;
             a.E_out[k] = E;
             atomicAdd(&a.hist[(uint32_t)(E + 2 * (int32_t)N)], 1u);
+            if (a.mhist) atomicAdd(&a.mhist[mt], 1u);
         }
         uint4 *gdst = reinterpret_cast<uint4 *>(a.new_pop + (size_t)k * N);
         const uint4 *lsrc = reinterpret_cast<const uint4 *>(rep_lds + L);
@@ -490,6 +512,55 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *scratch, T *total) {
     return res;
 }
 
+// Block-wide reduction with `op`; every thread receives the result.
+// scratch holds blockDim/64 entries.
+template <typename T, typename Op>
+__device__ __forceinline__ T block_reduce(T v, Op op, T *scratch) {
+    for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
+    const uint32_t nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63u) == 0) scratch[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T r = scratch[0];
+    for (uint32_t w = 1; w < nw; ++w) r = op(r, scratch[w]);
+    return r;
+}
+
+// Count of bin j (levels j*B .. j*B+B-1) of h[0..nb); zero outside 0..nc-1.
+__device__ __forceinline__ uint64_t bin_count(const uint32_t *h, uint32_t nb, uint32_t B, int64_t j) {
+    const int64_t nc = ((int64_t)nb + B - 1) / B;
+    if (j < 0 || j >= nc) return 0;
+    const uint32_t b0 = (uint32_t)j * B, b1 = min(b0 + B, nb);
+    uint64_t c = 0;
+    for (uint32_t b = b0; b < b1; ++b) c += h[b];
+    return c;
+}
+
+// Full width at half maximum (Sec. 4) of h[0..nb) in bins of B levels,
+// measured in levels: the histogram is the piecewise-linear curve through the
+// bin counts at the bin indices, zero beyond both ends, and the width is B
+// times the distance between its outermost crossings of H/2, H the largest
+// bin count.  Whole workgroup; the value is valid in thread 0.
+__device__ double hist_fwhm_levels(const uint32_t *h, uint32_t nb, uint32_t B, uint64_t *scratch) {
+    const uint32_t nc = (nb + B - 1) / B;
+    uint64_t H = 0;
+    for (uint32_t j = threadIdx.x; j < nc; j += blockDim.x) H = max(H, bin_count(h, nb, B, j));
+    H = block_reduce(H, [](uint64_t x, uint64_t y) { return x > y ? x : y; }, scratch);
+    if (H == 0) return 0.0;
+    uint64_t jl = nc, jr = 0;
+    for (uint32_t j = threadIdx.x; j < nc; j += blockDim.x)
+        if (2 * bin_count(h, nb, B, j) >= H) { jl = min(jl, (uint64_t)j); jr = max(jr, (uint64_t)j); }
+    jl = block_reduce(jl, [](uint64_t x, uint64_t y) { return x < y ? x : y; }, scratch);
+    jr = block_reduce(jr, [](uint64_t x, uint64_t y) { return x > y ? x : y; }, scratch);
+    if (threadIdx.x != 0) return 0.0;
+    const double half = 0.5 * (double)H;
+    const double l0 = (double)bin_count(h, nb, B, (int64_t)jl - 1), l1 = (double)bin_count(h, nb, B, jl);
+    const double r0 = (double)bin_count(h, nb, B, jr), r1 = (double)bin_count(h, nb, B, (int64_t)jr + 1);
+    const double xl = (double)((int64_t)jl - 1) + (half - l0) / (l1 - l0);
+    const double xr = (double)jr + (r0 - half) / (r0 - r1);
+    return (xr - xl) * (double)B;
+}
+
 constexpr uint32_t TILE_V = 32;  // elements per thread per tile in the one-workgroup weight scan
 constexpr uint32_t FILL_V = 16;  // elements per thread per tile in the count scan + slot map
 
@@ -560,8 +631,30 @@ __device__ __forceinline__ void post_body(const PostArgs &a) {
             a.mbF[a.step + 1] = a.mbF[a.step] + lnq;
         }
     }
+    if (a.mhist) {
+        // eq. (4)-(5): sum of M~ over the population and M-bar
+        int64_t ms = 0;
+        for (uint32_t b = tid; b <= a.N; b += blockDim.x) ms += (int64_t)a.mhist[b] * (int64_t)b;
+        ms = block_reduce(ms, [](int64_t x, int64_t y) { return x + y; }, reinterpret_cast<int64_t *>(scratch));
+        if (tid == 0) {
+            a.Mt_sum[a.step] = ms;
+            a.M_mean[a.step] = ((double)a.q * (double)ms - (double)a.N * (double)a.R_i) /
+                               ((double)(a.q - 1) * (double)a.R_i);
+        }
+    }
+    if (a.widths) {
+        const double we = hist_fwhm_levels(a.hist, nb, a.bin_e, scratch);
+        if (tid == 0) a.width_e[a.step] = we / (double)a.N;
+        if (a.mhist) {
+            const double wm = hist_fwhm_levels(a.mhist, a.N + 1, a.bin_m, scratch);
+            if (tid == 0) a.width_m[a.step] = (wm * (double)a.q) / ((double)(a.q - 1) * (double)a.N);
+        }
+    }
+    __syncthreads();
     if (a.zero_next)
         for (uint32_t b = tid; b < nb; b += blockDim.x) a.zero_next[b] = 0u;
+    if (a.mzero_next)
+        for (uint32_t b = tid; b <= a.N; b += blockDim.x) a.mzero_next[b] = 0u;
 
     if (!a.do_weights) return;
     // C_j = sum_{j' <= j} W(|E_j' - E_ref|), tiles of blockDim * TILE_V elements
@@ -778,7 +871,8 @@ void sweep_shape(uint32_t L, uint32_t lanes, uint32_t *G_log2, uint32_t *waves_p
 size_t sweep_lds_bytes(uint32_t N, uint32_t G_log2, uint32_t waves_per_block) {
     uint32_t L = 0;
     while (L * L < N) ++L;
-    return 128u + (size_t)((64u * waves_per_block) >> G_log2) * (N + 2 * L);
+    // a multi-wave replica also keeps its 255 per-state counters (eq. (5)) in LDS
+    return 128u + (size_t)((64u * waves_per_block) >> G_log2) * (N + 2 * L) + (G_log2 > 6 ? 1024u : 0u);
 }
 
 size_t max_lds_per_block(int device) {

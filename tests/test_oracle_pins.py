@@ -435,3 +435,111 @@ def test_validation_rejects_bad_descriptions():
     ]
     for b in bad:
         assert oracle.validate(b) != 0
+
+
+# --------------------------------------------------------------------------
+# eq. (4)-(5): magnetisation
+# --------------------------------------------------------------------------
+def test_mtilde_closed_forms():
+    """M~ = N for a ground state (M = N); a two-colouring with two states has
+    M~ = N/2; eq. (5) gives M = 0 for an exactly equal split over q states."""
+    for L, q in ((4, 3), (8, 8), (6, 2)):
+        N = L * L
+        assert oracle.mtilde(L, q, np.full(N, q - 1, np.uint8)) == N
+        cb = np.array([(x + y) % 2 for y in range(L) for x in range(L)], np.uint8)
+        assert oracle.mtilde(L, q, cb) == N // 2
+    s = np.arange(16, dtype=np.uint8) % 4           # 4 states, 4 sites each
+    assert oracle.mtilde(4, 4, s) == 4
+
+
+def test_magnetisation_stationary_mean_L2():
+    """Metropolis alone at fixed beta on 2 x 2, q = 3: the population mean of
+    M (eq. (4)-(5)) equals the exact Boltzmann average over all 81
+    configurations, and the M~ histogram adds up to R."""
+    L, q, R, beta = 2, 3, 30000, 0.7
+    betas = np.array([0.0] + [beta] * 4)
+    d = oracle.Desc(L, q, R, betas, 5, seed=21, resample=oracle.RESAMPLE_NONE)
+    o = oracle.run(d, magnetisation=True)
+    confs = np.array([[a // 27, (a // 9) % 3, (a // 3) % 3, a % 3] for a in range(81)], np.uint8)
+    E = np.array([oracle.energy(2, c) for c in confs], np.float64)
+    mt = np.array([np.bincount(c, minlength=q).max() for c in confs], np.float64)
+    M = (q * mt - 4) / (q - 1)
+    p = np.exp(-beta * E)
+    p /= p.sum()
+    mean, var = (p * M).sum(), (p * M * M).sum() - (p * M).sum() ** 2
+    assert abs(o["M_mean"][-1] - mean) < 5 * np.sqrt(var / R)
+    assert o["mhist"][-1].sum() == R
+    assert o["Mt_sum"][-1] == int((np.arange(5) * o["mhist"][-1]).sum())
+
+
+# --------------------------------------------------------------------------
+# Sec. 4: full width at half maximum of the population histograms
+# --------------------------------------------------------------------------
+def _fwhm_fine_grid(h, B, pts_per_bin=2000):
+    """Independent reading of the width: sample the piecewise-linear curve
+    through the bin counts (zero beyond the ends) on a fine grid and measure
+    the span of the points at or above half the maximum."""
+    c = np.add.reduceat(np.asarray(h, np.float64), np.arange(0, len(h), B))
+    xs = np.arange(-1, len(c) + 1)
+    ys = np.concatenate([[0.0], c, [0.0]])
+    grid = np.linspace(-1, len(c), (len(c) + 1) * pts_per_bin + 1)
+    above = grid[np.interp(grid, xs, ys) >= 0.5 * c.max()]
+    return (above[-1] - above[0]) * B, B / pts_per_bin
+
+
+def test_fwhm_closed_forms():
+    """A single filled level has width one level; n equal levels have width n;
+    a tent of height H and slope s has width H/s; bins of B levels over an
+    n-level plateau (n divisible by B) give n."""
+    assert oracle.fwhm(np.array([0, 0, 7, 0])) == 1.0
+    assert oracle.fwhm(np.array([5])) == 1.0
+    assert oracle.fwhm(np.array([0, 3, 3, 3, 3, 3, 0])) == 5.0
+    tent = np.array([max(0, 12 - 3 * abs(j - 10)) for j in range(21)])
+    assert oracle.fwhm(tent) == 4.0
+    assert oracle.fwhm(np.array([2, 2, 2, 2, 2, 2, 0, 0]), 2) == 6.0
+    assert oracle.fwhm(np.zeros(9, np.uint32)) == 0.0
+
+
+def test_fwhm_gaussian():
+    """Bin counts of a Gaussian of standard deviation sigma (in levels): the
+    width is 2 sqrt(2 ln 2) sigma up to the linear-interpolation error."""
+    sigma, c = 25.0, 200.0
+    j = np.arange(401)
+    h = np.rint(1e6 * np.exp(-0.5 * ((j - c) / sigma) ** 2)).astype(np.uint32)
+    want = 2 * np.sqrt(2 * np.log(2)) * sigma
+    assert abs(oracle.fwhm(h) - want) < 0.01
+
+
+def test_fwhm_against_fine_grid_reading():
+    """Random histograms with one or several peaks, bins of 1..5 levels: the
+    width agrees with a fine-grid measurement of the same curve to the grid
+    spacing, and with explicit re-binning."""
+    rng = np.random.default_rng(11)
+    for t in range(60):
+        n = int(rng.integers(1, 80))
+        h = rng.integers(0, 50, size=n).astype(np.uint32)
+        if t % 3 == 0:
+            h[: n // 2] = 0
+        B = int(rng.integers(1, 6))
+        got = oracle.fwhm(h, B)
+        if h.sum() == 0:
+            assert got == 0.0
+            continue
+        want, tol = _fwhm_fine_grid(h, B)
+        assert abs(got - want) <= 2 * tol, (t, got, want)
+        rebinned = np.add.reduceat(h, np.arange(0, n, B)).astype(np.uint32)
+        assert oracle.fwhm(rebinned) * B == got
+
+
+def test_widths_and_magnetisation_of_ground_states():
+    """A population entirely in ground states (eq. (6), no sweeps): M~ = N and
+    M-bar = N (eq. (5)); both histograms are single levels, so the widths are
+    one level: 1/N in e and q/((q-1) N) in m."""
+    L, q = 8, 5
+    N = L * L
+    d = oracle.Desc(L, q, 300, np.array([3.0]), 0, seed=3, resample=oracle.RESAMPLE_NONE,
+                    init=oracle.INIT_GROUND)
+    o = oracle.run(d, magnetisation=True, widths=True)
+    assert o["Mt_sum"][0] == 300 * N and o["M_mean"][0] == N
+    assert o["width_e"][0] == 1.0 / N
+    assert o["width_m"][0] == (1.0 * q) / ((q - 1) * N)
