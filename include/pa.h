@@ -249,6 +249,28 @@ pa_status pa_serve_wait(pa_ctx *ctx, uint64_t ticket, int64_t timeout_us, pa_tim
 pa_status pa_serve_cancel(pa_ctx *ctx, uint64_t ticket);
 pa_status pa_serve_stop(pa_ctx *ctx);
 
+/* ---- Analysis of run outputs (host only, no device work) -------------------
+ *
+ * pa_width_maxima: the largest histogram width along a run (Sec. 4, Tables
+ * I-III): width[0..K) (pa_result.width_e or width_m) at inverse temperatures
+ * beta[0..K); returns the first index i_max attaining the maximum, w_max =
+ * width[i_max] and T_max = 1 / beta[i_max] (infinite at beta = 0).  NaN
+ * widths are invalid.
+ *
+ * pa_free_energy_crossing: inverse temperature where the -beta F estimates of
+ * a cooling run and of a heating run from ground states cross (Sec. 6, eq. (2)
+ * with eq. (7)-(8); the crossing locates the transition point).  beta[0..K)
+ * strictly increasing; mbf_cool and mbf_heat are -beta F on that grid (the
+ * heating run's pa_result.minus_beta_F reversed by the caller).  With d_i =
+ * mbf_cool[i] - mbf_heat[i], the candidates are the intervals with d_i > 0 >=
+ * d_{i+1} (the cooling estimate falls below the heating one); the one with the
+ * largest d_i - d_{i+1} is taken and *beta_x is the zero of the straight line
+ * through its end points.  PA_ERR_INVALID if there is no such interval. */
+pa_status pa_width_maxima(const double *beta, const double *width, uint32_t K, uint32_t *i_max,
+                          double *w_max, double *T_max);
+pa_status pa_free_energy_crossing(const double *beta, const double *mbf_cool, const double *mbf_heat,
+                                  uint32_t K, double *beta_x);
+
 const char *pa_status_str(pa_status s);
 const char *pa_last_error(void);
 

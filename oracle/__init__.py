@@ -90,6 +90,8 @@ def lib():
         L.orc_lnQ.restype = dbl
         L.orc_fwhm.argtypes = [vp, u32, u32]
         L.orc_fwhm.restype = dbl
+        L.orc_width_maxima.argtypes = [vp, vp, u32, vp, vp, vp]
+        L.orc_crossing.argtypes = [vp, vp, vp, u32, vp]
         L.orc_run.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_Result)]
         L.orc_step.argtypes = [ctypes.POINTER(_Desc), u32, u32, vp, vp, u64, u64, vp, vp, vp]
         _lib = L
@@ -230,6 +232,25 @@ def fwhm(h: np.ndarray, B: int = 1) -> float:
     """Full width at half maximum of histogram h in bins of B levels (in levels)."""
     hh = np.ascontiguousarray(h, dtype=np.uint32)
     return float(lib().orc_fwhm(_ptr(hh), len(hh), int(B)))
+
+
+def width_maxima(beta, width):
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    w = np.ascontiguousarray(width, dtype=np.float64)
+    i, wm, tm = np.zeros(1, np.uint32), np.zeros(1), np.zeros(1)
+    if lib().orc_width_maxima(_ptr(b), _ptr(w), len(b), _ptr(i), _ptr(wm), _ptr(tm)):
+        raise ValueError("empty width curve")
+    return int(i[0]), float(wm[0]), float(tm[0])
+
+
+def crossing(beta, f_cool, f_heat):
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    c = np.ascontiguousarray(f_cool, dtype=np.float64)
+    h = np.ascontiguousarray(f_heat, dtype=np.float64)
+    x = np.zeros(1)
+    if lib().orc_crossing(_ptr(b), _ptr(c), _ptr(h), len(b), _ptr(x)):
+        raise ValueError("no crossing")
+    return float(x[0])
 
 
 def run(d: Desc, hist=False, final=False, magnetisation=False, widths=False):

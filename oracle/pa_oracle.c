@@ -470,6 +470,38 @@ double orc_fwhm(const uint32_t *h, uint32_t nb, uint32_t B)
     return width;
 }
 
+int orc_width_maxima(const double *beta, const double *width, uint32_t K, uint32_t *i_max,
+                     double *w_max, double *T_max)
+{
+    if (K == 0) return ORC_ERR_INVALID;
+    uint32_t best = 0;
+    for (uint32_t i = 1; i < K; ++i)
+        if (width[i] > width[best]) best = i;
+    *i_max = best;
+    *w_max = width[best];
+    *T_max = 1.0 / beta[best];
+    return ORC_OK;
+}
+
+int orc_crossing(const double *beta, const double *f_cool, const double *f_heat, uint32_t K,
+                 double *beta_x)
+{
+    int found = 0;
+    double best_change = 0.0;
+    for (uint32_t i = 0; i + 1 < K; ++i) {
+        double d_here = f_cool[i] - f_heat[i];
+        double d_next = f_cool[i + 1] - f_heat[i + 1];
+        if (!(d_here > 0.0 && d_next <= 0.0)) continue;
+        double change = d_here - d_next;
+        if (found && change <= best_change) continue;
+        found = 1;
+        best_change = change;
+        /* zero of the straight line through (beta_i, d_here), (beta_i+1, d_next) */
+        *beta_x = beta[i] + (beta[i + 1] - beta[i]) * (d_here / (d_here - d_next));
+    }
+    return found ? ORC_OK : ORC_ERR_INVALID;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Whole run.                                                                */
 /* ------------------------------------------------------------------------ */

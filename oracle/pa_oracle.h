@@ -81,6 +81,18 @@ uint32_t orc_mtilde(uint32_t L, uint32_t q, const uint8_t *s);
  * half the largest count.  Returns 0 for an empty histogram. */
 double orc_fwhm(const uint32_t *h, uint32_t nb, uint32_t B);
 
+/* Largest width along a run (Sec. 4, Tables I-III): first index of the
+ * maximum of width[0..K), its value and T = 1/beta there. */
+int orc_width_maxima(const double *beta, const double *width, uint32_t K, uint32_t *i_max,
+                     double *w_max, double *T_max);
+
+/* Crossing of the cooling and heating -beta F estimates (Sec. 6, Fig. 3) on an
+ * increasing beta grid: over the intervals where the cooling estimate goes
+ * from above the heating one to at or below it, the one with the largest
+ * change of the difference; the crossing is linear between its end points. */
+int orc_crossing(const double *beta, const double *f_cool, const double *f_heat, uint32_t K,
+                 double *beta_x);
+
 /* Initial configuration of slot k (random: uniform spins; ground: all equal). */
 void orc_init_replica(const orc_desc *d, uint64_t k, uint8_t *s);
 

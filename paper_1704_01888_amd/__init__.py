@@ -31,6 +31,7 @@ EXPORTS = [
     "pa_run_read_slots", "pa_run_finish", "pa_status_str", "pa_last_error",
     "pa_plan_batch", "pa_run_batch",
     "pa_serve_start", "pa_serve_submit", "pa_serve_wait", "pa_serve_cancel", "pa_serve_stop",
+    "pa_width_maxima", "pa_free_energy_crossing",
 ]
 PA_ERR_BUSY, PA_ERR_CANCELLED, PA_ERR_TIMEOUT = -6, -7, -8
 
@@ -121,6 +122,8 @@ def lib() -> ctypes.CDLL:
     L.pa_serve_wait.argtypes = [vp, u64, ctypes.c_int64, P(Timing)]
     L.pa_serve_cancel.argtypes = [vp, u64]
     L.pa_serve_stop.argtypes = [vp]
+    L.pa_width_maxima.argtypes = [vp, vp, u32, vp, vp, vp]
+    L.pa_free_energy_crossing.argtypes = [vp, vp, vp, u32, vp]
     L.pa_status_str.argtypes = [i32]
     L.pa_status_str.restype = ctypes.c_char_p
     L.pa_last_error.argtypes = []
@@ -188,6 +191,32 @@ def pa_weight_table(abs_dbeta: float, Kb: int, N: int):
     D = ctypes.c_uint32(0)
     _check(lib().pa_weight_table(float(abs_dbeta), int(Kb), int(N), _ptr(W), ctypes.byref(D)))
     return W, int(D.value)
+
+
+def width_maxima(beta, width):
+    """(i_max, w_max, T_max) of a width curve (pa_width_maxima)."""
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    w = np.ascontiguousarray(width, dtype=np.float64)
+    if len(b) != len(w):
+        raise ValueError("beta and width differ in length")
+    i = np.zeros(1, np.uint32)
+    wm = np.zeros(1)
+    tm = np.zeros(1)
+    _check(lib().pa_width_maxima(_ptr(b), _ptr(w), len(b), _ptr(i), _ptr(wm), _ptr(tm)))
+    return int(i[0]), float(wm[0]), float(tm[0])
+
+
+def free_energy_crossing(beta, mbf_cool, mbf_heat) -> float:
+    """Crossing of cooling and heating -beta F on an increasing beta grid
+    (pa_free_energy_crossing)."""
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    c = np.ascontiguousarray(mbf_cool, dtype=np.float64)
+    h = np.ascontiguousarray(mbf_heat, dtype=np.float64)
+    if not (len(b) == len(c) == len(h)):
+        raise ValueError("arrays differ in length")
+    x = np.zeros(1)
+    _check(lib().pa_free_energy_crossing(_ptr(b), _ptr(c), _ptr(h), len(b), _ptr(x)))
+    return float(x[0])
 
 
 class Context:

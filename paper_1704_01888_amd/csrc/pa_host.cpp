@@ -501,6 +501,37 @@ pa_status pa_weight_table(double abs_dbeta, uint32_t Kb, uint32_t N, uint64_t *W
     return PA_OK;
 }
 
+pa_status pa_width_maxima(const double *beta, const double *width, uint32_t K, uint32_t *i_max,
+                          double *w_max, double *T_max) {
+    if (!beta || !width || K == 0) return fail(PA_ERR_INVALID, "empty width curve");
+    uint32_t best = 0;
+    for (uint32_t i = 0; i < K; ++i) {
+        if (std::isnan(width[i])) return fail(PA_ERR_INVALID, "NaN width");
+        if (width[i] > width[best]) best = i;
+    }
+    if (i_max) *i_max = best;
+    if (w_max) *w_max = width[best];
+    if (T_max) *T_max = 1.0 / beta[best];
+    return PA_OK;
+}
+
+pa_status pa_free_energy_crossing(const double *beta, const double *mbf_cool, const double *mbf_heat,
+                                  uint32_t K, double *beta_x) {
+    if (!beta || !mbf_cool || !mbf_heat || !beta_x || K < 2) return fail(PA_ERR_INVALID, "need two or more points");
+    for (uint32_t i = 0; i + 1 < K; ++i)
+        if (!(beta[i + 1] > beta[i])) return fail(PA_ERR_INVALID, "beta must increase strictly");
+    double jump = -1.0;
+    for (uint32_t i = 0; i + 1 < K; ++i) {
+        const double d0 = mbf_cool[i] - mbf_heat[i], d1 = mbf_cool[i + 1] - mbf_heat[i + 1];
+        if (d0 > 0.0 && d1 <= 0.0 && d0 - d1 > jump) {
+            jump = d0 - d1;
+            *beta_x = beta[i] + (beta[i + 1] - beta[i]) * (d0 / (d0 - d1));
+        }
+    }
+    if (jump < 0.0) return fail(PA_ERR_INVALID, "the cooling and heating estimates do not cross");
+    return PA_OK;
+}
+
 pa_status pa_ctx_create(int device, pa_ctx **out) {
     if (!out) return fail(PA_ERR_INVALID, "null output");
     int n = 0;

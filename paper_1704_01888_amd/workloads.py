@@ -23,6 +23,40 @@ def beta_t(q: int) -> float:
     return math.log(1.0 + math.sqrt(q))
 
 
+# Table I protocol: the step is 1/N_beta on [f_lo, f_hi], 0.01 on [c_lo, f_lo)
+# and (f_hi, c_hi], and 0.05 below c_lo and above c_hi; (c_lo, f_lo, f_hi, c_hi).
+TABLE_REGIONS = {
+    6: (0.995, 1.135, 1.305, 1.545),
+    8: (1.11, 1.25, 1.42, 1.66),
+    10: (1.165, 1.305, 1.475, 1.715),
+    20: (1.595, 1.735, 1.905, 2.145),
+}
+
+
+def _segment(start: float, end: float, n: int):
+    """n equal steps from start to end, the last point exactly end."""
+    return [start + (end - start) * j / n for j in range(1, n)] + [end]
+
+
+def table_betas(q: int, n_beta: int = 1000, coarse_tail: int = 5) -> np.ndarray:
+    """Piecewise cooling protocol of Tables I-III for q in {6, 8, 10, 20}:
+    steps of 0.05 from 0 up to c_lo (anchored at c_lo; the first step is the
+    remainder), 0.01 up to f_lo, 1/n_beta up to f_hi, 0.01 up to c_hi, then
+    coarse_tail steps of 0.05 beyond c_hi (the paper does not state where the
+    runs end)."""
+    c_lo, f_lo, f_hi, c_hi = TABLE_REGIONS[q]
+    low = [c_lo - 0.05 * j for j in range(int(c_lo / 0.05) + 1)][::-1]
+    pts = [0.0] + [b for b in low if b > 0.0]
+    pts += _segment(c_lo, f_lo, int(round((f_lo - c_lo) / 0.01)))
+    n_fine = (f_hi - f_lo) * n_beta
+    if abs(n_fine - round(n_fine)) > 1e-9:
+        raise ValueError("n_beta must divide the fine region into whole steps")
+    pts += _segment(f_lo, f_hi, int(round(n_fine)))
+    pts += _segment(f_hi, c_hi, int(round((c_hi - f_hi) / 0.01)))
+    pts += [c_hi + 0.05 * j for j in range(1, coarse_tail + 1)]
+    return np.array(pts, dtype=np.float64)
+
+
 def small_runs(n_runs: int = 20, seed0: int = 1):
     """n_runs runs of 8x8, q=8, R=1000, 200 equal steps to beta = 1.6, theta = 10,
     multinomial resampling, seeds seed0, seed0+1, ... (dicts of desc fields)."""

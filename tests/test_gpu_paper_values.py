@@ -1,0 +1,76 @@
+"""The HIP path against numbers the paper prints (statistical; every run is
+seeded, so each test is deterministic).
+
+* Sec. 6 / Fig. 3: cooling (beta_0 = 0) and heating (ground states at
+  beta = 3, eq. (6)-(8)) estimates of -beta F for L = 32, R = 10^4,
+  dbeta = 0.01, theta = 10 cross at the asymptotic transition point
+  beta_t = ln(1 + sqrt q) within the grid resolution dbeta.
+* Sec. 5 / Fig. 2 left: cooling and heating energies coincide for the
+  second-order cases q = 2, 3 and split for the first-order q = 6, 10.
+* Table I: temperatures of the largest energy and magnetisation histogram
+  widths, R = 1000, theta = 100, N_beta = 1000 with the caption's piecewise
+  protocol, averaged over 200 runs (the width curves are averaged over the
+  runs, then maximised), to the two decimals printed.  The widths themselves
+  depend on the histogram binning, which the paper does not state; they are
+  not compared.
+"""
+import numpy as np
+import pytest
+
+import paper_1704_01888_amd as pa
+from paper_1704_01888_amd.workloads import beta_t, linear_betas, table_betas
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = pa.Context(0)
+    yield c
+    c.close()
+
+
+def _cool_heat(ctx, q):
+    beta = linear_betas(3.0, 300)
+    kw = dict(L=32, q=q, R=10000, theta=10, resample=pa.RESAMPLE_POISSON)
+    c = pa.pa_run(ctx, pa.Desc(beta=beta, seed=10 + q, **kw))
+    h = pa.pa_run(ctx, pa.Desc(beta=beta[::-1].copy(), seed=20 + q, init=pa.INIT_GROUND, **kw))
+    return beta, c, {k: v[::-1] for k, v in h.items() if k in ("minus_beta_F", "E_mean")}
+
+
+@pytest.mark.parametrize("q", [6, 10])
+def test_free_energy_crossing_at_beta_t(ctx, q):
+    beta, c, h = _cool_heat(ctx, q)
+    x = pa.free_energy_crossing(beta, c["minus_beta_F"], h["minus_beta_F"])
+    print(f"\nq={q}: crossing {x:.4f}, beta_t {beta_t(q):.4f}", flush=True)
+    assert abs(x - beta_t(q)) < 0.01
+
+
+@pytest.mark.parametrize("q,second_order", [(2, True), (3, True), (6, False), (10, False)])
+def test_hysteresis_of_the_energy(ctx, q, second_order):
+    beta, c, h = _cool_heat(ctx, q)
+    de = np.abs(c["E_mean"] - h["E_mean"]) / 1024.0
+    print(f"\nq={q}: mean |de| {de.mean():.4f}, max |de| {de.max():.4f}", flush=True)
+    if second_order:
+        assert de.mean() < 0.005
+    else:
+        assert de.max() > 0.2
+
+
+# Table I: (q, L) -> (T_max(e), T_max(m))
+TABLE_I = {(6, 16): (0.82, 0.82), (8, 16): (0.75, 0.75), (10, 16): (0.71, 0.71), (6, 32): (0.81, 0.81)}
+
+
+@pytest.mark.parametrize("q,L", sorted(TABLE_I))
+def test_table_I_temperatures_of_the_widest_histograms(ctx, q, L):
+    b = table_betas(q, 1000)
+    descs = [pa.Desc(L=L, q=q, R=1000, beta=b, theta=100, seed=1000 + r, resample=pa.RESAMPLE_POISSON,
+                     outputs=pa.OUT_MAG | pa.OUT_WIDTHS) for r in range(200)]
+    outs = pa.pa_run_batch(ctx, descs)
+    _, _, T_e = pa.width_maxima(b, np.mean([o["width_e"] for o in outs], axis=0))
+    _, _, T_m = pa.width_maxima(b, np.mean([o["width_m"] for o in outs], axis=0))
+    want_e, want_m = TABLE_I[(q, L)]
+    print(f"\nq={q} L={L}: T_max(e) {T_e:.3f} (paper {want_e}), T_max(m) {T_m:.3f} (paper {want_m})",
+          flush=True)
+    assert abs(T_e - want_e) <= 0.005 + 1e-9
+    assert abs(T_m - want_m) <= 0.005 + 1e-9

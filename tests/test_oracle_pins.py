@@ -543,3 +543,38 @@ def test_widths_and_magnetisation_of_ground_states():
     assert o["Mt_sum"][0] == 300 * N and o["M_mean"][0] == N
     assert o["width_e"][0] == 1.0 / N
     assert o["width_m"][0] == (1.0 * q) / ((q - 1) * N)
+
+
+# --------------------------------------------------------------------------
+# Sec. 6 (Fig. 3) free-energy crossing; Tables I-III width maxima
+# --------------------------------------------------------------------------
+def test_crossing_of_two_straight_lines():
+    """Lines -beta F = a - b beta and c - d beta cross at (a - c) / (b - d);
+    linear interpolation between grid points is exact for lines."""
+    beta = np.linspace(0.5, 2.0, 151)
+    for a, b, c, d in ((10.0, 3.0, 8.0, 1.5), (0.0, -1.0, -2.2, -2.9)):
+        x = (a - c) / (b - d)
+        fc, fh = a - b * beta, c - d * beta
+        assert abs(oracle.crossing(beta, fc, fh) - x) < 1e-12
+
+
+def test_crossing_takes_the_sharpest_sign_change():
+    """Noise-level sign changes of the difference elsewhere do not move the
+    crossing; a grid without a down-crossing is an error."""
+    beta = np.linspace(0.0, 3.0, 301)
+    x = 1.426
+    fc = 100.0 - 50.0 * (beta - x) * (beta > x)
+    fh = 100.0 + 80.0 * (x - beta) * (beta < x) * -1.0
+    # equal slopes far from x; tiny alternating noise near beta = 0.2 and 2.8
+    fh = fh + 1e-9 * np.where(np.abs(beta - 0.2) < 0.05, np.sin(200 * beta), 0.0)
+    fc = fc + 1e-9 * np.where(np.abs(beta - 2.8) < 0.05, np.cos(200 * beta), 0.0)
+    got = oracle.crossing(beta, fc, fh)
+    assert abs(got - x) < 0.01
+    with pytest.raises(ValueError):
+        oracle.crossing(beta, fh - 1.0, fh)
+
+
+def test_width_maxima_first_argmax():
+    beta = np.array([0.5, 1.0, 1.25, 2.0])
+    i, w, T = oracle.width_maxima(beta, np.array([0.1, 0.4, 0.4, 0.2]))
+    assert (i, w, T) == (1, 0.4, 1.0)
