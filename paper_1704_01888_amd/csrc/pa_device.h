@@ -17,8 +17,7 @@ struct SweepArgs {
     const uint32_t *anc;      // [R_new] ancestors, or nullptr for the identity
     uint8_t *new_pop;         // [R_new][N]
     int32_t *E_out;           // [R_new]
-    uint32_t *hist;           // [2N+1], accumulated with atomics
-    uint32_t *mhist;          // [N+1] histogram of M~ (eq. (5)), or nullptr
+    uint32_t *Mt_out;         // [R_new] M~ of eq. (5), or nullptr
     uint64_t T[4];            // thresholds for dE = 1..4 (<= 2^32)
     uint32_t L, q, N;
     uint32_t R_new;
@@ -31,9 +30,10 @@ struct SweepArgs {
 };
 
 struct PostArgs {
-    // population statistics of step i
-    const uint32_t *hist;     // [2N+1] population at step i
-    uint32_t *zero_next;      // histogram buffer to clear for step i+1, or nullptr
+    // population statistics of step i, from the energies E
+    uint32_t *hist;           // [2N+1] energy histogram of step i (output; also the
+                              // work area when the energies span more than the LDS window)
+    uint32_t store_hist;      // write the full histograms of step i to hist / mhist
     uint32_t nbins;           // 2N+1
     int32_t two_n;
     uint64_t R_i;
@@ -54,8 +54,8 @@ struct PostArgs {
     uint32_t D;
     uint64_t *C;              // [R_i] inclusive prefix sums
     // magnetisation (eq. (4)-(5)) and histogram widths of step i
-    const uint32_t *mhist;    // [N+1] histogram of M~ at step i, or nullptr
-    uint32_t *mzero_next;     // M~ histogram buffer to clear for step i+1, or nullptr
+    const uint32_t *Mt;       // [R_i] M~ of the population at step i, or nullptr
+    uint32_t *mhist;          // [N+1] M~ histogram of step i (output / work area)
     uint32_t q, N;
     int64_t *Mt_sum;          // [K]
     double *M_mean;           // [K]

@@ -107,8 +107,8 @@ struct Plan {
     uint32_t bin_e = 1, bin_m = 1;
     // workspace layout
     size_t off_pop[2], off_E, off_C, off_r, off_anc, off_counts, off_hist, off_Esum, off_Emean,
-        off_count, off_lnQ, off_mbF, off_Eref, off_W, off_w64, off_mhist, off_Mtsum, off_Mmean,
-        off_we, off_wm, total;
+        off_count, off_lnQ, off_mbF, off_Eref, off_W, off_w64, off_mhist, off_Mt, off_Mtsum,
+        off_Mmean, off_we, off_wm, total;
 };
 
 pa_status validate(const pa_run_desc *d) {
@@ -224,7 +224,7 @@ pa_status build_plan(const pa_run_desc *d, Plan &p, bool tables) {
     p.off_r = o; o += align256(4 * p.R_cap);
     p.off_anc = o; o += align256(4 * p.R_cap);
     p.off_counts = o; o += align256(4 * p.R_cap);
-    p.off_hist = o; o += align256((size_t)4 * p.nbins * (p.hist_all ? K : 2));
+    p.off_hist = o; o += align256((size_t)4 * p.nbins * (p.hist_all ? K : 1));
     p.off_Esum = o; o += align256(8 * (size_t)K);
     p.off_Emean = o; o += align256(8 * (size_t)K);
     p.off_count = o; o += align256(8 * (size_t)K);
@@ -233,7 +233,8 @@ pa_status build_plan(const pa_run_desc *d, Plan &p, bool tables) {
     p.off_Eref = o; o += align256(4 * (size_t)K);
     p.off_W = o; o += align256((size_t)8 * p.nbins * p.n_tables);
     p.off_w64 = o; o += align256((size_t)8 * p.nbins * p.n_tables);
-    p.off_mhist = o; o += p.mag ? align256((size_t)4 * (p.N + 1) * (p.hist_all ? K : 2)) : 0;
+    p.off_mhist = o; o += p.mag ? align256((size_t)4 * (p.N + 1) * (p.hist_all ? K : 1)) : 0;
+    p.off_Mt = o; o += p.mag ? align256(4 * p.R_cap) : 0;
     p.off_Mtsum = o; o += p.mag ? align256(8 * (size_t)K) : 0;
     p.off_Mmean = o; o += p.mag ? align256(8 * (size_t)K) : 0;
     p.off_we = o; o += p.widths ? align256(8 * (size_t)K) : 0;
@@ -326,16 +327,17 @@ void release_events(pa_run_state *r, double *ms, uint64_t *count) {
     r->timed.clear();
 }
 
+// Histogram buffers: one per step when they are outputs, else one reused.
 uint32_t *hist_of(pa_run_state *r, uint32_t i) {
     const Plan &p = r->plan;
-    const size_t slot = p.hist_all ? i : (i & 1u);
+    const size_t slot = p.hist_all ? i : 0u;
     return r->at<uint32_t>(p.off_hist) + slot * p.nbins;
 }
 
 uint32_t *mhist_of(pa_run_state *r, uint32_t i) {
     const Plan &p = r->plan;
     if (!p.mag) return nullptr;
-    const size_t slot = p.hist_all ? i : (i & 1u);
+    const size_t slot = p.hist_all ? i : 0u;
     return r->at<uint32_t>(p.off_mhist) + slot * (p.N + 1);
 }
 
@@ -344,9 +346,8 @@ uint32_t *mhist_of(pa_run_state *r, uint32_t i) {
 pa::PostArgs post_args(pa_run_state *r, uint32_t i) {
     const Plan &p = r->plan;
     pa::PostArgs s{};
-    const bool last = i + 1 >= p.desc.K;
     s.hist = hist_of(r, i);
-    s.zero_next = (!p.hist_all && !last) ? hist_of(r, i + 1) : nullptr;
+    s.store_hist = p.hist_all ? 1u : 0u;
     s.nbins = p.nbins;
     s.two_n = (int32_t)(2 * p.N);
     s.R_i = r->R_cur;
@@ -366,8 +367,8 @@ pa::PostArgs post_args(pa_run_state *r, uint32_t i) {
     s.W = r->at<uint64_t>(p.off_W) + (size_t)tab * p.nbins;
     s.D = p.D.empty() ? 0u : p.D[tab];
     s.C = r->at<uint64_t>(p.off_C);
+    s.Mt = p.mag ? r->at<uint32_t>(p.off_Mt) : nullptr;
     s.mhist = mhist_of(r, i);
-    s.mzero_next = (p.mag && !p.hist_all && !last) ? mhist_of(r, i + 1) : nullptr;
     s.q = p.desc.q;
     s.N = p.N;
     s.Mt_sum = p.mag ? r->at<int64_t>(p.off_Mtsum) : nullptr;
@@ -393,8 +394,7 @@ pa::SweepArgs sweep_args(pa_run_state *r, uint32_t i, uint32_t mode, const uint8
     a.anc = anc;
     a.new_pop = new_pop;
     a.E_out = r->at<int32_t>(p.off_E);
-    a.hist = hist_of(r, i);
-    a.mhist = mhist_of(r, i);
+    a.Mt_out = p.mag ? r->at<uint32_t>(p.off_Mt) : nullptr;
     for (int d = 0; d < 4; ++d) a.T[d] = p.T[(size_t)i * 4 + d];
     a.L = p.desc.L;
     a.q = p.desc.q;
@@ -690,8 +690,8 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
                                           hipMemcpyHostToDevice, s), "upload w64"))) {
         delete r; return st;
     }
-    const size_t hist_words = (size_t)p.nbins * (p.hist_all ? p.desc.K : 2);
-    const size_t mhist_words = p.mag ? (size_t)(p.N + 1) * (p.hist_all ? p.desc.K : 2) : 0;
+    const size_t hist_words = (size_t)p.nbins * (p.hist_all ? p.desc.K : 1);
+    const size_t mhist_words = p.mag ? (size_t)(p.N + 1) * (p.hist_all ? p.desc.K : 1) : 0;
     if ((st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_hist), hist_words, 0u, s), "fill")) ||
         (mhist_words &&
          (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_mhist), mhist_words, 0u, s), "fill"))) ||
@@ -773,8 +773,8 @@ pa_status pa_run_load(pa_run_state *r, uint32_t step, uint64_t R_cur, const uint
     r->R_prev = R_cur;
     r->first_step = step;
     r->R_first = R_cur;
-    // Upload into the idle buffer, then recompute E and the histogram with a
-    // sweep of zero rounds into the other buffer.
+    // Upload into the idle buffer, then recompute E with a sweep of zero
+    // rounds into the other buffer and the statistics with the post kernel.
     const int idle = 1 - r->cur;
     if ((st = hip_check(r, hipMemcpyAsync(r->ws + p.off_pop[idle], spins, (size_t)R_cur * p.N,
                                           hipMemcpyHostToDevice, s), "upload spins")))
@@ -782,10 +782,6 @@ pa_status pa_run_load(pa_run_state *r, uint32_t step, uint64_t R_cur, const uint
     r->mbF0 = minus_beta_F;
     if ((st = hip_check(r, hipMemcpyAsync(r->at<double>(p.off_mbF) + step, &r->mbF0, 8,
                                           hipMemcpyHostToDevice, s), "upload")))
-        return st;
-    if ((st = hip_check(r, pa::launch_fill_u32(hist_of(r, step), p.nbins, 0u, s), "fill")))
-        return st;
-    if (p.mag && (st = hip_check(r, pa::launch_fill_u32(mhist_of(r, step), p.N + 1, 0u, s), "fill")))
         return st;
     pa::SweepArgs a = sweep_args(r, step, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[idle]), nullptr,
                                  r->at<uint8_t>(p.off_pop[r->cur]), 0);

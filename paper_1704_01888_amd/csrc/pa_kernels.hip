@@ -331,13 +331,13 @@ __device__ __forceinline__ void sweeps_any(uint32_t *lds32, uint32_t g, uint32_t
 }
 
 // One workgroup `block` of the sweep launch of one run (a): gather or create
-// its replicas in LDS, theta sweeps, energies, histogram, store.
+// its replicas in LDS, theta sweeps, energies (and M~), store.
 template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     extern __shared__ __align__(16) uint8_t smem[];
     // thresholds indexed by dE + 4
     if (threadIdx.x == 32) reinterpret_cast<uint32_t *>(smem)[24] = 0u;   // energy sum (multi-wave)
-    if (a.mhist && a.G_log2 > 6) {   // per-state counters of a multi-wave replica, after its rows
+    if (a.Mt_out && a.G_log2 > 6) {  // per-state counters of a multi-wave replica, after its rows
         uint32_t *mcnt = reinterpret_cast<uint32_t *>(smem + 128 + a.N + 2 * a.L);
         for (uint32_t t = threadIdx.x; t < a.q; t += blockDim.x) mcnt[t] = 0u;
     }
@@ -399,7 +399,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     if constexpr (LT != 0) sweeps_fixed<LT, GT, QSMALL>(lds32, g, k, a, thr, theta);
     else sweeps_any<QSMALL, T64>(lds32, g, G, k, a, thr, theta);
 
-    // ---- energy (eq. (3)), histogram, store ------------------------------
+    // ---- energy (eq. (3)), store ------------------------------------------
     uint32_t bonds = 0;
     for (uint32_t dd = g; dd < N / 4u; dd += G) {
         const uint32_t xd = dd % DPR;
@@ -419,7 +419,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     }
     // ---- magnetisation (eq. (5)): M~ = the largest number of sites in one state
     uint32_t mt = 0;
-    if (a.mhist) {
+    if (a.Mt_out) {
         uint32_t *mcnt = reinterpret_cast<uint32_t *>(rep_lds + N + 2 * L);   // multi-wave only
         for (uint32_t st = 0; st < a.q; ++st) {
             const uint32_t pat = st * 0x01010101u;
@@ -438,8 +438,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         if (g == 0) {
             const int32_t E = -(int32_t)bonds;
             a.E_out[k] = E;
-            atomicAdd(&a.hist[(uint32_t)(E + 2 * (int32_t)N)], 1u);
-            if (a.mhist) atomicAdd(&a.mhist[mt], 1u);
+            if (a.Mt_out) a.Mt_out[k] = mt;
         }
         uint4 *gdst = reinterpret_cast<uint4 *>(a.new_pop + (size_t)k * N);
         const uint4 *lsrc = reinterpret_cast<const uint4 *>(rep_lds + L);
@@ -526,43 +525,164 @@ __device__ __forceinline__ T block_reduce(T v, Op op, T *scratch) {
     return r;
 }
 
-// Count of bin j (levels j*B .. j*B+B-1) of h[0..nb); zero outside 0..nc-1.
-__device__ __forceinline__ uint64_t bin_count(const uint32_t *h, uint32_t nb, uint32_t B, int64_t j) {
-    const int64_t nc = ((int64_t)nb + B - 1) / B;
+// A histogram over levels 0..nb-1 of which only the window lo .. lo+n-1 is
+// stored (h[b - lo]); every other level holds zero.
+struct HistView {
+    const uint32_t *h;
+    uint32_t lo, n, nb;
+    __device__ __forceinline__ uint32_t at(int64_t b) const {
+        return (b >= (int64_t)lo && b < (int64_t)lo + n) ? h[b - lo] : 0u;
+    }
+};
+
+// Count of bin j (levels j*B .. j*B+B-1); zero outside 0..nc-1.
+__device__ __forceinline__ uint64_t bin_count(const HistView &v, uint32_t B, int64_t j) {
+    const int64_t nc = ((int64_t)v.nb + B - 1) / B;
     if (j < 0 || j >= nc) return 0;
-    const uint32_t b0 = (uint32_t)j * B, b1 = min(b0 + B, nb);
+    const int64_t b0 = j * B, b1 = min(b0 + (int64_t)B, (int64_t)v.nb);
     uint64_t c = 0;
-    for (uint32_t b = b0; b < b1; ++b) c += h[b];
+    for (int64_t b = max(b0, (int64_t)v.lo); b < min(b1, (int64_t)v.lo + v.n); ++b) c += v.h[b - v.lo];
     return c;
 }
 
-// Full width at half maximum (Sec. 4) of h[0..nb) in bins of B levels,
+// Full width at half maximum (Sec. 4) of the histogram in bins of B levels,
 // measured in levels: the histogram is the piecewise-linear curve through the
 // bin counts at the bin indices, zero beyond both ends, and the width is B
 // times the distance between its outermost crossings of H/2, H the largest
 // bin count.  Whole workgroup; the value is valid in thread 0.
-__device__ double hist_fwhm_levels(const uint32_t *h, uint32_t nb, uint32_t B, uint64_t *scratch) {
-    const uint32_t nc = (nb + B - 1) / B;
+__device__ double hist_fwhm_levels(const HistView &v, uint32_t B, uint64_t *scratch) {
+    const uint32_t j_lo = v.lo / B, j_hi = (v.lo + v.n - 1) / B;   // bins that meet the window
     uint64_t H = 0;
-    for (uint32_t j = threadIdx.x; j < nc; j += blockDim.x) H = max(H, bin_count(h, nb, B, j));
+    for (uint32_t j = j_lo + threadIdx.x; j <= j_hi; j += blockDim.x) H = max(H, bin_count(v, B, j));
     H = block_reduce(H, [](uint64_t x, uint64_t y) { return x > y ? x : y; }, scratch);
     if (H == 0) return 0.0;
-    uint64_t jl = nc, jr = 0;
-    for (uint32_t j = threadIdx.x; j < nc; j += blockDim.x)
-        if (2 * bin_count(h, nb, B, j) >= H) { jl = min(jl, (uint64_t)j); jr = max(jr, (uint64_t)j); }
+    uint64_t jl = ~0ull, jr = 0;
+    for (uint32_t j = j_lo + threadIdx.x; j <= j_hi; j += blockDim.x)
+        if (2 * bin_count(v, B, j) >= H) { jl = min(jl, (uint64_t)j); jr = max(jr, (uint64_t)j); }
     jl = block_reduce(jl, [](uint64_t x, uint64_t y) { return x < y ? x : y; }, scratch);
     jr = block_reduce(jr, [](uint64_t x, uint64_t y) { return x > y ? x : y; }, scratch);
     if (threadIdx.x != 0) return 0.0;
     const double half = 0.5 * (double)H;
-    const double l0 = (double)bin_count(h, nb, B, (int64_t)jl - 1), l1 = (double)bin_count(h, nb, B, jl);
-    const double r0 = (double)bin_count(h, nb, B, jr), r1 = (double)bin_count(h, nb, B, (int64_t)jr + 1);
+    const double l0 = (double)bin_count(v, B, (int64_t)jl - 1), l1 = (double)bin_count(v, B, jl);
+    const double r0 = (double)bin_count(v, B, jr), r1 = (double)bin_count(v, B, (int64_t)jr + 1);
     const double xl = (double)((int64_t)jl - 1) + (half - l0) / (l1 - l0);
     const double xr = (double)jr + (r0 - half) / (r0 - r1);
     return (xr - xl) * (double)B;
 }
 
+// Calls f(x[j]) for j = 0 .. n-1 (4-byte elements, 16-byte aligned array) in
+// tiles of blockDim * 16 elements: each thread issues its four 128-bit loads
+// of a tile together.
+template <typename T, typename F>
+__device__ __forceinline__ void for_each_tiled(const T *x, uint64_t n, F f) {
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    constexpr uint32_t V = 16;
+    for (uint64_t base = 0; base < n; base += (uint64_t)blockDim.x * V) {
+        const uint64_t j0 = base + (uint64_t)threadIdx.x * V;
+        T v[V];
+        if (j0 + V <= n) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(x + j0);
+#pragma unroll
+            for (uint32_t q = 0; q < V / 4; ++q) {
+                const uint4 w = src[q];
+                v[4 * q] = (T)w.x; v[4 * q + 1] = (T)w.y; v[4 * q + 2] = (T)w.z; v[4 * q + 3] = (T)w.w;
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < V; ++q) f(v[q]);
+        } else {
+            for (uint32_t q = 0; q < V && j0 + q < n; ++q) f(x[j0 + q]);
+        }
+    }
+}
+
+// Sum, minimum and maximum over the workgroup; every thread receives them.
+struct SumMinMax { int64_t sum; int32_t mn, mx; };
+
+__device__ SumMinMax block_sum_min_max(int64_t sum, int32_t mn, int32_t mx) {
+    __shared__ int64_t s_sum[16];
+    __shared__ int32_t s_mn[16], s_mx[16];
+    for (int off = 32; off > 0; off >>= 1) {
+        sum += __shfl_xor(sum, off, 64);
+        mn = min(mn, __shfl_xor(mn, off, 64));
+        mx = max(mx, __shfl_xor(mx, off, 64));
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63u) == 0) { s_sum[threadIdx.x >> 6] = sum; s_mn[threadIdx.x >> 6] = mn; s_mx[threadIdx.x >> 6] = mx; }
+    __syncthreads();
+    SumMinMax r{s_sum[0], s_mn[0], s_mx[0]};
+    for (uint32_t w = 1; w < (blockDim.x >> 6); ++w) {
+        r.sum += s_sum[w]; r.mn = min(r.mn, s_mn[w]); r.mx = max(r.mx, s_mx[w]);
+    }
+    return r;
+}
+
+// Histogram of the n values x[j] + shift (each in 0 .. nb-1) by the whole
+// workgroup, with their sum and range.  If all nb levels fit the LDS array
+// lds[cap], the values are counted there directly; otherwise a first pass
+// finds their range and, if that fits, the window min .. max is counted in
+// LDS; failing both, out[0..nb) in global memory is zeroed and counted with
+// atomics.  sum (of x, not shifted), mn and mx are valid in every thread.
+struct HistBuild { HistView v; int64_t sum; int32_t mn, mx; };
+
+template <typename T>
+__device__ HistBuild build_hist(const T *x, uint64_t n, int32_t shift, uint32_t nb, uint32_t *lds,
+                                uint32_t cap, uint32_t *out) {
+    HistBuild r;
+    if (nb <= cap) {
+        for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) lds[b] = 0u;
+        __syncthreads();
+        for_each_tiled(x, n, [&](T e) { atomicAdd(&lds[(uint32_t)((int32_t)e + shift)], 1u); });
+        __syncthreads();
+        int64_t sum = 0;
+        int32_t mn = 0x7fffffff, mx = (int32_t)0x80000000;
+        for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+            const uint32_t h = lds[b];
+            if (h) {
+                const int32_t e = (int32_t)b - shift;
+                sum += (int64_t)h * e; mn = min(mn, e); mx = max(mx, e);
+            }
+        }
+        const SumMinMax t = block_sum_min_max(sum, mn, mx);
+        r.sum = t.sum; r.mn = t.mn; r.mx = t.mx;
+        r.v = HistView{lds, 0u, nb, nb};
+        return r;
+    }
+    int64_t sum = 0;
+    int32_t mn = 0x7fffffff, mx = (int32_t)0x80000000;
+    for_each_tiled(x, n, [&](T v) { const int32_t e = (int32_t)v; sum += e; mn = min(mn, e); mx = max(mx, e); });
+    const SumMinMax t = block_sum_min_max(sum, mn, mx);
+    r.sum = t.sum; r.mn = t.mn; r.mx = t.mx;
+    const uint32_t lo = (uint32_t)(r.mn + shift), width = (uint32_t)(r.mx - r.mn) + 1u;
+    if (width <= cap) {
+        for (uint32_t b = threadIdx.x; b < width; b += blockDim.x) lds[b] = 0u;
+        __syncthreads();
+        for_each_tiled(x, n, [&](T e) { atomicAdd(&lds[(uint32_t)((int32_t)e + shift) - lo], 1u); });
+        __syncthreads();
+        r.v = HistView{lds, lo, width, nb};
+    } else {
+        for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) out[b] = 0u;
+        __threadfence();
+        __syncthreads();
+        for_each_tiled(x, n, [&](T e) { atomicAdd(&out[(uint32_t)((int32_t)e + shift)], 1u); });
+        __threadfence();
+        __syncthreads();
+        r.v = HistView{out, 0u, nb, nb};
+    }
+    return r;
+}
+
+// Writes the full histogram (zeros outside the window) to out[0..nb), unless
+// it was built there.
+__device__ void store_hist(const HistView &v, uint32_t *out) {
+    if (v.h == out) return;
+    for (uint32_t b = threadIdx.x; b < v.nb; b += blockDim.x) out[b] = v.at(b);
+}
+
+constexpr uint32_t POST_LDS_BINS = 14336;   // 56 KB window for the histograms in LDS
+
 constexpr uint32_t TILE_V = 32;  // elements per thread per tile in the one-workgroup weight scan
-constexpr uint32_t FILL_V = 16;  // elements per thread per tile in the count scan + slot map
+constexpr uint32_t FILL_V = 16;
+constexpr uint32_t SHORT_RUN = 8;   // copies written by their own lane in the slot map  // elements per thread per tile in the count scan + slot map
 
 // ---------------------------------------------------------------------------
 // k_post(i): population sums of eq. (4) and ln Q_{i+1} of Sec. 2 step 2 /
@@ -571,90 +691,66 @@ constexpr uint32_t FILL_V = 16;  // elements per thread per tile in the count sc
 // One workgroup; histogram bins and energies are read with coalesced loads.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void post_body(const PostArgs &a) {
-    __shared__ int64_t s_esum[16];
-    __shared__ uint64_t s_cnt[16];
-    __shared__ int32_t s_min[16], s_max[16];
-    __shared__ double s_w[16];
-    __shared__ int32_t s_ref;
+    __shared__ uint32_t lds_hist[POST_LDS_BINS];
     __shared__ uint64_t scratch[17];
+    __shared__ double s_w[16];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nw = blockDim.x >> 6;
     const uint32_t nb = a.nbins;
 
-    int64_t esum = 0;
+    // eq. (4) sums and the energy histogram h[E + 2N] of step i
+    const HistBuild he = build_hist(a.E, a.R_i, a.two_n, nb, lds_hist, POST_LDS_BINS, a.hist);
+    const int32_t ref = a.dbeta_next >= 0.0 ? he.mn : he.mx;   // E_ref of step i+1
+    if (tid == 0) {
+        a.E_sum[a.step] = he.sum;
+        a.E_mean[a.step] = (double)he.sum / (double)a.R_i;
+        if (a.has_next) a.E_ref[a.step + 1] = ref;
+    }
+    // ln Q_{i+1} (Sec. 2 step 2, eq. (2)) from the histogram, and its count
     uint64_t cnt = 0;
-    int32_t bmin = 0x7fffffff, bmax = -1;
-    for (uint32_t b = tid; b < nb; b += blockDim.x) {
-        const uint32_t h = a.hist[b];
-        if (h) {
-            esum += (int64_t)h * ((int32_t)b - a.two_n);
-            cnt += h;
-            bmin = min(bmin, (int32_t)b);
-            bmax = max(bmax, (int32_t)b);
-        }
+    double acc = 0.0;
+    for (uint32_t b = tid; b < he.v.n; b += blockDim.x) {
+        const uint32_t h = he.v.h[b];
+        cnt += h;
+        if (a.has_next && h) acc += (double)h * a.w64_next[abs((int32_t)(b + he.v.lo) - a.two_n - ref)];
     }
-    esum = wave_sum(esum);
+    acc = wave_sum(acc);
     cnt = wave_sum(cnt);
-    for (int off = 32; off > 0; off >>= 1) {
-        bmin = min(bmin, __shfl_xor(bmin, off, 64));
-        bmax = max(bmax, __shfl_xor(bmax, off, 64));
-    }
-    if (lane == 0) { s_esum[wave] = esum; s_cnt[wave] = cnt; s_min[wave] = bmin; s_max[wave] = bmax; }
+    if (lane == 0) { s_w[wave] = acc; scratch[wave] = cnt; }
     __syncthreads();
     if (tid == 0) {
-        int64_t E = 0; uint64_t C = 0; int32_t mn = 0x7fffffff, mx = -1;
-        for (uint32_t w = 0; w < nw; ++w) {
-            E += s_esum[w]; C += s_cnt[w]; mn = min(mn, s_min[w]); mx = max(mx, s_max[w]);
-        }
-        a.E_sum[a.step] = E;
+        double S = 0.0;
+        uint64_t C = 0;
+        for (uint32_t w = 0; w < nw; ++w) { S += s_w[w]; C += scratch[w]; }
         a.count[a.step] = C;
-        a.E_mean[a.step] = (double)E / (double)a.R_i;
-        s_ref = (a.dbeta_next >= 0.0 ? mn : mx) - a.two_n;
-        if (a.has_next) a.E_ref[a.step + 1] = s_ref;
-    }
-    __syncthreads();
-    const int32_t ref = s_ref;
-
-    if (a.has_next) {
-        double acc = 0.0;
-        for (uint32_t b = tid; b < nb; b += blockDim.x) {
-            const uint32_t h = a.hist[b];
-            if (h) acc += (double)h * a.w64_next[abs((int32_t)b - a.two_n - ref)];
-        }
-        acc = wave_sum(acc);
-        if (lane == 0) s_w[wave] = acc;
-        __syncthreads();
-        if (tid == 0) {
-            double S = 0.0;
-            for (uint32_t w = 0; w < nw; ++w) S += s_w[w];
+        if (a.has_next) {
             const double lnq = -a.dbeta_next * (double)ref + log(S) - log((double)a.R_i);
             a.lnQ[a.step + 1] = lnq;
             a.mbF[a.step + 1] = a.mbF[a.step] + lnq;
         }
     }
-    if (a.mhist) {
-        // eq. (4)-(5): sum of M~ over the population and M-bar
-        int64_t ms = 0;
-        for (uint32_t b = tid; b <= a.N; b += blockDim.x) ms += (int64_t)a.mhist[b] * (int64_t)b;
-        ms = block_reduce(ms, [](int64_t x, int64_t y) { return x + y; }, reinterpret_cast<int64_t *>(scratch));
-        if (tid == 0) {
-            a.Mt_sum[a.step] = ms;
-            a.M_mean[a.step] = ((double)a.q * (double)ms - (double)a.N * (double)a.R_i) /
-                               ((double)(a.q - 1) * (double)a.R_i);
-        }
-    }
+    __syncthreads();
+    if (a.store_hist) store_hist(he.v, a.hist);
     if (a.widths) {
-        const double we = hist_fwhm_levels(a.hist, nb, a.bin_e, scratch);
+        const double we = hist_fwhm_levels(he.v, a.bin_e, scratch);
         if (tid == 0) a.width_e[a.step] = we / (double)a.N;
-        if (a.mhist) {
-            const double wm = hist_fwhm_levels(a.mhist, a.N + 1, a.bin_m, scratch);
-            if (tid == 0) a.width_m[a.step] = (wm * (double)a.q) / ((double)(a.q - 1) * (double)a.N);
-        }
     }
     __syncthreads();
-    if (a.zero_next)
-        for (uint32_t b = tid; b < nb; b += blockDim.x) a.zero_next[b] = 0u;
-    if (a.mzero_next)
-        for (uint32_t b = tid; b <= a.N; b += blockDim.x) a.mzero_next[b] = 0u;
+
+    if (a.Mt) {
+        // eq. (4)-(5): sum of M~ over the population, M-bar, the M~ histogram
+        const HistBuild hm = build_hist(a.Mt, a.R_i, 0, a.N + 1, lds_hist, POST_LDS_BINS, a.mhist);
+        if (tid == 0) {
+            a.Mt_sum[a.step] = hm.sum;
+            a.M_mean[a.step] = ((double)a.q * (double)hm.sum - (double)a.N * (double)a.R_i) /
+                               ((double)(a.q - 1) * (double)a.R_i);
+        }
+        if (a.store_hist) store_hist(hm.v, a.mhist);
+        if (a.widths) {
+            const double wm = hist_fwhm_levels(hm.v, a.bin_m, scratch);
+            if (tid == 0) a.width_m[a.step] = (wm * (double)a.q) / ((double)(a.q - 1) * (double)a.N);
+        }
+        __syncthreads();
+    }
 
     if (!a.do_weights) return;
     // C_j = sum_{j' <= j} W(|E_j' - E_ref|), tiles of blockDim * TILE_V elements
@@ -739,11 +835,31 @@ __device__ void countfill_block(const SlotmapArgs &a, uint64_t *scratch) {
         for (uint32_t v = 0; v < FILL_V; ++v) local += r[v];
         uint64_t total;
         uint64_t o = carry + block_exclusive_scan<uint64_t>(local, scratch, &total);
+        // Short runs of copies are written by their own lane, long ones
+        // (strongly skewed weights) by the whole wave.
+        uint64_t ov[FILL_V];
 #pragma unroll
         for (uint32_t v = 0; v < FILL_V; ++v) {
-            for (uint32_t c = 0; c < r[v]; ++c)
-                if (o + c < a.anc_cap) a.anc[o + c] = (uint32_t)(j0 + v);
+            ov[v] = o;
             o += r[v];
+            if (r[v] <= SHORT_RUN)
+                for (uint32_t c = 0; c < r[v]; ++c)
+                    if (ov[v] + c < a.anc_cap) a.anc[ov[v] + c] = (uint32_t)(j0 + v);
+        }
+        const uint32_t lane = tid & 63u;
+#pragma unroll
+        for (uint32_t v = 0; v < FILL_V; ++v) {
+            uint64_t todo = __ballot(r[v] > SHORT_RUN);
+            while (todo) {
+                const uint32_t src = (uint32_t)__ffsll((unsigned long long)todo) - 1u;
+                const uint64_t start = ((uint64_t)__shfl((uint32_t)(ov[v] >> 32), src, 64) << 32) |
+                                       (uint64_t)__shfl((uint32_t)ov[v], src, 64);
+                const uint32_t cnt = __shfl(r[v], src, 64);
+                const uint32_t who = __shfl((uint32_t)(j0 + v), src, 64);
+                for (uint32_t c = lane; c < cnt; c += 64u)
+                    if (start + c < a.anc_cap) a.anc[start + c] = who;
+                todo &= todo - 1;
+            }
         }
         if (full) {
             uint4 *cnt = reinterpret_cast<uint4 *>(a.counts_last + j0);
@@ -766,18 +882,40 @@ __device__ void countfill_block(const SlotmapArgs &a, uint64_t *scratch) {
 // k_sample: draw kk picks the first j with C_j > floor(x_kk * S / 2^64) and
 // counts it in r_j.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void sample_one(const SampleArgs &a, uint64_t kk) {
-    if (kk >= a.n_new) return;
-    const uint64_t S = a.C[a.R_prev - 1];
-    const uint4 w = philox((uint32_t)kk, 0u, a.step, DOM_RESAMPLE << 28, a.key0, a.key1);
-    const uint64_t x = ((uint64_t)w.y << 32) | (uint64_t)w.x;
-    const uint64_t u = __umul64hi(x, S);
-    uint64_t lo = 0, hi = a.R_prev - 1;
-    while (lo < hi) {
-        const uint64_t mid = lo + ((hi - lo) >> 1);
-        if (a.C[mid] > u) hi = mid; else lo = mid + 1;
+// Adds one to h[key] for every active lane; lanes of the wave that share the
+// key of one of the first few leaders are combined into one atomic (strongly
+// skewed weights send many draws of a wave to the same ancestor).
+__device__ __forceinline__ void wave_aggregated_inc(uint32_t *h, uint32_t key, bool active) {
+    uint64_t todo = __ballot(active);
+    // at most four combining rounds (the dominant keys); the rest add one each
+    for (int round = 0; round < 4 && todo; ++round) {
+        const uint32_t src = (uint32_t)__ffsll((unsigned long long)todo) - 1u;
+        const uint32_t k = __shfl(key, src, 64);
+        const bool mine = active && key == k;
+        const uint64_t same = __ballot(mine);
+        if ((threadIdx.x & 63u) == src) atomicAdd(&h[k], (uint32_t)__popcll(same));
+        todo &= ~same;
+        active = active && !mine;
     }
-    atomicAdd(&a.r[lo], 1u);
+    if (active) atomicAdd(&h[key], 1u);
+}
+
+__device__ __forceinline__ void sample_one(const SampleArgs &a, uint64_t kk) {
+    const bool live = kk < a.n_new;
+    uint32_t anc = 0;
+    if (live) {
+        const uint64_t S = a.C[a.R_prev - 1];
+        const uint4 w = philox((uint32_t)kk, 0u, a.step, DOM_RESAMPLE << 28, a.key0, a.key1);
+        const uint64_t x = ((uint64_t)w.y << 32) | (uint64_t)w.x;
+        const uint64_t u = __umul64hi(x, S);
+        uint64_t lo = 0, hi = a.R_prev - 1;
+        while (lo < hi) {
+            const uint64_t mid = lo + ((hi - lo) >> 1);
+            if (a.C[mid] > u) hi = mid; else lo = mid + 1;
+        }
+        anc = (uint32_t)lo;
+    }
+    wave_aggregated_inc(a.r, anc, live);
 }
 
 __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
