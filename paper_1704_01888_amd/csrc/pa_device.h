@@ -40,7 +40,7 @@ struct PostArgs {
     uint32_t step;            // i
     uint32_t has_next;        // i + 1 < K
     double dbeta_next;        // beta_{i+1} - beta_i
-    const double *w64_next;   // [2N+1] exp(-|dbeta_next| d)
+    double abs_dbeta_next;    // |beta_{i+1} - beta_i|
     int64_t *E_sum;           // [K]
     double *E_mean;           // [K]
     uint64_t *count;          // [K]   sum of the histogram (consistency check)
@@ -50,8 +50,9 @@ struct PostArgs {
     // weights of the resampling to step i+1
     uint32_t do_weights;
     const int32_t *E;         // [R_i] energies of the population at step i
-    const uint64_t *W;        // [D] fixed-point weights of step i+1
+    const uint64_t *W;        // [D] fixed-point weights of step i+1 (zero from D on)
     uint32_t D;
+    uint64_t w_const;         // nonzero: every weight equals it (dbeta = 0), W unused
     uint64_t *C;              // [R_i] inclusive prefix sums
     // magnetisation (eq. (4)-(5)) and histogram widths of step i
     const uint32_t *Mt;       // [R_i] M~ of the population at step i, or nullptr
@@ -81,6 +82,30 @@ struct SlotmapArgs {
     uint64_t anc_cap;         // capacity of anc (writes beyond it are dropped)
     uint32_t *counts_last;    // [R_prev] copy of the counts
 };
+
+// Lattices beyond one workgroup's LDS (L > 256): replicas stay in HBM; one
+// launch per half-sweep over (replica, tile of `rows` rows).
+struct TiledArgs {
+    const uint8_t *src;       // [*][N] population read by a half-sweep or copy
+    const uint32_t *anc;      // slot -> replica of src (ancestor), or nullptr for the identity
+    uint8_t *dst;             // [R][N] population written
+    uint64_t T[4];            // thresholds for dE = 1..4 (<= 2^32)
+    uint32_t L, q, N, R;
+    uint32_t rows, tiles;     // rows per tile, tiles per replica
+    uint32_t step, t, c;      // Philox step, sweep number, colour; c = 2: copy only
+    uint32_t key0, key1;
+    uint32_t init;            // k_tiled_init: SWEEP_INIT_RANDOM or SWEEP_INIT_GROUND
+    uint32_t *bonds;          // [R] equal-neighbour bond counts (measure; zero on entry)
+    uint32_t *cnt;            // [R][q] per-state site counts, or nullptr (zero on entry)
+    int32_t *E_out;           // [R]
+    uint32_t *Mt_out;         // [R] or nullptr
+};
+bool tiled_path(uint32_t L);
+uint32_t tiled_rows(uint32_t L);
+hipError_t launch_tiled_half(const TiledArgs &a, hipStream_t s);
+hipError_t launch_tiled_init(const TiledArgs &a, hipStream_t s);
+// energies (eq. (3)) and M~ (eq. (5)) of dst; leaves bonds and cnt zeroed
+hipError_t launch_tiled_measure(const TiledArgs &a, hipStream_t s);
 
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t s);
 hipError_t launch_post(const PostArgs &a, hipStream_t s);

@@ -75,15 +75,24 @@ uint64_t poisson_inversion(double lambda, double u) {
     }
 }
 
-uint32_t weight_table(double abs_dbeta, uint32_t Kb, uint32_t N, uint64_t *W) {
+// W[d] = round(2^Kb exp(-|dbeta| d)) for d < D, where D is the first d with
+// W[d] == 0 (or 2N+1); the weights decrease with d, so every W beyond D is 0.
+// Writes W[0..D) and returns D.
+uint32_t weight_prefix(double abs_dbeta, uint32_t Kb, uint32_t N, std::vector<uint64_t> &W) {
     const uint32_t nb = 2 * N + 1;
-    uint32_t D = nb;
     for (uint32_t d = 0; d < nb; ++d) {
         const double x = abs_dbeta * (double)d;
-        W[d] = (uint64_t)std::nearbyint(std::ldexp(std::exp(-x), (int)Kb));
-        if (W[d] == 0 && D == nb) D = d;
+        const uint64_t w = (uint64_t)std::nearbyint(std::ldexp(std::exp(-x), (int)Kb));
+        if (w == 0) return d;
+        W.push_back(w);
     }
-    for (uint32_t d = D; d < nb; ++d) W[d] = 0;
+    return nb;
+}
+
+uint32_t weight_table(double abs_dbeta, uint32_t Kb, uint32_t N, uint64_t *W) {
+    std::vector<uint64_t> pre;
+    const uint32_t D = weight_prefix(abs_dbeta, Kb, N, pre);
+    for (uint32_t d = 0; d < 2 * N + 1; ++d) W[d] = d < D ? pre[d] : 0u;
     return D;
 }
 
@@ -99,16 +108,18 @@ struct Plan {
     std::vector<uint64_t> T;              // [K][4]
     std::vector<double> dbeta;            // [K], dbeta[0] = 0
     std::vector<uint32_t> table_of_step;  // [K]
-    std::vector<uint64_t> W;              // [n_tables][nbins]
-    std::vector<uint32_t> D;              // [n_tables]
-    std::vector<double> w64;              // [n_tables][nbins]
+    std::vector<uint64_t> W;              // the tables' nonzero prefixes, concatenated
+    std::vector<uint64_t> W_off;          // [n_tables] start of table t in W
+    std::vector<uint32_t> D;              // [n_tables] length of table t
+    std::vector<double> abs_dbeta;        // [n_tables]
     uint32_t n_tables = 0;
     bool hist_all = false, mag = false, widths = false;
     uint32_t bin_e = 1, bin_m = 1;
     // workspace layout
     size_t off_pop[2], off_E, off_C, off_r, off_anc, off_counts, off_hist, off_Esum, off_Emean,
-        off_count, off_lnQ, off_mbF, off_Eref, off_W, off_w64, off_mhist, off_Mt, off_Mtsum,
-        off_Mmean, off_we, off_wm, total;
+        off_count, off_lnQ, off_mbF, off_Eref, off_W, off_mhist, off_Mt, off_Mtsum,
+        off_Mmean, off_we, off_wm, off_bonds, off_cnt, total;
+    bool tiled = false;   // replicas beyond one workgroup's LDS: tiled half-sweeps in HBM
 };
 
 pa_status validate(const pa_run_desc *d) {
@@ -129,12 +140,12 @@ pa_status validate(const pa_run_desc *d) {
         return fail(PA_ERR_INVALID, "unknown output bits");
     if (d->bin_e > 2 * d->L * d->L + 1 || d->bin_m > d->L * d->L + 1)
         return fail(PA_ERR_INVALID, "histogram bin wider than the histogram");
-    if ((d->L & 3u) || d->L < 4 || d->L > 256)
-        return fail(PA_ERR_UNSUPPORTED, "this device path needs L % 4 == 0 and 4 <= L <= 256");
+    if ((d->L & 3u) || d->L < 4 || d->L > 4096)
+        return fail(PA_ERR_UNSUPPORTED, "this device path needs L % 4 == 0 and 4 <= L <= 4096");
     return PA_OK;
 }
 
-pa_status build_plan(const pa_run_desc *d, Plan &p, bool tables) {
+pa_status build_plan(const pa_run_desc *d, Plan &p) {
     pa_status st = validate(d);
     if (st) return st;
     p.desc = *d;
@@ -198,15 +209,16 @@ pa_status build_plan(const pa_run_desc *d, Plan &p, bool tables) {
     }
     if (abs_list.empty()) abs_list.push_back(0.0);
     p.n_tables = (uint32_t)abs_list.size();
-    if (tables) {
-        p.W.assign((size_t)p.n_tables * p.nbins, 0);
-        p.D.assign(p.n_tables, 0);
-        p.w64.assign((size_t)p.n_tables * p.nbins, 0.0);
-        for (uint32_t t = 0; t < p.n_tables; ++t) {
-            p.D[t] = weight_table(abs_list[t], p.Kb, p.N, p.W.data() + (size_t)t * p.nbins);
-            for (uint32_t dd = 0; dd < p.nbins; ++dd)
-                p.w64[(size_t)t * p.nbins + dd] = std::exp(-(abs_list[t] * (double)dd));
-        }
+    p.abs_dbeta = abs_list;
+    // Weight tables: only the nonzero prefix of each (Sec. 2 step 2 weights of
+    // one |dbeta|); its length bounds the workspace, so it is computed always.
+    p.W.clear();
+    p.W_off.assign(p.n_tables, 0);
+    p.D.assign(p.n_tables, 0);
+    for (uint32_t t = 0; t < p.n_tables; ++t) {
+        p.W_off[t] = p.W.size();
+        // dbeta = 0: every weight is 2^Kb, no table
+        p.D[t] = abs_list[t] == 0.0 ? 0u : weight_prefix(abs_list[t], p.Kb, p.N, p.W);
     }
 
     // Workspace layout.
@@ -231,14 +243,16 @@ pa_status build_plan(const pa_run_desc *d, Plan &p, bool tables) {
     p.off_lnQ = o; o += align256(8 * (size_t)K);
     p.off_mbF = o; o += align256(8 * (size_t)K);
     p.off_Eref = o; o += align256(4 * (size_t)K);
-    p.off_W = o; o += align256((size_t)8 * p.nbins * p.n_tables);
-    p.off_w64 = o; o += align256((size_t)8 * p.nbins * p.n_tables);
+    p.off_W = o; o += align256((size_t)8 * p.W.size());
     p.off_mhist = o; o += p.mag ? align256((size_t)4 * (p.N + 1) * (p.hist_all ? K : 1)) : 0;
     p.off_Mt = o; o += p.mag ? align256(4 * p.R_cap) : 0;
     p.off_Mtsum = o; o += p.mag ? align256(8 * (size_t)K) : 0;
     p.off_Mmean = o; o += p.mag ? align256(8 * (size_t)K) : 0;
     p.off_we = o; o += p.widths ? align256(8 * (size_t)K) : 0;
     p.off_wm = o; o += (p.widths && p.mag) ? align256(8 * (size_t)K) : 0;
+    p.tiled = pa::tiled_path(d->L);
+    p.off_bonds = o; o += p.tiled ? align256(4 * p.R_cap) : 0;
+    p.off_cnt = o; o += (p.tiled && p.mag) ? align256((size_t)4 * p.R_cap * d->q) : 0;
     p.total = o;
     return PA_OK;
 }
@@ -355,7 +369,7 @@ pa::PostArgs post_args(pa_run_state *r, uint32_t i) {
     s.has_next = (i + 1 < p.desc.K) ? 1u : 0u;
     s.dbeta_next = s.has_next ? p.dbeta[i + 1] : 0.0;
     const uint32_t tab = s.has_next ? p.table_of_step[i + 1] : 0;
-    s.w64_next = r->at<double>(p.off_w64) + (size_t)tab * p.nbins;
+    s.abs_dbeta_next = s.has_next ? p.abs_dbeta[tab] : 0.0;
     s.E_sum = r->at<int64_t>(p.off_Esum);
     s.E_mean = r->at<double>(p.off_Emean);
     s.count = r->at<uint64_t>(p.off_count);
@@ -364,8 +378,9 @@ pa::PostArgs post_args(pa_run_state *r, uint32_t i) {
     s.E_ref = r->at<int32_t>(p.off_Eref);
     s.do_weights = (s.has_next && p.desc.resample != PA_RESAMPLE_NONE) ? 1u : 0u;
     s.E = r->at<int32_t>(p.off_E);
-    s.W = r->at<uint64_t>(p.off_W) + (size_t)tab * p.nbins;
-    s.D = p.D.empty() ? 0u : p.D[tab];
+    s.W = r->at<uint64_t>(p.off_W) + p.W_off[tab];
+    s.D = p.D[tab];
+    s.w_const = p.abs_dbeta[tab] == 0.0 ? (1ull << p.Kb) : 0ull;
     s.C = r->at<uint64_t>(p.off_C);
     s.Mt = p.mag ? r->at<uint32_t>(p.off_Mt) : nullptr;
     s.mhist = mhist_of(r, i);
@@ -410,6 +425,52 @@ pa::SweepArgs sweep_args(pa_run_state *r, uint32_t i, uint32_t mode, const uint8
     return a;
 }
 
+// Tiled (large-lattice) launches of step i on R_cur replicas.
+pa::TiledArgs tiled_args(pa_run_state *r, uint32_t i, const uint8_t *src, const uint32_t *anc,
+                         uint8_t *dst) {
+    const Plan &p = r->plan;
+    pa::TiledArgs a{};
+    a.src = src;
+    a.anc = anc;
+    a.dst = dst;
+    for (int d = 0; d < 4; ++d) a.T[d] = p.T[(size_t)i * 4 + d];
+    a.L = p.desc.L;
+    a.q = p.desc.q;
+    a.N = p.N;
+    a.R = (uint32_t)r->R_cur;
+    a.rows = pa::tiled_rows(p.desc.L);
+    a.tiles = (p.desc.L + a.rows - 1) / a.rows;
+    a.step = i;
+    a.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
+    a.key1 = (uint32_t)(p.desc.seed >> 32);
+    a.init = p.desc.init == PA_INIT_GROUND ? pa::SWEEP_INIT_GROUND : pa::SWEEP_INIT_RANDOM;
+    a.bonds = r->at<uint32_t>(p.off_bonds);
+    a.cnt = p.mag ? r->at<uint32_t>(p.off_cnt) : nullptr;
+    a.E_out = r->at<int32_t>(p.off_E);
+    a.Mt_out = p.mag ? r->at<uint32_t>(p.off_Mt) : nullptr;
+    return a;
+}
+
+// theta tiled sweeps from src (through anc) into dst, then the energies: the
+// first half-sweep reads the ancestors, the later ones update dst in place;
+// theta = 0 copies.
+hipError_t launch_tiled_sweeps(pa::TiledArgs a, uint32_t theta, hipStream_t s) {
+    hipError_t e;
+    if (theta == 0) {
+        a.c = 2;
+        if ((e = pa::launch_tiled_half(a, s)) != hipSuccess) return e;
+    }
+    for (uint32_t t = 0; t < theta; ++t)
+        for (uint32_t c = 0; c < 2; ++c) {
+            a.t = t;
+            a.c = c;
+            if ((e = pa::launch_tiled_half(a, s)) != hipSuccess) return e;
+            a.src = a.dst;
+            a.anc = nullptr;
+        }
+    return pa::launch_tiled_measure(a, s);
+}
+
 pa_status do_step(pa_run_state *r) {
     const Plan &p = r->plan;
     const uint32_t i = r->step + 1;
@@ -444,9 +505,16 @@ pa_status do_step(pa_run_state *r) {
     r->R_cur = R_new;
     const uint8_t *old_pop = r->at<uint8_t>(p.off_pop[r->cur]);
     uint8_t *new_pop = r->at<uint8_t>(p.off_pop[1 - r->cur]);
-    pa::SweepArgs a = sweep_args(r, i, pa::SWEEP_UPDATE, old_pop, anc, new_pop, p.desc.theta);
-    if ((st = timed_launch(r, PA_KERNEL_SWEEP, "sweep kernel", [&] { return pa::launch_sweep(a, r->stream); })))
-        return st;
+    if (p.tiled) {
+        const pa::TiledArgs ta = tiled_args(r, i, old_pop, anc, new_pop);
+        if ((st = timed_launch(r, PA_KERNEL_SWEEP, "tiled sweep kernels",
+                               [&] { return launch_tiled_sweeps(ta, p.desc.theta, r->stream); })))
+            return st;
+    } else {
+        pa::SweepArgs a = sweep_args(r, i, pa::SWEEP_UPDATE, old_pop, anc, new_pop, p.desc.theta);
+        if ((st = timed_launch(r, PA_KERNEL_SWEEP, "sweep kernel", [&] { return pa::launch_sweep(a, r->stream); })))
+            return st;
+    }
     r->cur = 1 - r->cur;
     r->step = i;
     return launch_post_for(r, i);
@@ -476,7 +544,7 @@ const char *pa_last_error(void) { return g_last_error.c_str(); }
 pa_status pa_plan(const pa_run_desc *desc, pa_plan_info *info) {
     if (!info) return fail(PA_ERR_INVALID, "null plan info");
     Plan p;
-    pa_status st = build_plan(desc, p, false);
+    pa_status st = build_plan(desc, p);
     if (st) return st;
     info->R_cap = p.R_cap;
     info->R_final = p.R_sched.back();
@@ -488,7 +556,7 @@ pa_status pa_plan(const pa_run_desc *desc, pa_plan_info *info) {
 
 pa_status pa_plan_tables(const pa_run_desc *desc, uint64_t *T, uint64_t *R_sched) {
     Plan p;
-    pa_status st = build_plan(desc, p, false);
+    pa_status st = build_plan(desc, p);
     if (st) return st;
     if (T) std::memcpy(T, p.T.data(), sizeof(uint64_t) * p.T.size());
     if (R_sched) std::memcpy(R_sched, p.R_sched.data(), sizeof(uint64_t) * p.R_sched.size());
@@ -658,7 +726,7 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
     if (!ctx || !out) return fail(PA_ERR_INVALID, "null context or output");
     pa_run_state *r = new (std::nothrow) pa_run_state;
     if (!r) return fail(PA_ERR_NOMEM, "out of host memory");
-    pa_status st = build_plan(desc, r->plan, true);
+    pa_status st = build_plan(desc, r->plan);
     if (st) { delete r; return st; }
     const Plan &p = r->plan;
     if (!d_ws || ws_bytes < p.total || ((uintptr_t)d_ws & 255u)) {
@@ -675,8 +743,10 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
     r->first_step = 0;
     r->R_first = p.desc.R;
     r->broken = false;
-    pa::sweep_shape(p.desc.L, ctx_lanes(ctx, p.desc.L), &r->G_log2, &r->wpb);
-    if (pa::sweep_lds_bytes(p.N, r->G_log2, r->wpb) > pa::max_lds_per_block(ctx->device)) {
+    r->G_log2 = 0;
+    r->wpb = 0;
+    if (!p.tiled) pa::sweep_shape(p.desc.L, ctx_lanes(ctx, p.desc.L), &r->G_log2, &r->wpb);
+    if (!p.tiled && pa::sweep_lds_bytes(p.N, r->G_log2, r->wpb) > pa::max_lds_per_block(ctx->device)) {
         delete r;
         return fail(PA_ERR_UNSUPPORTED, "lattice does not fit the LDS of one workgroup on this device");
     }
@@ -684,10 +754,9 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
 
     // Tables and initial state.
     hipStream_t s = r->stream;
-    if ((st = hip_check(r, hipMemcpyAsync(r->ws + p.off_W, p.W.data(), 8 * p.W.size(),
-                                          hipMemcpyHostToDevice, s), "upload W")) ||
-        (st = hip_check(r, hipMemcpyAsync(r->ws + p.off_w64, p.w64.data(), 8 * p.w64.size(),
-                                          hipMemcpyHostToDevice, s), "upload w64"))) {
+    if (!p.W.empty() &&
+        (st = hip_check(r, hipMemcpyAsync(r->ws + p.off_W, p.W.data(), 8 * p.W.size(),
+                                          hipMemcpyHostToDevice, s), "upload W"))) {
         delete r; return st;
     }
     const size_t hist_words = (size_t)p.nbins * (p.hist_all ? p.desc.K : 1);
@@ -696,7 +765,11 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
         (mhist_words &&
          (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_mhist), mhist_words, 0u, s), "fill"))) ||
         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_r), p.R_cap, 0u, s), "fill")) ||
-        (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_lnQ), 2 * (size_t)p.desc.K, 0u, s), "fill"))) {
+        (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_lnQ), 2 * (size_t)p.desc.K, 0u, s), "fill")) ||
+        (p.tiled &&
+         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_bonds), p.R_cap, 0u, s), "fill"))) ||
+        (p.tiled && p.mag &&
+         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_cnt), p.R_cap * p.desc.q, 0u, s), "fill")))) {
         delete r; return st;
     }
     // ln Z at beta_0: N ln q (Z = q^N at beta = 0, Sec. 6) or, for ground
@@ -709,7 +782,13 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
     }
     const uint32_t mode = p.desc.init == PA_INIT_GROUND ? pa::SWEEP_INIT_GROUND : pa::SWEEP_INIT_RANDOM;
     pa::SweepArgs a = sweep_args(r, 0, mode, nullptr, nullptr, r->at<uint8_t>(p.off_pop[0]), 0);
-    if ((st = timed_launch(r, PA_KERNEL_INIT, "init kernel", [&] { return pa::launch_sweep(a, s); })) ||
+    const pa::TiledArgs ta = tiled_args(r, 0, nullptr, nullptr, r->at<uint8_t>(p.off_pop[0]));
+    auto init = [&]() -> hipError_t {
+        if (!p.tiled) return pa::launch_sweep(a, s);
+        const hipError_t e = pa::launch_tiled_init(ta, s);
+        return e != hipSuccess ? e : pa::launch_tiled_measure(ta, s);
+    };
+    if ((st = timed_launch(r, PA_KERNEL_INIT, "init kernel", init)) ||
         (st = launch_post_for(r, 0))) {
         release_events(r, nullptr, nullptr);
         delete r; return st;
@@ -783,9 +862,15 @@ pa_status pa_run_load(pa_run_state *r, uint32_t step, uint64_t R_cur, const uint
     if ((st = hip_check(r, hipMemcpyAsync(r->at<double>(p.off_mbF) + step, &r->mbF0, 8,
                                           hipMemcpyHostToDevice, s), "upload")))
         return st;
-    pa::SweepArgs a = sweep_args(r, step, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[idle]), nullptr,
-                                 r->at<uint8_t>(p.off_pop[r->cur]), 0);
-    if ((st = hip_check(r, pa::launch_sweep(a, s), "load kernel"))) return st;
+    if (p.tiled) {
+        const pa::TiledArgs ta = tiled_args(r, step, r->at<uint8_t>(p.off_pop[idle]), nullptr,
+                                            r->at<uint8_t>(p.off_pop[r->cur]));
+        if ((st = hip_check(r, launch_tiled_sweeps(ta, 0, s), "load kernels"))) return st;
+    } else {
+        pa::SweepArgs a = sweep_args(r, step, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[idle]), nullptr,
+                                     r->at<uint8_t>(p.off_pop[r->cur]), 0);
+        if ((st = hip_check(r, pa::launch_sweep(a, s), "load kernel"))) return st;
+    }
     if ((st = launch_post_for(r, step))) return st;
     return hip_check(r, hipStreamSynchronize(s), "sync");
 }
@@ -881,6 +966,7 @@ struct StepLaunch {
     uint32_t n_res, sample_blocks, n_post;
     struct Group { uint32_t cls, first, count, blocks, threads; size_t lds; };
     std::vector<Group> groups;
+    std::vector<std::pair<pa::TiledArgs, uint32_t>> tiled;   // large lattices: (args, theta)
 };
 
 // Advance the host state of every run in `active` (each with step < K-1) by one
@@ -925,6 +1011,15 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
         }
         r->R_prev = R_prev;
         r->R_cur = R_new;
+        if (p.tiled) {
+            L.tiled.emplace_back(tiled_args(r, g, r->at<uint8_t>(p.off_pop[prev_buf]), anc,
+                                            r->at<uint8_t>(p.off_pop[new_buf])),
+                                 p.desc.theta);
+            r->cur = new_buf;
+            r->step = g;
+            po.push_back(post_args(r, g));
+            continue;
+        }
         pa::SweepArgs a = sweep_args(r, g, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[prev_buf]), anc,
                                      r->at<uint8_t>(p.off_pop[new_buf]), p.desc.theta);
         const uint64_t per_block = (64u * r->wpb) >> r->G_log2;
@@ -994,6 +1089,8 @@ pa_status launch_step(const StepLaunch &L, const uint8_t *dtab, hipStream_t s) {
             return st;
         run_index += G.count;
     }
+    for (const auto &t : L.tiled)
+        if ((st = hip_check(nullptr, launch_tiled_sweeps(t.first, t.second, s), "tiled sweeps"))) return st;
     return hip_check(nullptr, pa::launch_post_batch(reinterpret_cast<const pa::PostArgs *>(dtab + L.post_off),
                                                     L.n_post, s),
                      "batched post");
@@ -1012,7 +1109,7 @@ pa_status batch_layout(const pa_run_desc *descs, uint32_t n, BatchLayout &b) {
     b.run_off.resize(n);
     size_t o = 0;
     for (uint32_t r = 0; r < n; ++r) {
-        pa_status st = build_plan(&descs[r], b.plans[r], false);
+        pa_status st = build_plan(&descs[r], b.plans[r]);
         if (st) return fail(st, "run " + std::to_string(r) + ": " + g_last_error);
         b.run_off[r] = o;
         o += align256(b.plans[r].total);
@@ -1363,7 +1460,7 @@ pa_status pa_serve_submit(pa_ctx *ctx, const pa_run_desc *desc, pa_result *out, 
     Server *sv = ctx->server;
     auto q = std::make_shared<Request>();
     Plan p;
-    pa_status st = build_plan(desc, p, false);
+    pa_status st = build_plan(desc, p);
     if (st) return st;
     if (align256(p.total) > sv->run_bytes)
         return fail(PA_ERR_NOMEM, "the run's workspace exceeds the serving arena");

@@ -711,7 +711,8 @@ __device__ __forceinline__ void post_body(const PostArgs &a) {
     for (uint32_t b = tid; b < he.v.n; b += blockDim.x) {
         const uint32_t h = he.v.h[b];
         cnt += h;
-        if (a.has_next && h) acc += (double)h * a.w64_next[abs((int32_t)(b + he.v.lo) - a.two_n - ref)];
+        if (a.has_next && h)
+            acc += (double)h * exp(-(a.abs_dbeta_next * (double)abs((int32_t)(b + he.v.lo) - a.two_n - ref)));
     }
     acc = wave_sum(acc);
     cnt = wave_sum(cnt);
@@ -768,14 +769,14 @@ __device__ __forceinline__ void post_body(const PostArgs &a) {
             }
         } else {
 #pragma unroll
-            for (uint32_t v = 0; v < TILE_V; ++v) e[v] = j0 + v < n ? a.E[j0 + v] : ref + (int32_t)a.D;
+            for (uint32_t v = 0; v < TILE_V; ++v) e[v] = j0 + v < n ? a.E[j0 + v] : ref;
         }
         uint64_t w[TILE_V];
         uint64_t local = 0;
 #pragma unroll
         for (uint32_t v = 0; v < TILE_V; ++v) {
             const uint32_t dd = (uint32_t)abs(e[v] - ref);
-            w[v] = dd < a.D ? a.W[dd] : 0ull;
+            w[v] = j0 + v >= n ? 0ull : a.w_const ? a.w_const : (dd < a.D ? a.W[dd] : 0ull);
             local += w[v];
         }
         uint64_t total;
@@ -948,6 +949,167 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
         p[i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Lattices beyond one workgroup's LDS.  A replica stays in HBM as L rows of L
+// bytes.  A half-sweep is one launch over (replica, tile of `rows` rows): the
+// workgroup copies its rows and the row above and below (periodic) into LDS,
+// updates the colour-c sites of its rows and writes them back.  Colour-c sites
+// only read colour 1-c neighbours, which no workgroup changes in this launch,
+// so the tiles of one launch are independent, and a workgroup may overwrite
+// the rows it read (whole dwords whose other-colour bytes are unchanged).  The
+// first half-sweep of a step reads its rows from the ancestor's replica in the
+// previous buffer (the copy of Sec. 2 step 2, fused).  Pair p = y*L/4 + x/4
+// uses the same Philox counters as in LDS, so the result is the same as for a
+// replica held in LDS.
+// ---------------------------------------------------------------------------
+// Workgroup -> (replica, tile): each XCD takes a contiguous range, so that
+// neighbouring tiles of a replica share their halo rows in one L2.
+__device__ __forceinline__ void tile_of(uint32_t tiles, uint32_t &k, uint32_t &tile) {
+    uint32_t b = blockIdx.x;
+    if ((gridDim.x & 7u) == 0) b = (b & 7u) * (gridDim.x >> 3) + (b >> 3);
+    k = b / tiles;
+    tile = b % tiles;
+}
+
+// Copies rows y0-1 .. y0+n (periodic) of replica src (L/4 dwords per row) to
+// LDS rows 0 .. n+1; with halo = false only rows y0 .. y0+n (LDS rows 1 .. n+1).
+__device__ __forceinline__ void load_tile_rows(uint32_t *lds32, const uint32_t *src32, uint32_t L,
+                                               uint32_t y0, uint32_t n, bool above) {
+    const uint32_t DPR = L >> 2;
+    for (uint32_t i = threadIdx.x; i < n * DPR; i += blockDim.x) lds32[DPR + i] = src32[y0 * DPR + i];
+    const uint32_t ya = (y0 + L - 1) % L, yb = (y0 + n) % L;
+    for (uint32_t x = threadIdx.x; x < DPR; x += blockDim.x) {
+        if (above) lds32[x] = src32[ya * DPR + x];
+        lds32[(n + 1) * DPR + x] = src32[yb * DPR + x];
+    }
+}
+
+template <bool QSMALL, bool T64>
+__global__ void __launch_bounds__(256) k_tiled_half(TiledArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint32_t k, tile;
+    tile_of(a.tiles, k, tile);
+    if (threadIdx.x < 9) {
+        const int dE = (int)threadIdx.x - 4;
+        const uint64_t T = dE <= 0 ? (1ull << 32) : a.T[dE - 1];
+        if (T64) reinterpret_cast<uint64_t *>(smem)[threadIdx.x] = T;
+        else reinterpret_cast<uint32_t *>(smem)[threadIdx.x] = (uint32_t)(T - 1u);
+    }
+    const uint32_t L = a.L, DPR = L >> 2;
+    const uint32_t y0 = tile * a.rows, n = min(a.rows, L - y0);
+    uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem + 128);
+    const uint32_t src = a.anc ? a.anc[k] : k;
+    load_tile_rows(lds32, reinterpret_cast<const uint32_t *>(a.src + (size_t)src * a.N), L, y0, n, true);
+    __syncthreads();
+    if (a.c < 2) {
+        const Thresholds<T64> thr{smem};
+        const SweepKey key = sweep_key(k, a.step, (DOM_SWEEP << 28) | (a.t << 1) | a.c, a.key0, a.key1);
+        const uint32_t qm1 = a.q - 1u;
+        const uint32_t np = n * DPR, sy = blockDim.x / DPR, sx = blockDim.x % DPR;
+        uint32_t yl = threadIdx.x / DPR, xd = threadIdx.x % DPR;
+        uint64_t P0 = (uint64_t)PHILOX_M0 * (y0 * DPR + threadIdx.x);
+        const uint64_t MSTEP = (uint64_t)PHILOX_M0 * blockDim.x;
+        for (uint32_t pl = threadIdx.x; pl < np; pl += blockDim.x) {
+            const uint32_t par = (y0 + yl + a.c) & 1u;
+            const uint32_t idx = (yl + 1) * DPR + xd;
+            const uint32_t xo = par ? (xd == DPR - 1 ? idx - (DPR - 1) : idx + 1)
+                                    : (xd == 0 ? idx + (DPR - 1) : idx - 1);
+            const uint32_t D0 = lds32[idx], Dx = lds32[xo];
+            const uint32_t U = lds32[idx - DPR], Dn = lds32[idx + DPR];
+            const uint4 w = philox_sweep(P0, key);
+            lds32[idx] = update_pair<QSMALL, T64>(D0, Dx, U, Dn, PairSel(par), w, qm1, thr);
+            P0 += MSTEP;
+            xd += sx;
+            if (xd >= DPR) { xd -= DPR; ++yl; }
+            yl += sy;
+        }
+        __syncthreads();
+    }
+    uint32_t *dst32 = reinterpret_cast<uint32_t *>(a.dst + (size_t)k * a.N) + y0 * DPR;
+    for (uint32_t i = threadIdx.x; i < n * DPR; i += blockDim.x) dst32[i] = lds32[DPR + i];
+}
+
+__global__ void __launch_bounds__(256) k_tiled_init(TiledArgs a) {
+    uint32_t k, tile;
+    tile_of(a.tiles, k, tile);
+    const uint32_t DPR = a.L >> 2, y0 = tile * a.rows, n = min(a.rows, a.L - y0);
+    uint32_t *dst32 = reinterpret_cast<uint32_t *>(a.dst + (size_t)k * a.N);
+    if (a.init == SWEEP_INIT_RANDOM) {
+        // site n takes word n mod 4 of Philox(n / 4, k, 0, INIT)
+        for (uint32_t dd = y0 * DPR + threadIdx.x; dd < (y0 + n) * DPR; dd += blockDim.x) {
+            const uint4 w = philox(dd, k, 0u, DOM_INIT << 28, a.key0, a.key1);
+            dst32[dd] = mulhi32(w.x, a.q) | (mulhi32(w.y, a.q) << 8) | (mulhi32(w.z, a.q) << 16) |
+                        (mulhi32(w.w, a.q) << 24);
+        }
+    } else {
+        // eq. (6): all spins alpha, alpha uniform over the q states
+        const uint4 w = philox(0u, k, 0u, DOM_GROUND << 28, a.key0, a.key1);
+        const uint32_t alpha = mulhi32(w.x, a.q) * 0x01010101u;
+        for (uint32_t dd = y0 * DPR + threadIdx.x; dd < (y0 + n) * DPR; dd += blockDim.x) dst32[dd] = alpha;
+    }
+}
+
+// Bonds (eq. (3)) of the tile's rows (right and down neighbours) and, with
+// cnt, the number of sites in each state (eq. (5)); added to the replica's
+// totals.
+__global__ void __launch_bounds__(256) k_tiled_measure(TiledArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t s_part[4];
+    uint32_t k, tile;
+    tile_of(a.tiles, k, tile);
+    const uint32_t L = a.L, DPR = L >> 2;
+    const uint32_t y0 = tile * a.rows, n = min(a.rows, L - y0);
+    uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *scnt = reinterpret_cast<uint32_t *>(smem) + (a.rows + 2) * DPR;   // [q]
+    if (a.cnt)
+        for (uint32_t s = threadIdx.x; s < a.q; s += blockDim.x) scnt[s] = 0u;
+    load_tile_rows(lds32, reinterpret_cast<const uint32_t *>(a.dst + (size_t)k * a.N), L, y0, n, false);
+    __syncthreads();
+    uint32_t bonds = 0;
+    for (uint32_t i = threadIdx.x; i < n * DPR; i += blockDim.x) {
+        const uint32_t xd = i % DPR, idx = DPR + i;
+        const uint32_t D = lds32[idx];
+        const uint32_t Dr = lds32[xd == DPR - 1 ? idx - (DPR - 1) : idx + 1];
+        bonds += eq_bytes(D, __builtin_amdgcn_alignbyte(Dr, D, 1)) + eq_bytes(D, lds32[idx + DPR]);
+    }
+    bonds = wave_sum(bonds);
+    if ((threadIdx.x & 63u) == 0) s_part[threadIdx.x >> 6] = bonds;
+    if (a.cnt) {
+        for (uint32_t st = 0; st < a.q; ++st) {
+            const uint32_t pat = st * 0x01010101u;
+            uint32_t c = 0;
+            for (uint32_t i = threadIdx.x; i < n * DPR; i += blockDim.x) c += eq_bytes(lds32[DPR + i], pat);
+            c = wave_sum(c);
+            if ((threadIdx.x & 63u) == 0 && c) atomicAdd(&scnt[st], c);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = 0;
+        for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) b += s_part[w];
+        atomicAdd(&a.bonds[k], b);
+    }
+    if (a.cnt)
+        for (uint32_t s = threadIdx.x; s < a.q; s += blockDim.x)
+            if (scnt[s]) atomicAdd(&a.cnt[(size_t)k * a.q + s], scnt[s]);
+}
+
+// Per replica: E = -bonds, M~ = the largest state count; clears both sums.
+__global__ void k_tiled_finalize(TiledArgs a) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.R) return;
+    a.E_out[k] = -(int32_t)a.bonds[k];
+    a.bonds[k] = 0u;
+    if (a.cnt) {
+        uint32_t m = 0;
+        for (uint32_t s = 0; s < a.q; ++s) {
+            m = max(m, a.cnt[(size_t)k * a.q + s]);
+            a.cnt[(size_t)k * a.q + s] = 0u;
+        }
+        if (a.Mt_out) a.Mt_out[k] = m;
+    }
+}
+
 }  // namespace
 
 // Lanes-per-replica candidates of the fixed-shape kernels (first = default,
@@ -1102,6 +1264,41 @@ hipError_t launch_resample_batch(const SampleArgs *sruns, const uint32_t *start,
     if (n == 0) return hipSuccess;
     if (blocks) hipLaunchKernelGGL(k_sample_batch, dim3(blocks), dim3(256), 0, s, sruns, start, n);
     hipLaunchKernelGGL(k_countfill_batch, dim3(n), dim3(1024), 0, s, mruns);
+    return hipGetLastError();
+}
+
+bool tiled_path(uint32_t L) { return L > 256; }
+
+uint32_t tiled_rows(uint32_t L) {
+    // about 16 KB of rows per tile, at least two
+    const uint32_t r = 16384u / L;
+    return r < 2u ? 2u : (r > L ? L : r);
+}
+
+static size_t tiled_lds_bytes(const TiledArgs &a) { return 128 + (size_t)(a.rows + 2) * a.L; }
+
+hipError_t launch_tiled_half(const TiledArgs &a, hipStream_t s) {
+    const uint64_t blocks = (uint64_t)a.R * a.tiles;
+    if (blocks == 0) return hipSuccess;
+    const bool qsmall = a.q <= 128, t64 = a.T[3] == 0;
+    void (*kern)(TiledArgs) = qsmall ? (t64 ? k_tiled_half<true, true> : k_tiled_half<true, false>)
+                                     : (t64 ? k_tiled_half<false, true> : k_tiled_half<false, false>);
+    hipLaunchKernelGGL(kern, dim3((uint32_t)blocks), dim3(256), tiled_lds_bytes(a), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiled_init(const TiledArgs &a, hipStream_t s) {
+    const uint64_t blocks = (uint64_t)a.R * a.tiles;
+    if (blocks) hipLaunchKernelGGL(k_tiled_init, dim3((uint32_t)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiled_measure(const TiledArgs &a, hipStream_t s) {
+    const uint64_t blocks = (uint64_t)a.R * a.tiles;
+    if (blocks == 0) return hipSuccess;
+    const size_t lds = (size_t)(a.rows + 2) * a.L + 4 * 256;
+    hipLaunchKernelGGL(k_tiled_measure, dim3((uint32_t)blocks), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_tiled_finalize, dim3((a.R + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -82,7 +82,10 @@ def test_validation():
         (dict(good, beta=[0.0, -1.0]), pa.PA_ERR_INVALID),
         (dict(good, theta=2**27), pa.PA_ERR_INVALID),
         (dict(good, L=6), pa.PA_ERR_UNSUPPORTED),
-        (dict(good, L=260), pa.PA_ERR_UNSUPPORTED),
+        (dict(good, L=4100), pa.PA_ERR_UNSUPPORTED),
+        (dict(good, L=258), pa.PA_ERR_UNSUPPORTED),
+        (dict(good, outputs=16), pa.PA_ERR_INVALID),
+        (dict(good, outputs=pa.OUT_WIDTHS, bin_e=2 * 64 + 2), pa.PA_ERR_INVALID),
     ]:
         with pytest.raises(pa.PAError) as e:
             pa.pa_plan(pa.Desc(**bad))
@@ -119,3 +122,15 @@ def test_poisson_capacity_error_matches_oracle():
         seen_ok += lib_ok
         seen_err += not lib_ok
     assert seen_ok > 0 and seen_err > 0
+
+
+def test_large_lattices_plan_compact_tables():
+    """Lattices beyond LDS are planned (tiled device path); the weight tables
+    keep only their nonzero prefix, so the workspace is dominated by the two
+    population buffers even for 4096 x 4096 and many distinct dbeta."""
+    beta = np.array([1.6 * i / 400 for i in range(401)])
+    info = pa.pa_plan(pa.Desc(L=4096, q=10, R=4, beta=beta, theta=1, seed=1, resample=1))
+    pop = 2 * 4 * 4096 * 4096
+    assert pop <= info.workspace_bytes < pop + 200 * 2**20
+    info = pa.pa_plan(pa.Desc(L=260, q=10, R=100, beta=beta, theta=1, seed=1))
+    assert info.workspace_bytes < 2 * info.R_cap * 260 * 260 + 20 * 2**20
