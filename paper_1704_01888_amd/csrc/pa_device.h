@@ -92,7 +92,8 @@ struct TiledArgs {
     uint64_t T[4];            // thresholds for dE = 1..4 (<= 2^32)
     uint32_t L, q, N, R;
     uint32_t rows, tiles;     // rows per tile, tiles per replica
-    uint32_t step, t, c;      // Philox step, sweep number, colour; c = 2: copy only
+    uint32_t step;            // Philox step
+    uint32_t h0, halves;      // first half-sweep (sweep h/2, colour h%2) and count; 0: copy
     uint32_t key0, key1;
     uint32_t init;            // k_tiled_init: SWEEP_INIT_RANDOM or SWEEP_INIT_GROUND
     uint32_t *bonds;          // [R] equal-neighbour bond counts (measure; zero on entry)
@@ -102,6 +103,7 @@ struct TiledArgs {
 };
 bool tiled_path(uint32_t L);
 uint32_t tiled_rows(uint32_t L);
+uint32_t tiled_max_halves(uint32_t L);   // half-sweeps fused per tiled launch
 hipError_t launch_tiled_half(const TiledArgs &a, hipStream_t s);
 hipError_t launch_tiled_init(const TiledArgs &a, hipStream_t s);
 // energies (eq. (3)) and M~ (eq. (5)) of dst; leaves bonds and cnt zeroed

@@ -456,18 +456,15 @@ pa::TiledArgs tiled_args(pa_run_state *r, uint32_t i, const uint8_t *src, const 
 // theta = 0 copies.
 hipError_t launch_tiled_sweeps(pa::TiledArgs a, uint32_t theta, hipStream_t s) {
     hipError_t e;
-    if (theta == 0) {
-        a.c = 2;
+    const uint32_t total = 2 * theta;
+    a.h0 = 0;
+    do {
+        a.halves = std::min(total - a.h0, pa::tiled_max_halves(a.L));
         if ((e = pa::launch_tiled_half(a, s)) != hipSuccess) return e;
-    }
-    for (uint32_t t = 0; t < theta; ++t)
-        for (uint32_t c = 0; c < 2; ++c) {
-            a.t = t;
-            a.c = c;
-            if ((e = pa::launch_tiled_half(a, s)) != hipSuccess) return e;
-            a.src = a.dst;
-            a.anc = nullptr;
-        }
+        a.src = a.dst;
+        a.anc = nullptr;
+        a.h0 += a.halves;
+    } while (a.h0 < total);
     return pa::launch_tiled_measure(a, s);
 }
 

@@ -984,6 +984,13 @@ __device__ __forceinline__ void load_tile_rows(uint32_t *lds32, const uint32_t *
     }
 }
 
+// `a.halves` consecutive half-sweeps (numbers h0, h0+1, ...; half-sweep h is
+// sweep h/2, colour h%2) of one tile in one launch.  The tile's rows and
+// `halves` rows on each side (periodic) are staged in LDS; half-sweep j of the
+// launch updates the tile and halves-1-j rows on each side, so that the last
+// one leaves the tile exact.  The side rows are updated redundantly by the
+// neighbouring tiles too, with the same counters and hence the same results;
+// only the tile is written back.  halves = 0 copies.
 template <bool QSMALL, bool T64>
 __global__ void __launch_bounds__(256) k_tiled_half(TiledArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -995,30 +1002,37 @@ __global__ void __launch_bounds__(256) k_tiled_half(TiledArgs a) {
         if (T64) reinterpret_cast<uint64_t *>(smem)[threadIdx.x] = T;
         else reinterpret_cast<uint32_t *>(smem)[threadIdx.x] = (uint32_t)(T - 1u);
     }
-    const uint32_t L = a.L, DPR = L >> 2;
-    const uint32_t y0 = tile * a.rows, n = min(a.rows, L - y0);
+    const uint32_t L = a.L, DPR = L >> 2, S = a.halves;
+    const uint32_t y0 = tile * a.rows, n = min(a.rows, L - y0), nl = n + 2 * S;
     uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem + 128);
     const uint32_t src = a.anc ? a.anc[k] : k;
-    load_tile_rows(lds32, reinterpret_cast<const uint32_t *>(a.src + (size_t)src * a.N), L, y0, n, true);
+    const uint32_t *src32 = reinterpret_cast<const uint32_t *>(a.src + (size_t)src * a.N);
+    // local row r holds global row y0 - S + r (periodic)
+    for (uint32_t r = threadIdx.x >> 6; r < nl; r += blockDim.x >> 6) {
+        const uint32_t gy = (y0 + r + L - S) % L;
+        for (uint32_t x = threadIdx.x & 63u; x < DPR; x += 64u) lds32[r * DPR + x] = src32[gy * DPR + x];
+    }
     __syncthreads();
-    if (a.c < 2) {
-        const Thresholds<T64> thr{smem};
-        const SweepKey key = sweep_key(k, a.step, (DOM_SWEEP << 28) | (a.t << 1) | a.c, a.key0, a.key1);
-        const uint32_t qm1 = a.q - 1u;
-        const uint32_t np = n * DPR, sy = blockDim.x / DPR, sx = blockDim.x % DPR;
-        uint32_t yl = threadIdx.x / DPR, xd = threadIdx.x % DPR;
-        uint64_t P0 = (uint64_t)PHILOX_M0 * (y0 * DPR + threadIdx.x);
-        const uint64_t MSTEP = (uint64_t)PHILOX_M0 * blockDim.x;
+    const Thresholds<T64> thr{smem};
+    const uint32_t qm1 = a.q - 1u;
+    for (uint32_t j = 0; j < S; ++j) {
+        const uint32_t h = a.h0 + j, c = h & 1u;
+        const SweepKey key = sweep_key(k, a.step, (DOM_SWEEP << 28) | ((h >> 1) << 1) | c, a.key0, a.key1);
+        const uint32_t r0 = 1 + j, np = (nl - 2 - 2 * j) * DPR;       // rows r0 .. nl-2-j
+        const uint32_t sy = blockDim.x / DPR, sx = blockDim.x % DPR;
+        uint32_t yl = r0 + threadIdx.x / DPR, xd = threadIdx.x % DPR;
         for (uint32_t pl = threadIdx.x; pl < np; pl += blockDim.x) {
-            const uint32_t par = (y0 + yl + a.c) & 1u;
-            const uint32_t idx = (yl + 1) * DPR + xd;
+            uint32_t gy = y0 + yl + L - S;
+            gy = gy >= L ? gy - L : gy;
+            gy = gy >= L ? gy - L : gy;
+            const uint32_t par = (gy + c) & 1u;
+            const uint32_t idx = yl * DPR + xd;
             const uint32_t xo = par ? (xd == DPR - 1 ? idx - (DPR - 1) : idx + 1)
                                     : (xd == 0 ? idx + (DPR - 1) : idx - 1);
             const uint32_t D0 = lds32[idx], Dx = lds32[xo];
             const uint32_t U = lds32[idx - DPR], Dn = lds32[idx + DPR];
-            const uint4 w = philox_sweep(P0, key);
+            const uint4 w = philox_sweep((uint64_t)PHILOX_M0 * (gy * DPR + xd), key);
             lds32[idx] = update_pair<QSMALL, T64>(D0, Dx, U, Dn, PairSel(par), w, qm1, thr);
-            P0 += MSTEP;
             xd += sx;
             if (xd >= DPR) { xd -= DPR; ++yl; }
             yl += sy;
@@ -1026,7 +1040,83 @@ __global__ void __launch_bounds__(256) k_tiled_half(TiledArgs a) {
         __syncthreads();
     }
     uint32_t *dst32 = reinterpret_cast<uint32_t *>(a.dst + (size_t)k * a.N) + y0 * DPR;
-    for (uint32_t i = threadIdx.x; i < n * DPR; i += blockDim.x) dst32[i] = lds32[DPR + i];
+    for (uint32_t i = threadIdx.x; i < n * DPR; i += blockDim.x) dst32[i] = lds32[S * DPR + i];
+}
+
+// The same for L a power of two from 512 on: lane layout fixed at compile
+// time (each lane owns dword columns tid mod L/4 (+ 256 c) of every RS-th
+// row of the update range), two rows per iteration for independent work.
+// Rows beyond the update range are read from two padding rows and not stored.
+template <uint32_t LT, bool QSMALL, bool T64>
+__global__ void __launch_bounds__(256) k_tiled_fixed(TiledArgs a) {
+    constexpr uint32_t L = LT, DPR = L / 4, NT = 256;
+    constexpr uint32_t CPT = DPR > NT ? DPR / NT : 1;     // dword columns per lane
+    constexpr uint32_t RS = DPR >= NT ? 1 : NT / DPR;      // rows per pass of the workgroup
+    static_assert(RS <= 2, "two padding rows");
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint32_t k, tile;
+    tile_of(a.tiles, k, tile);
+    if (threadIdx.x < 9) {
+        const int dE = (int)threadIdx.x - 4;
+        const uint64_t T = dE <= 0 ? (1ull << 32) : a.T[dE - 1];
+        if (T64) reinterpret_cast<uint64_t *>(smem)[threadIdx.x] = T;
+        else reinterpret_cast<uint32_t *>(smem)[threadIdx.x] = (uint32_t)(T - 1u);
+    }
+    const uint32_t S = a.halves, y0 = tile * a.rows, n = a.rows, nl = n + 2 * S;
+    uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem + 128);
+    const uint32_t src = a.anc ? a.anc[k] : k;
+    const uint32_t *src32 = reinterpret_cast<const uint32_t *>(a.src + (size_t)src * a.N);
+    for (uint32_t r = threadIdx.x >> 6; r < nl; r += NT / 64) {
+        const uint32_t gy = (y0 + r + L - S) & (L - 1);
+#pragma unroll
+        for (uint32_t x = threadIdx.x & 63u; x < DPR; x += 64u) lds32[r * DPR + x] = src32[gy * DPR + x];
+    }
+    __syncthreads();
+    const Thresholds<T64> thr{smem};
+    const uint32_t qm1 = a.q - 1u;
+    const uint32_t xd0 = threadIdx.x % DPR, roff = DPR >= NT ? 0u : threadIdx.x / DPR;
+    for (uint32_t j = 0; j < S; ++j) {
+        const uint32_t h = a.h0 + j, c = h & 1u;
+        const SweepKey key = sweep_key(k, a.step, (DOM_SWEEP << 28) | ((h >> 1) << 1) | c, a.key0, a.key1);
+        const uint32_t r0 = 1 + j, nr = nl - 2 - 2 * j;
+        for (uint32_t rr = roff; rr < nr; rr += 2 * RS) {
+            uint32_t idx[2][CPT], D0[2][CPT], Dx[2][CPT], U[2][CPT], Dn[2][CPT];
+            uint4 w[2][CPT];
+            PairSel ps[2];
+#pragma unroll
+            for (uint32_t u = 0; u < 2; ++u) {
+                const uint32_t yl = r0 + rr + u * RS;
+                const uint32_t gy = (y0 + yl + L - S) & (L - 1);
+                const uint32_t par = (gy + c) & 1u;
+                ps[u] = PairSel(par);
+#pragma unroll
+                for (uint32_t cc = 0; cc < CPT; ++cc) {
+                    const uint32_t xd = xd0 + cc * NT;
+                    idx[u][cc] = yl * DPR + xd;
+                    const uint32_t xo = par ? (xd == DPR - 1 ? idx[u][cc] - (DPR - 1) : idx[u][cc] + 1)
+                                            : (xd == 0 ? idx[u][cc] + (DPR - 1) : idx[u][cc] - 1);
+                    D0[u][cc] = lds32[idx[u][cc]];
+                    Dx[u][cc] = lds32[xo];
+                    U[u][cc] = lds32[idx[u][cc] - DPR];
+                    Dn[u][cc] = lds32[idx[u][cc] + DPR];
+                    w[u][cc] = philox_sweep((uint64_t)PHILOX_M0 * (gy * DPR + xd), key);
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 2; ++u) {
+                const bool in = rr + u * RS < nr;
+#pragma unroll
+                for (uint32_t cc = 0; cc < CPT; ++cc) {
+                    const uint32_t nw = update_pair<QSMALL, T64>(D0[u][cc], Dx[u][cc], U[u][cc], Dn[u][cc],
+                                                                 ps[u], w[u][cc], qm1, thr);
+                    if (in) lds32[idx[u][cc]] = nw;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    uint32_t *dst32 = reinterpret_cast<uint32_t *>(a.dst + (size_t)k * a.N) + y0 * DPR;
+    for (uint32_t i = threadIdx.x; i < n * DPR; i += NT) dst32[i] = lds32[S * DPR + i];
 }
 
 __global__ void __launch_bounds__(256) k_tiled_init(TiledArgs a) {
@@ -1275,7 +1365,27 @@ uint32_t tiled_rows(uint32_t L) {
     return r < 2u ? 2u : (r > L ? L : r);
 }
 
-static size_t tiled_lds_bytes(const TiledArgs &a) { return 128 + (size_t)(a.rows + 2) * a.L; }
+// Each fused half-sweep beyond the first recomputes two rows per side; two
+// per launch measured best for L = 512 .. 4096 (one or four: 0-25 % slower,
+// taller tiles: slower still).
+uint32_t tiled_max_halves(uint32_t L) {
+    (void)L;
+    return 2u;
+}
+
+// two padding rows for the fixed-layout kernel
+static size_t tiled_lds_bytes(const TiledArgs &a) { return 128 + (size_t)(a.rows + 2 * a.halves + 2) * a.L; }
+
+template <bool QSMALL, bool T64>
+static void *tiled_fixed_kernel(uint32_t L) {
+    switch (L) {
+        case 512: return (void *)k_tiled_fixed<512, QSMALL, T64>;
+        case 1024: return (void *)k_tiled_fixed<1024, QSMALL, T64>;
+        case 2048: return (void *)k_tiled_fixed<2048, QSMALL, T64>;
+        case 4096: return (void *)k_tiled_fixed<4096, QSMALL, T64>;
+        default: return nullptr;
+    }
+}
 
 hipError_t launch_tiled_half(const TiledArgs &a, hipStream_t s) {
     const uint64_t blocks = (uint64_t)a.R * a.tiles;
@@ -1283,6 +1393,11 @@ hipError_t launch_tiled_half(const TiledArgs &a, hipStream_t s) {
     const bool qsmall = a.q <= 128, t64 = a.T[3] == 0;
     void (*kern)(TiledArgs) = qsmall ? (t64 ? k_tiled_half<true, true> : k_tiled_half<true, false>)
                                      : (t64 ? k_tiled_half<false, true> : k_tiled_half<false, false>);
+    if (a.halves > 0 && a.L % a.rows == 0) {
+        void *f = qsmall ? (t64 ? tiled_fixed_kernel<true, true>(a.L) : tiled_fixed_kernel<true, false>(a.L))
+                         : (t64 ? tiled_fixed_kernel<false, true>(a.L) : tiled_fixed_kernel<false, false>(a.L));
+        if (f) kern = (void (*)(TiledArgs))f;
+    }
     hipLaunchKernelGGL(kern, dim3((uint32_t)blocks), dim3(256), tiled_lds_bytes(a), s, a);
     return hipGetLastError();
 }
