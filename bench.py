@@ -185,7 +185,19 @@ def main():
                     help="requests of the serving line (0 = skip)")
     ap.add_argument("--cpu-steps", type=int, default=12,
                     help="temperature steps of the oracle's CPU-baseline sample (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device-to-device three times (reference kernel of "
+                         "known size for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copied_bytes": 256 << 20, "times": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described but not built.", file=sys.stderr)

@@ -118,7 +118,7 @@ struct Plan {
     // workspace layout
     size_t off_pop[2], off_E, off_C, off_r, off_anc, off_counts, off_hist, off_Esum, off_Emean,
         off_count, off_lnQ, off_mbF, off_Eref, off_W, off_mhist, off_Mt, off_Mtsum,
-        off_Mmean, off_we, off_wm, off_bonds, off_cnt, total;
+        off_Mmean, off_we, off_wm, off_bonds, off_cnt, off_pop_x, total;
     bool tiled = false;   // replicas beyond one workgroup's LDS: tiled half-sweeps in HBM
 };
 
@@ -253,6 +253,7 @@ pa_status build_plan(const pa_run_desc *d, Plan &p) {
     p.tiled = pa::tiled_path(d->L);
     p.off_bonds = o; o += p.tiled ? align256(4 * p.R_cap) : 0;
     p.off_cnt = o; o += (p.tiled && p.mag) ? align256((size_t)4 * p.R_cap * d->q) : 0;
+    p.off_pop_x = o; o += p.tiled ? popb : 0;   // third population buffer of the tiled sweeps
     p.total = o;
     return PA_OK;
 }
@@ -451,20 +452,25 @@ pa::TiledArgs tiled_args(pa_run_state *r, uint32_t i, const uint8_t *src, const 
     return a;
 }
 
-// theta tiled sweeps from src (through anc) into dst, then the energies: the
-// first half-sweep reads the ancestors, the later ones update dst in place;
-// theta = 0 copies.
-hipError_t launch_tiled_sweeps(pa::TiledArgs a, uint32_t theta, hipStream_t s) {
+// theta tiled sweeps from src (through anc) into dst, then the energies
+// (theta = 0 copies).  A launch that fuses several half-sweeps recomputes the
+// rows next to its tile, so it must not read rows that neighbouring tiles of
+// the same launch write: no launch works in place.  The launches alternate
+// between dst and the spare buffer `x`, the last one writing dst.
+hipError_t launch_tiled_sweeps(pa::TiledArgs a, uint32_t theta, uint8_t *x, hipStream_t s) {
     hipError_t e;
-    const uint32_t total = 2 * theta;
+    const uint32_t total = 2 * theta, S = pa::tiled_max_halves(a.L);
+    const uint32_t launches = total == 0 ? 1u : (total + S - 1) / S;
+    uint8_t *const dst = a.dst;
     a.h0 = 0;
-    do {
-        a.halves = std::min(total - a.h0, pa::tiled_max_halves(a.L));
+    for (uint32_t i = 0; i < launches; ++i) {
+        a.halves = std::min(total - a.h0, S);
+        a.dst = ((launches - 1 - i) & 1u) ? x : dst;
         if ((e = pa::launch_tiled_half(a, s)) != hipSuccess) return e;
         a.src = a.dst;
         a.anc = nullptr;
         a.h0 += a.halves;
-    } while (a.h0 < total);
+    }
     return pa::launch_tiled_measure(a, s);
 }
 
@@ -504,8 +510,9 @@ pa_status do_step(pa_run_state *r) {
     uint8_t *new_pop = r->at<uint8_t>(p.off_pop[1 - r->cur]);
     if (p.tiled) {
         const pa::TiledArgs ta = tiled_args(r, i, old_pop, anc, new_pop);
+        uint8_t *x = r->at<uint8_t>(p.off_pop_x);
         if ((st = timed_launch(r, PA_KERNEL_SWEEP, "tiled sweep kernels",
-                               [&] { return launch_tiled_sweeps(ta, p.desc.theta, r->stream); })))
+                               [&] { return launch_tiled_sweeps(ta, p.desc.theta, x, r->stream); })))
             return st;
     } else {
         pa::SweepArgs a = sweep_args(r, i, pa::SWEEP_UPDATE, old_pop, anc, new_pop, p.desc.theta);
@@ -862,7 +869,8 @@ pa_status pa_run_load(pa_run_state *r, uint32_t step, uint64_t R_cur, const uint
     if (p.tiled) {
         const pa::TiledArgs ta = tiled_args(r, step, r->at<uint8_t>(p.off_pop[idle]), nullptr,
                                             r->at<uint8_t>(p.off_pop[r->cur]));
-        if ((st = hip_check(r, launch_tiled_sweeps(ta, 0, s), "load kernels"))) return st;
+        if ((st = hip_check(r, launch_tiled_sweeps(ta, 0, r->at<uint8_t>(p.off_pop_x), s), "load kernels")))
+            return st;
     } else {
         pa::SweepArgs a = sweep_args(r, step, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[idle]), nullptr,
                                      r->at<uint8_t>(p.off_pop[r->cur]), 0);
@@ -963,7 +971,8 @@ struct StepLaunch {
     uint32_t n_res, sample_blocks, n_post;
     struct Group { uint32_t cls, first, count, blocks, threads; size_t lds; };
     std::vector<Group> groups;
-    std::vector<std::pair<pa::TiledArgs, uint32_t>> tiled;   // large lattices: (args, theta)
+    struct Tiled { pa::TiledArgs a; uint32_t theta; uint8_t *x; };
+    std::vector<Tiled> tiled;   // large lattices, launched one by one
 };
 
 // Advance the host state of every run in `active` (each with step < K-1) by one
@@ -1009,9 +1018,9 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
         r->R_prev = R_prev;
         r->R_cur = R_new;
         if (p.tiled) {
-            L.tiled.emplace_back(tiled_args(r, g, r->at<uint8_t>(p.off_pop[prev_buf]), anc,
-                                            r->at<uint8_t>(p.off_pop[new_buf])),
-                                 p.desc.theta);
+            L.tiled.push_back({tiled_args(r, g, r->at<uint8_t>(p.off_pop[prev_buf]), anc,
+                                          r->at<uint8_t>(p.off_pop[new_buf])),
+                               p.desc.theta, r->at<uint8_t>(p.off_pop_x)});
             r->cur = new_buf;
             r->step = g;
             po.push_back(post_args(r, g));
@@ -1087,7 +1096,7 @@ pa_status launch_step(const StepLaunch &L, const uint8_t *dtab, hipStream_t s) {
         run_index += G.count;
     }
     for (const auto &t : L.tiled)
-        if ((st = hip_check(nullptr, launch_tiled_sweeps(t.first, t.second, s), "tiled sweeps"))) return st;
+        if ((st = hip_check(nullptr, launch_tiled_sweeps(t.a, t.theta, t.x, s), "tiled sweeps"))) return st;
     return hip_check(nullptr, pa::launch_post_batch(reinterpret_cast<const pa::PostArgs *>(dtab + L.post_off),
                                                     L.n_post, s),
                      "batched post");

@@ -467,7 +467,8 @@ template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64>
 __global__ void __launch_bounds__(1024) k_sweep_batch(const SweepArgs *runs, const uint32_t *start,
                                                       uint32_t n) {
     const uint32_t r = segment_of(start, n, blockIdx.x);
-    const SweepArgs a = runs[r];
+    // by reference: a local copy would go to scratch memory (T[] is indexed at run time)
+    const SweepArgs &a = runs[r];
     sweep_body<LT, GT, QSMALL, T64>(a, blockIdx.x - start[r]);
 }
 
@@ -680,7 +681,7 @@ __device__ void store_hist(const HistView &v, uint32_t *out) {
 
 constexpr uint32_t POST_LDS_BINS = 14336;   // 56 KB window for the histograms in LDS
 
-constexpr uint32_t TILE_V = 32;  // elements per thread per tile in the one-workgroup weight scan
+constexpr uint32_t TILE_V = 16;  // elements per thread per tile in the one-workgroup weight scan
 constexpr uint32_t FILL_V = 16;
 constexpr uint32_t SHORT_RUN = 8;   // copies written by their own lane in the slot map  // elements per thread per tile in the count scan + slot map
 
@@ -759,8 +760,12 @@ __device__ __forceinline__ void post_body(const PostArgs &a) {
     uint64_t carry = 0;
     for (uint64_t base = 0; base < n; base += (uint64_t)blockDim.x * TILE_V) {
         const uint64_t j0 = base + (uint64_t)tid * TILE_V;
+        // valid entries of this thread's tile; the others get E_ref + D, whose
+        // weight is zero (keeps the loop free of 64-bit compares, so that all
+        // table reads of a thread are in flight together)
+        const uint32_t m = j0 >= n ? 0u : (n - j0 < TILE_V ? (uint32_t)(n - j0) : TILE_V);
         int32_t e[TILE_V];
-        if (j0 + TILE_V <= n) {
+        if (m == TILE_V) {
             const int4 *src = reinterpret_cast<const int4 *>(a.E + j0);
 #pragma unroll
             for (uint32_t v = 0; v < TILE_V / 4; ++v) {
@@ -769,15 +774,23 @@ __device__ __forceinline__ void post_body(const PostArgs &a) {
             }
         } else {
 #pragma unroll
-            for (uint32_t v = 0; v < TILE_V; ++v) e[v] = j0 + v < n ? a.E[j0 + v] : ref;
+            for (uint32_t v = 0; v < TILE_V; ++v) e[v] = v < m ? a.E[j0 + v] : ref + (int32_t)a.D;
         }
         uint64_t w[TILE_V];
         uint64_t local = 0;
+        if (a.w_const) {
 #pragma unroll
-        for (uint32_t v = 0; v < TILE_V; ++v) {
-            const uint32_t dd = (uint32_t)abs(e[v] - ref);
-            w[v] = j0 + v >= n ? 0ull : a.w_const ? a.w_const : (dd < a.D ? a.W[dd] : 0ull);
-            local += w[v];
+            for (uint32_t v = 0; v < TILE_V; ++v) {
+                w[v] = v < m ? a.w_const : 0ull;
+                local += w[v];
+            }
+        } else {
+#pragma unroll
+            for (uint32_t v = 0; v < TILE_V; ++v) {
+                const uint32_t dd = (uint32_t)abs(e[v] - ref);
+                w[v] = dd < a.D ? a.W[dd] : 0ull;
+                local += w[v];
+            }
         }
         uint64_t total;
         uint64_t run = carry + block_exclusive_scan<uint64_t>(local, scratch, &total);
@@ -951,16 +964,13 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
 
 // ---------------------------------------------------------------------------
 // Lattices beyond one workgroup's LDS.  A replica stays in HBM as L rows of L
-// bytes.  A half-sweep is one launch over (replica, tile of `rows` rows): the
-// workgroup copies its rows and the row above and below (periodic) into LDS,
-// updates the colour-c sites of its rows and writes them back.  Colour-c sites
-// only read colour 1-c neighbours, which no workgroup changes in this launch,
-// so the tiles of one launch are independent, and a workgroup may overwrite
-// the rows it read (whole dwords whose other-colour bytes are unchanged).  The
-// first half-sweep of a step reads its rows from the ancestor's replica in the
-// previous buffer (the copy of Sec. 2 step 2, fused).  Pair p = y*L/4 + x/4
-// uses the same Philox counters as in LDS, so the result is the same as for a
-// replica held in LDS.
+// bytes.  A launch runs a few half-sweeps over (replica, tile of `rows` rows):
+// the workgroup copies its rows and the rows around them (periodic) into LDS,
+// updates them and writes its own rows to the other buffer, so the tiles of
+// one launch are independent.  The first launch of a step reads its rows from
+// the ancestor's replica in the previous population (the copy of Sec. 2 step
+// 2, fused).  Pair p = y*L/4 + x/4 uses the same Philox counters as in LDS,
+// so the result is the same as for a replica held in LDS.
 // ---------------------------------------------------------------------------
 // Workgroup -> (replica, tile): each XCD takes a contiguous range, so that
 // neighbouring tiles of a replica share their halo rows in one L2.
@@ -990,7 +1000,9 @@ __device__ __forceinline__ void load_tile_rows(uint32_t *lds32, const uint32_t *
 // launch updates the tile and halves-1-j rows on each side, so that the last
 // one leaves the tile exact.  The side rows are updated redundantly by the
 // neighbouring tiles too, with the same counters and hence the same results;
-// only the tile is written back.  halves = 0 copies.
+// only the tile is written back.  halves = 0 copies.  The launch must not
+// write the buffer it reads (neighbouring tiles would read rows already
+// advanced by this launch).
 template <bool QSMALL, bool T64>
 __global__ void __launch_bounds__(256) k_tiled_half(TiledArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];

@@ -1,7 +1,9 @@
 """Lattices beyond one workgroup's LDS (L > 256, tiled half-sweeps in HBM)
 against the CPU oracle through the C ABI: spins, energies, histograms,
 ancestors, magnetisation and widths bit-exact; FP64 estimators within 1e-12.
-Sizes span several row tiles with a ragged last tile, up to L = 4096."""
+Sizes span several row tiles with a ragged last tile, up to L = 4096; theta
+from 0 to 3 gives one to three tiled launches per step (each launch fuses two
+half-sweeps and alternates between two buffers)."""
 import numpy as np
 import pytest
 
@@ -44,11 +46,11 @@ CASES = [
     # 63-row tiles, the last one 8 rows
     dict(L=260, q=10, R=6, beta=linear_betas(1.5, 3), theta=2, seed=41, resample=0, bin_e=3),
     # q beyond the 7-bit fast path
-    dict(L=320, q=200, R=5, beta=linear_betas(2.0, 2), theta=2, seed=42, resample=1, bin_m=2),
+    dict(L=320, q=200, R=5, beta=linear_betas(2.0, 2), theta=3, seed=42, resample=1, bin_m=2),
     # heating from ground states
     dict(L=512, q=8, R=4, beta=linear_betas(3.0, 2)[::-1].copy(), theta=1, seed=43, resample=0, init=1),
     # resampling off
-    dict(L=1024, q=3, R=3, beta=linear_betas(1.0, 1), theta=1, seed=44, resample=2),
+    dict(L=1024, q=3, R=3, beta=linear_betas(1.0, 1), theta=2, seed=44, resample=2),
     # no sweeps: the step only copies the ancestors
     dict(L=272, q=6, R=7, beta=linear_betas(1.2, 3), theta=0, seed=45, resample=1),
 ]
