@@ -183,7 +183,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain lines")
     ap.add_argument("--serve-requests", type=int, default=32,
                     help="requests of the serving line (0 = skip)")
-    ap.add_argument("--cpu-steps", type=int, default=12,
+    ap.add_argument("--cpu-steps", type=int, default=50,
                     help="temperature steps of the oracle's CPU-baseline sample (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device-to-device three times (reference kernel of "
