@@ -1,6 +1,9 @@
 // pa_host.cpp -- host side of the population-annealing library: validation,
 // plan (population schedule, Metropolis thresholds, resampling weight tables),
-// workspace layout, the per-step launch sequence, and the C ABI of pa.h.
+// workspace layout, the per-step launch sequence (in-LDS or tiled sweeps),
+// batched runs and their HIP-graph replay, the serving loop (scheduler thread,
+// device arena, continuous batching), the host-only analysis calls, and the C
+// ABI of pa.h.
 //
 // The plan implements, on the host, the parts of Sec. 2 of arXiv:1704.01888
 // whose arithmetic must be bit-identical everywhere: the population sizes

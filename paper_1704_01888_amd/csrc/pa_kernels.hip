@@ -4,16 +4,21 @@
 //   k_sweep        : initial population (step 1 of Sec. 2) or, per step, the
 //                    gather of each new replica from its ancestor (eq. (1)) plus
 //                    theta checkerboard Metropolis sweeps (step 3) held in LDS,
-//                    then the energy of eq. (3) and the population histogram.
-//   k_post         : population sums for eq. (4), the reference energy and
-//                    ln Q of step 2 / eq. (2) in FP64, then the integer weights
-//                    W(|E_j - E_ref|) of the next resampling and their scan.
+//                    then the energy of eq. (3) (and M~ of eq. (5)) per replica.
+//   k_tiled_*      : the same for lattices beyond one workgroup's LDS, in HBM.
+//   k_post         : the energy (and M~) histograms from the per-replica values,
+//                    population sums for eq. (4), the reference energy and ln Q
+//                    of step 2 / eq. (2) in FP64, histogram widths (Sec. 4),
+//                    then the integer weights W(|E_j - E_ref|) of the next
+//                    resampling and their scan.
 //   k_sample       : the multinomial draws of the resampling step.
 //   k_countfill    : exclusive scan of the copy numbers -> ancestor of each new slot.
+//   *_batch        : the same for several runs in one launch.
 //
-// One replica lives inside one wavefront (G = 4..64 lanes of it), so the two
-// half-sweeps of a sweep need no workgroup barrier: LDS operations of a wave
-// execute in order, and a compiler fence keeps the half-sweeps apart.
+// A replica held in LDS is updated by G lanes: part of a wave (small L), one
+// wave, or several waves.  Within one wave the two half-sweeps of a sweep need
+// no workgroup barrier (LDS operations of a wave execute in order; a compiler
+// fence keeps the half-sweeps apart); a multi-wave replica uses barriers.
 #include "pa_device.h"
 
 namespace pa {
