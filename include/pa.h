@@ -85,7 +85,10 @@ enum {
 /* A PA run (Sec. 2): lattice L x L periodic (Sec. 3), q states, target
  * population R, inverse temperatures beta[0..K-1], theta sweeps per step. */
 typedef struct {
-    uint32_t L;          /* lattice side; this device path needs L % 4 == 0, 4 <= L <= 256 */
+    uint32_t L;          /* lattice side; this device path needs L % 4 == 0, 4 <= L <= 4096
+                            (L <= 256: one replica per workgroup in LDS; larger L: tiled
+                            half-sweeps with the replicas in HBM and a third population
+                            buffer in the workspace) */
     uint32_t q;          /* 2 <= q <= 255                                               */
     uint64_t R;          /* 1 <= R <= 2^31                                              */
     uint32_t K;          /* number of temperatures, K >= 1                              */
@@ -163,11 +166,12 @@ void pa_ctx_destroy(pa_ctx *ctx);
  * stream and report the summed durations in pa_result.kernel_ms. */
 pa_status pa_ctx_set_profiling(pa_ctx *ctx, int enable);
 
-/* Sweep kernel shape.  For L a power of two the sweep kernel exists for two
- * lane counts per replica (fewer than a wave: several replicas per wave; more
- * than a wave: one replica per workgroup); results do not depend on the
- * choice.  pa_ctx_get_lanes reports the lanes later runs will use and the
- * candidates; pa_ctx_set_lanes picks one (0 = default) for later runs.
+/* Sweep kernel shape.  For L a power of two up to 256 the sweep kernel exists
+ * for two lane counts per replica (fewer than a wave: several replicas per
+ * wave; more than a wave: one replica per workgroup); results do not depend
+ * on the choice.  pa_ctx_get_lanes reports the lanes later runs will use and
+ * the candidates (0 lanes and no candidates for the tiled path, L > 256);
+ * pa_ctx_set_lanes picks one (0 = default) for later runs.
  * pa_autotune times every candidate on a synthetic population of about 64 MB
  * (K = 3, theta = 4) in the caller's workspace (at least pa_plan's size for
  * it; 256 MB is enough for every L), keeps the fastest in the context and

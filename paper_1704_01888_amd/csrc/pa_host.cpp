@@ -672,9 +672,9 @@ pa_status pa_ctx_get_lanes(pa_ctx *ctx, uint32_t L, uint32_t *lanes, uint32_t *c
     if (!ctx) return fail(PA_ERR_INVALID, "null context");
     uint32_t cand[2] = {0, 0};
     const uint32_t n = pa::lane_candidates(L, cand);
-    uint32_t gl, wpb;
-    pa::sweep_shape(L, ctx_lanes(ctx, L), &gl, &wpb);
-    if (lanes) *lanes = 1u << gl;
+    uint32_t gl = 0, wpb;
+    if (!pa::tiled_path(L)) pa::sweep_shape(L, ctx_lanes(ctx, L), &gl, &wpb);
+    if (lanes) *lanes = pa::tiled_path(L) ? 0u : 1u << gl;
     if (candidates) { candidates[0] = cand[0]; candidates[1] = cand[1]; }
     if (n_candidates) *n_candidates = n;
     return PA_OK;

@@ -104,3 +104,43 @@ def test_batch_mixing_tiled_and_lds_runs(ctx):
     got = pa.pa_run_batch(ctx, descs)
     for c, d, g in zip(cases, descs, got):
         _compare(g, pa.pa_run(ctx, d))
+
+
+def test_tiled_runs_in_graphs_and_serving(ctx):
+    """A tiled run inside a replayed HIP graph and inside the serving loop
+    gives the results of pa_run."""
+    import torch
+    cases = [CASES[0], dict(L=16, q=8, R=300, beta=linear_betas(1.3, 3), theta=2, seed=49, resample=0)]
+    descs = [pa.Desc(outputs=pa.OUT_FINAL | pa.OUT_MAG, **c) for c in cases]
+    single = [pa.pa_run(ctx, d) for d in descs]
+    ws = torch.empty(pa.pa_plan_batch(descs), dtype=torch.uint8, device="cuda:0")
+    ctx.set_graphs(True)
+    try:
+        for rep in range(2):
+            for g, s in zip(pa.pa_run_batch(ctx, descs, workspace=ws), single):
+                _compare(g, s)
+            torch.cuda.synchronize()
+    finally:
+        ctx.set_graphs(False)
+    server = pa.Server(ctx, arena_bytes=256 << 20, max_slots=4)
+    try:
+        tickets = [server.submit(d) for d in descs]
+        for t, s in zip(tickets, single):
+            got, _ = server.wait(t)
+            _compare(got, s)
+    finally:
+        server.stop()
+
+
+def test_tiled_previous_population_is_kept(ctx):
+    """After a step the previous population (read_slots previous=True) is the
+    population before the step: the tiled launches never write it."""
+    kw = dict(L=320, q=6, R=6, beta=linear_betas(1.2, 2), theta=3, seed=50, resample=0)
+    run = pa.Run(ctx, pa.Desc(**kw))
+    before = run.read()["spins"]
+    run.advance(1)
+    slots = np.arange(before.shape[0], dtype=np.uint32)
+    assert (run.read_slots(slots, previous=True) == before).all()
+    run.finish()
+    cur, cand = ctx.get_lanes(512)
+    assert cur == 0 and cand == []
