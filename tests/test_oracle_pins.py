@@ -578,3 +578,19 @@ def test_width_maxima_first_argmax():
     beta = np.array([0.5, 1.0, 1.25, 2.0])
     i, w, T = oracle.width_maxima(beta, np.array([0.1, 0.4, 0.4, 0.2]))
     assert (i, w, T) == (1, 0.4, 1.0)
+
+
+@pytest.mark.parametrize("q", [6, 10])
+def test_oracle_free_energy_crossing_at_beta_t(q):
+    """Sec. 6 / Fig. 3 with the oracle alone: cooling from beta = 0 (ln Z = N ln q)
+    and heating from ground states at beta = 3 (eq. (6)-(8)) give -beta F curves
+    that cross within one grid step of the transition point ln(1 + sqrt q) of the
+    2D Potts model (16 x 16, R = 2000, dbeta = 0.02, theta = 5; the finite-size
+    shift at this size is below one step).  A wrong normalisation or sign in
+    eq. (2) or eq. (8) moves the crossing far away."""
+    n = 150
+    beta = np.array([3.0 * i / n for i in range(n + 1)])
+    c = oracle.run(oracle.Desc(16, q, 2000, beta, 5, 10 + q))
+    h = oracle.run(oracle.Desc(16, q, 2000, beta[::-1].copy(), 5, 20 + q, init=oracle.INIT_GROUND))
+    x = oracle.crossing(beta, c["minus_beta_F"], h["minus_beta_F"][::-1])
+    assert abs(x - math.log(1 + math.sqrt(q))) < 0.02
