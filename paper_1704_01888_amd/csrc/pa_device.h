@@ -25,7 +25,8 @@ struct SweepArgs {
     uint32_t theta;
     uint32_t mode;            // SweepMode
     uint32_t key0, key1;      // Philox key
-    uint32_t G_log2;          // log2 of lanes per replica (2..6)
+    uint32_t G;               // lanes per replica: a power of two up to 64 (several replicas
+                              // per wave) or a multiple of 64 (one replica per workgroup)
     uint32_t waves_per_block;
 };
 
@@ -117,7 +118,7 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 
 // Batched forms: several runs per launch.  Sweep launches group runs of one
 // kernel class (sweep_class); `start` [n+1] gives each run's first workgroup.
-uint32_t sweep_class(uint32_t L, uint32_t q, bool t64, uint32_t G_log2);
+uint32_t sweep_class(uint32_t L, uint32_t q, bool t64, uint32_t G);
 void *sweep_kernel(uint32_t cls, bool batch);
 hipError_t launch_sweep_batch(uint32_t cls, const SweepArgs *runs, const uint32_t *start, uint32_t n,
                               uint32_t blocks, uint32_t threads, size_t lds, hipStream_t s);
@@ -129,8 +130,12 @@ hipError_t launch_resample_batch(const SampleArgs *sruns, const uint32_t *start,
 uint32_t lane_candidates(uint32_t L, uint32_t *out /*[2]*/);
 // Lanes per replica (log2) and waves per block for a lattice side L; `lanes`
 // selects a candidate (anything else: the default).
-void sweep_shape(uint32_t L, uint32_t lanes, uint32_t *G_log2, uint32_t *waves_per_block);
-size_t sweep_lds_bytes(uint32_t N, uint32_t G_log2, uint32_t waves_per_block);
+void sweep_shape(uint32_t L, uint32_t lanes, uint32_t *G, uint32_t *waves_per_block);
+size_t sweep_lds_bytes(uint32_t N, uint32_t G, uint32_t waves_per_block);
+uint64_t replicas_per_block(uint32_t G, uint32_t waves_per_block);
+// index of L in the table of lattices with lane choices (-1: none), and its size
+int lane_choice_index(uint32_t L);
+constexpr int LANE_CHOICE_COUNT = 9;
 // Largest dynamic LDS a workgroup may use on the current device.
 size_t max_lds_per_block(int device);
 

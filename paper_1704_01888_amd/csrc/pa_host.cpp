@@ -273,7 +273,7 @@ struct GraphCache {
 struct pa_ctx {
     int device;
     int profiling;
-    uint32_t lanes[7];   // chosen lanes per replica for L = 4, 8, ..., 256 (0 = default)
+    uint32_t lanes[pa::LANE_CHOICE_COUNT];   // chosen lanes per replica per lattice with choices (0 = default)
     Server *server;
     int graphs;          // batched runs replay a captured HIP graph
     hipStream_t graph_stream;
@@ -282,9 +282,8 @@ struct pa_ctx {
 };
 
 static uint32_t ctx_lanes(const pa_ctx *c, uint32_t L) {
-    for (int i = 0; i < 7; ++i)
-        if (L == (4u << i)) return c ? c->lanes[i] : 0u;
-    return 0;
+    const int i = pa::lane_choice_index(L);
+    return (c && i >= 0) ? c->lanes[i] : 0u;
 }
 
 struct pa_run_state {
@@ -295,7 +294,7 @@ struct pa_run_state {
     uint32_t step;       // current step (population at beta_step)
     int cur;             // pop buffer holding the current population
     uint64_t R_cur, R_prev;
-    uint32_t G_log2, wpb;
+    uint32_t G, wpb;     // sweep shape: lanes per replica, waves per workgroup
     double mbF0;
     uint32_t first_step;  // step of the initial or loaded population
     uint64_t R_first;
@@ -424,7 +423,7 @@ pa::SweepArgs sweep_args(pa_run_state *r, uint32_t i, uint32_t mode, const uint8
     a.mode = mode;
     a.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
     a.key1 = (uint32_t)(p.desc.seed >> 32);
-    a.G_log2 = r->G_log2;
+    a.G = r->G;
     a.waves_per_block = r->wpb;
     return a;
 }
@@ -662,8 +661,7 @@ pa_status pa_ctx_set_lanes(pa_ctx *ctx, uint32_t L, uint32_t lanes) {
     if (n == 0) return fail(PA_ERR_INVALID, "no lane choices for this lattice side");
     if (lanes != 0 && lanes != cand[0] && !(n > 1 && lanes == cand[1]))
         return fail(PA_ERR_INVALID, "lanes is not a candidate for this lattice side");
-    for (int i = 0; i < 7; ++i)
-        if (L == (4u << i)) ctx->lanes[i] = lanes;
+    ctx->lanes[pa::lane_choice_index(L)] = lanes;
     return PA_OK;
 }
 
@@ -672,9 +670,9 @@ pa_status pa_ctx_get_lanes(pa_ctx *ctx, uint32_t L, uint32_t *lanes, uint32_t *c
     if (!ctx) return fail(PA_ERR_INVALID, "null context");
     uint32_t cand[2] = {0, 0};
     const uint32_t n = pa::lane_candidates(L, cand);
-    uint32_t gl = 0, wpb;
-    if (!pa::tiled_path(L)) pa::sweep_shape(L, ctx_lanes(ctx, L), &gl, &wpb);
-    if (lanes) *lanes = pa::tiled_path(L) ? 0u : 1u << gl;
+    uint32_t G = 0, wpb;
+    if (!pa::tiled_path(L)) pa::sweep_shape(L, ctx_lanes(ctx, L), &G, &wpb);
+    if (lanes) *lanes = G;
     if (candidates) { candidates[0] = cand[0]; candidates[1] = cand[1]; }
     if (n_candidates) *n_candidates = n;
     return PA_OK;
@@ -750,10 +748,10 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
     r->first_step = 0;
     r->R_first = p.desc.R;
     r->broken = false;
-    r->G_log2 = 0;
+    r->G = 0;
     r->wpb = 0;
-    if (!p.tiled) pa::sweep_shape(p.desc.L, ctx_lanes(ctx, p.desc.L), &r->G_log2, &r->wpb);
-    if (!p.tiled && pa::sweep_lds_bytes(p.N, r->G_log2, r->wpb) > pa::max_lds_per_block(ctx->device)) {
+    if (!p.tiled) pa::sweep_shape(p.desc.L, ctx_lanes(ctx, p.desc.L), &r->G, &r->wpb);
+    if (!p.tiled && pa::sweep_lds_bytes(p.N, r->G, r->wpb) > pa::max_lds_per_block(ctx->device)) {
         delete r;
         return fail(PA_ERR_UNSUPPORTED, "lattice does not fit the LDS of one workgroup on this device");
     }
@@ -1031,12 +1029,12 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
         }
         pa::SweepArgs a = sweep_args(r, g, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[prev_buf]), anc,
                                      r->at<uint8_t>(p.off_pop[new_buf]), p.desc.theta);
-        const uint64_t per_block = (64u * r->wpb) >> r->G_log2;
+        const uint64_t per_block = pa::replicas_per_block(r->G, r->wpb);
         SW e;
-        e.cls = pa::sweep_class(p.desc.L, p.desc.q, a.T[3] == 0, r->G_log2);
+        e.cls = pa::sweep_class(p.desc.L, p.desc.q, a.T[3] == 0, r->G);
         e.blocks = (uint32_t)((R_new + per_block - 1) / per_block);
         e.threads = 64u * r->wpb;
-        e.lds = pa::sweep_lds_bytes(p.N, r->G_log2, r->wpb);
+        e.lds = pa::sweep_lds_bytes(p.N, r->G, r->wpb);
         e.a = a;
         sw.push_back(e);
         r->cur = new_buf;
@@ -1185,7 +1183,7 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
             key.append((const char *)descs[r].beta, sizeof(double) * descs[r].K);
         key.append((const char *)&d_ws, sizeof d_ws);
         key.append((const char *)&ws_bytes, sizeof ws_bytes);
-        for (int i = 0; i < 7; ++i) key.append((const char *)&ctx->lanes[i], 4);
+        for (int i = 0; i < pa::LANE_CHOICE_COUNT; ++i) key.append((const char *)&ctx->lanes[i], 4);
         hipGraphExec_t exec = nullptr;
         for (auto &g : ctx->graph_cache)
             if (g.key == key) exec = g.exec;

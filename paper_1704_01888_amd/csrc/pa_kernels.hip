@@ -342,7 +342,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     extern __shared__ __align__(16) uint8_t smem[];
     // thresholds indexed by dE + 4
     if (threadIdx.x == 32) reinterpret_cast<uint32_t *>(smem)[24] = 0u;   // energy sum (multi-wave)
-    if (a.Mt_out && a.G_log2 > 6) {  // per-state counters of a multi-wave replica, after its rows
+    if (a.Mt_out && a.G > 64) {      // per-state counters of a multi-wave replica, after its rows
         uint32_t *mcnt = reinterpret_cast<uint32_t *>(smem + 128 + a.N + 2 * a.L);
         for (uint32_t t = threadIdx.x; t < a.q; t += blockDim.x) mcnt[t] = 0u;
     }
@@ -355,15 +355,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     __syncthreads();
     const Thresholds<T64> thr{smem};
 
-    const uint32_t G_log2 = a.G_log2;
-    const uint32_t G = 1u << G_log2;                             // lanes per replica
-    const bool multiwave = G > 64;
+    const uint32_t G = a.G;                                      // lanes per replica
+    const bool multiwave = G > 64;                               // one replica per block
     const uint32_t wave = threadIdx.x >> 6;
-    const uint32_t g = threadIdx.x & (G - 1u);
-    const uint32_t rpb = (64u * a.waves_per_block) >> G_log2;    // replicas per block
-    const uint32_t rep = threadIdx.x >> G_log2;                  // replica within block
+    const uint32_t g = multiwave ? threadIdx.x : (threadIdx.x & (G - 1u));
+    const uint32_t rpb = multiwave ? 1u : (64u * a.waves_per_block) / G;   // replicas per block
+    const uint32_t rep = multiwave ? 0u : threadIdx.x / G;                 // replica within block
     const uint64_t k64 = (uint64_t)block * rpb + rep;
-    const uint64_t first_in_wave = (uint64_t)block * rpb + ((wave * 64u) >> G_log2);
+    const uint64_t first_in_wave = multiwave ? (uint64_t)block : (uint64_t)block * rpb + (wave * 64u) / G;
     if (first_in_wave >= a.R_new) return;                        // whole wave (replica) idle
     const bool live = k64 < a.R_new;
     const uint32_t k = G >= 64 ? __builtin_amdgcn_readfirstlane((uint32_t)k64) : (uint32_t)k64;
@@ -1221,34 +1220,40 @@ __global__ void k_tiled_finalize(TiledArgs a) {
 
 // Lanes-per-replica candidates of the fixed-shape kernels (first = default,
 // chosen by measurement on MI355X; pa_autotune can pick the other).
-static const uint32_t kLaneChoices[7][2] = {
-    {4, 4},        // L = 4
-    {8, 4},        // L = 8
-    {16, 8},       // L = 16
-    {64, 32},      // L = 32
-    {64, 256},     // L = 64
-    {256, 512},    // L = 128
-    {1024, 512},   // L = 256
+// Lanes per replica that have a compile-time sweep kernel, per lattice side:
+// a lane owns one dword column, so the lanes are a multiple of L/4 and divide
+// the L*L/4 pairs.  The first entry is the default.
+struct LaneChoice { uint32_t L, lanes[2]; };
+static const LaneChoice kLaneChoices[LANE_CHOICE_COUNT] = {
+    {4, {4, 4}},
+    {8, {8, 4}},
+    {16, {16, 8}},
+    {32, {64, 32}},
+    {64, {64, 256}},
+    {96, {192, 384}},     // three or six waves per replica
+    {128, {256, 512}},
+    {192, {384, 768}},
+    {256, {1024, 512}},
 };
 
-static int pow2_index(uint32_t L) {
-    for (int i = 0; i < 7; ++i)
-        if (L == (4u << i)) return i;
+int lane_choice_index(uint32_t L) {
+    for (int i = 0; i < LANE_CHOICE_COUNT; ++i)
+        if (kLaneChoices[i].L == L) return i;
     return -1;
 }
 
 uint32_t lane_candidates(uint32_t L, uint32_t *out) {
-    const int i = pow2_index(L);
+    const int i = lane_choice_index(L);
     if (i < 0) return 0;
-    out[0] = kLaneChoices[i][0];
-    if (kLaneChoices[i][1] == kLaneChoices[i][0]) return 1;
-    out[1] = kLaneChoices[i][1];
+    out[0] = kLaneChoices[i].lanes[0];
+    if (kLaneChoices[i].lanes[1] == kLaneChoices[i].lanes[0]) return 1;
+    out[1] = kLaneChoices[i].lanes[1];
     return 2;
 }
 
-void sweep_shape(uint32_t L, uint32_t lanes, uint32_t *G_log2, uint32_t *waves_per_block) {
+void sweep_shape(uint32_t L, uint32_t lanes, uint32_t *G_out, uint32_t *waves_per_block) {
     uint32_t G = 0;
-    if (pow2_index(L) >= 0) {
+    if (lane_choice_index(L) >= 0) {
         uint32_t cand[2];
         const uint32_t n = lane_candidates(L, cand);
         G = cand[0];
@@ -1261,25 +1266,27 @@ void sweep_shape(uint32_t L, uint32_t lanes, uint32_t *G_log2, uint32_t *waves_p
         else if (L >= 96) G = 128;
         else { G = 4; while (G < 64 && 2 * G <= (L * L) / 4u) G *= 2; }
     }
-    uint32_t gl = 0;
-    while ((1u << gl) < G) ++gl;
-    *G_log2 = gl;
-    if (gl > 6) {                      // one replica per workgroup of G/64 waves
-        *waves_per_block = 1u << (gl - 6);
+    *G_out = G;
+    if (G > 64) {                      // one replica per workgroup of G/64 waves
+        *waves_per_block = G / 64;
         return;
     }
     const uint32_t N = L * L;
-    const uint32_t rpw = 64u >> gl;
+    const uint32_t rpw = 64u / G;
     uint32_t wpb = 4;
     while (wpb > 1 && (size_t)wpb * rpw * (N + 2 * L) > 32768u) wpb >>= 1;
     *waves_per_block = wpb;
 }
 
-size_t sweep_lds_bytes(uint32_t N, uint32_t G_log2, uint32_t waves_per_block) {
+uint64_t replicas_per_block(uint32_t G, uint32_t waves_per_block) {
+    return G > 64 ? 1u : (64u * waves_per_block) / G;
+}
+
+size_t sweep_lds_bytes(uint32_t N, uint32_t G, uint32_t waves_per_block) {
     uint32_t L = 0;
     while (L * L < N) ++L;
     // a multi-wave replica also keeps its 255 per-state counters (eq. (5)) in LDS
-    return 128u + (size_t)((64u * waves_per_block) >> G_log2) * (N + 2 * L) + (G_log2 > 6 ? 1024u : 0u);
+    return 128u + (size_t)replicas_per_block(G, waves_per_block) * (N + 2 * L) + (G > 64 ? 1024u : 0u);
 }
 
 size_t max_lds_per_block(int device) {
@@ -1290,11 +1297,11 @@ size_t max_lds_per_block(int device) {
 }
 
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t s) {
-    const uint64_t per_block = (64u * a.waves_per_block) >> a.G_log2;   // replicas per block
+    const uint64_t per_block = replicas_per_block(a.G, a.waves_per_block);
     const uint64_t blocks = (a.R_new + per_block - 1) / per_block;
     if (blocks == 0) return hipSuccess;
-    const size_t lds = sweep_lds_bytes(a.N, a.G_log2, a.waves_per_block);
-    void *kern = sweep_kernel(sweep_class(a.L, a.q, a.T[3] == 0, a.G_log2), false);
+    const size_t lds = sweep_lds_bytes(a.N, a.G, a.waves_per_block);
+    void *kern = sweep_kernel(sweep_class(a.L, a.q, a.T[3] == 0, a.G), false);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -1317,14 +1324,14 @@ hipError_t launch_resample(const SampleArgs &a, const SlotmapArgs &m, hipStream_
 }
 
 // Kernel class: lattice side, lanes per replica, q <= 128, 64-bit thresholds.
-uint32_t sweep_class(uint32_t L, uint32_t q, bool t64, uint32_t G_log2) {
-    return (L << 8) | (G_log2 << 2) | ((q <= 128) ? 2u : 0u) | (t64 ? 1u : 0u);
+uint32_t sweep_class(uint32_t L, uint32_t q, bool t64, uint32_t G) {
+    return (L << 16) | (G << 2) | ((q <= 128) ? 2u : 0u) | (t64 ? 1u : 0u);
 }
 
 // The instance for a class: fixed-shape when L is a power of two with a
 // candidate lane count and the 32-bit threshold form applies, else generic.
 void *sweep_kernel(uint32_t cls, bool batch) {
-    const uint32_t L = cls >> 8, G = 1u << ((cls >> 2) & 63u);
+    const uint32_t L = cls >> 16, G = (cls >> 2) & 0x3FFFu;
     const bool qs = (cls & 2u) != 0, t64 = (cls & 1u) != 0;
 #define PA_INST(LV, GV)                                                                       \
     if (L == LV && G == GV)                                                                   \
@@ -1336,7 +1343,9 @@ void *sweep_kernel(uint32_t cls, bool batch) {
         PA_INST(16, 16) PA_INST(16, 8)
         PA_INST(32, 64) PA_INST(32, 32)
         PA_INST(64, 64) PA_INST(64, 256)
+        PA_INST(96, 192) PA_INST(96, 384)
         PA_INST(128, 256) PA_INST(128, 512)
+        PA_INST(192, 384) PA_INST(192, 768)
         PA_INST(256, 1024) PA_INST(256, 512)
     }
 #undef PA_INST
