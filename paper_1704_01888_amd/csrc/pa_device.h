@@ -135,7 +135,7 @@ size_t sweep_lds_bytes(uint32_t N, uint32_t G, uint32_t waves_per_block);
 uint64_t replicas_per_block(uint32_t G, uint32_t waves_per_block);
 // index of L in the table of lattices with lane choices (-1: none), and its size
 int lane_choice_index(uint32_t L);
-constexpr int LANE_CHOICE_COUNT = 9;
+constexpr int LANE_CHOICE_COUNT = 10;
 // Largest dynamic LDS a workgroup may use on the current device.
 size_t max_lds_per_block(int device);
 

@@ -248,8 +248,9 @@ __device__ __forceinline__ void sweeps_fixed(uint32_t *lds32, uint32_t g, uint32
     constexpr uint32_t L = LT, N = L * L, P = N / 4, DPR = L / 4;
     constexpr uint32_t G = GT;
     constexpr uint32_t PPL = P / G, RS = G / DPR;
-    constexpr uint32_t UNR = PPL >= 2 ? 2 : 1;
+    constexpr uint32_t UNR = PPL % 2 == 0 ? 2 : (PPL % 3 == 0 ? 3 : 1);   // pairs interleaved
     static_assert(G % DPR == 0 && P % G == 0 && PPL % UNR == 0, "shape");
+    static_assert(PPL == UNR || (RS * UNR) % 2 == 0, "slot parity must not change between iterations");
     const uint32_t xd = g % DPR, y0 = g / DPR;
     const int32_t dl = xd == 0 ? (int32_t)(DPR - 1) : -1;
     const int32_t dr = xd == DPR - 1 ? -(int32_t)(DPR - 1) : 1;
@@ -262,7 +263,7 @@ __device__ __forceinline__ void sweeps_fixed(uint32_t *lds32, uint32_t g, uint32
         for (uint32_t c = 0; c < 2u; ++c) {
             const SweepKey key = sweep_key(k, a.step, (DOM_SWEEP << 28) | (t << 1) | c, a.key0, a.key1);
             // parity of unrolled slot u (j is a multiple of UNR, and RS * UNR is even
-            // unless PPL == 1)
+            // unless there is a single iteration)
             PairSel ps[UNR];
             int32_t dx[UNR];
 #pragma unroll
@@ -1229,6 +1230,7 @@ static const LaneChoice kLaneChoices[LANE_CHOICE_COUNT] = {
     {8, {8, 4}},
     {16, {16, 8}},
     {32, {64, 32}},
+    {48, {192, 192}},     // three waves per replica
     {64, {64, 256}},
     {96, {192, 384}},     // three or six waves per replica
     {128, {256, 512}},
@@ -1342,6 +1344,7 @@ void *sweep_kernel(uint32_t cls, bool batch) {
         PA_INST(8, 8) PA_INST(8, 4)
         PA_INST(16, 16) PA_INST(16, 8)
         PA_INST(32, 64) PA_INST(32, 32)
+        PA_INST(48, 192)
         PA_INST(64, 64) PA_INST(64, 256)
         PA_INST(96, 192) PA_INST(96, 384)
         PA_INST(128, 256) PA_INST(128, 512)

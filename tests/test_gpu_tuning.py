@@ -19,7 +19,7 @@ def ctx():
 
 CASES = {
     4: dict(R=300, q=3), 8: dict(R=500, q=8), 16: dict(R=300, q=10), 32: dict(R=120, q=6),
-    64: dict(R=40, q=20), 96: dict(R=20, q=8), 128: dict(R=9, q=10), 192: dict(R=5, q=6),
+    48: dict(R=60, q=5), 64: dict(R=40, q=20), 96: dict(R=20, q=8), 128: dict(R=9, q=10), 192: dict(R=5, q=6),
     256: dict(R=3, q=200),
 }
 
