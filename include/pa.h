@@ -77,9 +77,11 @@ enum {
                           PA_OUT_MAG, M~ histograms [K][N+1])              */
     PA_OUT_MAG = 2,    /* magnetisation, eq. (4)-(5): sum of M~ and M-bar   */
     PA_OUT_FINAL = 4,  /* final population, energies and last ancestors  */
-    PA_OUT_WIDTHS = 8  /* full width at half maximum of the energy histogram
+    PA_OUT_WIDTHS = 8, /* full width at half maximum of the energy histogram
                           (and, with PA_OUT_MAG, of the magnetisation
                           histogram) at every step, Sec. 4              */
+    PA_OUT_DIGEST = 16 /* a 64-bit digest of the whole population at every
+                          step (see pa_result.digest)                   */
 };
 
 /* A PA run (Sec. 2): lattice L x L periodic (Sec. 3), q states, target
@@ -125,6 +127,11 @@ typedef struct {
     uint32_t *mhist;         /* [K][N+1], #{j: M~_j = m}; PA_OUT_MAG with PA_OUT_HIST */
     double   *width_e;       /* PA_OUT_WIDTHS: FWHM of the histogram of e = E/N       */
     double   *width_m;       /* PA_OUT_WIDTHS with PA_OUT_MAG: FWHM of the histogram of m = M/N */
+    uint64_t *digest;        /* PA_OUT_DIGEST: sum over slots k < R_i and dwords n < N/4 of
+                                r * d mod 2^64, d = spins 4n..4n+3 of slot k (little endian),
+                                r = (w1 << 32 | w0) | 1 with w = Philox(n, k, i, 5 << 28);
+                                equal populations in equal slots give equal digests, and any
+                                single changed dword changes the digest              */
     uint8_t  *final_spins;   /* [R_{K-1}][N]; NULL unless PA_OUT_FINAL              */
     int32_t  *final_E;       /* [R_{K-1}];     NULL unless PA_OUT_FINAL              */
     uint32_t *last_anc;      /* [R_{K-1}] ancestors of the last resampling (identity if K == 1) */

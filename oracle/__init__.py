@@ -52,7 +52,7 @@ class _Result(ctypes.Structure):
         ("R_i", ctypes.c_void_p), ("E_sum", ctypes.c_void_p), ("E_mean", ctypes.c_void_p),
         ("lnQ", ctypes.c_void_p), ("minus_beta_F", ctypes.c_void_p),
         ("M_mean", ctypes.c_void_p), ("Mt_sum", ctypes.c_void_p), ("mhist", ctypes.c_void_p),
-        ("width_e", ctypes.c_void_p), ("width_m", ctypes.c_void_p),
+        ("width_e", ctypes.c_void_p), ("width_m", ctypes.c_void_p), ("digest", ctypes.c_void_p),
         ("hist", ctypes.c_void_p),
         ("final_spins", ctypes.c_void_p), ("final_E", ctypes.c_void_p),
         ("last_anc", ctypes.c_void_p), ("n_threads", ctypes.c_int),
@@ -91,6 +91,8 @@ def lib():
         L.orc_fwhm.argtypes = [vp, u32, u32]
         L.orc_fwhm.restype = dbl
         L.orc_width_maxima.argtypes = [vp, vp, u32, vp, vp, vp]
+        L.orc_digest.argtypes = [ctypes.POINTER(_Desc), u32, vp, u64]
+        L.orc_digest.restype = u64
         L.orc_crossing.argtypes = [vp, vp, vp, u32, vp]
         L.orc_run.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_Result)]
         L.orc_step.argtypes = [ctypes.POINTER(_Desc), u32, u32, vp, vp, u64, u64, vp, vp, vp]
@@ -234,6 +236,12 @@ def fwhm(h: np.ndarray, B: int = 1) -> float:
     return float(lib().orc_fwhm(_ptr(hh), len(hh), int(B)))
 
 
+def digest(d: Desc, i: int, spins: np.ndarray) -> int:
+    """Digest of the population `spins` [R][N] at step i (orc_digest)."""
+    s = np.ascontiguousarray(spins, dtype=np.uint8)
+    return int(lib().orc_digest(ctypes.byref(d.c()), int(i), _ptr(s), s.shape[0]))
+
+
 def width_maxima(beta, width):
     b = np.ascontiguousarray(beta, dtype=np.float64)
     w = np.ascontiguousarray(width, dtype=np.float64)
@@ -253,7 +261,7 @@ def crossing(beta, f_cool, f_heat):
     return float(x[0])
 
 
-def run(d: Desc, hist=False, final=False, magnetisation=False, widths=False):
+def run(d: Desc, hist=False, final=False, magnetisation=False, widths=False, digest=False):
     """Whole PA run; returns a dict of numpy arrays."""
     R_sched, R_cap, Kb = plan(d)
     K, N = d.K, d.N
@@ -271,6 +279,9 @@ def run(d: Desc, hist=False, final=False, magnetisation=False, widths=False):
         res.M_mean = _ptr(out["M_mean"])
         res.Mt_sum = _ptr(out["Mt_sum"])
         res.mhist = _ptr(out["mhist"])
+    if digest:
+        out["digest"] = np.zeros(K, dtype=np.uint64)
+        res.digest = _ptr(out["digest"])
     if widths:
         out["width_e"] = np.zeros(K)
         res.width_e = _ptr(out["width_e"])

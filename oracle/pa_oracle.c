@@ -470,6 +470,29 @@ double orc_fwhm(const uint32_t *h, uint32_t nb, uint32_t B)
     return width;
 }
 
+uint64_t orc_digest(const orc_desc *d, uint32_t i, const uint8_t *spins, uint64_t R)
+{
+    uint32_t N = d->L * d->L;
+    uint32_t key[2] = {(uint32_t)(d->seed & 0xffffffffu), (uint32_t)(d->seed >> 32)};
+    uint64_t sum = 0;
+    int64_t nk = (int64_t)R;
+    /* a sum modulo 2^64: the order of the terms does not matter */
+#pragma omp parallel for reduction(+ : sum) schedule(static)
+    for (int64_t k = 0; k < nk; ++k) {
+        const uint8_t *s = spins + (uint64_t)k * N;
+        for (uint32_t n = 0; n < N / 4; ++n) {
+            uint32_t ctr[4] = {n, (uint32_t)k, i, (uint32_t)ORC_DOM_DIGEST << 28};
+            uint32_t w[4];
+            orc_philox4x32_10(ctr, key, w);
+            uint64_t r = (((uint64_t)w[1] << 32) | (uint64_t)w[0]) | 1u;
+            uint64_t dw = (uint64_t)s[4 * n] | ((uint64_t)s[4 * n + 1] << 8) |
+                          ((uint64_t)s[4 * n + 2] << 16) | ((uint64_t)s[4 * n + 3] << 24);
+            sum += r * dw;
+        }
+    }
+    return sum;
+}
+
 int orc_width_maxima(const double *beta, const double *width, uint32_t K, uint32_t *i_max,
                      double *w_max, double *T_max)
 {
@@ -513,6 +536,7 @@ static void observe(const orc_desc *d, uint32_t i, const uint8_t *spins, const i
     for (uint64_t k = 0; k < R_i; ++k) sum += E[k];
     out->R_i[i] = R_i;
     out->E_sum[i] = sum;
+    if (out->digest) out->digest[i] = orc_digest(d, i, spins, R_i);
     /* eq. (4): population average. */
     out->E_mean[i] = (double)sum / (double)R_i;
     uint32_t *eh = out->hist ? out->hist + (uint64_t)i * (2 * N + 1)

@@ -31,7 +31,7 @@ enum { ORC_OK = 0, ORC_ERR_INVALID = -1, ORC_ERR_NOMEM = -2, ORC_ERR_CAPACITY = 
 
 /* Philox counter word 3 carries a domain tag in its top four bits. */
 enum { ORC_DOM_INIT = 0, ORC_DOM_SWEEP = 1, ORC_DOM_RESAMPLE = 2, ORC_DOM_PLAN = 3,
-       ORC_DOM_GROUND = 4 };
+       ORC_DOM_GROUND = 4, ORC_DOM_DIGEST = 5 };
 
 typedef struct {
     uint32_t L, q;         /* lattice side (even, >= 2) and number of Potts states      */
@@ -80,6 +80,13 @@ uint32_t orc_mtilde(uint32_t L, uint32_t q, const uint8_t *s);
  * ends; the width is B times the distance between its outermost crossings of
  * half the largest count.  Returns 0 for an empty histogram. */
 double orc_fwhm(const uint32_t *h, uint32_t nb, uint32_t B);
+
+/* Digest of a population at step i: the sum, modulo 2^64, over slots k < R
+ * and dwords n < N/4 of r * d, where d packs spins 4n..4n+3 of slot k
+ * (little endian) and r = (w1 << 32 | w0) | 1 with w = Philox(n, k, i,
+ * DIGEST << 28).  A checksum for comparing whole populations, not part of
+ * the method. */
+uint64_t orc_digest(const orc_desc *d, uint32_t i, const uint8_t *spins, uint64_t R);
 
 /* Largest width along a run (Sec. 4, Tables I-III): first index of the
  * maximum of width[0..K), its value and T = 1/beta there. */
@@ -130,6 +137,7 @@ typedef struct {
     uint32_t *mhist;        /* [K][N+1] histogram of M~, or NULL                */
     double   *width_e;      /* FWHM of the histogram of e = E/N (Sec. 4), or NULL */
     double   *width_m;      /* FWHM of the histogram of m = M/N (Sec. 4), or NULL */
+    uint64_t *digest;       /* population digest at each step (orc_digest), or NULL */
     uint32_t *hist;         /* [K][2N+1] energy histogram, or NULL              */
     uint8_t  *final_spins;  /* [R_{K-1}][N], or NULL                            */
     int32_t  *final_E;      /* [R_{K-1}], or NULL                               */

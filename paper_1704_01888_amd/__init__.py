@@ -20,7 +20,7 @@ PA_OK, PA_ERR_INVALID, PA_ERR_NOMEM, PA_ERR_DEVICE, PA_ERR_CAPACITY, PA_ERR_UNSU
     0, -1, -2, -3, -4, -5
 RESAMPLE_POISSON, RESAMPLE_MULTINOMIAL, RESAMPLE_NONE = 0, 1, 2
 INIT_RANDOM, INIT_GROUND = 0, 1
-OUT_HIST, OUT_MAG, OUT_FINAL, OUT_WIDTHS = 1, 2, 4, 8
+OUT_HIST, OUT_MAG, OUT_FINAL, OUT_WIDTHS, OUT_DIGEST = 1, 2, 4, 8, 16
 KERNEL_NAMES = ("init", "sweep", "post", "resample")
 
 EXPORTS = [
@@ -57,7 +57,7 @@ class Result(ctypes.Structure):
         ("R_i", ctypes.c_void_p), ("E_sum", ctypes.c_void_p), ("E_mean", ctypes.c_void_p),
         ("lnQ", ctypes.c_void_p), ("minus_beta_F", ctypes.c_void_p), ("hist", ctypes.c_void_p),
         ("Mt_sum", ctypes.c_void_p), ("M_mean", ctypes.c_void_p), ("mhist", ctypes.c_void_p),
-        ("width_e", ctypes.c_void_p), ("width_m", ctypes.c_void_p),
+        ("width_e", ctypes.c_void_p), ("width_m", ctypes.c_void_p), ("digest", ctypes.c_void_p),
         ("final_spins", ctypes.c_void_p), ("final_E", ctypes.c_void_p),
         ("last_anc", ctypes.c_void_p), ("kernel_ms", ctypes.c_void_p),
         ("kernel_launches", ctypes.c_void_p),
@@ -305,6 +305,9 @@ def _alloc_result(desc: Desc, info: PlanInfo):
         if desc.outputs & OUT_MAG:
             out["width_m"] = np.zeros(K)
             res.width_m = _ptr(out["width_m"])
+    if desc.outputs & OUT_DIGEST:
+        out["digest"] = np.zeros(K, np.uint64)
+        res.digest = _ptr(out["digest"])
     if desc.outputs & OUT_FINAL:
         RF = int(info.R_final)
         out["final_spins"] = np.zeros((RF, N), np.uint8)

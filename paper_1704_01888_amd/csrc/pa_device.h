@@ -10,7 +10,8 @@ namespace pa {
 enum SweepMode : uint32_t { SWEEP_UPDATE = 0, SWEEP_INIT_RANDOM = 1, SWEEP_INIT_GROUND = 2 };
 
 // Philox domain tags (counter word 3, bits 28..31).
-enum : uint32_t { DOM_INIT = 0, DOM_SWEEP = 1, DOM_RESAMPLE = 2, DOM_PLAN = 3, DOM_GROUND = 4 };
+enum : uint32_t { DOM_INIT = 0, DOM_SWEEP = 1, DOM_RESAMPLE = 2, DOM_PLAN = 3, DOM_GROUND = 4,
+                  DOM_DIGEST = 5 };
 
 struct SweepArgs {
     const uint8_t *old_pop;   // [R_prev][N] (UPDATE mode)
@@ -18,6 +19,7 @@ struct SweepArgs {
     uint8_t *new_pop;         // [R_new][N]
     int32_t *E_out;           // [R_new]
     uint32_t *Mt_out;         // [R_new] M~ of eq. (5), or nullptr
+    uint64_t *H_out;          // [R_new] digest term of each replica, or nullptr
     uint64_t T[4];            // thresholds for dE = 1..4 (<= 2^32)
     uint32_t L, q, N;
     uint32_t R_new;
@@ -57,6 +59,8 @@ struct PostArgs {
     uint64_t *C;              // [R_i] inclusive prefix sums
     // magnetisation (eq. (4)-(5)) and histogram widths of step i
     const uint32_t *Mt;       // [R_i] M~ of the population at step i, or nullptr
+    const uint64_t *H;        // [R_i] digest terms of the population, or nullptr
+    uint64_t *digest;         // [K]
     uint32_t *mhist;          // [N+1] M~ histogram of step i (output / work area)
     uint32_t q, N;
     int64_t *Mt_sum;          // [K]
@@ -99,6 +103,8 @@ struct TiledArgs {
     uint32_t init;            // k_tiled_init: SWEEP_INIT_RANDOM or SWEEP_INIT_GROUND
     uint32_t *bonds;          // [R] equal-neighbour bond counts (measure; zero on entry)
     uint32_t *cnt;            // [R][q] per-state site counts, or nullptr (zero on entry)
+    uint64_t *Hacc;           // [R] digest sums of the tiles, or nullptr (zero on entry)
+    uint64_t *H_out;          // [R] digest term of each replica, or nullptr
     int32_t *E_out;           // [R]
     uint32_t *Mt_out;         // [R] or nullptr
 };

@@ -116,12 +116,12 @@ struct Plan {
     std::vector<uint32_t> D;              // [n_tables] length of table t
     std::vector<double> abs_dbeta;        // [n_tables]
     uint32_t n_tables = 0;
-    bool hist_all = false, mag = false, widths = false;
+    bool hist_all = false, mag = false, widths = false, digest = false;
     uint32_t bin_e = 1, bin_m = 1;
     // workspace layout
     size_t off_pop[2], off_E, off_C, off_r, off_anc, off_counts, off_hist, off_Esum, off_Emean,
         off_count, off_lnQ, off_mbF, off_Eref, off_W, off_mhist, off_Mt, off_Mtsum,
-        off_Mmean, off_we, off_wm, off_bonds, off_cnt, off_pop_x, total;
+        off_Mmean, off_we, off_wm, off_bonds, off_cnt, off_pop_x, off_H, off_Hacc, off_digest, total;
     bool tiled = false;   // replicas beyond one workgroup's LDS: tiled half-sweeps in HBM
 };
 
@@ -139,7 +139,7 @@ pa_status validate(const pa_run_desc *d) {
             return fail(PA_ERR_INVALID, "beta must be finite and >= 0");
     if (d->init == PA_INIT_RANDOM && d->beta[0] != 0.0)
         return fail(PA_ERR_INVALID, "a random initial population needs beta[0] == 0");
-    if (d->outputs & ~(uint32_t)(PA_OUT_HIST | PA_OUT_MAG | PA_OUT_FINAL | PA_OUT_WIDTHS))
+    if (d->outputs & ~(uint32_t)(PA_OUT_HIST | PA_OUT_MAG | PA_OUT_FINAL | PA_OUT_WIDTHS | PA_OUT_DIGEST))
         return fail(PA_ERR_INVALID, "unknown output bits");
     if (d->bin_e > 2 * d->L * d->L + 1 || d->bin_m > d->L * d->L + 1)
         return fail(PA_ERR_INVALID, "histogram bin wider than the histogram");
@@ -228,6 +228,7 @@ pa_status build_plan(const pa_run_desc *d, Plan &p) {
     p.hist_all = (d->outputs & PA_OUT_HIST) != 0;
     p.mag = (d->outputs & PA_OUT_MAG) != 0;
     p.widths = (d->outputs & PA_OUT_WIDTHS) != 0;
+    p.digest = (d->outputs & PA_OUT_DIGEST) != 0;
     p.bin_e = d->bin_e ? d->bin_e : 1u;
     p.bin_m = d->bin_m ? d->bin_m : 1u;
     size_t o = 0;
@@ -257,6 +258,9 @@ pa_status build_plan(const pa_run_desc *d, Plan &p) {
     p.off_bonds = o; o += p.tiled ? align256(4 * p.R_cap) : 0;
     p.off_cnt = o; o += (p.tiled && p.mag) ? align256((size_t)4 * p.R_cap * d->q) : 0;
     p.off_pop_x = o; o += p.tiled ? popb : 0;   // third population buffer of the tiled sweeps
+    p.off_H = o; o += p.digest ? align256(8 * p.R_cap) : 0;
+    p.off_Hacc = o; o += (p.digest && p.tiled) ? align256(8 * p.R_cap) : 0;
+    p.off_digest = o; o += p.digest ? align256(8 * (size_t)K) : 0;
     p.total = o;
     return PA_OK;
 }
@@ -386,6 +390,8 @@ pa::PostArgs post_args(pa_run_state *r, uint32_t i) {
     s.w_const = p.abs_dbeta[tab] == 0.0 ? (1ull << p.Kb) : 0ull;
     s.C = r->at<uint64_t>(p.off_C);
     s.Mt = p.mag ? r->at<uint32_t>(p.off_Mt) : nullptr;
+    s.H = p.digest ? r->at<uint64_t>(p.off_H) : nullptr;
+    s.digest = p.digest ? r->at<uint64_t>(p.off_digest) : nullptr;
     s.mhist = mhist_of(r, i);
     s.q = p.desc.q;
     s.N = p.N;
@@ -413,6 +419,7 @@ pa::SweepArgs sweep_args(pa_run_state *r, uint32_t i, uint32_t mode, const uint8
     a.new_pop = new_pop;
     a.E_out = r->at<int32_t>(p.off_E);
     a.Mt_out = p.mag ? r->at<uint32_t>(p.off_Mt) : nullptr;
+    a.H_out = p.digest ? r->at<uint64_t>(p.off_H) : nullptr;
     for (int d = 0; d < 4; ++d) a.T[d] = p.T[(size_t)i * 4 + d];
     a.L = p.desc.L;
     a.q = p.desc.q;
@@ -449,6 +456,8 @@ pa::TiledArgs tiled_args(pa_run_state *r, uint32_t i, const uint8_t *src, const 
     a.init = p.desc.init == PA_INIT_GROUND ? pa::SWEEP_INIT_GROUND : pa::SWEEP_INIT_RANDOM;
     a.bonds = r->at<uint32_t>(p.off_bonds);
     a.cnt = p.mag ? r->at<uint32_t>(p.off_cnt) : nullptr;
+    a.Hacc = p.digest ? r->at<uint64_t>(p.off_Hacc) : nullptr;
+    a.H_out = p.digest ? r->at<uint64_t>(p.off_H) : nullptr;
     a.E_out = r->at<int32_t>(p.off_E);
     a.Mt_out = p.mag ? r->at<uint32_t>(p.off_Mt) : nullptr;
     return a;
@@ -774,7 +783,9 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
         (p.tiled &&
          (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_bonds), p.R_cap, 0u, s), "fill"))) ||
         (p.tiled && p.mag &&
-         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_cnt), p.R_cap * p.desc.q, 0u, s), "fill")))) {
+         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_cnt), p.R_cap * p.desc.q, 0u, s), "fill"))) ||
+        (p.tiled && p.digest &&
+         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_Hacc), 2 * p.R_cap, 0u, s), "fill")))) {
         delete r; return st;
     }
     // ln Z at beta_0: N ln q (Z = q^N at beta = 0, Sec. 6) or, for ground
@@ -924,6 +935,7 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
             {(p.mag && p.hist_all) ? out->mhist : nullptr, p.off_mhist, 4 * (size_t)K * (p.N + 1)},
             {p.widths ? out->width_e : nullptr, p.off_we, 8 * (size_t)K},
             {(p.widths && p.mag) ? out->width_m : nullptr, p.off_wm, 8 * (size_t)K},
+            {p.digest ? out->digest : nullptr, p.off_digest, 8 * (size_t)K},
         };
         for (auto &c : cp) {
             if (st || !c.dst) continue;

@@ -71,6 +71,12 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     return philox_from((uint64_t)PHILOX_M0 * c0, c1, c2, c3, k0, k1);
 }
 
+__device__ __forceinline__ uint64_t digest_term(uint32_t n, uint32_t k, uint32_t step, uint32_t d,
+                                                uint32_t key0, uint32_t key1) {
+    const uint4 w = philox(n, k, step, DOM_DIGEST << 28, key0, key1);
+    return ((((uint64_t)w.y << 32) | (uint64_t)w.x) | 1ull) * (uint64_t)d;
+}
+
 __device__ __forceinline__ uint32_t mulhi32(uint32_t w, uint32_t n) { return __umulhi(w, n); }
 
 // floor(w * n / 2^32) through the full 32x32->64 multiply: v_mad_u64_u32
@@ -85,6 +91,11 @@ __device__ __forceinline__ uint32_t mulhi32_wide(uint32_t w, uint32_t n) {
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
     return __builtin_amdgcn_perm(hi, lo, sel);   // byte sel 0-3 from lo, 4-7 from hi
 }
+
+// Digest term of one dword of a replica: r * d mod 2^64, r the 64-bit word of
+// Philox(n, k, step, DIGEST) made odd (so any change of d changes the term).
+__device__ __forceinline__ uint64_t digest_term(uint32_t n, uint32_t k, uint32_t step, uint32_t d,
+                                                uint32_t key0, uint32_t key1);
 
 // Number of equal bytes between two words.
 __device__ __forceinline__ uint32_t eq_bytes(uint32_t a, uint32_t b) {
@@ -343,6 +354,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     extern __shared__ __align__(16) uint8_t smem[];
     // thresholds indexed by dE + 4
     if (threadIdx.x == 32) reinterpret_cast<uint32_t *>(smem)[24] = 0u;   // energy sum (multi-wave)
+    if (threadIdx.x == 33) reinterpret_cast<uint64_t *>(smem)[13] = 0ull; // digest sum (multi-wave)
     if (a.Mt_out && a.G > 64) {      // per-state counters of a multi-wave replica, after its rows
         uint32_t *mcnt = reinterpret_cast<uint32_t *>(smem + 128 + a.N + 2 * a.L);
         for (uint32_t t = threadIdx.x; t < a.q; t += blockDim.x) mcnt[t] = 0u;
@@ -439,11 +451,24 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
             for (uint32_t st = 0; st < a.q; ++st) mt = max(mt, mcnt[st]);
         }
     }
+    // ---- digest term of the replica (order-free sum over its dwords)
+    uint64_t dig = 0;
+    if (a.H_out) {
+        for (uint32_t dd = g; dd < N / 4u; dd += G) dig += digest_term(dd, k, a.step, rows32[dd], a.key0, a.key1);
+        for (uint32_t off = (G < 64 ? G : 64) >> 1; off > 0; off >>= 1) dig += __shfl_xor(dig, off, 64);
+        if (multiwave) {
+            unsigned long long *sum = reinterpret_cast<unsigned long long *>(smem) + 13;
+            if ((threadIdx.x & 63u) == 0) atomicAdd(sum, (unsigned long long)dig);
+            __syncthreads();
+            dig = *sum;
+        }
+    }
     if (live) {
         if (g == 0) {
             const int32_t E = -(int32_t)bonds;
             a.E_out[k] = E;
             if (a.Mt_out) a.Mt_out[k] = mt;
+            if (a.H_out) a.H_out[k] = dig;
         }
         uint4 *gdst = reinterpret_cast<uint4 *>(a.new_pop + (size_t)k * N);
         const uint4 *lsrc = reinterpret_cast<const uint4 *>(rep_lds + L);
@@ -743,6 +768,14 @@ __device__ __forceinline__ void post_body(const PostArgs &a) {
     }
     __syncthreads();
 
+    if (a.H) {
+        // digest of the population: the sum of the replicas' terms
+        uint64_t dsum = 0;
+        for (uint64_t j = tid; j < a.R_i; j += blockDim.x) dsum += a.H[j];
+        dsum = block_reduce(dsum, [](uint64_t x, uint64_t y) { return x + y; }, scratch);
+        if (tid == 0) a.digest[a.step] = dsum;
+        __syncthreads();
+    }
     if (a.Mt) {
         // eq. (4)-(5): sum of M~ over the population, M-bar, the M~ histogram
         const HistBuild hm = build_hist(a.Mt, a.R_i, 0, a.N + 1, lds_hist, POST_LDS_BINS, a.mhist);
@@ -1181,6 +1214,14 @@ __global__ void __launch_bounds__(256) k_tiled_measure(TiledArgs a) {
     }
     bonds = wave_sum(bonds);
     if ((threadIdx.x & 63u) == 0) s_part[threadIdx.x >> 6] = bonds;
+    if (a.Hacc) {
+        uint64_t dig = 0;
+        for (uint32_t i = threadIdx.x; i < n * DPR; i += blockDim.x)
+            dig += digest_term(y0 * DPR + i, k, a.step, lds32[DPR + i], a.key0, a.key1);
+        dig = wave_sum(dig);
+        if ((threadIdx.x & 63u) == 0) atomicAdd(reinterpret_cast<unsigned long long *>(&a.Hacc[k]),
+                                                (unsigned long long)dig);
+    }
     if (a.cnt) {
         for (uint32_t st = 0; st < a.q; ++st) {
             const uint32_t pat = st * 0x01010101u;
@@ -1207,6 +1248,10 @@ __global__ void k_tiled_finalize(TiledArgs a) {
     if (k >= a.R) return;
     a.E_out[k] = -(int32_t)a.bonds[k];
     a.bonds[k] = 0u;
+    if (a.Hacc) {
+        a.H_out[k] = a.Hacc[k];
+        a.Hacc[k] = 0ull;
+    }
     if (a.cnt) {
         uint32_t m = 0;
         for (uint32_t s = 0; s < a.q; ++s) {

@@ -9,7 +9,7 @@ from paper_1704_01888_amd.workloads import linear_betas
 
 pytestmark = pytest.mark.gpu
 
-KEYS_EXACT = ("R_i", "E_sum", "E_mean", "hist", "final_spins", "final_E", "last_anc")
+KEYS_EXACT = ("R_i", "E_sum", "E_mean", "hist", "final_spins", "final_E", "last_anc", "digest")
 
 
 @pytest.fixture(scope="module")
@@ -40,13 +40,13 @@ MIXED = [
 
 
 def test_batch_equals_separate_runs_and_oracle(ctx):
-    descs = [pa.Desc(outputs=pa.OUT_HIST | pa.OUT_FINAL, **c) for c in MIXED]
+    descs = [pa.Desc(outputs=pa.OUT_HIST | pa.OUT_FINAL | pa.OUT_DIGEST, **c) for c in MIXED]
     print(f"\nbatch of {len(descs)} runs", flush=True)
     got = pa.pa_run_batch(ctx, descs)
     for c, d, g in zip(MIXED, descs, got):
         single = pa.pa_run(ctx, d)
         _same(g, single)
-        want = oracle.run(oracle.Desc(**c), hist=True, final=True)
+        want = oracle.run(oracle.Desc(**c), hist=True, final=True, digest=True)
         _same(g, want)
 
 

@@ -13,7 +13,7 @@ from paper_1704_01888_amd.workloads import linear_betas
 
 pytestmark = pytest.mark.gpu
 
-ALL = pa.OUT_HIST | pa.OUT_FINAL | pa.OUT_MAG | pa.OUT_WIDTHS
+ALL = pa.OUT_HIST | pa.OUT_FINAL | pa.OUT_MAG | pa.OUT_WIDTHS | pa.OUT_DIGEST
 
 
 @pytest.fixture(scope="module")
@@ -25,7 +25,7 @@ def ctx():
 
 def _compare(got, want):
     for k in ("R_i", "E_sum", "E_mean", "hist", "last_anc", "final_E", "final_spins",
-              "Mt_sum", "M_mean", "mhist", "width_e", "width_m"):
+              "Mt_sum", "M_mean", "mhist", "width_e", "width_m", "digest"):
         if k in want and k in got:
             assert (got[k] == want[k]).all(), k
     np.testing.assert_allclose(got["lnQ"], want["lnQ"], rtol=1e-12, atol=1e-13)
@@ -38,7 +38,7 @@ def _both(ctx, outputs=ALL, **kw):
     got = pa.pa_run(ctx, pa.Desc(outputs=outputs, **kw))
     want = oracle.run(oracle.Desc(**kw), hist=bool(outputs & pa.OUT_HIST),
                       final=bool(outputs & pa.OUT_FINAL), magnetisation=bool(outputs & pa.OUT_MAG),
-                      widths=bool(outputs & pa.OUT_WIDTHS))
+                      widths=bool(outputs & pa.OUT_WIDTHS), digest=bool(outputs & pa.OUT_DIGEST))
     return got, want
 
 
@@ -64,7 +64,7 @@ def test_large_lattice_parity(ctx, case):
 
 def test_largest_lattice_4096(ctx):
     case = dict(L=4096, q=10, R=2, beta=linear_betas(1.4, 1), theta=1, seed=46, resample=1)
-    got, want = _both(ctx, outputs=pa.OUT_FINAL | pa.OUT_MAG, **case)
+    got, want = _both(ctx, outputs=pa.OUT_FINAL | pa.OUT_MAG | pa.OUT_DIGEST, **case)
     _compare(got, want)
 
 

@@ -84,7 +84,7 @@ def test_validation():
         (dict(good, L=6), pa.PA_ERR_UNSUPPORTED),
         (dict(good, L=4100), pa.PA_ERR_UNSUPPORTED),
         (dict(good, L=258), pa.PA_ERR_UNSUPPORTED),
-        (dict(good, outputs=16), pa.PA_ERR_INVALID),
+        (dict(good, outputs=32), pa.PA_ERR_INVALID),
         (dict(good, outputs=pa.OUT_WIDTHS, bin_e=2 * 64 + 2), pa.PA_ERR_INVALID),
     ]:
         with pytest.raises(pa.PAError) as e:
