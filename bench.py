@@ -51,10 +51,10 @@ OPS_PER_ATTEMPT = (INSTR_PER_ATTEMPT - MAD_PER_ATTEMPT) + MAD_PER_ATTEMPT * MAD_
 
 # HBM bytes per k_sweep launch on this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by 2.00 and 1.00, the factors the plain 256 MiB copy of
-# --copy-calibration gives): (7571.2 * 2 + 20156.1) KiB;
+# --copy-calibration gives): (7584.7 * 2 + 20156.1) KiB;
 # profiles/k_sweep_32x32_q10_R20000.md.  The algorithmic bytes are 2 * R * N =
 # 41 MB (gather + store); repeated ancestors are served from cache.
-SWEEP_TRAFFIC_BYTES = (7571.2 * 2.0 + 20156.1) * 1024
+SWEEP_TRAFFIC_BYTES = (7584.7 * 2.0 + 20156.1) * 1024
 
 WORKLOAD = dict(L=32, q=10, R=20000, K=401, beta_max=1.6, theta=10, seed=2)
 
@@ -188,7 +188,24 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device-to-device three times (reference kernel of "
                          "known size for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--profile-run", metavar="L,q,R,K,theta",
+                    help="only one plain run of this shape (beta 0 -> 1.0 in K-1 equal steps, "
+                         "multinomial, seed 7), for profiling; prints its kernel times")
     args = ap.parse_args()
+    if args.profile_run:
+        import torch
+        import paper_1704_01888_amd as pa
+        L, q, R, K, theta = (int(x) for x in args.profile_run.split(","))
+        ctx = pa.Context(0)
+        d = pa.Desc(L, q, R, np.array([1.0 * i / (K - 1) for i in range(K)]), theta, 7,
+                    resample=pa.RESAMPLE_MULTINOMIAL)
+        ctx.set_profiling(True)
+        out = pa.pa_run(ctx, d)
+        att = attempts_of(out["R_i"], theta, L * L)
+        ms = dict(zip(pa.KERNEL_NAMES, (float(x) for x in out["kernel_ms"])))
+        print(json.dumps({"L": L, "q": q, "R": R, "K": K, "theta": theta, "kernel_ms": ms,
+                          "sweep_attempts_per_ns": att / (ms["sweep"] * 1e6)}))
+        return
     if args.copy_calibration:
         import torch
         a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
