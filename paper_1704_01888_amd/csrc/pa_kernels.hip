@@ -1094,15 +1094,15 @@ __global__ void __launch_bounds__(256) k_tiled_half(TiledArgs a) {
 }
 
 // The same for L a power of two from 512 on: lane layout fixed at compile
-// time (each lane owns dword columns tid mod L/4 (+ 256 c) of every RS-th
-// row of the update range), two rows per iteration for independent work.
-// Rows beyond the update range are read from two padding rows and not stored.
-template <uint32_t LT, bool QSMALL, bool T64>
-__global__ void __launch_bounds__(256) k_tiled_fixed(TiledArgs a) {
-    constexpr uint32_t L = LT, DPR = L / 4, NT = 256;
+// time (each of the NT lanes owns dword columns tid mod L/4 (+ NT c) of every
+// RS-th row of the update range), two rows per iteration for independent work.
+// Rows beyond the update range are read from RS padding rows and not stored.
+template <uint32_t LT, uint32_t NTT, bool QSMALL, bool T64>
+__global__ void __launch_bounds__(NTT) k_tiled_fixed(TiledArgs a) {
+    constexpr uint32_t L = LT, DPR = L / 4, NT = NTT;
     constexpr uint32_t CPT = DPR > NT ? DPR / NT : 1;     // dword columns per lane
     constexpr uint32_t RS = DPR >= NT ? 1 : NT / DPR;      // rows per pass of the workgroup
-    static_assert(RS <= 2, "two padding rows");
+    static_assert(RS <= 2, "at most two padding rows");
     extern __shared__ __align__(16) uint8_t smem[];
     uint32_t k, tile;
     tile_of(a.tiles, k, tile);
@@ -1447,16 +1447,30 @@ uint32_t tiled_max_halves(uint32_t L) {
     return 2u;
 }
 
-// two padding rows for the fixed-layout kernel
-static size_t tiled_lds_bytes(const TiledArgs &a) { return 128 + (size_t)(a.rows + 2 * a.halves + 2) * a.L; }
+// Threads per workgroup of the fixed-layout tiled kernel.  At L = 4096 a tile
+// holds few rows, so the LDS that limits workgroups per CU is better shared by
+// 512 threads (32 waves per CU instead of 16: 589 -> 689 attempts/ns at theta
+// 10); at L = 1024 and 2048 512 threads measured slower (-19 % and -2 %).
+static uint32_t tiled_threads(uint32_t L) { return L >= 4096 ? 512u : 256u; }
+
+// LDS of a tiled launch: tile and side rows, plus the padding rows the
+// fixed-layout kernel reads past the update range (one row per row step of a
+// lane: RS = threads / (L/4) rows, at least one).  The budget decides how many
+// workgroups share a CU (at L = 4096 two padding rows left room for 3, one
+// for 4: 12 or 16 waves).
+static size_t tiled_lds_bytes(const TiledArgs &a, bool fixed) {
+    const uint32_t nt = tiled_threads(a.L);
+    const uint32_t rs = a.L / 4u >= nt ? 1u : nt / (a.L / 4u);
+    return 128 + (size_t)(a.rows + 2 * a.halves + (fixed ? rs : 0u)) * a.L;
+}
 
 template <bool QSMALL, bool T64>
 static void *tiled_fixed_kernel(uint32_t L) {
     switch (L) {
-        case 512: return (void *)k_tiled_fixed<512, QSMALL, T64>;
-        case 1024: return (void *)k_tiled_fixed<1024, QSMALL, T64>;
-        case 2048: return (void *)k_tiled_fixed<2048, QSMALL, T64>;
-        case 4096: return (void *)k_tiled_fixed<4096, QSMALL, T64>;
+        case 512: return (void *)k_tiled_fixed<512, 256, QSMALL, T64>;
+        case 1024: return (void *)k_tiled_fixed<1024, 256, QSMALL, T64>;
+        case 2048: return (void *)k_tiled_fixed<2048, 256, QSMALL, T64>;
+        case 4096: return (void *)k_tiled_fixed<4096, 512, QSMALL, T64>;
         default: return nullptr;
     }
 }
@@ -1467,12 +1481,14 @@ hipError_t launch_tiled_half(const TiledArgs &a, hipStream_t s) {
     const bool qsmall = a.q <= 128, t64 = a.T[3] == 0;
     void (*kern)(TiledArgs) = qsmall ? (t64 ? k_tiled_half<true, true> : k_tiled_half<true, false>)
                                      : (t64 ? k_tiled_half<false, true> : k_tiled_half<false, false>);
+    bool fixed = false;
     if (a.halves > 0 && a.L % a.rows == 0) {
         void *f = qsmall ? (t64 ? tiled_fixed_kernel<true, true>(a.L) : tiled_fixed_kernel<true, false>(a.L))
                          : (t64 ? tiled_fixed_kernel<false, true>(a.L) : tiled_fixed_kernel<false, false>(a.L));
-        if (f) kern = (void (*)(TiledArgs))f;
+        if (f) { kern = (void (*)(TiledArgs))f; fixed = true; }
     }
-    hipLaunchKernelGGL(kern, dim3((uint32_t)blocks), dim3(256), tiled_lds_bytes(a), s, a);
+    const uint32_t threads = fixed ? tiled_threads(a.L) : 256u;
+    hipLaunchKernelGGL(kern, dim3((uint32_t)blocks), dim3(threads), tiled_lds_bytes(a, fixed), s, a);
     return hipGetLastError();
 }
 
