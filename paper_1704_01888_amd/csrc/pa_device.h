@@ -50,8 +50,11 @@ struct PostArgs {
     double *lnQ;              // [K]
     double *mbF;              // [K]   -beta F
     int32_t *E_ref;           // [K]   reference energy used by step i+1
-    // weights of the resampling to step i+1
+    // weights of the resampling to step i+1: workgroup 0 of a post launch
+    // computes the statistics above, workgroups 1, 2, ... the inclusive scan
+    // C over blocks of `wblock` replicas each
     uint32_t do_weights;
+    uint32_t wblock;          // replicas per weight workgroup (scan_block(R_i))
     const int32_t *E;         // [R_i] energies of the population at step i
     const uint64_t *W;        // [D] fixed-point weights of step i+1 (zero from D on)
     uint32_t D;
@@ -77,16 +80,40 @@ struct SampleArgs {
     uint64_t n_new;
     uint32_t step;
     uint32_t key0, key1;
-    uint32_t *r;              // [R_prev] copy counts (pre-zeroed)
+    uint32_t *r;              // [R_prev] copy counts (zero on entry)
 };
 
+// Count scan and slot map, one workgroup per block of `block` ancestors.  The
+// counts r of this step stay as they are (later workgroups read earlier
+// blocks); the counts buffer of the other step parity, r_clear, is zeroed over
+// [0, clear_n) for the next step's draws.
 struct SlotmapArgs {
-    uint32_t *r;              // [R_prev] copy counts, cleared on exit
+    const uint32_t *r;        // [R_prev] copy counts
     uint64_t R_prev;
     uint32_t *anc;            // [anc_cap]
     uint64_t anc_cap;         // capacity of anc (writes beyond it are dropped)
     uint32_t *counts_last;    // [R_prev] copy of the counts
+    uint32_t block;           // ancestors per workgroup (scan_block(R_prev))
+    uint32_t *r_clear;        // counts of the other parity
+    uint64_t clear_n;
 };
+
+// Elements per workgroup of the multi-workgroup scans: rows of 4096 (four
+// per thread), enough rows that at most 64 workgroups share a population.
+// Each workgroup recomputes the sums before its block, so the work grows with
+// the number of workgroups times the population.
+__host__ __device__ inline uint32_t scan_block(uint64_t n) {
+    const uint64_t row = 4096, max_blocks = 64;
+    const uint64_t rows = (n + row * max_blocks - 1) / (row * max_blocks);
+    return (uint32_t)(row * (rows ? rows : 1));
+}
+// Workgroups of a post launch: statistics plus the weight blocks.
+__host__ __device__ inline uint32_t post_blocks(const PostArgs &a) {
+    return 1u + (a.do_weights ? (uint32_t)((a.R_i + a.wblock - 1) / a.wblock) : 0u);
+}
+__host__ __device__ inline uint32_t countfill_blocks(const SlotmapArgs &m) {
+    return (uint32_t)((m.R_prev + m.block - 1) / m.block);
+}
 
 // Lattices beyond one workgroup's LDS (L > 256): replicas stay in HBM; one
 // launch per half-sweep over (replica, tile of `rows` rows).
@@ -128,9 +155,13 @@ uint32_t sweep_class(uint32_t L, uint32_t q, bool t64, uint32_t G);
 void *sweep_kernel(uint32_t cls, bool batch);
 hipError_t launch_sweep_batch(uint32_t cls, const SweepArgs *runs, const uint32_t *start, uint32_t n,
                               uint32_t blocks, uint32_t threads, size_t lds, hipStream_t s);
-hipError_t launch_post_batch(const PostArgs *runs, uint32_t n, hipStream_t s);
+// Post and count-scan launches: run r owns workgroups pstart[r] .. pstart[r+1]-1
+// (post_blocks / countfill_blocks of its records).
+hipError_t launch_post_batch(const PostArgs *runs, const uint32_t *pstart, uint32_t n, uint32_t blocks,
+                             hipStream_t s);
 hipError_t launch_resample_batch(const SampleArgs *sruns, const uint32_t *start, uint32_t n,
-                                 uint32_t blocks, const SlotmapArgs *mruns, hipStream_t s);
+                                 uint32_t blocks, const SlotmapArgs *mruns, const uint32_t *mstart,
+                                 uint32_t mblocks, hipStream_t s);
 
 // Lanes-per-replica candidates for L (0 if L has no fixed-shape kernel).
 uint32_t lane_candidates(uint32_t L, uint32_t *out /*[2]*/);

@@ -237,7 +237,7 @@ pa_status build_plan(const pa_run_desc *d, Plan &p) {
     p.off_pop[1] = o; o += popb;
     p.off_E = o; o += align256(4 * p.R_cap);
     p.off_C = o; o += align256(8 * p.R_cap);
-    p.off_r = o; o += align256(4 * p.R_cap);
+    p.off_r = o; o += align256(4 * 2 * p.R_cap);   // copy counts, one buffer per step parity
     p.off_anc = o; o += align256(4 * p.R_cap);
     p.off_counts = o; o += align256(4 * p.R_cap);
     p.off_hist = o; o += align256((size_t)4 * p.nbins * (p.hist_all ? K : 1));
@@ -298,6 +298,7 @@ struct pa_run_state {
     uint32_t step;       // current step (population at beta_step)
     int cur;             // pop buffer holding the current population
     uint64_t R_cur, R_prev;
+    uint64_t r_dirty[2];  // extent of nonzero copy counts in each parity buffer
     uint32_t G, wpb;     // sweep shape: lanes per replica, waves per workgroup
     double mbF0;
     uint32_t first_step;  // step of the initial or loaded population
@@ -384,6 +385,7 @@ pa::PostArgs post_args(pa_run_state *r, uint32_t i) {
     s.mbF = r->at<double>(p.off_mbF);
     s.E_ref = r->at<int32_t>(p.off_Eref);
     s.do_weights = (s.has_next && p.desc.resample != PA_RESAMPLE_NONE) ? 1u : 0u;
+    s.wblock = pa::scan_block(s.R_i);
     s.E = r->at<int32_t>(p.off_E);
     s.W = r->at<uint64_t>(p.off_W) + p.W_off[tab];
     s.D = p.D[tab];
@@ -485,6 +487,38 @@ hipError_t launch_tiled_sweeps(pa::TiledArgs a, uint32_t theta, uint8_t *x, hipS
     return pa::launch_tiled_measure(a, s);
 }
 
+// Copy-count buffer of step parity `par`.
+uint32_t *counts_buf(pa_run_state *r, uint32_t par) {
+    return r->at<uint32_t>(r->plan.off_r) + (size_t)(par & 1u) * r->plan.R_cap;
+}
+
+// Records of the resampling into step i (draws from the R_prev replicas of
+// step i-1, R_new of them).  The draws count into the buffer of parity i,
+// which is zero; the count scan clears the other buffer for step i+1.
+void resample_args(pa_run_state *r, uint32_t i, uint64_t R_prev, uint64_t R_new, pa::SampleArgs &s,
+                   pa::SlotmapArgs &m) {
+    const Plan &p = r->plan;
+    s = pa::SampleArgs{};
+    s.C = r->at<uint64_t>(p.off_C);
+    s.R_prev = R_prev;
+    s.n_new = R_new;
+    s.step = i;
+    s.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
+    s.key1 = (uint32_t)(p.desc.seed >> 32);
+    s.r = counts_buf(r, i);
+    m = pa::SlotmapArgs{};
+    m.r = s.r;
+    m.R_prev = R_prev;
+    m.anc = r->at<uint32_t>(p.off_anc);
+    m.anc_cap = p.R_cap;
+    m.counts_last = r->at<uint32_t>(p.off_counts);
+    m.block = pa::scan_block(R_prev);
+    m.r_clear = counts_buf(r, i + 1);
+    m.clear_n = r->r_dirty[(i + 1) & 1u];
+    r->r_dirty[(i + 1) & 1u] = 0;
+    r->r_dirty[i & 1u] = R_prev;
+}
+
 pa_status do_step(pa_run_state *r) {
     const Plan &p = r->plan;
     const uint32_t i = r->step + 1;
@@ -494,20 +528,9 @@ pa_status do_step(pa_run_state *r) {
     if (p.desc.resample != PA_RESAMPLE_NONE) {
         // C (inclusive weight scan over the step i-1 population) was written
         // by the post kernel of step i-1.
-        pa::SampleArgs s{};
-        s.C = r->at<uint64_t>(p.off_C);
-        s.R_prev = R_prev;
-        s.n_new = R_new;
-        s.step = i;
-        s.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
-        s.key1 = (uint32_t)(p.desc.seed >> 32);
-        s.r = r->at<uint32_t>(p.off_r);
-        pa::SlotmapArgs m{};
-        m.r = s.r;
-        m.R_prev = R_prev;
-        m.anc = r->at<uint32_t>(p.off_anc);
-        m.anc_cap = p.R_cap;
-        m.counts_last = r->at<uint32_t>(p.off_counts);
+        pa::SampleArgs s;
+        pa::SlotmapArgs m;
+        resample_args(r, i, R_prev, R_new, s, m);
         if ((st = timed_launch(r, PA_KERNEL_RESAMPLE, "resample kernel",
                                [&] { return pa::launch_resample(s, m, r->stream); })))
             return st;
@@ -756,6 +779,7 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
     r->R_prev = p.desc.R;
     r->first_step = 0;
     r->R_first = p.desc.R;
+    r->r_dirty[0] = r->r_dirty[1] = 0;
     r->broken = false;
     r->G = 0;
     r->wpb = 0;
@@ -778,7 +802,7 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
     if ((st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_hist), hist_words, 0u, s), "fill")) ||
         (mhist_words &&
          (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_mhist), mhist_words, 0u, s), "fill"))) ||
-        (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_r), p.R_cap, 0u, s), "fill")) ||
+        (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_r), 2 * p.R_cap, 0u, s), "fill")) ||
         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_lnQ), 2 * (size_t)p.desc.K, 0u, s), "fill")) ||
         (p.tiled &&
          (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_bonds), p.R_cap, 0u, s), "fill"))) ||
@@ -868,6 +892,13 @@ pa_status pa_run_load(pa_run_state *r, uint32_t step, uint64_t R_cur, const uint
     r->R_prev = R_cur;
     r->first_step = step;
     r->R_first = R_cur;
+    // the draws of step + 1 count into a zero buffer
+    const uint32_t next = (step + 1) & 1u;
+    if (r->r_dirty[next]) {
+        if ((st = hip_check(r, pa::launch_fill_u32(counts_buf(r, next), r->r_dirty[next], 0u, s), "fill")))
+            return st;
+        r->r_dirty[next] = 0;
+    }
     // Upload into the idle buffer, then recompute E with a sweep of zero
     // rounds into the other buffer and the statistics with the post kernel.
     const int idle = 1 - r->cur;
@@ -975,13 +1006,14 @@ namespace {
 
 size_t step_desc_bytes(size_t n) {
     return align256(n * sizeof(pa::SampleArgs)) + align256((n + 1) * 4) +
-           align256(n * sizeof(pa::SlotmapArgs)) + align256(n * sizeof(pa::SweepArgs)) +
-           align256(2 * (n + 1) * 4 + 4 * n) + align256(n * sizeof(pa::PostArgs));
+           align256(n * sizeof(pa::SlotmapArgs)) + align256((n + 1) * 4) + align256(n * sizeof(pa::SweepArgs)) +
+           align256(2 * (n + 1) * 4 + 4 * n) + align256(n * sizeof(pa::PostArgs)) + align256((n + 1) * 4);
 }
 
 struct StepLaunch {
-    size_t sample_off, sample_start_off, slot_off, sweep_off, sweep_start_off, post_off;
-    uint32_t n_res, sample_blocks, n_post;
+    size_t sample_off, sample_start_off, slot_off, slot_start_off, sweep_off, sweep_start_off, post_off,
+        post_start_off;
+    uint32_t n_res, sample_blocks, slot_blocks, n_post, post_blocks;
     struct Group { uint32_t cls, first, count, blocks, threads; size_t lds; };
     std::vector<Group> groups;
     struct Tiled { pa::TiledArgs a; uint32_t theta; uint8_t *x; };
@@ -995,12 +1027,12 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
     const size_t n = active.size();
     StepLaunch L{};
     std::vector<pa::SampleArgs> sa;
-    std::vector<uint32_t> sstart;
+    std::vector<uint32_t> sstart, mstart;
     std::vector<pa::SlotmapArgs> sm;
     std::vector<pa::PostArgs> po;
     struct SW { uint32_t cls, blocks, threads; size_t lds; pa::SweepArgs a; };
     std::vector<SW> sw;
-    uint32_t sblocks = 0;
+    uint32_t sblocks = 0, mblocks = 0;
     for (pa_run_state *r : active) {
         const Plan &p = r->plan;
         const uint32_t g = r->step + 1;
@@ -1008,23 +1040,14 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
         const int prev_buf = r->cur, new_buf = 1 - r->cur;
         const uint32_t *anc = nullptr;
         if (p.desc.resample != PA_RESAMPLE_NONE) {
-            pa::SampleArgs a{};
-            a.C = r->at<uint64_t>(p.off_C);
-            a.R_prev = R_prev;
-            a.n_new = R_new;
-            a.step = g;
-            a.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
-            a.key1 = (uint32_t)(p.desc.seed >> 32);
-            a.r = r->at<uint32_t>(p.off_r);
+            pa::SampleArgs a;
+            pa::SlotmapArgs m;
+            resample_args(r, g, R_prev, R_new, a, m);
             sstart.push_back(sblocks);
             sblocks += (uint32_t)((R_new + 255) / 256);
             sa.push_back(a);
-            pa::SlotmapArgs m{};
-            m.r = a.r;
-            m.R_prev = R_prev;
-            m.anc = r->at<uint32_t>(p.off_anc);
-            m.anc_cap = p.R_cap;
-            m.counts_last = r->at<uint32_t>(p.off_counts);
+            mstart.push_back(mblocks);
+            mblocks += pa::countfill_blocks(m);
             sm.push_back(m);
             anc = m.anc;
         }
@@ -1057,13 +1080,17 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
     if (blob.size() < cursor + step_desc_bytes(n)) blob.resize(cursor + step_desc_bytes(n), 0);
     L.n_res = (uint32_t)sa.size();
     L.sample_blocks = sblocks;
+    L.slot_blocks = mblocks;
     sstart.push_back(sblocks);
+    mstart.push_back(mblocks);
     L.sample_off = take(n * sizeof(pa::SampleArgs));
     L.sample_start_off = take((n + 1) * 4);
     L.slot_off = take(n * sizeof(pa::SlotmapArgs));
+    L.slot_start_off = take((n + 1) * 4);
     std::memcpy(blob.data() + L.sample_off, sa.data(), sa.size() * sizeof(pa::SampleArgs));
     std::memcpy(blob.data() + L.sample_start_off, sstart.data(), sstart.size() * 4);
     std::memcpy(blob.data() + L.slot_off, sm.data(), sm.size() * sizeof(pa::SlotmapArgs));
+    std::memcpy(blob.data() + L.slot_start_off, mstart.data(), mstart.size() * 4);
     // sweep groups: runs of one kernel class contiguous in the table
     std::stable_sort(sw.begin(), sw.end(), [](const SW &x, const SW &y) { return x.cls < y.cls; });
     L.sweep_off = take(n * sizeof(pa::SweepArgs));
@@ -1084,8 +1111,18 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
         std::memcpy(blob.data() + L.sweep_off + k * sizeof(pa::SweepArgs), &sw[k].a, sizeof(pa::SweepArgs));
     std::memcpy(blob.data() + L.sweep_start_off, starts.data(), starts.size() * 4);
     L.n_post = (uint32_t)po.size();
+    std::vector<uint32_t> pstart;
+    uint32_t pblocks = 0;
+    for (const auto &a : po) {
+        pstart.push_back(pblocks);
+        pblocks += pa::post_blocks(a);
+    }
+    pstart.push_back(pblocks);
+    L.post_blocks = pblocks;
     L.post_off = take(n * sizeof(pa::PostArgs));
+    L.post_start_off = take((n + 1) * 4);
     std::memcpy(blob.data() + L.post_off, po.data(), po.size() * sizeof(pa::PostArgs));
+    std::memcpy(blob.data() + L.post_start_off, pstart.data(), pstart.size() * 4);
     return L;
 }
 
@@ -1095,7 +1132,8 @@ pa_status launch_step(const StepLaunch &L, const uint8_t *dtab, hipStream_t s) {
         (st = hip_check(nullptr, pa::launch_resample_batch(
                                      reinterpret_cast<const pa::SampleArgs *>(dtab + L.sample_off),
                                      reinterpret_cast<const uint32_t *>(dtab + L.sample_start_off), L.n_res,
-                                     L.sample_blocks, reinterpret_cast<const pa::SlotmapArgs *>(dtab + L.slot_off), s),
+                                     L.sample_blocks, reinterpret_cast<const pa::SlotmapArgs *>(dtab + L.slot_off),
+                                     reinterpret_cast<const uint32_t *>(dtab + L.slot_start_off), L.slot_blocks, s),
                         "batched resample")))
         return st;
     uint32_t run_index = 0;
@@ -1111,7 +1149,8 @@ pa_status launch_step(const StepLaunch &L, const uint8_t *dtab, hipStream_t s) {
     for (const auto &t : L.tiled)
         if ((st = hip_check(nullptr, launch_tiled_sweeps(t.a, t.theta, t.x, s), "tiled sweeps"))) return st;
     return hip_check(nullptr, pa::launch_post_batch(reinterpret_cast<const pa::PostArgs *>(dtab + L.post_off),
-                                                    L.n_post, s),
+                                                    reinterpret_cast<const uint32_t *>(dtab + L.post_start_off),
+                                                    L.n_post, L.post_blocks, s),
                      "batched post");
 }
 

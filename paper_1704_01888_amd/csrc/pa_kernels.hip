@@ -542,6 +542,36 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *scratch, T *total) {
     return res;
 }
 
+// Inclusive scan over the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+    const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const T n = __shfl_up(v, off, 64);
+        if (lane >= off) v += n;
+    }
+    return v;
+}
+
+// Exclusive offset of this wave's total among the waves of the block (in wave
+// order); *total receives the block sum.  scratch holds blockDim/64 entries.
+template <typename T>
+__device__ __forceinline__ T block_wave_offset(T wave_total, T *scratch, T *total) {
+    const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63u) == 0) scratch[wave] = wave_total;
+    __syncthreads();
+    T off = T(0), tot = T(0);
+    for (uint32_t w = 0; w < nw; ++w) {
+        const T x = scratch[w];
+        off += w < wave ? x : T(0);
+        tot += x;
+    }
+    *total = tot;
+    __syncthreads();
+    return off;
+}
+
 // Block-wide reduction with `op`; every thread receives the result.
 // scratch holds blockDim/64 entries.
 template <typename T, typename Op>
@@ -601,27 +631,28 @@ __device__ double hist_fwhm_levels(const HistView &v, uint32_t B, uint64_t *scra
     return (xr - xl) * (double)B;
 }
 
-// Calls f(x[j]) for j = 0 .. n-1 (4-byte elements, 16-byte aligned array) in
-// tiles of blockDim * 16 elements: each thread issues its four 128-bit loads
-// of a tile together.
+// Calls f(x[j]) for j = 0 .. n-1 (4-byte elements, 16-byte aligned array), in
+// no particular order, in tiles of blockDim * 16 elements: each thread issues
+// its four 128-bit loads of a tile together, and each load of a wave covers
+// 1 KB of consecutive elements.
 template <typename T, typename F>
 __device__ __forceinline__ void for_each_tiled(const T *x, uint64_t n, F f) {
     static_assert(sizeof(T) == 4, "4-byte elements");
     constexpr uint32_t V = 16;
-    for (uint64_t base = 0; base < n; base += (uint64_t)blockDim.x * V) {
-        const uint64_t j0 = base + (uint64_t)threadIdx.x * V;
-        T v[V];
-        if (j0 + V <= n) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(x + j0);
+    const uint64_t tile = (uint64_t)blockDim.x * V;
+    for (uint64_t base = 0; base < n; base += tile) {
+        if (base + tile <= n) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(x + base) + threadIdx.x;
+            T v[V];
 #pragma unroll
             for (uint32_t q = 0; q < V / 4; ++q) {
-                const uint4 w = src[q];
+                const uint4 w = src[q * blockDim.x];
                 v[4 * q] = (T)w.x; v[4 * q + 1] = (T)w.y; v[4 * q + 2] = (T)w.z; v[4 * q + 3] = (T)w.w;
             }
 #pragma unroll
             for (uint32_t q = 0; q < V; ++q) f(v[q]);
         } else {
-            for (uint32_t q = 0; q < V && j0 + q < n; ++q) f(x[j0 + q]);
+            for (uint64_t j = base + threadIdx.x; j < n; j += blockDim.x) f(x[j]);
         }
     }
 }
@@ -711,19 +742,61 @@ __device__ void store_hist(const HistView &v, uint32_t *out) {
 
 constexpr uint32_t POST_LDS_BINS = 14336;   // 56 KB window for the histograms in LDS
 
-constexpr uint32_t TILE_V = 16;  // elements per thread per tile in the one-workgroup weight scan
-constexpr uint32_t FILL_V = 16;
-constexpr uint32_t SHORT_RUN = 8;   // copies written by their own lane in the slot map  // elements per thread per tile in the count scan + slot map
+constexpr uint32_t SHORT_RUN = 8;   // copies written by their own lane in the slot map
+
+// Multi-workgroup scans: workgroup b of a launch takes the elements
+// [b*block, (b+1)*block) in rows of blockDim*4, thread t the four elements
+// 4t .. 4t+3 of each row, so that every load and store of a wave covers
+// consecutive memory.  The sum over the elements before the block is
+// recomputed by each workgroup from the inputs, so that the workgroups need
+// no communication.
+
+// C_j = sum_{j' <= j} wf(E_j') for first <= j < last (E 16-byte aligned, C
+// 32-byte aligned, first a multiple of 4).
+template <typename WF>
+__device__ __forceinline__ void weight_block(const int32_t *E, uint32_t first, uint32_t last, WF wf,
+                                             uint64_t *C, uint64_t *scratch) {
+    uint64_t carry = 0;
+    for_each_tiled(E, first, [&](int32_t e) { carry += wf(e); });
+    carry = block_reduce(carry, [](uint64_t x, uint64_t y) { return x + y; }, scratch);
+    __syncthreads();
+    for (uint32_t base = first; base < last; base += blockDim.x * 4u) {
+        const uint32_t j = base + threadIdx.x * 4u;
+        uint64_t w[4];
+        if (j + 4u <= last) {
+            const int4 x = *reinterpret_cast<const int4 *>(E + j);
+            w[0] = wf(x.x); w[1] = wf(x.y); w[2] = wf(x.z); w[3] = wf(x.w);
+        } else {
+#pragma unroll
+            for (uint32_t v = 0; v < 4; ++v) w[v] = j + v < last ? wf(E[j + v]) : 0ull;
+        }
+        w[1] += w[0]; w[2] += w[1]; w[3] += w[2];
+        const uint64_t incl = wave_inclusive_scan(w[3]);
+        uint64_t total;
+        const uint64_t off = carry + block_wave_offset(__shfl(incl, 63, 64), scratch, &total) + incl - w[3];
+#pragma unroll
+        for (uint32_t v = 0; v < 4; ++v) w[v] += off;
+        if (j + 4u <= last) {
+            ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(C + j);
+            dst[0] = make_ulonglong2(w[0], w[1]);
+            dst[1] = make_ulonglong2(w[2], w[3]);
+        } else {
+#pragma unroll
+            for (uint32_t v = 0; v < 4; ++v)
+                if (j + v < last) C[j + v] = w[v];
+        }
+        carry += total;
+    }
+}
 
 // ---------------------------------------------------------------------------
-// k_post(i): population sums of eq. (4) and ln Q_{i+1} of Sec. 2 step 2 /
-// eq. (2) from the energy histogram of step i, then (if resampling follows)
-// the integer weights W(|E_j - E_ref|) of step i+1 and their inclusive scan C.
-// One workgroup; histogram bins and energies are read with coalesced loads.
+// k_post(i), workgroup 0: population sums of eq. (4) and ln Q_{i+1} of Sec. 2
+// step 2 / eq. (2) from the energy histogram of step i, the magnetisation,
+// widths and digest.  Workgroups 1, 2, ...: if resampling follows, the integer
+// weights W(|E_j - E_ref|) of step i+1 and their inclusive scan C, one block
+// of replicas each.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void post_body(const PostArgs &a) {
-    __shared__ uint32_t lds_hist[POST_LDS_BINS];
-    __shared__ uint64_t scratch[17];
+__device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist, uint64_t *scratch) {
     __shared__ double s_w[16];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nw = blockDim.x >> 6;
     const uint32_t nb = a.nbins;
@@ -792,139 +865,128 @@ __device__ __forceinline__ void post_body(const PostArgs &a) {
         __syncthreads();
     }
 
-    if (!a.do_weights) return;
-    // C_j = sum_{j' <= j} W(|E_j' - E_ref|), tiles of blockDim * TILE_V elements
-    const uint64_t n = a.R_i;
-    uint64_t carry = 0;
-    for (uint64_t base = 0; base < n; base += (uint64_t)blockDim.x * TILE_V) {
-        const uint64_t j0 = base + (uint64_t)tid * TILE_V;
-        // valid entries of this thread's tile; the others get E_ref + D, whose
-        // weight is zero (keeps the loop free of 64-bit compares, so that all
-        // table reads of a thread are in flight together)
-        const uint32_t m = j0 >= n ? 0u : (n - j0 < TILE_V ? (uint32_t)(n - j0) : TILE_V);
-        int32_t e[TILE_V];
-        if (m == TILE_V) {
-            const int4 *src = reinterpret_cast<const int4 *>(a.E + j0);
-#pragma unroll
-            for (uint32_t v = 0; v < TILE_V / 4; ++v) {
-                const int4 x = src[v];
-                e[4 * v] = x.x; e[4 * v + 1] = x.y; e[4 * v + 2] = x.z; e[4 * v + 3] = x.w;
-            }
-        } else {
-#pragma unroll
-            for (uint32_t v = 0; v < TILE_V; ++v) e[v] = v < m ? a.E[j0 + v] : ref + (int32_t)a.D;
-        }
-        uint64_t w[TILE_V];
-        uint64_t local = 0;
-        if (a.w_const) {
-#pragma unroll
-            for (uint32_t v = 0; v < TILE_V; ++v) {
-                w[v] = v < m ? a.w_const : 0ull;
-                local += w[v];
-            }
-        } else {
-#pragma unroll
-            for (uint32_t v = 0; v < TILE_V; ++v) {
-                const uint32_t dd = (uint32_t)abs(e[v] - ref);
-                w[v] = dd < a.D ? a.W[dd] : 0ull;
-                local += w[v];
-            }
-        }
-        uint64_t total;
-        uint64_t run = carry + block_exclusive_scan<uint64_t>(local, scratch, &total);
-#pragma unroll
-        for (uint32_t v = 0; v < TILE_V; ++v) {
-            run += w[v];
-            w[v] = run;
-        }
-        if (j0 + TILE_V <= n) {
-            ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(a.C + j0);
-#pragma unroll
-            for (uint32_t v = 0; v < TILE_V; v += 2) dst[v / 2] = make_ulonglong2(w[v], w[v + 1]);
-        } else {
-#pragma unroll
-            for (uint32_t v = 0; v < TILE_V; ++v)
-                if (j0 + v < n) a.C[j0 + v] = w[v];
-        }
-        carry += total;
+}
+
+// Weight workgroup b: E_ref of step i+1 (the minimum or maximum energy of the
+// population, as the statistics workgroup finds it) and C over block b.  The
+// distances that occur are 0 .. max - min; their weights are read from LDS
+// when they fit there.
+__device__ __forceinline__ void post_weights(const PostArgs &a, uint32_t b, uint32_t *lds, uint64_t *scratch) {
+    const uint32_t n = (uint32_t)a.R_i, tid = threadIdx.x;
+    const uint32_t first = b * a.wblock, last = min(first + a.wblock, n);
+    int32_t mn = 0x7fffffff, mx = (int32_t)0x80000000;
+    for_each_tiled(a.E, n, [&](int32_t e) { mn = min(mn, e); mx = max(mx, e); });
+    const SumMinMax t = block_sum_min_max(0, mn, mx);
+    const int32_t ref = a.dbeta_next >= 0.0 ? t.mn : t.mx;
+    if (a.w_const) {
+        const uint64_t wc = a.w_const;
+        weight_block(a.E, first, last, [=](int32_t) { return wc; }, a.C, scratch);
+        return;
+    }
+    const uint32_t span = (uint32_t)(t.mx - t.mn) + 1u;
+    const uint32_t nW = a.D < span ? a.D : span;
+    if (nW <= POST_LDS_BINS / 2) {
+        uint64_t *Wl = reinterpret_cast<uint64_t *>(lds);
+        for (uint32_t d = tid; d < nW; d += blockDim.x) Wl[d] = a.W[d];
+        __syncthreads();
+        weight_block(a.E, first, last, [=](int32_t e) {
+            const uint32_t d = (uint32_t)abs(e - ref);
+            return d < nW ? Wl[d] : 0ull;
+        }, a.C, scratch);
+    } else {
+        const uint64_t *Wg = a.W;
+        const uint32_t D = a.D;
+        weight_block(a.E, first, last, [=](int32_t e) {
+            const uint32_t d = (uint32_t)abs(e - ref);
+            return d < D ? Wg[d] : 0ull;
+        }, a.C, scratch);
     }
 }
 
-__global__ void __launch_bounds__(1024) k_post(PostArgs a) { post_body(a); }
+__device__ __forceinline__ void post_block(const PostArgs &a, uint32_t b) {
+    __shared__ __align__(16) uint32_t lds[POST_LDS_BINS];
+    __shared__ uint64_t scratch[17];
+    if (b == 0) post_stats(a, lds, scratch);
+    else post_weights(a, b - 1, lds, scratch);
+}
 
-// Batched form: workgroup r handles run r.
-__global__ void __launch_bounds__(1024) k_post_batch(const PostArgs *runs) {
-    const PostArgs a = runs[blockIdx.x];
-    post_body(a);
+__global__ void __launch_bounds__(1024) k_post(PostArgs a) { post_block(a, blockIdx.x); }
+
+// Batched form: run r owns workgroups start[r] .. start[r+1]-1.
+__global__ void __launch_bounds__(1024) k_post_batch(const PostArgs *runs, const uint32_t *start, uint32_t n) {
+    const uint32_t r = segment_of(start, n, blockIdx.x);
+    const PostArgs a = runs[r];
+    post_block(a, blockIdx.x - start[r]);
 }
 
 // ---------------------------------------------------------------------------
-// Count scan and slot map: o = exclusive scan of the copy numbers r;
-// anc[o_j + c] = j for c < r_j (new population in ancestor order, eq. (1));
-// r is cleared for the next step.  Run by one whole workgroup.
+// Count scan and slot map, workgroup b of the launch: o = exclusive scan of the
+// copy numbers r; anc[o_j + c] = j for c < r_j (new population in ancestor
+// order, eq. (1)) for the ancestors j of block b; the other parity's counts
+// are cleared for the next step.
 // ---------------------------------------------------------------------------
-__device__ void countfill_block(const SlotmapArgs &a, uint64_t *scratch) {
-    const uint32_t tid = threadIdx.x;
-    const uint64_t n = a.R_prev;
+__device__ void countfill_block(const SlotmapArgs &a, uint32_t b, uint64_t *scratch) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t n = (uint32_t)a.R_prev;   // R_prev < 2^32
+    const uint32_t first = b * a.block, last = min(first + a.block, n);
+    const uint64_t stride = (uint64_t)countfill_blocks(a) * a.block;
+    for (uint64_t c0 = first; c0 < a.clear_n; c0 += stride) {
+        const uint64_t c1 = min(c0 + a.block, a.clear_n);
+        for (uint64_t i = c0 + tid; i < c1; i += blockDim.x) a.r_clear[i] = 0u;
+    }
     uint64_t carry = 0;
-    for (uint64_t base = 0; base < n; base += (uint64_t)blockDim.x * FILL_V) {
-        const uint64_t j0 = base + (uint64_t)tid * FILL_V;
-        uint32_t r[FILL_V];
-        const bool full = j0 + FILL_V <= n;
-        if (full) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(a.r + j0);
-#pragma unroll
-            for (uint32_t v = 0; v < FILL_V / 4; ++v) {
-                const uint4 x = src[v];
-                r[4 * v] = x.x; r[4 * v + 1] = x.y; r[4 * v + 2] = x.z; r[4 * v + 3] = x.w;
-            }
+    for_each_tiled(a.r, first, [&](uint32_t c) { carry += c; });
+    carry = block_reduce(carry, [](uint64_t x, uint64_t y) { return x + y; }, scratch);
+    __syncthreads();
+    for (uint32_t base = first; base < last; base += blockDim.x * 4u) {
+        const uint32_t j = base + tid * 4u;
+        uint32_t r[4];
+        if (j + 4u <= last) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(a.r + j);
+            r[0] = x.x; r[1] = x.y; r[2] = x.z; r[3] = x.w;
         } else {
 #pragma unroll
-            for (uint32_t v = 0; v < FILL_V; ++v) r[v] = j0 + v < n ? a.r[j0 + v] : 0u;
+            for (uint32_t v = 0; v < 4; ++v) r[v] = j + v < last ? a.r[j + v] : 0u;
         }
-        uint64_t local = 0;
-#pragma unroll
-        for (uint32_t v = 0; v < FILL_V; ++v) local += r[v];
-        uint64_t total;
-        uint64_t o = carry + block_exclusive_scan<uint64_t>(local, scratch, &total);
+        // offsets within the row in 32 bits (a row's counts sum to at most the
+        // new population, below 2^32)
+        const uint32_t sum = r[0] + r[1] + r[2] + r[3];
+        const uint32_t incl = wave_inclusive_scan(sum);
+        uint32_t total;
+        const uint32_t woff = block_wave_offset(__shfl(incl, 63, 64), reinterpret_cast<uint32_t *>(scratch), &total);
+        const uint64_t o0 = carry + woff + incl - sum;
         // Short runs of copies are written by their own lane, long ones
         // (strongly skewed weights) by the whole wave.
-        uint64_t ov[FILL_V];
+        uint64_t o = o0;
 #pragma unroll
-        for (uint32_t v = 0; v < FILL_V; ++v) {
-            ov[v] = o;
-            o += r[v];
+        for (uint32_t v = 0; v < 4; ++v) {
             if (r[v] <= SHORT_RUN)
                 for (uint32_t c = 0; c < r[v]; ++c)
-                    if (ov[v] + c < a.anc_cap) a.anc[ov[v] + c] = (uint32_t)(j0 + v);
+                    if (o + c < a.anc_cap) a.anc[o + c] = j + v;
+            o += r[v];
         }
-        const uint32_t lane = tid & 63u;
+        o = o0;
 #pragma unroll
-        for (uint32_t v = 0; v < FILL_V; ++v) {
+        for (uint32_t v = 0; v < 4; ++v) {
             uint64_t todo = __ballot(r[v] > SHORT_RUN);
             while (todo) {
                 const uint32_t src = (uint32_t)__ffsll((unsigned long long)todo) - 1u;
-                const uint64_t start = ((uint64_t)__shfl((uint32_t)(ov[v] >> 32), src, 64) << 32) |
-                                       (uint64_t)__shfl((uint32_t)ov[v], src, 64);
+                const uint64_t start = ((uint64_t)__shfl((uint32_t)(o >> 32), src, 64) << 32) |
+                                       (uint64_t)__shfl((uint32_t)o, src, 64);
                 const uint32_t cnt = __shfl(r[v], src, 64);
-                const uint32_t who = __shfl((uint32_t)(j0 + v), src, 64);
+                const uint32_t who = __shfl(j + v, src, 64);
                 for (uint32_t c = lane; c < cnt; c += 64u)
                     if (start + c < a.anc_cap) a.anc[start + c] = who;
                 todo &= todo - 1;
             }
+            o += r[v];
         }
-        if (full) {
-            uint4 *cnt = reinterpret_cast<uint4 *>(a.counts_last + j0);
-            uint4 *rz = reinterpret_cast<uint4 *>(a.r + j0);
-#pragma unroll
-            for (uint32_t v = 0; v < FILL_V / 4; ++v) {
-                cnt[v] = make_uint4(r[4 * v], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
-                rz[v] = make_uint4(0, 0, 0, 0);
-            }
+        if (j + 4u <= last) {
+            *reinterpret_cast<uint4 *>(a.counts_last + j) = make_uint4(r[0], r[1], r[2], r[3]);
         } else {
 #pragma unroll
-            for (uint32_t v = 0; v < FILL_V; ++v)
-                if (j0 + v < n) { a.counts_last[j0 + v] = r[v]; a.r[j0 + v] = 0u; }
+            for (uint32_t v = 0; v < 4; ++v)
+                if (j + v < last) a.counts_last[j + v] = r[v];
         }
         carry += total;
     }
@@ -984,14 +1046,16 @@ __global__ void __launch_bounds__(256) k_sample_batch(const SampleArgs *runs, co
 
 __global__ void __launch_bounds__(1024) k_countfill(SlotmapArgs m) {
     __shared__ uint64_t scratch[17];
-    countfill_block(m, scratch);
+    countfill_block(m, blockIdx.x, scratch);
 }
 
-// Batched form: workgroup r handles run r.
-__global__ void __launch_bounds__(1024) k_countfill_batch(const SlotmapArgs *runs) {
+// Batched form: run r owns workgroups start[r] .. start[r+1]-1.
+__global__ void __launch_bounds__(1024) k_countfill_batch(const SlotmapArgs *runs, const uint32_t *start,
+                                                          uint32_t n) {
     __shared__ uint64_t scratch[17];
-    const SlotmapArgs m = runs[blockIdx.x];
-    countfill_block(m, scratch);
+    const uint32_t r = segment_of(start, n, blockIdx.x);
+    const SlotmapArgs m = runs[r];
+    countfill_block(m, blockIdx.x - start[r], scratch);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
@@ -1359,14 +1423,14 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_post(const PostArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_post, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_post, dim3(post_blocks(a)), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_resample(const SampleArgs &a, const SlotmapArgs &m, hipStream_t s) {
     const uint64_t blocks = (a.n_new + 255) / 256;
     if (blocks) hipLaunchKernelGGL(k_sample, dim3((uint32_t)blocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_countfill, dim3(1), dim3(1024), 0, s, m);
+    hipLaunchKernelGGL(k_countfill, dim3(countfill_blocks(m)), dim3(1024), 0, s, m);
     return hipGetLastError();
 }
 
@@ -1417,17 +1481,19 @@ hipError_t launch_sweep_batch(uint32_t cls, const SweepArgs *runs, const uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_post_batch(const PostArgs *runs, uint32_t n, hipStream_t s) {
+hipError_t launch_post_batch(const PostArgs *runs, const uint32_t *pstart, uint32_t n, uint32_t blocks,
+                             hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_post_batch, dim3(n), dim3(1024), 0, s, runs);
+    hipLaunchKernelGGL(k_post_batch, dim3(blocks), dim3(1024), 0, s, runs, pstart, n);
     return hipGetLastError();
 }
 
 hipError_t launch_resample_batch(const SampleArgs *sruns, const uint32_t *start, uint32_t n,
-                                 uint32_t blocks, const SlotmapArgs *mruns, hipStream_t s) {
+                                 uint32_t blocks, const SlotmapArgs *mruns, const uint32_t *mstart,
+                                 uint32_t mblocks, hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (blocks) hipLaunchKernelGGL(k_sample_batch, dim3(blocks), dim3(256), 0, s, sruns, start, n);
-    hipLaunchKernelGGL(k_countfill_batch, dim3(n), dim3(1024), 0, s, mruns);
+    hipLaunchKernelGGL(k_countfill_batch, dim3(mblocks), dim3(1024), 0, s, mruns, mstart, n);
     return hipGetLastError();
 }
 
