@@ -51,10 +51,10 @@ OPS_PER_ATTEMPT = (INSTR_PER_ATTEMPT - MAD_PER_ATTEMPT) + MAD_PER_ATTEMPT * MAD_
 
 # HBM bytes per k_sweep launch on this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by 2.00 and 1.00, the factors the plain 256 MiB copy of
-# --copy-calibration gives): (7584.7 * 2 + 20156.1) KiB;
+# --copy-calibration gives): (7585.2 * 2 + 20156.1) KiB;
 # profiles/k_sweep_32x32_q10_R20000.md.  The algorithmic bytes are 2 * R * N =
 # 41 MB (gather + store); repeated ancestors are served from cache.
-SWEEP_TRAFFIC_BYTES = (7584.7 * 2.0 + 20156.1) * 1024
+SWEEP_TRAFFIC_BYTES = (7585.2 * 2.0 + 20156.1) * 1024
 
 WORKLOAD = dict(L=32, q=10, R=20000, K=401, beta_max=1.6, theta=10, seed=2)
 

@@ -994,6 +994,8 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
     return st;
 }
 
+}  // extern "C"
+
 // ---------------------------------------------------------------------------
 // Several runs per launch (batched runs and the serving loop): every run keeps
 // its own workspace region and plan; one "global step" advances each listed
@@ -1276,7 +1278,7 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
     return first;
 }
 
-pa_status pa_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes, void *stream,
+extern "C" pa_status pa_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes, void *stream,
                  pa_result *out) {
     pa_run_state *r = nullptr;
     pa_status st = pa_run_begin(ctx, desc, d_ws, ws_bytes, stream, &r);
@@ -1286,7 +1288,6 @@ pa_status pa_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_b
     return st ? st : st2;
 }
 
-}  // extern "C"
 
 // ---------------------------------------------------------------------------
 // Serving loop: continuous batching of PA runs inside a caller-provided arena.

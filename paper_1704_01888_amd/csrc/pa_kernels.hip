@@ -25,6 +25,8 @@ namespace pa {
 
 namespace {
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 constexpr uint32_t PHILOX_M0 = 0xD2511F53u;
 constexpr uint32_t PHILOX_M1 = 0xCD9E8D57u;
 constexpr uint32_t PHILOX_W0 = 0x9E3779B9u;
@@ -470,9 +472,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
             if (a.Mt_out) a.Mt_out[k] = mt;
             if (a.H_out) a.H_out[k] = dig;
         }
-        uint4 *gdst = reinterpret_cast<uint4 *>(a.new_pop + (size_t)k * N);
-        const uint4 *lsrc = reinterpret_cast<const uint4 *>(rep_lds + L);
-        for (uint32_t o = g; o < N / 16u; o += G) gdst[o] = lsrc[o];
+        // streaming stores: the new population is read back by the next step's
+        // gather, not through this kernel's L2, whose write-back at the end of
+        // the launch then has little to do
+        u32x4 *gdst = reinterpret_cast<u32x4 *>(a.new_pop + (size_t)k * N);
+        const u32x4 *lsrc = reinterpret_cast<const u32x4 *>(rep_lds + L);
+        for (uint32_t o = g; o < N / 16u; o += G) __builtin_nontemporal_store(lsrc[o], &gdst[o]);
     }
 }
 
