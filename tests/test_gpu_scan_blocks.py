@@ -6,8 +6,9 @@ Blocks hold one row of 4096 replicas up to 64 blocks and more rows beyond
 (R > 262144). The copy counts alternate between two buffers by step parity;
 each count-scan launch clears the other buffer over the extent the step before
 used, in strides of the launch's blocks. The cases: a population of several
-rows per block, and a Poisson population fluctuating around one block (4096)
-so that the clearing runs past one stride. Bar as for every parity test:
+rows per block; a Poisson population fluctuating around one block (4096), so
+that the clearing runs past one stride; strongly skewed weights (long runs of
+copies in the slot map). Bar as for every parity test:
 population sizes, histograms, copy numbers, ancestors, spins and digests
 bit-exact, ln Q and -beta F within 1e-12.
 """
@@ -28,6 +29,10 @@ CASES = [
     dict(L=4, q=5, R=300000, beta=linear_betas(1.4, 3), theta=2, seed=62, resample=0),
     # Poisson around one block: R_i crosses 4096 from step to step
     dict(L=8, q=4, R=4096, beta=linear_betas(1.2, 40), theta=1, seed=63, resample=0),
+    # strongly skewed weights (steps of up to 1.5 in beta): one ancestor takes
+    # about 14700 of 20000 copies, about 20 take more than 8 (written by the wave)
+    dict(L=8, q=3, R=20000, beta=np.array([0.0, 0.5, 1.5, 3.0]), theta=1, seed=64, resample=1),
+    dict(L=8, q=3, R=20000, beta=np.array([0.0, 0.5, 1.5, 3.0]), theta=1, seed=64, resample=0),
 ]
 
 
@@ -45,7 +50,7 @@ def _compare(got, want):
     np.testing.assert_allclose(got["minus_beta_F"], want["minus_beta_F"], rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"L{c['L']}R{c['R']}r{c['resample']}")
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"L{c['L']}R{c['R']}r{c['resample']}b{c['beta'][-1]:g}")
 def test_scan_blocks_parity(ctx, case):
     print(f"\ncase: L={case['L']} q={case['q']} R={case['R']} K={len(case['beta'])} "
           f"resample={case['resample']}", flush=True)
@@ -55,6 +60,8 @@ def test_scan_blocks_parity(ctx, case):
     if case["R"] == 4096:
         # the population did cross the block size in both directions
         assert (want["R_i"] > 4096).any() and (want["R_i"] <= 4096).any()
+    if case["beta"][-1] == 3.0:
+        assert np.bincount(want["last_anc"]).max() > 1000
 
 
 def test_scan_blocks_batched(ctx):
