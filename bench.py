@@ -29,25 +29,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Potts spin-flip attempts/ns on 1 MI355X (batched vs plain), p99 run latency"
 
-# VALU issue peak of MI355X for the instructions the sweep is made of:
-# 256 CUs x 64 lanes/clock x 2.4 GHz = 39.3e12 lane-ops/s.  Measured on the
-# device with dependent-free streams of one instruction kind: v_perm_b32,
-# v_bitop3_b32, v_bcnt_u32_b32, v_add3_u32, v_cmp + v_cndmask issue at
-# 36.7-38.3e12/s; v_mad_u64_u32 at 33.6e12/s (1.17 slots); v_mul_hi_u32 at
-# 20.8e12/s (1.9 slots).  (Plain VOP2 xor issues at twice the peak, 75e12/s;
-# the fp32 vector rate 157.3 TFLOP/s counts packed FMA.)
+# VALU issue peak of MI355X, one wave64 instruction per CU per clock:
+# 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 lane-instructions/s.  Measured with
+# streams of independent instructions: an uninterrupted stream of simple ops
+# (v_and/v_xor/v_add/v_sub/v_bitop3) issues at 1.5-1.67x that, every other
+# kind the sweep uses at 0.90-0.96x (v_perm, v_bcnt, v_lshl_add, v_xad,
+# v_and_or; a simple op with a scalar operand too), and mixed streams at
+# 0.95-1.055x (perm + bitop3 + xor: 1.055x).  The sweep is such a mix, so this
+# peak is its bound up to about 5 %; MIX_PEAK_LANE_OPS is the best measured
+# mixed-stream rate.  (The fp32 vector figure, 157.3 TFLOP/s, is the
+# dual-issue FMA rate, which integer mixes cannot use.)
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+MIX_PEAK_LANE_OPS = 1.055 * VALU_PEAK_LANE_OPS
 
-# Issue slots per spin-flip attempt of the sweep kernel (32x32 instance), from
-# its AMD assembly: the inner block updates 4 pairs (8 attempts) with 295 VALU
-# instructions, 73 of them v_mad_u64_u32 (Philox and the proposal), i.e. 36.9
-# instructions (9.1 wide multiplies) per attempt; the SQ_INSTS_VALU counter
-# agrees (38.6 per attempt including the gather/energy epilogue).  Weighted:
-# (36.9 - 9.1) + 9.1 * 1.17 = 38.5 slots.
-INSTR_PER_ATTEMPT = 295 / 8
-MAD_PER_ATTEMPT = 73 / 8
-MAD_SLOTS = 1.17
-OPS_PER_ATTEMPT = (INSTR_PER_ATTEMPT - MAD_PER_ATTEMPT) + MAD_PER_ATTEMPT * MAD_SLOTS
+# VALU lane-instructions per spin-flip attempt of k_sweep on this workload,
+# from rocprofv3 SQ_INSTS_VALU x 64 / attempts (gather, sweeps and energy
+# epilogue; profiles/k_sweep_32x32_q10_R20000.md).  The inner block alone:
+# 295 instructions per 8 attempts, 72 of them v_mad_u64_u32.
+INSTR_PER_ATTEMPT = 38.80
 
 # HBM bytes per k_sweep launch on this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by 2.00 and 1.00, the factors the plain 256 MiB copy of
@@ -259,7 +258,7 @@ def main():
     sweep_s = kernel_ms[sweep] / 1e3
     sweep_avg_ms = kernel_ms[sweep] / max(kernel_n[sweep], 1)
     sweep_rate = prof_att / sweep_s if sweep_s > 0 else 0.0   # attempts/s inside the sweep kernel
-    achieved = sweep_rate * OPS_PER_ATTEMPT / 1e12
+    achieved = sweep_rate * INSTR_PER_ATTEMPT / 1e12
     peak = VALU_PEAK_LANE_OPS / 1e12
     result = {
         "metric": METRIC,
@@ -286,10 +285,11 @@ def main():
             "kernel": "k_sweep",
             "achieved": achieved,
             "peak": peak,
-            "unit": "T lane-ops/s",
+            "unit": "T lane-instructions/s",
             "frac": achieved / peak,
             "traffic": SWEEP_TRAFFIC_BYTES,
-            "ops_per_attempt": OPS_PER_ATTEMPT,
+            "instr_per_attempt": INSTR_PER_ATTEMPT,
+            "frac_of_measured_mix_peak": achieved / (MIX_PEAK_LANE_OPS / 1e12),
             "sweep_attempts_per_ns": sweep_rate / 1e9,
             "sweep_avg_launch_ms": sweep_avg_ms,
         },
