@@ -382,7 +382,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     const bool live = k64 < a.R_new;
     const uint32_t k = G >= 64 ? __builtin_amdgcn_readfirstlane((uint32_t)k64) : (uint32_t)k64;
 
-    const uint32_t L = a.L, N = a.N, DPR = L >> 2;
+    // compile-time shape where the kernel has one (LT != 0): the prologue and
+    // epilogue loops then have constant bounds and strides
+    const uint32_t L = LT ? LT : a.L, N = LT ? LT * LT : a.N, DPR = L >> 2;
     uint8_t *rep_lds = smem + 128 + (size_t)rep * (N + 2 * L);
     uint32_t *lds32 = reinterpret_cast<uint32_t *>(rep_lds);
     uint32_t *rows32 = lds32 + DPR;                              // row 0
