@@ -173,10 +173,12 @@ void pa_ctx_destroy(pa_ctx *ctx);
  * stream and report the summed durations in pa_result.kernel_ms. */
 pa_status pa_ctx_set_profiling(pa_ctx *ctx, int enable);
 
-/* Sweep kernel shape.  For L a power of two up to 256 the sweep kernel exists
- * for two lane counts per replica (fewer than a wave: several replicas per
- * wave; more than a wave: one replica per workgroup); results do not depend
- * on the choice.  pa_ctx_get_lanes reports the lanes later runs will use and
+/* Sweep kernel shape.  For L a power of two up to 256 and for L = 12, 20, 24,
+ * 48, 96, 192 the sweep kernel exists for one or two lane counts per replica
+ * (a divisor of 64: several replicas per wave; a multiple of 64: one replica
+ * per workgroup; neither, at L = 12, 20, 24: replicas spanning waves, several
+ * per workgroup); results do not depend on the choice.  Other L use one
+ * generic shape.  pa_ctx_get_lanes reports the lanes later runs will use and
  * the candidates (0 lanes and no candidates for the tiled path, L > 256);
  * pa_ctx_set_lanes picks one (0 = default) for later runs.
  * pa_autotune times every candidate on a synthetic population of about 64 MB

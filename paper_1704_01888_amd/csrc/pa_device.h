@@ -168,11 +168,12 @@ uint32_t lane_candidates(uint32_t L, uint32_t *out /*[2]*/);
 // Lanes per replica (log2) and waves per block for a lattice side L; `lanes`
 // selects a candidate (anything else: the default).
 void sweep_shape(uint32_t L, uint32_t lanes, uint32_t *G, uint32_t *waves_per_block);
-size_t sweep_lds_bytes(uint32_t N, uint32_t G, uint32_t waves_per_block);
+// q_counters: q when the sweep counts states for M~ (eq. (5)), else 0
+size_t sweep_lds_bytes(uint32_t N, uint32_t G, uint32_t waves_per_block, uint32_t q_counters);
 uint64_t replicas_per_block(uint32_t G, uint32_t waves_per_block);
 // index of L in the table of lattices with lane choices (-1: none), and its size
 int lane_choice_index(uint32_t L);
-constexpr int LANE_CHOICE_COUNT = 10;
+constexpr int LANE_CHOICE_COUNT = 13;
 // Largest dynamic LDS a workgroup may use on the current device.
 size_t max_lds_per_block(int device);
 

@@ -784,7 +784,8 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
     r->G = 0;
     r->wpb = 0;
     if (!p.tiled) pa::sweep_shape(p.desc.L, ctx_lanes(ctx, p.desc.L), &r->G, &r->wpb);
-    if (!p.tiled && pa::sweep_lds_bytes(p.N, r->G, r->wpb) > pa::max_lds_per_block(ctx->device)) {
+    if (!p.tiled && pa::sweep_lds_bytes(p.N, r->G, r->wpb, p.mag ? p.desc.q : 0u) >
+                        pa::max_lds_per_block(ctx->device)) {
         delete r;
         return fail(PA_ERR_UNSUPPORTED, "lattice does not fit the LDS of one workgroup on this device");
     }
@@ -1071,7 +1072,7 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
         e.cls = pa::sweep_class(p.desc.L, p.desc.q, a.T[3] == 0, r->G);
         e.blocks = (uint32_t)((R_new + per_block - 1) / per_block);
         e.threads = 64u * r->wpb;
-        e.lds = pa::sweep_lds_bytes(p.N, r->G, r->wpb);
+        e.lds = pa::sweep_lds_bytes(p.N, r->G, r->wpb, p.mag ? p.desc.q : 0u);
         e.a = a;
         sw.push_back(e);
         r->cur = new_buf;
@@ -1101,6 +1102,7 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
     for (size_t k = 0; k < sw.size();) {
         StepLaunch::Group G{sw[k].cls, (uint32_t)starts.size(), 0, 0, sw[k].threads, sw[k].lds};
         while (k < sw.size() && sw[k].cls == G.cls) {
+            G.lds = std::max(G.lds, sw[k].lds);   // runs of one class may differ in q and outputs
             starts.push_back(G.blocks);
             G.blocks += sw[k].blocks;
             ++G.count;

@@ -309,7 +309,7 @@ __device__ __forceinline__ void sweeps_fixed(uint32_t *lds32, uint32_t g, uint32
                     if (j + u == PPL - 1 && bottom) lds32[idx[u] - L * DPR] = nw;
                 }
             }
-            replica_fence(G > 64);
+            replica_fence(64u % G != 0u);
         }
     }
 }
@@ -344,7 +344,7 @@ __device__ __forceinline__ void sweeps_any(uint32_t *lds32, uint32_t g, uint32_t
                 if (j0 >= H) { j0 -= H; ++y; }
                 y += dy;
             }
-            replica_fence(G > 64);
+            replica_fence(64u % G != 0u);
         }
     }
 }
@@ -357,9 +357,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     // thresholds indexed by dE + 4
     if (threadIdx.x == 32) reinterpret_cast<uint32_t *>(smem)[24] = 0u;   // energy sum (multi-wave)
     if (threadIdx.x == 33) reinterpret_cast<uint64_t *>(smem)[13] = 0ull; // digest sum (multi-wave)
-    if (a.Mt_out && a.G > 64) {      // per-state counters of a multi-wave replica, after its rows
+    if (a.Mt_out && a.G > 64 && a.G % 64u == 0) {   // per-state counters of a multi-wave replica, after its rows
         uint32_t *mcnt = reinterpret_cast<uint32_t *>(smem + 128 + a.N + 2 * a.L);
         for (uint32_t t = threadIdx.x; t < a.q; t += blockDim.x) mcnt[t] = 0u;
+    }
+    if (64u % a.G != 0 && a.G % 64u != 0) {       // sums of spanning replicas, after all rows
+        const uint32_t nr = blockDim.x / a.G;
+        uint8_t *acc = smem + 128 + (size_t)nr * (a.N + 2 * a.L);
+        const uint32_t words = nr * (3u + (a.Mt_out ? a.q : 0u));
+        for (uint32_t t = threadIdx.x; t < words; t += blockDim.x) reinterpret_cast<uint32_t *>(acc)[t] = 0u;
     }
     if (threadIdx.x < 9) {
         const int dE = (int)threadIdx.x - 4;
@@ -370,17 +376,26 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     __syncthreads();
     const Thresholds<T64> thr{smem};
 
-    const uint32_t G = a.G;                                      // lanes per replica
-    const bool multiwave = G > 64;                               // one replica per block
+    // Lanes per replica G: a divisor of 64 (one or several replicas per wave),
+    // a multiple of 64 (one replica per block of G/64 waves), or neither
+    // (replicas span wave boundaries, several per block: "spanning").  Every
+    // replica not inside one wave separates its half-sweeps with barriers.
+    const uint32_t G = GT ? GT : a.G;
+    const bool multiwave = G > 64 && G % 64u == 0;               // one replica per block
+    const bool span = 64u % G != 0 && !multiwave;
+    const bool barrier = multiwave || span;
     const uint32_t wave = threadIdx.x >> 6;
-    const uint32_t g = multiwave ? threadIdx.x : (threadIdx.x & (G - 1u));
+    const uint32_t g = multiwave ? threadIdx.x : threadIdx.x % G;
     const uint32_t rpb = multiwave ? 1u : (64u * a.waves_per_block) / G;   // replicas per block
     const uint32_t rep = multiwave ? 0u : threadIdx.x / G;                 // replica within block
     const uint64_t k64 = (uint64_t)block * rpb + rep;
-    const uint64_t first_in_wave = multiwave ? (uint64_t)block : (uint64_t)block * rpb + (wave * 64u) / G;
-    if (first_in_wave >= a.R_new) return;                        // whole wave (replica) idle
+    // idle waves leave; with barriers only a whole idle block may
+    const uint64_t first_idle = multiwave ? (uint64_t)block
+                                          : (uint64_t)block * rpb + (span ? 0u : (wave * 64u) / G);
+    if (first_idle >= a.R_new) return;
     const bool live = k64 < a.R_new;
-    const uint32_t k = G >= 64 ? __builtin_amdgcn_readfirstlane((uint32_t)k64) : (uint32_t)k64;
+    // wave-uniform when a wave holds (part of) one replica only
+    const uint32_t k = G % 64u == 0 ? __builtin_amdgcn_readfirstlane((uint32_t)k64) : (uint32_t)k64;
 
     // compile-time shape where the kernel has one (LT != 0): the prologue and
     // epilogue loops then have constant bounds and strides
@@ -408,12 +423,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         const uint32_t alpha = mulhi32(w.x, a.q) * 0x01010101u;
         for (uint32_t dd = g; dd < N / 4u; dd += G) rows32[dd] = alpha;
     }
-    replica_fence(multiwave);
+    replica_fence(barrier);
     for (uint32_t dd = g; dd < DPR; dd += G) {                   // periodic halo rows
         lds32[dd] = rows32[(L - 1) * DPR + dd];
         lds32[(L + 1) * DPR + dd] = rows32[dd];
     }
-    replica_fence(multiwave);
+    replica_fence(barrier);
 
     // ---- theta checkerboard sweeps --------------------------------------
     const uint32_t theta = (a.mode == SWEEP_UPDATE) ? a.theta : 0u;
@@ -431,12 +446,24 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         const uint32_t right = __builtin_amdgcn_alignbyte(Dr, D, 1);
         bonds += eq_bytes(D, right) + eq_bytes(D, Dd);
     }
-    for (uint32_t off = (G < 64 ? G : 64) >> 1; off > 0; off >>= 1) bonds += __shfl_xor(bonds, off, 64);
-    if (multiwave) {
-        uint32_t *sum = reinterpret_cast<uint32_t *>(smem) + 24;
-        if ((threadIdx.x & 63u) == 0) atomicAdd(sum, bonds);
+    // per-replica sums of spanning replicas: digest [rpb] u64, bonds [rpb],
+    // per-state counts [rpb][q] u32, after all replicas' rows
+    uint8_t *acc = smem + 128 + (size_t)rpb * (N + 2 * L);
+    unsigned long long *acc_d = reinterpret_cast<unsigned long long *>(acc);
+    uint32_t *acc_e = reinterpret_cast<uint32_t *>(acc + 8u * rpb);
+    uint32_t *acc_m = acc_e + rpb;
+    if (span) {
+        atomicAdd(&acc_e[rep], bonds);
         __syncthreads();
-        bonds = *sum;
+        bonds = acc_e[rep];
+    } else {
+        for (uint32_t off = (G < 64 ? G : 64) >> 1; off > 0; off >>= 1) bonds += __shfl_xor(bonds, off, 64);
+        if (multiwave) {
+            uint32_t *sum = reinterpret_cast<uint32_t *>(smem) + 24;
+            if ((threadIdx.x & 63u) == 0) atomicAdd(sum, bonds);
+            __syncthreads();
+            bonds = *sum;
+        }
     }
     // ---- magnetisation (eq. (5)): M~ = the largest number of sites in one state
     uint32_t mt = 0;
@@ -446,20 +473,31 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
             const uint32_t pat = st * 0x01010101u;
             uint32_t c = 0;
             for (uint32_t dd = g; dd < N / 4u; dd += G) c += eq_bytes(rows32[dd], pat);
+            if (span) {
+                atomicAdd(&acc_m[rep * a.q + st], c);
+                continue;
+            }
             for (uint32_t off = (G < 64 ? G : 64) >> 1; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
             if (!multiwave) mt = max(mt, c);
             else if ((threadIdx.x & 63u) == 0) atomicAdd(&mcnt[st], c);
         }
-        if (multiwave) {
+        if (multiwave || span) {
             __syncthreads();
-            for (uint32_t st = 0; st < a.q; ++st) mt = max(mt, mcnt[st]);
+            const uint32_t *cnt = span ? acc_m + rep * a.q : mcnt;
+            for (uint32_t st = 0; st < a.q; ++st) mt = max(mt, cnt[st]);
         }
     }
     // ---- digest term of the replica (order-free sum over its dwords)
     uint64_t dig = 0;
     if (a.H_out) {
         for (uint32_t dd = g; dd < N / 4u; dd += G) dig += digest_term(dd, k, a.step, rows32[dd], a.key0, a.key1);
-        for (uint32_t off = (G < 64 ? G : 64) >> 1; off > 0; off >>= 1) dig += __shfl_xor(dig, off, 64);
+        if (span) {
+            atomicAdd(&acc_d[rep], (unsigned long long)dig);
+            __syncthreads();
+            dig = acc_d[rep];
+        } else {
+            for (uint32_t off = (G < 64 ? G : 64) >> 1; off > 0; off >>= 1) dig += __shfl_xor(dig, off, 64);
+        }
         if (multiwave) {
             unsigned long long *sum = reinterpret_cast<unsigned long long *>(smem) + 13;
             if ((threadIdx.x & 63u) == 0) atomicAdd(sum, (unsigned long long)dig);
@@ -1344,7 +1382,10 @@ struct LaneChoice { uint32_t L, lanes[2]; };
 static const LaneChoice kLaneChoices[LANE_CHOICE_COUNT] = {
     {4, {4, 4}},
     {8, {8, 4}},
+    {12, {36, 12}},       // replicas span waves: 16 per block of 9 or 3 waves
     {16, {16, 8}},
+    {20, {20, 10}},       // 16 or 32 replicas per block of 5 waves
+    {24, {48, 72}},       // 4 or 8 replicas per block of 3 or 9 waves
     {32, {64, 32}},
     {48, {192, 192}},     // three waves per replica
     {64, {64, 256}},
@@ -1385,8 +1426,14 @@ void sweep_shape(uint32_t L, uint32_t lanes, uint32_t *G_out, uint32_t *waves_pe
         else { G = 4; while (G < 64 && 2 * G <= (L * L) / 4u) G *= 2; }
     }
     *G_out = G;
-    if (G > 64) {                      // one replica per workgroup of G/64 waves
+    if (G > 64 && G % 64 == 0) {       // one replica per workgroup of G/64 waves
         *waves_per_block = G / 64;
+        return;
+    }
+    if (64 % G != 0) {                 // replicas span waves: lcm(G, 64) lanes per workgroup
+        uint32_t w = 1;
+        while ((64 * w) % G != 0) ++w;
+        *waves_per_block = w;
         return;
     }
     const uint32_t N = L * L;
@@ -1397,14 +1444,19 @@ void sweep_shape(uint32_t L, uint32_t lanes, uint32_t *G_out, uint32_t *waves_pe
 }
 
 uint64_t replicas_per_block(uint32_t G, uint32_t waves_per_block) {
-    return G > 64 ? 1u : (64u * waves_per_block) / G;
+    return (G > 64 && G % 64 == 0) ? 1u : (64u * waves_per_block) / G;
 }
 
-size_t sweep_lds_bytes(uint32_t N, uint32_t G, uint32_t waves_per_block) {
+size_t sweep_lds_bytes(uint32_t N, uint32_t G, uint32_t waves_per_block, uint32_t q_counters) {
     uint32_t L = 0;
     while (L * L < N) ++L;
-    // a multi-wave replica also keeps its 255 per-state counters (eq. (5)) in LDS
-    return 128u + (size_t)replicas_per_block(G, waves_per_block) * (N + 2 * L) + (G > 64 ? 1024u : 0u);
+    const uint64_t rpb = replicas_per_block(G, waves_per_block);
+    size_t b = 128u + (size_t)rpb * (N + 2 * L);
+    // a multi-wave replica also keeps its 255 per-state counters (eq. (5)) in LDS;
+    // spanning replicas keep their digest, bond and per-state sums after the rows
+    if (G > 64 && G % 64 == 0) b += 1024u;
+    else if (64 % G != 0) b += (size_t)rpb * (12u + 4u * q_counters);
+    return b;
 }
 
 size_t max_lds_per_block(int device) {
@@ -1418,7 +1470,7 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t s) {
     const uint64_t per_block = replicas_per_block(a.G, a.waves_per_block);
     const uint64_t blocks = (a.R_new + per_block - 1) / per_block;
     if (blocks == 0) return hipSuccess;
-    const size_t lds = sweep_lds_bytes(a.N, a.G, a.waves_per_block);
+    const size_t lds = sweep_lds_bytes(a.N, a.G, a.waves_per_block, a.Mt_out ? a.q : 0u);
     void *kern = sweep_kernel(sweep_class(a.L, a.q, a.T[3] == 0, a.G), false);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1458,7 +1510,10 @@ void *sweep_kernel(uint32_t cls, bool batch) {
     if (!t64) {
         PA_INST(4, 4)
         PA_INST(8, 8) PA_INST(8, 4)
+        PA_INST(12, 12) PA_INST(12, 36)
         PA_INST(16, 16) PA_INST(16, 8)
+        PA_INST(20, 10) PA_INST(20, 20)
+        PA_INST(24, 48) PA_INST(24, 72)
         PA_INST(32, 64) PA_INST(32, 32)
         PA_INST(48, 192)
         PA_INST(64, 64) PA_INST(64, 256)
