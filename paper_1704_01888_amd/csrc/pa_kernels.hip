@@ -1568,8 +1568,8 @@ uint32_t tiled_rows(uint32_t L) {
 }
 
 // Each fused half-sweep beyond the first recomputes two rows per side; two
-// per launch measured best for L = 512 .. 4096 (one or four: 0-25 % slower,
-// taller tiles: slower still).
+// per launch measured best for L = 512 .. 4096 (one, three or four: 0-25 %
+// slower, taller tiles: slower still).
 uint32_t tiled_max_halves(uint32_t L) {
     (void)L;
     return 2u;
