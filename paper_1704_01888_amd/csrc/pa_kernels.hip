@@ -1381,17 +1381,17 @@ __global__ void k_tiled_finalize(TiledArgs a) {
 struct LaneChoice { uint32_t L, lanes[2]; };
 static const LaneChoice kLaneChoices[LANE_CHOICE_COUNT] = {
     {4, {4, 4}},
-    {8, {8, 4}},
+    {8, {16, 8}},
     {12, {36, 12}},       // replicas span waves: 16 per block of 9 or 3 waves
-    {16, {16, 8}},
+    {16, {64, 32}},
     {20, {20, 10}},       // 16 or 32 replicas per block of 5 waves
-    {24, {48, 72}},       // 4 or 8 replicas per block of 3 or 9 waves
-    {32, {64, 32}},
-    {48, {192, 192}},     // three waves per replica
-    {64, {64, 256}},
-    {96, {192, 384}},     // three or six waves per replica
-    {128, {256, 512}},
-    {192, {384, 768}},
+    {24, {48, 144}},      // 4 replicas per block of 3 or 9 waves
+    {32, {256, 128}},
+    {48, {192, 576}},     // three or nine waves per replica
+    {64, {512, 1024}},
+    {96, {768, 384}},     // twelve or six waves per replica
+    {128, {1024, 512}},
+    {192, {768, 384}},
     {256, {1024, 512}},
 };
 
@@ -1509,16 +1509,16 @@ void *sweep_kernel(uint32_t cls, bool batch) {
                      : (qs ? (void *)k_sweep<LV, GV, true, false> : (void *)k_sweep<LV, GV, false, false>);
     if (!t64) {
         PA_INST(4, 4)
-        PA_INST(8, 8) PA_INST(8, 4)
+        PA_INST(8, 8) PA_INST(8, 4) PA_INST(8, 16)
         PA_INST(12, 12) PA_INST(12, 36)
-        PA_INST(16, 16) PA_INST(16, 8)
+        PA_INST(16, 16) PA_INST(16, 8) PA_INST(16, 32) PA_INST(16, 64)
         PA_INST(20, 10) PA_INST(20, 20)
-        PA_INST(24, 48) PA_INST(24, 72)
-        PA_INST(32, 64) PA_INST(32, 32)
-        PA_INST(48, 192)
-        PA_INST(64, 64) PA_INST(64, 256)
-        PA_INST(96, 192) PA_INST(96, 384)
-        PA_INST(128, 256) PA_INST(128, 512)
+        PA_INST(24, 48) PA_INST(24, 72) PA_INST(24, 144)
+        PA_INST(32, 64) PA_INST(32, 32) PA_INST(32, 128) PA_INST(32, 256)
+        PA_INST(48, 192) PA_INST(48, 576)
+        PA_INST(64, 64) PA_INST(64, 256) PA_INST(64, 128) PA_INST(64, 512) PA_INST(64, 1024)
+        PA_INST(96, 192) PA_INST(96, 384) PA_INST(96, 768)
+        PA_INST(128, 256) PA_INST(128, 512) PA_INST(128, 128) PA_INST(128, 1024)
         PA_INST(192, 384) PA_INST(192, 768)
         PA_INST(256, 1024) PA_INST(256, 512)
     }

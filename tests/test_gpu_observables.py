@@ -61,16 +61,19 @@ def test_magnetisation_and_widths_parity(ctx, case):
 
 
 def test_multiwave_replicas_of_64x64(ctx):
-    """64 x 64 with 256 lanes (four waves) per replica."""
-    cur, cand = ctx.get_lanes(64)
-    assert 256 in cand
+    """64 x 64 with each candidate of several waves per replica (per-state
+    counts, bond and digest sums across waves)."""
+    _, cand = ctx.get_lanes(64)
+    multi = [g for g in cand if g > 64]
+    assert multi
     case = dict(L=64, q=8, R=50, beta=linear_betas(1.5, 4), theta=2, seed=39, resample=0, bin_e=2)
+    want = _oracle(case)
     try:
-        ctx.set_lanes(64, 256)
-        got = pa.pa_run(ctx, pa.Desc(outputs=ALL, **case))
+        for g in multi:
+            ctx.set_lanes(64, g)
+            _check_same(pa.pa_run(ctx, pa.Desc(outputs=ALL, **case)), want)
     finally:
-        ctx.set_lanes(64, cur)
-    _check_same(got, _oracle(case))
+        ctx.set_lanes(64, 0)
 
 
 def test_magnetisation_without_stored_histograms(ctx):
