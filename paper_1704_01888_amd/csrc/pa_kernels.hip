@@ -556,37 +556,6 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// Exclusive scan of one value per thread over the block; *total receives the
-// block sum.  scratch holds blockDim/64 + 1 entries.
-template <typename T>
-__device__ __forceinline__ T block_exclusive_scan(T v, T *scratch, T *total) {
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    T incl = v;
-#pragma unroll
-    for (uint32_t off = 1; off < 64; off <<= 1) {
-        const T n = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += n;
-    }
-    if (lane == 63) scratch[wave] = incl;
-    __syncthreads();
-    if (wave == 0) {
-        T w = lane < nw ? scratch[lane] : T(0);
-        T wi = w;
-#pragma unroll
-        for (uint32_t off = 1; off < 16; off <<= 1) {
-            const T n = __shfl_up(wi, off, 64);
-            if (lane >= off) wi += n;
-        }
-        if (lane < nw) scratch[lane] = wi - w;
-        if (lane == nw - 1) scratch[nw] = wi;
-    }
-    __syncthreads();
-    const T res = scratch[wave] + incl - v;
-    *total = scratch[nw];
-    __syncthreads();
-    return res;
-}
-
 // Inclusive scan over the 64 lanes of a wave.
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T v) {
@@ -1225,10 +1194,14 @@ __global__ void __launch_bounds__(NTT) k_tiled_fixed(TiledArgs a) {
     uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem + 128);
     const uint32_t src = a.anc ? a.anc[k] : k;
     const uint32_t *src32 = reinterpret_cast<const uint32_t *>(a.src + (size_t)src * a.N);
+    static_assert(DPR % 64 == 0, "whole waves per row");
     for (uint32_t r = threadIdx.x >> 6; r < nl; r += NT / 64) {
         const uint32_t gy = (y0 + r + L - S) & (L - 1);
 #pragma unroll
-        for (uint32_t x = threadIdx.x & 63u; x < DPR; x += 64u) lds32[r * DPR + x] = src32[gy * DPR + x];
+        for (uint32_t c = 0; c < DPR / 64; ++c) {
+            const uint32_t x = (threadIdx.x & 63u) + 64u * c;
+            lds32[r * DPR + x] = src32[gy * DPR + x];
+        }
     }
     __syncthreads();
     const Thresholds<T64> thr{smem};
