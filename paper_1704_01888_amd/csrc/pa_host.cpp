@@ -1001,8 +1001,9 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
 // Several runs per launch (batched runs and the serving loop): every run keeps
 // its own workspace region and plan; one "global step" advances each listed
 // run by one temperature step with segmented launches (one sampling launch
-// over all runs' draws, one count-scan workgroup per run, one sweep launch per
-// kernel class, one post workgroup per run).  The descriptor records are built
+// over all runs' draws, one count-scan launch over all runs' blocks, one sweep
+// launch per kernel class, one post launch over all runs' statistics and
+// weight workgroups).  The descriptor records are built
 // on the host and uploaded before the launches.
 // ---------------------------------------------------------------------------
 namespace {

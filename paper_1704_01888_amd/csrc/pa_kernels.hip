@@ -6,19 +6,22 @@
 //                    theta checkerboard Metropolis sweeps (step 3) held in LDS,
 //                    then the energy of eq. (3) (and M~ of eq. (5)) per replica.
 //   k_tiled_*      : the same for lattices beyond one workgroup's LDS, in HBM.
-//   k_post         : the energy (and M~) histograms from the per-replica values,
-//                    population sums for eq. (4), the reference energy and ln Q
-//                    of step 2 / eq. (2) in FP64, histogram widths (Sec. 4),
-//                    then the integer weights W(|E_j - E_ref|) of the next
-//                    resampling and their scan.
+//   k_post         : workgroup 0: the energy (and M~) histograms from the
+//                    per-replica values, population sums for eq. (4), the
+//                    reference energy and ln Q of step 2 / eq. (2) in FP64,
+//                    histogram widths (Sec. 4); workgroups 1, 2, ...: the
+//                    integer weights W(|E_j - E_ref|) of the next resampling
+//                    and their scan, one block of replicas each.
 //   k_sample       : the multinomial draws of the resampling step.
-//   k_countfill    : exclusive scan of the copy numbers -> ancestor of each new slot.
+//   k_countfill    : exclusive scan of the copy numbers -> ancestor of each new
+//                    slot, one block of ancestors per workgroup.
 //   *_batch        : the same for several runs in one launch.
 //
 // A replica held in LDS is updated by G lanes: part of a wave (small L), one
-// wave, or several waves.  Within one wave the two half-sweeps of a sweep need
-// no workgroup barrier (LDS operations of a wave execute in order; a compiler
-// fence keeps the half-sweeps apart); a multi-wave replica uses barriers.
+// or several waves, or lanes spanning wave boundaries.  Within one wave the two
+// half-sweeps of a sweep need no workgroup barrier (LDS operations of a wave
+// execute in order; a compiler fence keeps the half-sweeps apart); a replica
+// spread over several waves uses barriers.
 #include "pa_device.h"
 
 namespace pa {
