@@ -951,13 +951,9 @@ __device__ void countfill_block(const SlotmapArgs &a, uint32_t b, uint64_t *scra
         const uint64_t c1 = min(c0 + a.block, a.clear_n);
         for (uint64_t i = c0 + tid; i < c1; i += blockDim.x) a.r_clear[i] = 0u;
     }
-    uint64_t carry = 0;
-    for_each_tiled(a.r, first, [&](uint32_t c) { carry += c; });
-    carry = block_reduce(carry, [](uint64_t x, uint64_t y) { return x + y; }, scratch);
-    __syncthreads();
-    for (uint32_t base = first; base < last; base += blockDim.x * 4u) {
-        const uint32_t j = base + tid * 4u;
-        uint32_t r[4];
+    // the block's rows do not depend on the sum before it: the first row's
+    // counts are loaded before that sum, so that the two reads overlap
+    auto load_row = [&](uint32_t j, uint32_t r[4]) {
         if (j + 4u <= last) {
             const uint4 x = *reinterpret_cast<const uint4 *>(a.r + j);
             r[0] = x.x; r[1] = x.y; r[2] = x.z; r[3] = x.w;
@@ -965,6 +961,16 @@ __device__ void countfill_block(const SlotmapArgs &a, uint32_t b, uint64_t *scra
 #pragma unroll
             for (uint32_t v = 0; v < 4; ++v) r[v] = j + v < last ? a.r[j + v] : 0u;
         }
+    };
+    uint32_t r[4];
+    load_row(first + tid * 4u, r);
+    uint64_t carry = 0;
+    for_each_tiled(a.r, first, [&](uint32_t c) { carry += c; });
+    carry = block_reduce(carry, [](uint64_t x, uint64_t y) { return x + y; }, scratch);
+    __syncthreads();
+    for (uint32_t base = first; base < last; base += blockDim.x * 4u) {
+        const uint32_t j = base + tid * 4u;
+        if (base != first) load_row(j, r);
         // offsets within the row in 32 bits (a row's counts sum to at most the
         // new population, below 2^32)
         const uint32_t sum = r[0] + r[1] + r[2] + r[3];
