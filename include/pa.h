@@ -203,8 +203,13 @@ pa_status pa_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_b
  * pa_run_read: synchronous copy of the current population (any pointer NULL
  *   to skip): spins[R_cur][N], E[R_cur], anc[R_cur] (ancestors of the last
  *   resampling), counts[R_prev] (copy numbers of the last resampling).
+ * pa_run_read_free_energy: synchronous read of the current step and its
+ *   -beta F (eq. (2), accumulated so far).
  * pa_run_load: replace the current population by host spins[R_cur][N] at step
- *   `step` with -beta F value minus_beta_F (resume from a checkpoint).
+ *   `step` with -beta F value minus_beta_F (resume from a checkpoint: the
+ *   population and -beta F of pa_run_read and pa_run_read_free_energy at that
+ *   step; the continuation is bit-identical, and pa_run_finish then reports
+ *   the steps from `step` on).
  * pa_run_read_slots: see below.
  * pa_run_finish: wait, copy the per-step results into `out` (may be NULL) and
  *   release the run. */
@@ -214,6 +219,7 @@ pa_status pa_run_advance(pa_run_state *run, uint32_t n_steps);
 pa_status pa_run_sync(pa_run_state *run);
 pa_status pa_run_read(pa_run_state *run, uint32_t *step, uint64_t *R_cur, uint64_t *R_prev,
                       uint8_t *spins, int32_t *E, uint32_t *anc, uint32_t *counts);
+pa_status pa_run_read_free_energy(pa_run_state *run, uint32_t *step, double *minus_beta_F);
 pa_status pa_run_load(pa_run_state *run, uint32_t step, uint64_t R_cur, const uint8_t *spins,
                       double minus_beta_F);
 /* Synchronous copy of n selected replicas: from the current population

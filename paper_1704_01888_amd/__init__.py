@@ -28,6 +28,7 @@ EXPORTS = [
     "pa_ctx_set_profiling", "pa_ctx_set_lanes", "pa_ctx_get_lanes", "pa_autotune",
     "pa_ctx_set_graphs",
     "pa_run", "pa_run_begin", "pa_run_advance", "pa_run_sync", "pa_run_read", "pa_run_load",
+    "pa_run_read_free_energy",
     "pa_run_read_slots", "pa_run_finish", "pa_status_str", "pa_last_error",
     "pa_plan_batch", "pa_run_batch",
     "pa_serve_start", "pa_serve_submit", "pa_serve_wait", "pa_serve_cancel", "pa_serve_stop",
@@ -113,6 +114,7 @@ def lib() -> ctypes.CDLL:
     L.pa_run_sync.argtypes = [vp]
     L.pa_run_read.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.pa_run_load.argtypes = [vp, u32, u64, vp, dbl]
+    L.pa_run_read_free_energy.argtypes = [vp, vp, vp]
     L.pa_run_finish.argtypes = [vp, P(Result)]
     L.pa_run_read_slots.argtypes = [vp, ctypes.c_int, vp, u32, vp]
     L.pa_plan_batch.argtypes = [P(RunDesc), u32, P(u64)]
@@ -379,6 +381,35 @@ class Run:
         s = np.ascontiguousarray(spins, dtype=np.uint8)
         _check(lib().pa_run_load(self.handle, int(step), int(s.shape[0]), _ptr(s),
                                  float(minus_beta_F)))
+
+    def free_energy(self):
+        """(step, -beta F of the current step)."""
+        step, v = ctypes.c_uint32(), ctypes.c_double()
+        _check(lib().pa_run_read_free_energy(self.handle, ctypes.byref(step), ctypes.byref(v)))
+        return int(step.value), float(v.value)
+
+    def checkpoint(self, path):
+        """Write the current step, population and -beta F with the run
+        description to `path` (numpy .npz, no pickled objects)."""
+        spins = self.read(E=False, anc=False, counts=False)["spins"]
+        step, mbf = self.free_energy()
+        d = self.desc
+        np.savez(path, step=step, spins=spins, minus_beta_F=mbf, L=d.L, q=d.q, R=d.R, beta=d.beta,
+                 theta=d.theta, seed=d.seed, resample=d.resample, init=d.init, outputs=d.outputs,
+                 bin_e=d.bin_e, bin_m=d.bin_m)
+
+    @classmethod
+    def resume(cls, ctx: "Context", path, workspace=None) -> "Run":
+        """A run continued from a checkpoint file; it finishes bit-identically
+        to the run the checkpoint was taken from (results from the checkpoint
+        step on)."""
+        with np.load(path) as z:
+            desc = Desc(int(z["L"]), int(z["q"]), int(z["R"]), z["beta"], int(z["theta"]),
+                        int(z["seed"]), resample=int(z["resample"]), init=int(z["init"]),
+                        outputs=int(z["outputs"]), bin_e=int(z["bin_e"]), bin_m=int(z["bin_m"]))
+            run = cls(ctx, desc, workspace)
+            run.load(int(z["step"]), z["spins"], float(z["minus_beta_F"]))
+        return run
 
     def read_slots(self, slots, previous=False):
         sl = np.ascontiguousarray(slots, dtype=np.uint32)

@@ -880,6 +880,15 @@ pa_status pa_run_read(pa_run_state *r, uint32_t *step, uint64_t *R_cur, uint64_t
     return PA_OK;
 }
 
+pa_status pa_run_read_free_energy(pa_run_state *r, uint32_t *step, double *minus_beta_F) {
+    if (!r || !minus_beta_F) return fail(PA_ERR_INVALID, "null run or output");
+    pa_status st = hip_check(r, hipStreamSynchronize(r->stream), "sync");
+    if (st) return st;
+    if (step) *step = r->step;
+    return hip_check(r, hipMemcpy(minus_beta_F, r->at<double>(r->plan.off_mbF) + r->step, 8,
+                                  hipMemcpyDeviceToHost), "read");
+}
+
 pa_status pa_run_load(pa_run_state *r, uint32_t step, uint64_t R_cur, const uint8_t *spins,
                       double minus_beta_F) {
     if (!r || !spins) return fail(PA_ERR_INVALID, "null run or spins");

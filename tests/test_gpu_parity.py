@@ -155,6 +155,31 @@ def test_load_resume_is_bit_identical(ctx):
     np.testing.assert_allclose(res["minus_beta_F"][5:], full["minus_beta_F"][5:], rtol=RTOL)
 
 
+def test_checkpoint_file_mid_run(ctx, tmp_path):
+    """A checkpoint file written mid-run (population, step, -beta F of that
+    step, run description) resumes in a new run that finishes bit-identically
+    to the original, which continues after writing it."""
+    kw = dict(L=32, q=10, R=900, beta=lin_beta(1.5, 10), theta=2, seed=23, resample=0,
+              outputs=pa.OUT_FINAL | pa.OUT_HIST | pa.OUT_DIGEST)
+    d = pa.Desc(**kw)
+    run = pa.Run(ctx, d)
+    run.advance(4)
+    step, mbf = run.free_energy()
+    assert step == 4
+    path = tmp_path / "ckpt.npz"
+    run.checkpoint(path)
+    run.advance(d.K - 1 - 4)
+    full = run.finish()
+    assert full["minus_beta_F"][4] == mbf
+    res_run = pa.Run.resume(ctx, path)
+    res_run.advance(d.K - 1 - 4)
+    res = res_run.finish()
+    assert (res["final_spins"] == full["final_spins"]).all()
+    for k in ("R_i", "E_sum", "hist", "digest"):
+        assert (res[k][4:] == full[k][4:]).all(), k
+    np.testing.assert_allclose(res["minus_beta_F"][4:], full["minus_beta_F"][4:], rtol=RTOL)
+
+
 def _sampled_full_size_step(ctx, kw, n_steps, n_samples, seed):
     """Full-size run: every step's ancestors bit-exact against the oracle's
     resampling of the device energies; a random sample of replicas re-swept by
