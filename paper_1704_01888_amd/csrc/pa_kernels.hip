@@ -352,6 +352,22 @@ __device__ __forceinline__ void sweeps_any(uint32_t *lds32, uint32_t g, uint32_t
     }
 }
 
+// f(i) for i = g, g + G, ... below n.  With the count and the stride known at
+// compile time (NC, GC != 0) the loop has a constant trip count, so that its
+// independent iterations (the loads of a gather) issue together.
+template <uint32_t NC, uint32_t GC, typename F>
+__device__ __forceinline__ void lane_stride(uint32_t g, uint32_t n, uint32_t G, F f) {
+    if constexpr (NC != 0 && GC != 0) {
+#pragma unroll
+        for (uint32_t c = 0; c < (NC + GC - 1) / GC; ++c) {
+            const uint32_t i = g + c * GC;
+            if (NC % GC == 0 || i < NC) f(i);
+        }
+    } else {
+        for (uint32_t i = g; i < n; i += G) f(i);
+    }
+}
+
 // One workgroup `block` of the sweep launch of one run (a): gather or create
 // its replicas in LDS, theta sweeps, energies (and M~), store.
 template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64>
@@ -412,7 +428,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         const uint32_t src = live ? (a.anc ? a.anc[k] : k) : 0u;
         const uint4 *gsrc = reinterpret_cast<const uint4 *>(a.old_pop + (size_t)src * N);
         uint4 *ldst = reinterpret_cast<uint4 *>(rep_lds + L);
-        for (uint32_t o = g; o < N / 16u; o += G) ldst[o] = live ? gsrc[o] : make_uint4(0, 0, 0, 0);
+        lane_stride<LT * LT / 16, GT>(g, N / 16u, G, [&](uint32_t o) {
+            ldst[o] = live ? gsrc[o] : make_uint4(0, 0, 0, 0);
+        });
     } else if (a.mode == SWEEP_INIT_RANDOM) {
         // Site n takes word n mod 4 of Philox(n / 4, k, 0, INIT).
         for (uint32_t dd = g; dd < N / 4u; dd += G) {
@@ -424,13 +442,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         // eq. (6): all spins alpha, alpha uniform over the q states.
         const uint4 w = philox(0u, k, 0u, DOM_GROUND << 28, a.key0, a.key1);
         const uint32_t alpha = mulhi32(w.x, a.q) * 0x01010101u;
-        for (uint32_t dd = g; dd < N / 4u; dd += G) rows32[dd] = alpha;
+        lane_stride<LT * LT / 4, GT>(g, N / 4u, G, [&](uint32_t dd) { rows32[dd] = alpha; });
     }
     replica_fence(barrier);
-    for (uint32_t dd = g; dd < DPR; dd += G) {                   // periodic halo rows
+    lane_stride<LT / 4, GT>(g, DPR, G, [&](uint32_t dd) {       // periodic halo rows
         lds32[dd] = rows32[(L - 1) * DPR + dd];
         lds32[(L + 1) * DPR + dd] = rows32[dd];
-    }
+    });
     replica_fence(barrier);
 
     // ---- theta checkerboard sweeps --------------------------------------
@@ -440,7 +458,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
 
     // ---- energy (eq. (3)), store ------------------------------------------
     uint32_t bonds = 0;
-    for (uint32_t dd = g; dd < N / 4u; dd += G) {
+    lane_stride<LT * LT / 4, GT>(g, N / 4u, G, [&](uint32_t dd) {
         const uint32_t xd = dd % DPR;
         const uint32_t idx = DPR + dd;
         const uint32_t D = lds32[idx];
@@ -448,7 +466,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         const uint32_t Dd = lds32[idx + DPR];
         const uint32_t right = __builtin_amdgcn_alignbyte(Dr, D, 1);
         bonds += eq_bytes(D, right) + eq_bytes(D, Dd);
-    }
+    });
     // per-replica sums of spanning replicas: digest [rpb] u64, bonds [rpb],
     // per-state counts [rpb][q] u32, after all replicas' rows
     uint8_t *acc = smem + 128 + (size_t)rpb * (N + 2 * L);
@@ -520,7 +538,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         // the launch then has little to do
         u32x4 *gdst = reinterpret_cast<u32x4 *>(a.new_pop + (size_t)k * N);
         const u32x4 *lsrc = reinterpret_cast<const u32x4 *>(rep_lds + L);
-        for (uint32_t o = g; o < N / 16u; o += G) __builtin_nontemporal_store(lsrc[o], &gdst[o]);
+        lane_stride<LT * LT / 16, GT>(g, N / 16u, G, [&](uint32_t o) {
+            __builtin_nontemporal_store(lsrc[o], &gdst[o]);
+        });
     }
 }
 
