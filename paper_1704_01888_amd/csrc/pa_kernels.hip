@@ -41,6 +41,17 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
+// The truth table of a three-input bitop weighs its operands 0xF0, 0xCC, 0xAA.
+// Bitwise select m ? a : b.
+__device__ __forceinline__ uint32_t bit_select(uint32_t m, uint32_t a, uint32_t b) {
+    return __builtin_amdgcn_bitop3_b32(a, b, m, 0xE4);
+}
+
+// ~a & b.
+__device__ __forceinline__ uint32_t and_not(uint32_t a, uint32_t b) {
+    return __builtin_amdgcn_bitop3_b32(a, b, 0u, 0x0C);
+}
+
 // Rounds 2..10 of Philox after a first round whose product M0 * c0 is given.
 __device__ __forceinline__ uint4 philox_from(uint64_t p0, uint32_t c1, uint32_t c2, uint32_t c3,
                                              uint32_t k0, uint32_t k1) {
@@ -138,7 +149,9 @@ __device__ __forceinline__ uint32_t site_update(uint32_t sb, uint32_t n, uint32_
     const uint32_t xa = n ^ sb, xb = n ^ spb;
     uint32_t eq_a, ne_b;
     if (QSMALL) {
-        eq_a = ~(xa + 0x7F7F7F7Fu) & 0x80808080u;
+        // one xor-add and one bitop (written as ~(x + c) & m, the compiler
+        // forms the sum as m - x and spends a third instruction)
+        eq_a = and_not(xa + 0x7F7F7F7Fu, 0x80808080u);
         ne_b = (xb + 0x7F7F7F7Fu) & 0x80808080u;
     } else {
         eq_a = ~(((xa & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | xa) & 0x80808080u;
@@ -180,7 +193,7 @@ __device__ __forceinline__ uint32_t update_pair(uint32_t D0, uint32_t Dx, uint32
     const uint32_t t0 = site_update<QSMALL, T64>(sb0, n0, w.x, w.y, qm1, thr);
     const uint32_t t1 = site_update<QSMALL, T64>(sb1, n1, w.z, w.w, qm1, thr);
     const uint32_t X = perm(t1, t0, 0x05040100u);         // s0', s0', s1', s1'
-    return (X & ps.mask) | (D0 & ~ps.mask);
+    return bit_select(ps.mask, X, D0);
 }
 
 // Philox for the sweep counter (p, k, step, c3) with k, step, c3 and the key
@@ -368,6 +381,19 @@ __device__ __forceinline__ void lane_stride(uint32_t g, uint32_t n, uint32_t G, 
     }
 }
 
+// Sum over the 64 lanes of a wave (all active), wave-uniform: four DPP adds
+// (quad_perm [1,0,3,2] and [2,3,0,1], row_ror 4 and 8) leave every lane of a
+// row of 16 with the row's sum; the four row sums are read from lanes 0, 16,
+// 32 and 48.
+__device__ __forceinline__ uint32_t wave_total(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
+    return (uint32_t)(__builtin_amdgcn_readlane((int)v, 0) + __builtin_amdgcn_readlane((int)v, 16) +
+                      __builtin_amdgcn_readlane((int)v, 32) + __builtin_amdgcn_readlane((int)v, 48));
+}
+
 // One workgroup `block` of the sweep launch of one run (a): gather or create
 // its replicas in LDS, theta sweeps, energies (and M~), store.
 template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64>
@@ -478,7 +504,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         __syncthreads();
         bonds = acc_e[rep];
     } else {
-        for (uint32_t off = (G < 64 ? G : 64) >> 1; off > 0; off >>= 1) bonds += __shfl_xor(bonds, off, 64);
+        if (G % 64u == 0) bonds = wave_total(bonds);
+        else for (uint32_t off = G >> 1; off > 0; off >>= 1) bonds += __shfl_xor(bonds, off, 64);
         if (multiwave) {
             uint32_t *sum = reinterpret_cast<uint32_t *>(smem) + 24;
             if ((threadIdx.x & 63u) == 0) atomicAdd(sum, bonds);
@@ -498,7 +525,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
                 atomicAdd(&acc_m[rep * a.q + st], c);
                 continue;
             }
-            for (uint32_t off = (G < 64 ? G : 64) >> 1; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+            if (G % 64u == 0) c = wave_total(c);
+            else for (uint32_t off = G >> 1; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
             if (!multiwave) mt = max(mt, c);
             else if ((threadIdx.x & 63u) == 0) atomicAdd(&mcnt[st], c);
         }
