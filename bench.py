@@ -45,7 +45,7 @@ MIX_PEAK_LANE_OPS = 1.055 * VALU_PEAK_LANE_OPS
 # VALU lane-instructions per spin-flip attempt of k_sweep on this workload,
 # from rocprofv3 SQ_INSTS_VALU x 64 / attempts (gather, sweeps and energy
 # epilogue; profiles/k_sweep_32x32_q10_R20000.md; 256 lanes per replica).
-INSTR_PER_ATTEMPT = 36.40
+INSTR_PER_ATTEMPT = 35.41
 
 # HBM bytes per k_sweep launch on this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by 2.00 and 1.00, the factors the plain 256 MiB copy of

@@ -120,15 +120,39 @@ __device__ __forceinline__ uint32_t eq_bytes(uint32_t a, uint32_t b) {
     return 4u - __popc(nz);
 }
 
-// Acceptance thresholds in LDS, indexed by dE + 4.  Entries for dE <= 0 accept
-// always.  T64: the exact 64-bit form "w < T" with T <= 2^32; otherwise the
-// 32-bit form "w <= T - 1", valid when every T >= 1 (the host checks).
+// LDS header of the sweep and tiled workgroups (replica rows follow it):
+// acceptance thresholds, and the energy and digest sums of a multi-wave
+// replica (bytes 96 and 104).  Thresholds are indexed by dE + 4; entries for
+// dE <= 0 accept always.  T64: the exact 64-bit form "w < T" (T <= 2^32) at
+// byte 0; otherwise the 32-bit form "w <= T - 1", valid when every T >= 1 (the
+// host checks), at byte THR32_OFF, the address the pair update computes.
+constexpr uint32_t LDS_HDR = 640;
+constexpr uint32_t THR32_OFF = 496;
+
+template <bool T64>
+__device__ __forceinline__ void load_thresholds(uint8_t *hdr, const uint64_t *T) {
+    if (threadIdx.x < 9) {
+        const int dE = (int)threadIdx.x - 4;
+        const uint64_t t = dE <= 0 ? (1ull << 32) : T[dE - 1];
+        if (T64) reinterpret_cast<uint64_t *>(hdr)[threadIdx.x] = t;
+        else reinterpret_cast<uint32_t *>(hdr + THR32_OFF)[threadIdx.x] = (uint32_t)(t - 1u);
+    }
+}
+
 template <bool T64>
 struct Thresholds {
-    const void *tab;
-    __device__ __forceinline__ bool accept(uint32_t idx, uint32_t w) const {
-        if (T64) return static_cast<const uint64_t *>(tab)[idx] > (uint64_t)w;
-        return w <= static_cast<const uint32_t *>(tab)[idx];
+    const uint8_t *hdr;
+    // 64-bit form, by index dE + 4
+    __device__ __forceinline__ bool accept_idx(uint32_t idx, uint32_t w) const {
+        return reinterpret_cast<const uint64_t *>(hdr)[idx] > (uint64_t)w;
+    }
+    // LDS byte address of the header
+    __device__ __forceinline__ uint32_t lds_base() const {
+        return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint8_t *)hdr;
+    }
+    // 32-bit form, by LDS byte address lds_base() + THR32_OFF + 4 (dE + 4)
+    __device__ __forceinline__ bool accept_at(uint32_t at, uint32_t w) const {
+        return w <= *(const __attribute__((address_space(3))) uint32_t *)(uintptr_t)at;
     }
 };
 
@@ -158,9 +182,18 @@ __device__ __forceinline__ uint32_t site_update(uint32_t sb, uint32_t n, uint32_
         ne_b = (((xb & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | xb) & 0x80808080u;
     }
     // #equal(current) + #unequal(proposed) = 4 + dE
-    uint32_t idx = __popc(ne_b) + __popc(eq_a);
-    asm volatile("" : "+v"(idx));   // keep the index one add (no re-association)
-    return thr.accept(idx, w_acc) ? spb : sb;
+    if (T64) {
+        uint32_t idx = __popc(ne_b) + __popc(eq_a);
+        asm volatile("" : "+v"(idx));   // keep the index one add (no re-association)
+        return thr.accept_idx(idx, w_acc) ? spb : sb;
+    }
+    // Every flag byte is 0x80 or 0, |0x80 - 0x3E| = 66 and |0 - 0x3E| = 62: two
+    // byte-SADs added to the header's address give it + 8 * 62 + 4 (4 + dE) =
+    // + THR32_OFF + 4 (4 + dE), the LDS address of the threshold, without a
+    // separate count, shift and base.
+    const uint32_t at = __builtin_amdgcn_sad_u8(
+        ne_b, 0x3E3E3E3Eu, __builtin_amdgcn_sad_u8(eq_a, 0x3E3E3E3Eu, thr.lds_base()));
+    return thr.accept_at(at, w_acc) ? spb : sb;
 }
 
 // Per-parity constants of a pair update (see update_pair).
@@ -399,25 +432,19 @@ __device__ __forceinline__ uint32_t wave_total(uint32_t v) {
 template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     extern __shared__ __align__(16) uint8_t smem[];
-    // thresholds indexed by dE + 4
     if (threadIdx.x == 32) reinterpret_cast<uint32_t *>(smem)[24] = 0u;   // energy sum (multi-wave)
     if (threadIdx.x == 33) reinterpret_cast<uint64_t *>(smem)[13] = 0ull; // digest sum (multi-wave)
     if (a.Mt_out && a.G > 64 && a.G % 64u == 0) {   // per-state counters of a multi-wave replica, after its rows
-        uint32_t *mcnt = reinterpret_cast<uint32_t *>(smem + 128 + a.N + 2 * a.L);
+        uint32_t *mcnt = reinterpret_cast<uint32_t *>(smem + LDS_HDR + a.N + 2 * a.L);
         for (uint32_t t = threadIdx.x; t < a.q; t += blockDim.x) mcnt[t] = 0u;
     }
     if (64u % a.G != 0 && a.G % 64u != 0) {       // sums of spanning replicas, after all rows
         const uint32_t nr = blockDim.x / a.G;
-        uint8_t *acc = smem + 128 + (size_t)nr * (a.N + 2 * a.L);
+        uint8_t *acc = smem + LDS_HDR + (size_t)nr * (a.N + 2 * a.L);
         const uint32_t words = nr * (3u + (a.Mt_out ? a.q : 0u));
         for (uint32_t t = threadIdx.x; t < words; t += blockDim.x) reinterpret_cast<uint32_t *>(acc)[t] = 0u;
     }
-    if (threadIdx.x < 9) {
-        const int dE = (int)threadIdx.x - 4;
-        const uint64_t T = dE <= 0 ? (1ull << 32) : a.T[dE - 1];
-        if (T64) reinterpret_cast<uint64_t *>(smem)[threadIdx.x] = T;
-        else reinterpret_cast<uint32_t *>(smem)[threadIdx.x] = (uint32_t)(T - 1u);
-    }
+    load_thresholds<T64>(smem, a.T);
     __syncthreads();
     const Thresholds<T64> thr{smem};
 
@@ -445,7 +472,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     // compile-time shape where the kernel has one (LT != 0): the prologue and
     // epilogue loops then have constant bounds and strides
     const uint32_t L = LT ? LT : a.L, N = LT ? LT * LT : a.N, DPR = L >> 2;
-    uint8_t *rep_lds = smem + 128 + (size_t)rep * (N + 2 * L);
+    uint8_t *rep_lds = smem + LDS_HDR + (size_t)rep * (N + 2 * L);
     uint32_t *lds32 = reinterpret_cast<uint32_t *>(rep_lds);
     uint32_t *rows32 = lds32 + DPR;                              // row 0
 
@@ -495,7 +522,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     });
     // per-replica sums of spanning replicas: digest [rpb] u64, bonds [rpb],
     // per-state counts [rpb][q] u32, after all replicas' rows
-    uint8_t *acc = smem + 128 + (size_t)rpb * (N + 2 * L);
+    uint8_t *acc = smem + LDS_HDR + (size_t)rpb * (N + 2 * L);
     unsigned long long *acc_d = reinterpret_cast<unsigned long long *>(acc);
     uint32_t *acc_e = reinterpret_cast<uint32_t *>(acc + 8u * rpb);
     uint32_t *acc_m = acc_e + rpb;
@@ -1181,15 +1208,10 @@ __global__ void __launch_bounds__(256) k_tiled_half(TiledArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint32_t k, tile;
     tile_of(a.tiles, k, tile);
-    if (threadIdx.x < 9) {
-        const int dE = (int)threadIdx.x - 4;
-        const uint64_t T = dE <= 0 ? (1ull << 32) : a.T[dE - 1];
-        if (T64) reinterpret_cast<uint64_t *>(smem)[threadIdx.x] = T;
-        else reinterpret_cast<uint32_t *>(smem)[threadIdx.x] = (uint32_t)(T - 1u);
-    }
+    load_thresholds<T64>(smem, a.T);
     const uint32_t L = a.L, DPR = L >> 2, S = a.halves;
     const uint32_t y0 = tile * a.rows, n = min(a.rows, L - y0), nl = n + 2 * S;
-    uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem + 128);
+    uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem + LDS_HDR);
     const uint32_t src = a.anc ? a.anc[k] : k;
     const uint32_t *src32 = reinterpret_cast<const uint32_t *>(a.src + (size_t)src * a.N);
     // local row r holds global row y0 - S + r (periodic)
@@ -1241,14 +1263,9 @@ __global__ void __launch_bounds__(NTT) k_tiled_fixed(TiledArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint32_t k, tile;
     tile_of(a.tiles, k, tile);
-    if (threadIdx.x < 9) {
-        const int dE = (int)threadIdx.x - 4;
-        const uint64_t T = dE <= 0 ? (1ull << 32) : a.T[dE - 1];
-        if (T64) reinterpret_cast<uint64_t *>(smem)[threadIdx.x] = T;
-        else reinterpret_cast<uint32_t *>(smem)[threadIdx.x] = (uint32_t)(T - 1u);
-    }
+    load_thresholds<T64>(smem, a.T);
     const uint32_t S = a.halves, y0 = tile * a.rows, n = a.rows, nl = n + 2 * S;
-    uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem + 128);
+    uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem + LDS_HDR);
     const uint32_t src = a.anc ? a.anc[k] : k;
     const uint32_t *src32 = reinterpret_cast<const uint32_t *>(a.src + (size_t)src * a.N);
     static_assert(DPR % 64 == 0, "whole waves per row");
@@ -1481,7 +1498,7 @@ size_t sweep_lds_bytes(uint32_t N, uint32_t G, uint32_t waves_per_block, uint32_
     uint32_t L = 0;
     while (L * L < N) ++L;
     const uint64_t rpb = replicas_per_block(G, waves_per_block);
-    size_t b = 128u + (size_t)rpb * (N + 2 * L);
+    size_t b = LDS_HDR + (size_t)rpb * (N + 2 * L);
     // a multi-wave replica also keeps its 255 per-state counters (eq. (5)) in LDS;
     // spanning replicas keep their digest, bond and per-state sums after the rows
     if (G > 64 && G % 64 == 0) b += 1024u;
@@ -1619,7 +1636,7 @@ static uint32_t tiled_threads(uint32_t L) { return L >= 4096 ? 512u : 256u; }
 static size_t tiled_lds_bytes(const TiledArgs &a, bool fixed) {
     const uint32_t nt = tiled_threads(a.L);
     const uint32_t rs = a.L / 4u >= nt ? 1u : nt / (a.L / 4u);
-    return 128 + (size_t)(a.rows + 2 * a.halves + (fixed ? rs : 0u)) * a.L;
+    return LDS_HDR + (size_t)(a.rows + 2 * a.halves + (fixed ? rs : 0u)) * a.L;
 }
 
 template <bool QSMALL, bool T64>
