@@ -29,6 +29,7 @@ namespace pa {
 namespace {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr uint32_t PHILOX_M0 = 0xD2511F53u;
 constexpr uint32_t PHILOX_M1 = 0xCD9E8D57u;
@@ -120,48 +121,101 @@ __device__ __forceinline__ uint32_t eq_bytes(uint32_t a, uint32_t b) {
     return 4u - __popc(nz);
 }
 
-// LDS header of the sweep and tiled workgroups (replica rows follow it):
-// acceptance thresholds, and the energy and digest sums of a multi-wave
-// replica (bytes 96 and 104).  Thresholds are indexed by dE + 4; entries for
-// dE <= 0 accept always.  T64: the exact 64-bit form "w < T" (T <= 2^32) at
-// byte 0; otherwise the 32-bit form "w <= T - 1", valid when every T >= 1 (the
-// host checks), at byte THR32_OFF, the address the pair update computes.
-constexpr uint32_t LDS_HDR = 640;
-constexpr uint32_t THR32_OFF = 496;
+// LDS of the sweep and tiled workgroups: a 128-byte header (the 64-bit
+// thresholds, and the energy and digest sums of a multi-wave replica at bytes
+// 96 and 104), the replica or tile rows, sums, and last the pair threshold
+// table.  Thresholds are indexed by i = dE + 4; entries for dE <= 0 accept
+// always.  T64: the exact 64-bit form "w < T" (T <= 2^32) in the header;
+// otherwise the 32-bit form "w <= T - 1", valid when every T >= 1 (the host
+// checks), in the pair table: entry (i0, i1), at byte 8 i0 + 72 i1 of it, holds
+// the thresholds of i0 and i1 (81 entries, 648 bytes).  The table starts at
+// least PAIR_SAD_BIAS bytes into the LDS, the constant the pair update's four
+// flag SADs add, so that their sum can start from table - PAIR_SAD_BIAS.
+constexpr uint32_t LDS_HDR = 128;
+constexpr uint32_t PAIR_SAD_BIAS = 704, PAIR_TAB_BYTES = 648;
+
+__host__ __device__ inline uint32_t pair_tab_off(uint32_t end) {
+    const uint32_t e = (end + 7u) & ~7u;
+    return e > PAIR_SAD_BIAS ? e : PAIR_SAD_BIAS;
+}
+
+// End of a sweep workgroup's LDS before the pair table: header, rpb replicas of
+// N + 2L bytes, then the per-state counters of a multi-wave replica (eq. (5))
+// or the digest, bond and per-state sums of spanning replicas.
+__host__ __device__ inline uint32_t sweep_lds_end(uint32_t N, uint32_t L, uint32_t G, uint32_t rpb,
+                                                  uint32_t q_counters) {
+    uint32_t b = LDS_HDR + rpb * (N + 2u * L);
+    if (G > 64u && G % 64u == 0) b += 1024u;
+    else if (64u % G != 0) b += rpb * (12u + 4u * q_counters);
+    return b;
+}
+
+// End of a tiled workgroup's LDS before the pair table: tile and side rows,
+// plus the padding rows the fixed-layout kernel reads past the update range
+// (one row per row step of a lane: RS = nt / (L/4) rows, at least one).
+__host__ __device__ inline uint32_t tiled_lds_end(uint32_t rows, uint32_t halves, uint32_t L,
+                                                  uint32_t nt, bool fixed) {
+    const uint32_t rs = L / 4u >= nt ? 1u : nt / (L / 4u);
+    return LDS_HDR + (rows + 2u * halves + (fixed ? rs : 0u)) * L;
+}
 
 template <bool T64>
-__device__ __forceinline__ void load_thresholds(uint8_t *hdr, const uint64_t *T) {
-    if (threadIdx.x < 9) {
-        const int dE = (int)threadIdx.x - 4;
-        const uint64_t t = dE <= 0 ? (1ull << 32) : T[dE - 1];
-        if (T64) reinterpret_cast<uint64_t *>(hdr)[threadIdx.x] = t;
-        else reinterpret_cast<uint32_t *>(hdr + THR32_OFF)[threadIdx.x] = (uint32_t)(t - 1u);
+__device__ __forceinline__ void load_thresholds(uint8_t *smem, uint32_t tab, const uint64_t *T) {
+    if (T64) {
+        if (threadIdx.x < 9) {
+            const int dE = (int)threadIdx.x - 4;
+            reinterpret_cast<uint64_t *>(smem)[threadIdx.x] = dE <= 0 ? (1ull << 32) : T[dE - 1];
+        }
+        return;
+    }
+    for (uint32_t t = threadIdx.x; t < 81u; t += blockDim.x) {
+        const uint32_t i0 = t % 9u, i1 = t / 9u;
+        const uint32_t a = i0 <= 4u ? 0xFFFFFFFFu : (uint32_t)(T[i0 - 5u] - 1u);
+        const uint32_t b = i1 <= 4u ? 0xFFFFFFFFu : (uint32_t)(T[i1 - 5u] - 1u);
+        *reinterpret_cast<uint2 *>(smem + tab + 8u * i0 + 72u * i1) = make_uint2(a, b);
     }
 }
 
 template <bool T64>
 struct Thresholds {
-    const uint8_t *hdr;
+    const uint8_t *smem;
+    uint32_t tab;   // byte offset of the pair table
     // 64-bit form, by index dE + 4
     __device__ __forceinline__ bool accept_idx(uint32_t idx, uint32_t w) const {
-        return reinterpret_cast<const uint64_t *>(hdr)[idx] > (uint64_t)w;
+        return reinterpret_cast<const uint64_t *>(smem)[idx] > (uint64_t)w;
     }
-    // LDS byte address of the header
-    __device__ __forceinline__ uint32_t lds_base() const {
-        return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint8_t *)hdr;
+    // LDS byte address of the pair table, less PAIR_SAD_BIAS
+    __device__ __forceinline__ uint32_t sad_start() const {
+        return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint8_t *)smem + tab -
+               PAIR_SAD_BIAS;
     }
-    // 32-bit form, by LDS byte address lds_base() + THR32_OFF + 4 (dE + 4)
-    __device__ __forceinline__ bool accept_at(uint32_t at, uint32_t w) const {
-        return w <= *(const __attribute__((address_space(3))) uint32_t *)(uintptr_t)at;
+    // the two thresholds at LDS byte address `at`
+    __device__ __forceinline__ u32x2 pair_at(uint32_t at) const {
+        return *(const __attribute__((address_space(3))) u32x2 *)(uintptr_t)at;
     }
 };
 
+// Flags (0x80 per byte) of the equal / unequal bytes of x = a ^ b.  With
+// q <= 128 every byte of x has bit 7 clear, so adding 0x7F to each byte never
+// carries into the next one and bit 7 of the sum marks a nonzero byte; for
+// larger q the low seven bits are masked first.
+template <bool QSMALL>
+__device__ __forceinline__ uint32_t flags_eq(uint32_t x) {
+    // one xor-add and one bitop (written as ~(x + c) & m, the compiler forms
+    // the sum as m - x and spends a third instruction)
+    if (QSMALL) return and_not(x + 0x7F7F7F7Fu, 0x80808080u);
+    return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+}
+template <bool QSMALL>
+__device__ __forceinline__ uint32_t flags_ne(uint32_t x) {
+    if (QSMALL) return (x + 0x7F7F7F7Fu) & 0x80808080u;
+    return (((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+}
+
 // Metropolis update of one site (Sec. 2 step 3; proposal and acceptance as in
-// the header comment of pa.h).  sb = current spin in all four bytes, n = the
-// four neighbours, one per byte.  Returns the new spin in all four bytes.
-// With q <= 128 every byte of n ^ sb has bit 7 clear, so adding 0x7F to each
-// byte never carries into the next one and bit 7 of the sum marks a differing
-// byte; for larger q the low seven bits are masked first.
+// the header comment of pa.h) with the 64-bit thresholds.  sb = current spin in
+// all four bytes, n = the four neighbours, one per byte.  Returns the new spin
+// in all four bytes.
 template <bool QSMALL, bool T64>
 __device__ __forceinline__ uint32_t site_update(uint32_t sb, uint32_t n, uint32_t w_prop,
                                                 uint32_t w_acc, uint32_t qm1,
@@ -170,35 +224,16 @@ __device__ __forceinline__ uint32_t site_update(uint32_t sb, uint32_t n, uint32_
     const uint32_t rr = mulhi32_wide(w_prop, qm1);
     const uint32_t sp = rr + (rr >= s ? 1u : 0u);
     const uint32_t spb = perm(0u, sp, 0u);                 // broadcast byte 0
-    const uint32_t xa = n ^ sb, xb = n ^ spb;
-    uint32_t eq_a, ne_b;
-    if (QSMALL) {
-        // one xor-add and one bitop (written as ~(x + c) & m, the compiler
-        // forms the sum as m - x and spends a third instruction)
-        eq_a = and_not(xa + 0x7F7F7F7Fu, 0x80808080u);
-        ne_b = (xb + 0x7F7F7F7Fu) & 0x80808080u;
-    } else {
-        eq_a = ~(((xa & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | xa) & 0x80808080u;
-        ne_b = (((xb & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | xb) & 0x80808080u;
-    }
+    const uint32_t eq_a = flags_eq<QSMALL>(n ^ sb), ne_b = flags_ne<QSMALL>(n ^ spb);
     // #equal(current) + #unequal(proposed) = 4 + dE
-    if (T64) {
-        uint32_t idx = __popc(ne_b) + __popc(eq_a);
-        asm volatile("" : "+v"(idx));   // keep the index one add (no re-association)
-        return thr.accept_idx(idx, w_acc) ? spb : sb;
-    }
-    // Every flag byte is 0x80 or 0, |0x80 - 0x3E| = 66 and |0 - 0x3E| = 62: two
-    // byte-SADs added to the header's address give it + 8 * 62 + 4 (4 + dE) =
-    // + THR32_OFF + 4 (4 + dE), the LDS address of the threshold, without a
-    // separate count, shift and base.
-    const uint32_t at = __builtin_amdgcn_sad_u8(
-        ne_b, 0x3E3E3E3Eu, __builtin_amdgcn_sad_u8(eq_a, 0x3E3E3E3Eu, thr.lds_base()));
-    return thr.accept_at(at, w_acc) ? spb : sb;
+    uint32_t idx = __popc(ne_b) + __popc(eq_a);
+    asm volatile("" : "+v"(idx));   // keep the index one add (no re-association)
+    return thr.accept_idx(idx, w_acc) ? spb : sb;
 }
 
 // Per-parity constants of a pair update (see update_pair).
 struct PairSel {
-    uint32_t selH, selV, sel0, sel1, mask;
+    uint32_t selH, selV, sel0, sel1, selS, mask;
     PairSel() = default;
     __device__ __forceinline__ explicit PairSel(uint32_t par) {
         const uint32_t pb = par * 0x01010101u;
@@ -206,6 +241,7 @@ struct PairSel {
         selV = 0x06020400u + pb;
         sel0 = pb;
         sel1 = pb + 0x02020202u;
+        selS = pb + 0x02020000u;
         mask = 0x00FF00FFu << (par << 3);
     }
 };
@@ -219,6 +255,30 @@ __device__ __forceinline__ uint32_t update_pair(uint32_t D0, uint32_t Dx, uint32
                                                 const Thresholds<T64> &thr) {
     const uint32_t H = perm(Dx, D0, ps.selH);            // x0-1, x0+1, x0+1, x0+3
     const uint32_t V = perm(Dn, U, ps.selV);             // up0, down0, up1, down1
+    if constexpr (!T64) {
+        // Bytes 0-1 of H, V, S and P belong to site 0, bytes 2-3 to site 1.
+        const uint32_t S = perm(0u, D0, ps.selS);        // s0, s0, s1, s1
+        const uint32_t r0 = mulhi32_wide(w.x, qm1), r1 = mulhi32_wide(w.z, qm1);
+        const uint32_t p0 = r0 + (r0 >= (S & 0xFFu) ? 1u : 0u);
+        const uint32_t p1 = r1 + (r1 >= ((S >> 16) & 0xFFu) ? 1u : 0u);
+        const uint32_t P = perm(p1, p0, 0x04040000u);    // s0', s0', s1', s1'
+        // Flag bytes are 0x80 or 0.  A byte-SAD against 0x1C1C3C3C adds 60 + 8
+        // or 60 per byte of site 0 and 28 + 72 or 28 per byte of site 1, so the
+        // four SADs of the equal flags of s and the unequal flags of s' add
+        // PAIR_SAD_BIAS + 8 i0 + 72 i1 (i = #equal(s) + #unequal(s') = dE + 4
+        // per site): from sad_start(), the LDS address of the pair's two
+        // thresholds, with no counts.
+        uint32_t at = thr.sad_start();
+        at = __builtin_amdgcn_sad_u8(flags_eq<QSMALL>(H ^ S), 0x1C1C3C3Cu, at);
+        at = __builtin_amdgcn_sad_u8(flags_eq<QSMALL>(V ^ S), 0x1C1C3C3Cu, at);
+        at = __builtin_amdgcn_sad_u8(flags_ne<QSMALL>(H ^ P), 0x1C1C3C3Cu, at);
+        at = __builtin_amdgcn_sad_u8(flags_ne<QSMALL>(V ^ P), 0x1C1C3C3Cu, at);
+        const u32x2 T = thr.pair_at(at);
+        const uint32_t t0 = w.y <= T.x ? P : S;
+        const uint32_t t1 = w.w <= T.y ? P : S;
+        const uint32_t X = perm(t1, t0, 0x07060100u);     // s0', s0', s1', s1' (accepted)
+        return bit_select(ps.mask, X, D0);
+    }
     const uint32_t n0 = perm(V, H, 0x05040100u);
     const uint32_t n1 = perm(V, H, 0x07060302u);
     const uint32_t sb0 = perm(0u, D0, ps.sel0);
@@ -322,6 +382,7 @@ __device__ __forceinline__ void sweeps_fixed(uint32_t *lds32, uint32_t g, uint32
     const uint32_t qm1 = a.q - 1u;
     const bool top = y0 == 0, bottom = y0 + (PPL - 1) * RS == L - 1;
     for (uint32_t t = 0; t < theta; ++t) {
+        #pragma unroll   // both colours in one body: the parity constants stay fixed
         for (uint32_t c = 0; c < 2u; ++c) {
             const SweepKey key = sweep_key(k, a.step, (DOM_SWEEP << 28) | (t << 1) | c, a.key0, a.key1);
             // parity of unrolled slot u (j is a multiple of UNR, and RS * UNR is even
@@ -444,10 +505,6 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         const uint32_t words = nr * (3u + (a.Mt_out ? a.q : 0u));
         for (uint32_t t = threadIdx.x; t < words; t += blockDim.x) reinterpret_cast<uint32_t *>(acc)[t] = 0u;
     }
-    load_thresholds<T64>(smem, a.T);
-    __syncthreads();
-    const Thresholds<T64> thr{smem};
-
     // Lanes per replica G: a divisor of 64 (one or several replicas per wave),
     // a multiple of 64 (one replica per block of G/64 waves), or neither
     // (replicas span wave boundaries, several per block: "spanning").  Every
@@ -459,6 +516,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     const uint32_t wave = threadIdx.x >> 6;
     const uint32_t g = multiwave ? threadIdx.x : threadIdx.x % G;
     const uint32_t rpb = multiwave ? 1u : (64u * a.waves_per_block) / G;   // replicas per block
+
+    // the pair threshold table after rows and sums (the host sizes the LDS alike)
+    const uint32_t tab = pair_tab_off(sweep_lds_end(a.N, a.L, G, rpb, a.Mt_out ? a.q : 0u));
+    load_thresholds<T64>(smem, tab, a.T);
+    __syncthreads();
+    const Thresholds<T64> thr{smem, tab};
     const uint32_t rep = multiwave ? 0u : threadIdx.x / G;                 // replica within block
     const uint64_t k64 = (uint64_t)block * rpb + rep;
     // idle waves leave; with barriers only a whole idle block may
@@ -1208,7 +1271,8 @@ __global__ void __launch_bounds__(256) k_tiled_half(TiledArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint32_t k, tile;
     tile_of(a.tiles, k, tile);
-    load_thresholds<T64>(smem, a.T);
+    const uint32_t tab = pair_tab_off(tiled_lds_end(a.rows, a.halves, a.L, blockDim.x, false));
+    load_thresholds<T64>(smem, tab, a.T);
     const uint32_t L = a.L, DPR = L >> 2, S = a.halves;
     const uint32_t y0 = tile * a.rows, n = min(a.rows, L - y0), nl = n + 2 * S;
     uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem + LDS_HDR);
@@ -1220,7 +1284,7 @@ __global__ void __launch_bounds__(256) k_tiled_half(TiledArgs a) {
         for (uint32_t x = threadIdx.x & 63u; x < DPR; x += 64u) lds32[r * DPR + x] = src32[gy * DPR + x];
     }
     __syncthreads();
-    const Thresholds<T64> thr{smem};
+    const Thresholds<T64> thr{smem, tab};
     const uint32_t qm1 = a.q - 1u;
     for (uint32_t j = 0; j < S; ++j) {
         const uint32_t h = a.h0 + j, c = h & 1u;
@@ -1263,7 +1327,8 @@ __global__ void __launch_bounds__(NTT) k_tiled_fixed(TiledArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     uint32_t k, tile;
     tile_of(a.tiles, k, tile);
-    load_thresholds<T64>(smem, a.T);
+    const uint32_t tab = pair_tab_off(tiled_lds_end(a.rows, a.halves, L, NT, true));
+    load_thresholds<T64>(smem, tab, a.T);
     const uint32_t S = a.halves, y0 = tile * a.rows, n = a.rows, nl = n + 2 * S;
     uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem + LDS_HDR);
     const uint32_t src = a.anc ? a.anc[k] : k;
@@ -1278,7 +1343,7 @@ __global__ void __launch_bounds__(NTT) k_tiled_fixed(TiledArgs a) {
         }
     }
     __syncthreads();
-    const Thresholds<T64> thr{smem};
+    const Thresholds<T64> thr{smem, tab};
     const uint32_t qm1 = a.q - 1u;
     const uint32_t xd0 = threadIdx.x % DPR, roff = DPR >= NT ? 0u : threadIdx.x / DPR;
     for (uint32_t j = 0; j < S; ++j) {
@@ -1498,12 +1563,7 @@ size_t sweep_lds_bytes(uint32_t N, uint32_t G, uint32_t waves_per_block, uint32_
     uint32_t L = 0;
     while (L * L < N) ++L;
     const uint64_t rpb = replicas_per_block(G, waves_per_block);
-    size_t b = LDS_HDR + (size_t)rpb * (N + 2 * L);
-    // a multi-wave replica also keeps its 255 per-state counters (eq. (5)) in LDS;
-    // spanning replicas keep their digest, bond and per-state sums after the rows
-    if (G > 64 && G % 64 == 0) b += 1024u;
-    else if (64 % G != 0) b += (size_t)rpb * (12u + 4u * q_counters);
-    return b;
+    return pair_tab_off(sweep_lds_end(N, L, G, (uint32_t)rpb, q_counters)) + PAIR_TAB_BYTES;
 }
 
 size_t max_lds_per_block(int device) {
@@ -1634,9 +1694,8 @@ static uint32_t tiled_threads(uint32_t L) { return L >= 4096 ? 512u : 256u; }
 // workgroups share a CU (at L = 4096 two padding rows left room for 3, one
 // for 4: 12 or 16 waves).
 static size_t tiled_lds_bytes(const TiledArgs &a, bool fixed) {
-    const uint32_t nt = tiled_threads(a.L);
-    const uint32_t rs = a.L / 4u >= nt ? 1u : nt / (a.L / 4u);
-    return LDS_HDR + (size_t)(a.rows + 2 * a.halves + (fixed ? rs : 0u)) * a.L;
+    const uint32_t nt = fixed ? tiled_threads(a.L) : 256u;
+    return pair_tab_off(tiled_lds_end(a.rows, a.halves, a.L, nt, fixed)) + PAIR_TAB_BYTES;
 }
 
 template <bool QSMALL, bool T64>
