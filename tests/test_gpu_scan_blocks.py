@@ -8,7 +8,8 @@ each count-scan launch clears the other buffer over the extent the step before
 used, in strides of the launch's blocks. The cases: a population of several
 rows per block; a Poisson population fluctuating around one block (4096), so
 that the clearing runs past one stride; strongly skewed weights (long runs of
-copies in the slot map). Bar as for every parity test:
+copies in the slot map); a population of three rows per block. Bar as for
+every parity test:
 population sizes, histograms, copy numbers, ancestors, spins and digests
 bit-exact, ln Q and -beta F within 1e-12.
 """
@@ -33,6 +34,8 @@ CASES = [
     # about 14700 of 20000 copies, about 20 take more than 8 (written by the wave)
     dict(L=8, q=3, R=20000, beta=np.array([0.0, 0.5, 1.5, 3.0]), theta=1, seed=64, resample=1),
     dict(L=8, q=3, R=20000, beta=np.array([0.0, 0.5, 1.5, 3.0]), theta=1, seed=64, resample=0),
+    # 600000 replicas: 49 blocks of three 4096-rows each
+    dict(L=4, q=3, R=600000, beta=linear_betas(1.2, 2), theta=1, seed=65, resample=1),
 ]
 
 
