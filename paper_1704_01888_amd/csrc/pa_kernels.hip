@@ -1350,24 +1350,35 @@ __global__ void __launch_bounds__(NTT) k_tiled_fixed(TiledArgs a) {
         const uint32_t h = a.h0 + j, c = h & 1u;
         const SweepKey key = sweep_key(k, a.step, (DOM_SWEEP << 28) | ((h >> 1) << 1) | c, a.key0, a.key1);
         const uint32_t r0 = 1 + j, nr = nl - 2 - 2 * j;
+        // A lane's rows of this half-sweep are r0 + roff + 2 RS i + u RS: their
+        // parity, hence the pair selectors and the offset of the left or right
+        // neighbour dword, stays fixed for each u.
+        PairSel ps[2];
+        int32_t dxo[2][CPT];
+#pragma unroll
+        for (uint32_t u = 0; u < 2; ++u) {
+            const uint32_t par = (y0 + r0 + roff + u * RS + L - S + c) & 1u;
+            ps[u] = PairSel(par);
+#pragma unroll
+            for (uint32_t cc = 0; cc < CPT; ++cc) {
+                const uint32_t xd = xd0 + cc * NT;
+                dxo[u][cc] = par ? (xd == DPR - 1 ? -(int32_t)(DPR - 1) : 1)
+                                 : (xd == 0 ? (int32_t)(DPR - 1) : -1);
+            }
+        }
         for (uint32_t rr = roff; rr < nr; rr += 2 * RS) {
             uint32_t idx[2][CPT], D0[2][CPT], Dx[2][CPT], U[2][CPT], Dn[2][CPT];
             uint4 w[2][CPT];
-            PairSel ps[2];
 #pragma unroll
             for (uint32_t u = 0; u < 2; ++u) {
                 const uint32_t yl = r0 + rr + u * RS;
                 const uint32_t gy = (y0 + yl + L - S) & (L - 1);
-                const uint32_t par = (gy + c) & 1u;
-                ps[u] = PairSel(par);
 #pragma unroll
                 for (uint32_t cc = 0; cc < CPT; ++cc) {
                     const uint32_t xd = xd0 + cc * NT;
                     idx[u][cc] = yl * DPR + xd;
-                    const uint32_t xo = par ? (xd == DPR - 1 ? idx[u][cc] - (DPR - 1) : idx[u][cc] + 1)
-                                            : (xd == 0 ? idx[u][cc] + (DPR - 1) : idx[u][cc] - 1);
                     D0[u][cc] = lds32[idx[u][cc]];
-                    Dx[u][cc] = lds32[xo];
+                    Dx[u][cc] = lds32[idx[u][cc] + dxo[u][cc]];
                     U[u][cc] = lds32[idx[u][cc] - DPR];
                     Dn[u][cc] = lds32[idx[u][cc] + DPR];
                     w[u][cc] = philox_sweep((uint64_t)PHILOX_M0 * (gy * DPR + xd), key);
