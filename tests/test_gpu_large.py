@@ -53,6 +53,10 @@ CASES = [
     dict(L=1024, q=3, R=3, beta=linear_betas(1.0, 1), theta=2, seed=44, resample=2),
     # no sweeps: the step only copies the ancestors
     dict(L=272, q=6, R=7, beta=linear_betas(1.2, 3), theta=0, seed=45, resample=1),
+    # beta up to 6: the dE = 4 threshold is zero (exact 64-bit threshold form);
+    # a power-of-two side (fixed layout) and another one
+    dict(L=512, q=5, R=3, beta=linear_betas(6.0, 2), theta=1, seed=51, resample=0),
+    dict(L=264, q=5, R=3, beta=linear_betas(6.0, 2), theta=1, seed=52, resample=1),
 ]
 
 

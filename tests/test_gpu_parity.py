@@ -68,6 +68,9 @@ FULL_CASES = [
     dict(L=32, q=2, R=400, beta=lin_beta(1.0, 10), theta=3, seed=2**33 + 7, resample=0),
     dict(L=8, q=255, R=100, beta=lin_beta(2.0, 8), theta=3, seed=11, resample=0),
     dict(L=8, q=4, R=1, beta=lin_beta(1.0, 5), theta=3, seed=12, resample=1),
+    # beta up to 6: the dE = 4 threshold is zero (exact 64-bit threshold form)
+    dict(L=16, q=4, R=300, beta=lin_beta(6.0, 6), theta=2, seed=14, resample=1),
+    dict(L=12, q=3, R=200, beta=lin_beta(6.0, 4), theta=2, seed=15, resample=0),
 ]
 
 
