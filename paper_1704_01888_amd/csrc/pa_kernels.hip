@@ -1249,7 +1249,14 @@ __device__ __forceinline__ void tile_of(uint32_t tiles, uint32_t &k, uint32_t &t
 __device__ __forceinline__ void load_tile_rows(uint32_t *lds32, const uint32_t *src32, uint32_t L,
                                                uint32_t y0, uint32_t n, bool above) {
     const uint32_t DPR = L >> 2;
-    for (uint32_t i = threadIdx.x; i < n * DPR; i += blockDim.x) lds32[DPR + i] = src32[y0 * DPR + i];
+    if ((L & 15u) == 0) {
+        // rows of 16-byte multiples: the tile's rows, contiguous in HBM, in 16-byte loads
+        const uint4 *src = reinterpret_cast<const uint4 *>(src32 + y0 * DPR);
+        uint4 *dst = reinterpret_cast<uint4 *>(lds32 + DPR);
+        for (uint32_t i = threadIdx.x; i < n * DPR / 4u; i += blockDim.x) dst[i] = src[i];
+    } else {
+        for (uint32_t i = threadIdx.x; i < n * DPR; i += blockDim.x) lds32[DPR + i] = src32[y0 * DPR + i];
+    }
     const uint32_t ya = (y0 + L - 1) % L, yb = (y0 + n) % L;
     for (uint32_t x = threadIdx.x; x < DPR; x += blockDim.x) {
         if (above) lds32[x] = src32[ya * DPR + x];
@@ -1336,10 +1343,21 @@ __global__ void __launch_bounds__(NTT) k_tiled_fixed(TiledArgs a) {
     static_assert(DPR % 64 == 0, "whole waves per row");
     for (uint32_t r = threadIdx.x >> 6; r < nl; r += NT / 64) {
         const uint32_t gy = (y0 + r + L - S) & (L - 1);
+        if constexpr (DPR % 256 == 0) {
+            // 16-byte loads: a wave covers 1 KB of the row per load
+            const uint4 *srow = reinterpret_cast<const uint4 *>(src32 + gy * DPR);
+            uint4 *lrow = reinterpret_cast<uint4 *>(lds32 + r * DPR);
 #pragma unroll
-        for (uint32_t c = 0; c < DPR / 64; ++c) {
-            const uint32_t x = (threadIdx.x & 63u) + 64u * c;
-            lds32[r * DPR + x] = src32[gy * DPR + x];
+            for (uint32_t c = 0; c < DPR / 256; ++c) {
+                const uint32_t x4 = (threadIdx.x & 63u) + 64u * c;
+                lrow[x4] = srow[x4];
+            }
+        } else {
+#pragma unroll
+            for (uint32_t c = 0; c < DPR / 64; ++c) {
+                const uint32_t x = (threadIdx.x & 63u) + 64u * c;
+                lds32[r * DPR + x] = src32[gy * DPR + x];
+            }
         }
     }
     __syncthreads();
@@ -1397,8 +1415,11 @@ __global__ void __launch_bounds__(NTT) k_tiled_fixed(TiledArgs a) {
         }
         __syncthreads();
     }
-    uint32_t *dst32 = reinterpret_cast<uint32_t *>(a.dst + (size_t)k * a.N) + y0 * DPR;
-    for (uint32_t i = threadIdx.x; i < n * DPR; i += NT) dst32[i] = lds32[S * DPR + i];
+    // the tile's rows, contiguous in HBM, in 16-byte stores (rows of L bytes, L a
+    // power of two from 512)
+    uint4 *dst = reinterpret_cast<uint4 *>(a.dst + (size_t)k * a.N + (size_t)y0 * L);
+    const uint4 *lsrc = reinterpret_cast<const uint4 *>(lds32 + S * DPR);
+    for (uint32_t i = threadIdx.x; i < n * DPR / 4u; i += NT) dst[i] = lsrc[i];
 }
 
 __global__ void __launch_bounds__(256) k_tiled_init(TiledArgs a) {
@@ -1437,12 +1458,22 @@ __global__ void __launch_bounds__(256) k_tiled_measure(TiledArgs a) {
         for (uint32_t s = threadIdx.x; s < a.q; s += blockDim.x) scnt[s] = 0u;
     load_tile_rows(lds32, reinterpret_cast<const uint32_t *>(a.dst + (size_t)k * a.N), L, y0, n, false);
     __syncthreads();
+    // Bonds to the right and down of every site of the tile: a lane keeps one
+    // dword column (and its right neighbour, periodic) and steps over rows.
     uint32_t bonds = 0;
-    for (uint32_t i = threadIdx.x; i < n * DPR; i += blockDim.x) {
-        const uint32_t xd = i % DPR, idx = DPR + i;
-        const uint32_t D = lds32[idx];
-        const uint32_t Dr = lds32[xd == DPR - 1 ? idx - (DPR - 1) : idx + 1];
-        bonds += eq_bytes(D, __builtin_amdgcn_alignbyte(Dr, D, 1)) + eq_bytes(D, lds32[idx + DPR]);
+    auto column = [&](uint32_t x, uint32_t r0, uint32_t rstep) {
+        const uint32_t xr = x == DPR - 1 ? 0u : x + 1u;
+        for (uint32_t r = r0; r < n; r += rstep) {
+            const uint32_t *row = lds32 + (r + 1) * DPR;
+            const uint32_t D = row[x];
+            bonds += eq_bytes(D, __builtin_amdgcn_alignbyte(row[xr], D, 1)) + eq_bytes(D, row[DPR + x]);
+        }
+    };
+    if (DPR <= blockDim.x) {
+        const uint32_t per = blockDim.x / DPR;            // rows per pass of the workgroup
+        if (threadIdx.x < per * DPR) column(threadIdx.x % DPR, threadIdx.x / DPR, per);
+    } else {
+        for (uint32_t x = threadIdx.x; x < DPR; x += blockDim.x) column(x, 0u, 1u);
     }
     bonds = wave_sum(bonds);
     if ((threadIdx.x & 63u) == 0) s_part[threadIdx.x >> 6] = bonds;
