@@ -274,9 +274,22 @@ __device__ __forceinline__ uint32_t update_pair(uint32_t D0, uint32_t Dx, uint32
         at = __builtin_amdgcn_sad_u8(flags_ne<QSMALL>(H ^ P), 0x1C1C3C3Cu, at);
         at = __builtin_amdgcn_sad_u8(flags_ne<QSMALL>(V ^ P), 0x1C1C3C3Cu, at);
         const u32x2 T = thr.pair_at(at);
-        const uint32_t t0 = w.y <= T.x ? P : S;
-        const uint32_t t1 = w.w <= T.y ? P : S;
-        const uint32_t X = perm(t1, t0, 0x07060100u);     // s0', s0', s1', s1' (accepted)
+        // X = bytes 0-1 of (w.y <= T.x ? P : S), bytes 2-3 of (w.w <= T.y ? P : S):
+        // the second select takes the upper halves of S and P and writes only
+        // the upper half of X (SDWA, lower half preserved), so no byte permute
+        // merges the two sites.  A compare's VCC
+        // is read two wait states later, as the compiler's own code does.
+        uint32_t X;
+        asm("v_cmp_le_u32 vcc, %[wy], %[tx]\n\t"
+            "s_nop 1\n\t"
+            "v_cndmask_b32 %[X], %[S], %[P], vcc\n\t"
+            "v_cmp_le_u32 vcc, %[ww], %[ty]\n\t"
+            "s_nop 1\n\t"
+            "v_cndmask_b32_sdwa %[X], %[S], %[P], vcc dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE "
+            "src0_sel:WORD_1 src1_sel:WORD_1"
+            : [X] "=&v"(X)
+            : [wy] "v"(w.y), [tx] "v"(T.x), [ww] "v"(w.w), [ty] "v"(T.y), [S] "v"(S), [P] "v"(P)
+            : "vcc");
         return bit_select(ps.mask, X, D0);
     }
     const uint32_t n0 = perm(V, H, 0x05040100u);
