@@ -1557,7 +1557,7 @@ static const LaneChoice kLaneChoices[LANE_CHOICE_COUNT] = {
     {48, {192, 576}},     // three or nine waves per replica
     {64, {512, 1024}},
     {96, {768, 384}},     // twelve or six waves per replica
-    {128, {1024, 512}},
+    {128, {512, 1024}},
     {192, {768, 384}},
     {256, {1024, 512}},
 };
