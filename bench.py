@@ -45,14 +45,14 @@ MIX_PEAK_LANE_OPS = 1.055 * VALU_PEAK_LANE_OPS
 # VALU lane-instructions per spin-flip attempt of k_sweep on this workload,
 # from rocprofv3 SQ_INSTS_VALU x 64 / attempts (gather, sweeps and energy
 # epilogue; profiles/k_sweep_32x32_q10_R20000.md; 256 lanes per replica).
-INSTR_PER_ATTEMPT = 33.43
+INSTR_PER_ATTEMPT = 33.30
 
 # HBM bytes per k_sweep launch on this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by 2.00 and 1.00, the factors the plain 256 MiB copy of
-# --copy-calibration gives): (10654.0 * 2 + 20624.8) KiB;
+# --copy-calibration gives): (10652.0 * 2 + 20624.8) KiB;
 # profiles/k_sweep_32x32_q10_R20000.md.  The algorithmic bytes are 2 * R * N =
 # 41 MB (gather + store); repeated ancestors are served from cache.
-SWEEP_TRAFFIC_BYTES = (10654.0 * 2.0 + 20624.8) * 1024
+SWEEP_TRAFFIC_BYTES = (10652.0 * 2.0 + 20624.8) * 1024
 
 WORKLOAD = dict(L=32, q=10, R=20000, K=401, beta_max=1.6, theta=10, seed=2)
 

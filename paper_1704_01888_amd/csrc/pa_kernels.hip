@@ -506,18 +506,6 @@ __device__ __forceinline__ uint32_t wave_total(uint32_t v) {
 template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     extern __shared__ __align__(16) uint8_t smem[];
-    if (threadIdx.x == 32) reinterpret_cast<uint32_t *>(smem)[24] = 0u;   // energy sum (multi-wave)
-    if (threadIdx.x == 33) reinterpret_cast<uint64_t *>(smem)[13] = 0ull; // digest sum (multi-wave)
-    if (a.Mt_out && a.G > 64 && a.G % 64u == 0) {   // per-state counters of a multi-wave replica, after its rows
-        uint32_t *mcnt = reinterpret_cast<uint32_t *>(smem + LDS_HDR + a.N + 2 * a.L);
-        for (uint32_t t = threadIdx.x; t < a.q; t += blockDim.x) mcnt[t] = 0u;
-    }
-    if (64u % a.G != 0 && a.G % 64u != 0) {       // sums of spanning replicas, after all rows
-        const uint32_t nr = blockDim.x / a.G;
-        uint8_t *acc = smem + LDS_HDR + (size_t)nr * (a.N + 2 * a.L);
-        const uint32_t words = nr * (3u + (a.Mt_out ? a.q : 0u));
-        for (uint32_t t = threadIdx.x; t < words; t += blockDim.x) reinterpret_cast<uint32_t *>(acc)[t] = 0u;
-    }
     // Lanes per replica G: a divisor of 64 (one or several replicas per wave),
     // a multiple of 64 (one replica per block of G/64 waves), or neither
     // (replicas span wave boundaries, several per block: "spanning").  Every
@@ -525,6 +513,18 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     const uint32_t G = GT ? GT : a.G;
     const bool multiwave = G > 64 && G % 64u == 0;               // one replica per block
     const bool span = 64u % G != 0 && !multiwave;
+    if (threadIdx.x == 32) reinterpret_cast<uint32_t *>(smem)[24] = 0u;   // energy sum (multi-wave)
+    if (threadIdx.x == 33) reinterpret_cast<uint64_t *>(smem)[13] = 0ull; // digest sum (multi-wave)
+    if (a.Mt_out && multiwave) {   // per-state counters of a multi-wave replica, after its rows
+        uint32_t *mcnt = reinterpret_cast<uint32_t *>(smem + LDS_HDR + a.N + 2 * a.L);
+        for (uint32_t t = threadIdx.x; t < a.q; t += blockDim.x) mcnt[t] = 0u;
+    }
+    if (span) {       // sums of spanning replicas, after all rows
+        const uint32_t nr = blockDim.x / G;
+        uint8_t *acc = smem + LDS_HDR + (size_t)nr * (a.N + 2 * a.L);
+        const uint32_t words = nr * (3u + (a.Mt_out ? a.q : 0u));
+        for (uint32_t t = threadIdx.x; t < words; t += blockDim.x) reinterpret_cast<uint32_t *>(acc)[t] = 0u;
+    }
     const bool barrier = multiwave || span;
     const uint32_t wave = threadIdx.x >> 6;
     const uint32_t g = multiwave ? threadIdx.x : threadIdx.x % G;
