@@ -800,28 +800,41 @@ __device__ double hist_fwhm_levels(const HistView &v, uint32_t B, uint64_t *scra
 }
 
 // Calls f(x[j]) for j = 0 .. n-1 (4-byte elements, 16-byte aligned array), in
-// no particular order, in tiles of blockDim * 16 elements: each thread issues
-// its four 128-bit loads of a tile together, and each load of a wave covers
-// 1 KB of consecutive elements.
+// no particular order, in tiles of blockDim * 32 elements: each thread issues
+// its eight 128-bit loads of a tile together, and each load of a wave covers
+// 1 KB of consecutive elements.  A partial last tile keeps that layout, each
+// 128-bit load bounded on its own, so that it costs one memory latency like a
+// full one (a population of up to 32768 replicas is read in one round by 1024
+// threads).
 template <typename T, typename F>
 __device__ __forceinline__ void for_each_tiled(const T *x, uint64_t n, F f) {
     static_assert(sizeof(T) == 4, "4-byte elements");
-    constexpr uint32_t V = 16;
-    const uint64_t tile = (uint64_t)blockDim.x * V;
+    constexpr uint32_t V = 32;
+    const uint32_t tile = blockDim.x * V;
     for (uint64_t base = 0; base < n; base += tile) {
-        if (base + tile <= n) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(x + base) + threadIdx.x;
-            T v[V];
+        const T *xb = x + base;
+        T v[V];
+        // element 4 (q blockDim + t) + r of the tile: row q, thread t
+        const uint32_t left = n - base < tile ? (uint32_t)(n - base) : tile;
+        const uint32_t m4 = left & ~3u;
+        bool ok[V / 4];
 #pragma unroll
-            for (uint32_t q = 0; q < V / 4; ++q) {
-                const uint4 w = src[q * blockDim.x];
+        for (uint32_t q = 0; q < V / 4; ++q) {
+            const uint32_t o = 4u * (q * blockDim.x + threadIdx.x);
+            ok[q] = o < m4;
+            if (ok[q]) {
+                const uint4 w = *reinterpret_cast<const uint4 *>(xb + o);
                 v[4 * q] = (T)w.x; v[4 * q + 1] = (T)w.y; v[4 * q + 2] = (T)w.z; v[4 * q + 3] = (T)w.w;
             }
-#pragma unroll
-            for (uint32_t q = 0; q < V; ++q) f(v[q]);
-        } else {
-            for (uint64_t j = base + threadIdx.x; j < n; j += blockDim.x) f(x[j]);
         }
+        // the last tile's final left mod 4 elements, one by one
+        if (threadIdx.x < left - m4) f(xb[m4 + threadIdx.x]);
+#pragma unroll
+        for (uint32_t q = 0; q < V / 4; ++q)
+            if (ok[q]) {
+#pragma unroll
+                for (uint32_t r = 0; r < 4; ++r) f(v[4 * q + r]);
+            }
     }
 }
 
