@@ -702,8 +702,12 @@ __global__ void __launch_bounds__(1024) k_sweep_batch(const SweepArgs *runs, con
 }
 
 // ---------------------------------------------------------------------------
-// Workgroup helpers (1024 threads = 16 waves).
+// Workgroup helpers (1024 threads = 16 waves).  k_post and k_countfill, the
+// kernels they serve, always run workgroups of WG_THREADS, so the per-wave
+// partials are combined in unrolled loops whose LDS reads issue together.
 // ---------------------------------------------------------------------------
+constexpr uint32_t WG_THREADS = 1024, WG_WAVES = WG_THREADS / 64;
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -726,11 +730,12 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
 // order); *total receives the block sum.  scratch holds blockDim/64 entries.
 template <typename T>
 __device__ __forceinline__ T block_wave_offset(T wave_total, T *scratch, T *total) {
-    const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63u) == 0) scratch[wave] = wave_total;
     __syncthreads();
     T off = T(0), tot = T(0);
-    for (uint32_t w = 0; w < nw; ++w) {
+#pragma unroll
+    for (uint32_t w = 0; w < WG_WAVES; ++w) {
         const T x = scratch[w];
         off += w < wave ? x : T(0);
         tot += x;
@@ -745,12 +750,12 @@ __device__ __forceinline__ T block_wave_offset(T wave_total, T *scratch, T *tota
 template <typename T, typename Op>
 __device__ __forceinline__ T block_reduce(T v, Op op, T *scratch) {
     for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
-    const uint32_t nw = blockDim.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63u) == 0) scratch[threadIdx.x >> 6] = v;
     __syncthreads();
     T r = scratch[0];
-    for (uint32_t w = 1; w < nw; ++w) r = op(r, scratch[w]);
+#pragma unroll
+    for (uint32_t w = 1; w < WG_WAVES; ++w) r = op(r, scratch[w]);
     return r;
 }
 
@@ -842,8 +847,8 @@ __device__ __forceinline__ void for_each_tiled(const T *x, uint64_t n, F f) {
 struct SumMinMax { int64_t sum; int32_t mn, mx; };
 
 __device__ SumMinMax block_sum_min_max(int64_t sum, int32_t mn, int32_t mx) {
-    __shared__ int64_t s_sum[16];
-    __shared__ int32_t s_mn[16], s_mx[16];
+    __shared__ int64_t s_sum[WG_WAVES];
+    __shared__ int32_t s_mn[WG_WAVES], s_mx[WG_WAVES];
     for (int off = 32; off > 0; off >>= 1) {
         sum += __shfl_xor(sum, off, 64);
         mn = min(mn, __shfl_xor(mn, off, 64));
@@ -853,7 +858,8 @@ __device__ SumMinMax block_sum_min_max(int64_t sum, int32_t mn, int32_t mx) {
     if ((threadIdx.x & 63u) == 0) { s_sum[threadIdx.x >> 6] = sum; s_mn[threadIdx.x >> 6] = mn; s_mx[threadIdx.x >> 6] = mx; }
     __syncthreads();
     SumMinMax r{s_sum[0], s_mn[0], s_mx[0]};
-    for (uint32_t w = 1; w < (blockDim.x >> 6); ++w) {
+#pragma unroll
+    for (uint32_t w = 1; w < WG_WAVES; ++w) {
         r.sum += s_sum[w]; r.mn = min(r.mn, s_mn[w]); r.mx = max(r.mx, s_mx[w]);
     }
     return r;
@@ -978,8 +984,8 @@ __device__ __forceinline__ void weight_block(const int32_t *E, uint32_t first, u
 // of replicas each.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist, uint64_t *scratch) {
-    __shared__ double s_w[16];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nw = blockDim.x >> 6;
+    __shared__ double s_w[WG_WAVES];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const uint32_t nb = a.nbins;
 
     // eq. (4) sums and the energy histogram h[E + 2N] of step i
@@ -1006,7 +1012,8 @@ __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist
     if (tid == 0) {
         double S = 0.0;
         uint64_t C = 0;
-        for (uint32_t w = 0; w < nw; ++w) { S += s_w[w]; C += scratch[w]; }
+#pragma unroll
+        for (uint32_t w = 0; w < WG_WAVES; ++w) { S += s_w[w]; C += scratch[w]; }
         a.count[a.step] = C;
         if (a.has_next) {
             const double lnq = -a.dbeta_next * (double)ref + log(S) - log((double)a.R_i);
@@ -1048,20 +1055,124 @@ __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist
 
 }
 
+// A population of at most 32 blockDim 4-byte values held in registers, in
+// the tile layout of for_each_tiled: row q, thread t holds the cnt(q) values
+// 4 (q blockDim + t) + r, r < cnt(q) (4 for a whole row).  One round of
+// 128-bit loads; the last n mod 4 values are read by the thread whose row
+// position they fill.
+struct TileRegs {
+    static constexpr uint32_t Q = 8;
+    int32_t v[4 * Q];
+    uint32_t m4, rem, qr;   // n rounded down to a multiple of 4, n mod 4, the row holding m4
+    bool own;               // this thread holds the last rem values (in row qr)
+
+    __device__ __forceinline__ uint32_t cnt(uint32_t q) const {
+        return 4u * (q * blockDim.x + threadIdx.x) < m4 ? 4u : (own && q == qr ? rem : 0u);
+    }
+    __device__ __forceinline__ void load(const int32_t *x, uint32_t n) {
+        const uint32_t row = 4u * blockDim.x;
+        m4 = n & ~3u; rem = n - m4; qr = m4 / row;
+        own = rem != 0u && threadIdx.x == (m4 % row) / 4u;
+        int32_t er[3] = {0, 0, 0};
+        if (own) {
+#pragma unroll
+            for (uint32_t r = 0; r < 3; ++r) if (r < rem) er[r] = x[m4 + r];
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < Q; ++q) {
+            const uint32_t o = 4u * (q * blockDim.x + threadIdx.x);
+            if (o < m4) {
+                const int4 w = *reinterpret_cast<const int4 *>(x + o);
+                v[4 * q] = w.x; v[4 * q + 1] = w.y; v[4 * q + 2] = w.z; v[4 * q + 3] = w.w;
+            } else {
+                v[4 * q] = er[0]; v[4 * q + 1] = er[1]; v[4 * q + 2] = er[2]; v[4 * q + 3] = 0;
+            }
+        }
+    }
+    template <typename F>
+    __device__ __forceinline__ void each(F f) const {
+#pragma unroll
+        for (uint32_t q = 0; q < Q; ++q) {
+            const uint32_t c = cnt(q);
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r)
+                if (r < c) f(v[4 * q + r]);
+        }
+    }
+};
+
+// weight_block for a population held in TileRegs whose blocks are its rows
+// (block b = row b, first = 4 b blockDim): the carry sums the rows before b,
+// and row b is scanned and stored as C.
+template <typename WF>
+__device__ __forceinline__ void weight_row_regs(const TileRegs &tr, uint32_t b, WF wf, uint64_t *C,
+                                                uint64_t *scratch) {
+    uint64_t carry = 0;
+    int32_t e[4] = {0, 0, 0, 0};
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < TileRegs::Q; ++q) {
+        if (q < b) {
+            const uint32_t cq = tr.cnt(q);
+#pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) carry += r < cq ? wf(tr.v[4 * q + r]) : 0ull;
+        }
+        if (q == b) {
+            e[0] = tr.v[4 * q]; e[1] = tr.v[4 * q + 1]; e[2] = tr.v[4 * q + 2]; e[3] = tr.v[4 * q + 3];
+            c = tr.cnt(q);
+        }
+    }
+    carry = block_reduce(carry, [](uint64_t x, uint64_t y) { return x + y; }, scratch);
+    __syncthreads();
+    uint64_t w[4];
+#pragma unroll
+    for (uint32_t r = 0; r < 4; ++r) w[r] = r < c ? wf(e[r]) : 0ull;
+    w[1] += w[0]; w[2] += w[1]; w[3] += w[2];
+    const uint64_t incl = wave_inclusive_scan(w[3]);
+    uint64_t total;
+    const uint64_t off = carry + block_wave_offset(__shfl(incl, 63, 64), scratch, &total) + incl - w[3];
+#pragma unroll
+    for (uint32_t r = 0; r < 4; ++r) w[r] += off;
+    const uint32_t j = 4u * (b * blockDim.x + threadIdx.x);
+    if (c == 4u) {
+        ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(C + j);
+        dst[0] = make_ulonglong2(w[0], w[1]);
+        dst[1] = make_ulonglong2(w[2], w[3]);
+    } else {
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r)
+            if (r < c) C[j + r] = w[r];
+    }
+}
+
 // Weight workgroup b: E_ref of step i+1 (the minimum or maximum energy of the
 // population, as the statistics workgroup finds it) and C over block b.  The
 // distances that occur are 0 .. max - min; their weights are read from LDS
-// when they fit there.
+// when they fit there.  A population of at most 32 blockDim replicas in
+// blocks of one row each (R_i <= 32768 with 1024 threads) is read once, into
+// registers, for the range, the carry and the block.
 __device__ __forceinline__ void post_weights(const PostArgs &a, uint32_t b, uint32_t *lds, uint64_t *scratch) {
     const uint32_t n = (uint32_t)a.R_i, tid = threadIdx.x;
     const uint32_t first = b * a.wblock, last = min(first + a.wblock, n);
+    const bool in_regs = n <= 32u * blockDim.x && a.wblock == 4u * blockDim.x;
+    TileRegs tr;
     int32_t mn = 0x7fffffff, mx = (int32_t)0x80000000;
-    for_each_tiled(a.E, n, [&](int32_t e) { mn = min(mn, e); mx = max(mx, e); });
+    const auto range = [&](int32_t e) { mn = min(mn, e); mx = max(mx, e); };
+    if (in_regs) {
+        tr.load(a.E, n);
+        tr.each(range);
+    } else {
+        for_each_tiled(a.E, n, range);
+    }
     const SumMinMax t = block_sum_min_max(0, mn, mx);
     const int32_t ref = a.dbeta_next >= 0.0 ? t.mn : t.mx;
+    const auto weights = [&](auto wf) {
+        if (in_regs) weight_row_regs(tr, b, wf, a.C, scratch);
+        else weight_block(a.E, first, last, wf, a.C, scratch);
+    };
     if (a.w_const) {
         const uint64_t wc = a.w_const;
-        weight_block(a.E, first, last, [=](int32_t) { return wc; }, a.C, scratch);
+        weights([=](int32_t) { return wc; });
         return;
     }
     const uint32_t span = (uint32_t)(t.mx - t.mn) + 1u;
@@ -1070,17 +1181,17 @@ __device__ __forceinline__ void post_weights(const PostArgs &a, uint32_t b, uint
         uint64_t *Wl = reinterpret_cast<uint64_t *>(lds);
         for (uint32_t d = tid; d < nW; d += blockDim.x) Wl[d] = a.W[d];
         __syncthreads();
-        weight_block(a.E, first, last, [=](int32_t e) {
+        weights([=](int32_t e) {
             const uint32_t d = (uint32_t)abs(e - ref);
             return d < nW ? Wl[d] : 0ull;
-        }, a.C, scratch);
+        });
     } else {
         const uint64_t *Wg = a.W;
         const uint32_t D = a.D;
-        weight_block(a.E, first, last, [=](int32_t e) {
+        weights([=](int32_t e) {
             const uint32_t d = (uint32_t)abs(e - ref);
             return d < D ? Wg[d] : 0ull;
-        }, a.C, scratch);
+        });
     }
 }
 
@@ -1091,10 +1202,10 @@ __device__ __forceinline__ void post_block(const PostArgs &a, uint32_t b) {
     else post_weights(a, b - 1, lds, scratch);
 }
 
-__global__ void __launch_bounds__(1024) k_post(PostArgs a) { post_block(a, blockIdx.x); }
+__global__ void __launch_bounds__(WG_THREADS) k_post(PostArgs a) { post_block(a, blockIdx.x); }
 
 // Batched form: run r owns workgroups start[r] .. start[r+1]-1.
-__global__ void __launch_bounds__(1024) k_post_batch(const PostArgs *runs, const uint32_t *start, uint32_t n) {
+__global__ void __launch_bounds__(WG_THREADS) k_post_batch(const PostArgs *runs, const uint32_t *start, uint32_t n) {
     const uint32_t r = segment_of(start, n, blockIdx.x);
     const PostArgs a = runs[r];
     post_block(a, blockIdx.x - start[r]);
@@ -1231,13 +1342,13 @@ __global__ void __launch_bounds__(256) k_sample_batch(const SampleArgs *runs, co
     sample_one(a, (uint64_t)(blockIdx.x - start[r]) * blockDim.x + threadIdx.x);
 }
 
-__global__ void __launch_bounds__(1024) k_countfill(SlotmapArgs m) {
+__global__ void __launch_bounds__(WG_THREADS) k_countfill(SlotmapArgs m) {
     __shared__ uint64_t scratch[17];
     countfill_block(m, blockIdx.x, scratch);
 }
 
 // Batched form: run r owns workgroups start[r] .. start[r+1]-1.
-__global__ void __launch_bounds__(1024) k_countfill_batch(const SlotmapArgs *runs, const uint32_t *start,
+__global__ void __launch_bounds__(WG_THREADS) k_countfill_batch(const SlotmapArgs *runs, const uint32_t *start,
                                                           uint32_t n) {
     __shared__ uint64_t scratch[17];
     const uint32_t r = segment_of(start, n, blockIdx.x);
@@ -1657,14 +1768,14 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_post(const PostArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_post, dim3(post_blocks(a)), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_post, dim3(post_blocks(a)), dim3(WG_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_resample(const SampleArgs &a, const SlotmapArgs &m, hipStream_t s) {
     const uint64_t blocks = (a.n_new + 255) / 256;
     if (blocks) hipLaunchKernelGGL(k_sample, dim3((uint32_t)blocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_countfill, dim3(countfill_blocks(m)), dim3(1024), 0, s, m);
+    hipLaunchKernelGGL(k_countfill, dim3(countfill_blocks(m)), dim3(WG_THREADS), 0, s, m);
     return hipGetLastError();
 }
 
@@ -1721,7 +1832,7 @@ hipError_t launch_sweep_batch(uint32_t cls, const SweepArgs *runs, const uint32_
 hipError_t launch_post_batch(const PostArgs *runs, const uint32_t *pstart, uint32_t n, uint32_t blocks,
                              hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_post_batch, dim3(blocks), dim3(1024), 0, s, runs, pstart, n);
+    hipLaunchKernelGGL(k_post_batch, dim3(blocks), dim3(WG_THREADS), 0, s, runs, pstart, n);
     return hipGetLastError();
 }
 
@@ -1730,7 +1841,7 @@ hipError_t launch_resample_batch(const SampleArgs *sruns, const uint32_t *start,
                                  uint32_t mblocks, hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (blocks) hipLaunchKernelGGL(k_sample_batch, dim3(blocks), dim3(256), 0, s, sruns, start, n);
-    hipLaunchKernelGGL(k_countfill_batch, dim3(mblocks), dim3(1024), 0, s, mruns, mstart, n);
+    hipLaunchKernelGGL(k_countfill_batch, dim3(mblocks), dim3(WG_THREADS), 0, s, mruns, mstart, n);
     return hipGetLastError();
 }
 
