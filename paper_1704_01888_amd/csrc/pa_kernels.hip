@@ -708,6 +708,44 @@ __global__ void __launch_bounds__(1024) k_sweep_batch(const SweepArgs *runs, con
 // ---------------------------------------------------------------------------
 constexpr uint32_t WG_THREADS = 1024, WG_WAVES = WG_THREADS / 64;
 
+// Lane moves of a 4- or 8-byte value: DPP pattern CTRL, and one lane's value.
+template <uint32_t CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T v) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+    } else {
+        static_assert(sizeof(T) == 8, "4- or 8-byte values");
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int lane) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// op over the 64 lanes of a wave (all active; op associative and
+// commutative), wave-uniform: the DPP steps of wave_total, then the four row
+// results read from lanes 0, 16, 32 and 48.  No lane addresses, unlike
+// ds_bpermute shuffles.
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_allreduce(T v, Op op) {
+    v = op(v, dpp_move<0xB1>(v));
+    v = op(v, dpp_move<0x4E>(v));
+    v = op(v, dpp_move<0x124>(v));
+    v = op(v, dpp_move<0x128>(v));
+    return op(op(lane_value(v, 0), lane_value(v, 16)), op(lane_value(v, 32), lane_value(v, 48)));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -749,7 +787,7 @@ __device__ __forceinline__ T block_wave_offset(T wave_total, T *scratch, T *tota
 // scratch holds blockDim/64 entries.
 template <typename T, typename Op>
 __device__ __forceinline__ T block_reduce(T v, Op op, T *scratch) {
-    for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
+    v = wave_allreduce(v, op);
     __syncthreads();
     if ((threadIdx.x & 63u) == 0) scratch[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -849,11 +887,9 @@ struct SumMinMax { int64_t sum; int32_t mn, mx; };
 __device__ SumMinMax block_sum_min_max(int64_t sum, int32_t mn, int32_t mx) {
     __shared__ int64_t s_sum[WG_WAVES];
     __shared__ int32_t s_mn[WG_WAVES], s_mx[WG_WAVES];
-    for (int off = 32; off > 0; off >>= 1) {
-        sum += __shfl_xor(sum, off, 64);
-        mn = min(mn, __shfl_xor(mn, off, 64));
-        mx = max(mx, __shfl_xor(mx, off, 64));
-    }
+    sum = wave_allreduce(sum, [](int64_t x, int64_t y) { return x + y; });
+    mn = wave_allreduce(mn, [](int32_t x, int32_t y) { return min(x, y); });
+    mx = wave_allreduce(mx, [](int32_t x, int32_t y) { return max(x, y); });
     __syncthreads();
     if ((threadIdx.x & 63u) == 0) { s_sum[threadIdx.x >> 6] = sum; s_mn[threadIdx.x >> 6] = mn; s_mx[threadIdx.x >> 6] = mx; }
     __syncthreads();
@@ -878,22 +914,32 @@ __device__ HistBuild build_hist(const T *x, uint64_t n, int32_t shift, uint32_t 
                                 uint32_t cap, uint32_t *out) {
     HistBuild r;
     if (nb <= cap) {
-        for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) lds[b] = 0u;
+        // C interleaved copies of every level (lds[level * C + c], the lane
+        // picking c), C = 8, 4, 2 or 1 as they fit beside the folded counts
+        // at lds[nb * C ..]: a population concentrated on a few energies
+        // sends many lanes of a wave to the same level, and LDS atomics on
+        // one address serialise.
+        const uint32_t C = nb * 9u <= cap ? 8u : nb * 5u <= cap ? 4u : nb * 3u <= cap ? 2u : 1u;
+        uint32_t *folded = C > 1u ? lds + nb * C : lds;
+        for (uint32_t b = threadIdx.x; b < nb * C; b += blockDim.x) lds[b] = 0u;
         __syncthreads();
-        for_each_tiled(x, n, [&](T e) { atomicAdd(&lds[(uint32_t)((int32_t)e + shift)], 1u); });
+        const uint32_t c = threadIdx.x & (C - 1u);
+        for_each_tiled(x, n, [&](T e) { atomicAdd(&lds[(uint32_t)((int32_t)e + shift) * C + c], 1u); });
         __syncthreads();
         int64_t sum = 0;
         int32_t mn = 0x7fffffff, mx = (int32_t)0x80000000;
         for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
-            const uint32_t h = lds[b];
+            uint32_t h = 0;
+            for (uint32_t k = 0; k < C; ++k) h += lds[b * C + k];
+            if (C > 1u) folded[b] = h;
             if (h) {
                 const int32_t e = (int32_t)b - shift;
                 sum += (int64_t)h * e; mn = min(mn, e); mx = max(mx, e);
             }
         }
-        const SumMinMax t = block_sum_min_max(sum, mn, mx);
+        const SumMinMax t = block_sum_min_max(sum, mn, mx);   // synchronises the workgroup first
         r.sum = t.sum; r.mn = t.mn; r.mx = t.mx;
-        r.v = HistView{lds, 0u, nb, nb};
+        r.v = HistView{folded, 0u, nb, nb};
         return r;
     }
     int64_t sum = 0;
