@@ -1033,6 +1033,9 @@ __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist
     __shared__ double s_w[WG_WAVES];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const uint32_t nb = a.nbins;
+    // -beta F of step i, read first: the ln Q_{i+1} chain of thread 0 below
+    // would otherwise wait a memory latency for it
+    const double mbF_i = (tid == 0 && a.has_next) ? a.mbF[a.step] : 0.0;
 
     // eq. (4) sums and the energy histogram h[E + 2N] of step i
     const HistBuild he = build_hist(a.E, a.R_i, a.two_n, nb, lds_hist, POST_LDS_BINS, a.hist);
@@ -1052,7 +1055,7 @@ __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist
             acc += (double)h * exp(-(a.abs_dbeta_next * (double)abs((int32_t)(b + he.v.lo) - a.two_n - ref)));
     }
     acc = wave_sum(acc);
-    cnt = wave_sum(cnt);
+    cnt = wave_allreduce(cnt, [](uint64_t x, uint64_t y) { return x + y; });
     if (lane == 0) { s_w[wave] = acc; scratch[wave] = cnt; }
     __syncthreads();
     if (tid == 0) {
@@ -1064,7 +1067,7 @@ __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist
         if (a.has_next) {
             const double lnq = -a.dbeta_next * (double)ref + log(S) - log((double)a.R_i);
             a.lnQ[a.step + 1] = lnq;
-            a.mbF[a.step + 1] = a.mbF[a.step] + lnq;
+            a.mbF[a.step + 1] = mbF_i + lnq;
         }
     }
     __syncthreads();
