@@ -752,15 +752,29 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// Inclusive scan over the 64 lanes of a wave.
+// Inclusive scan over the 64 lanes of a wave (all active), by DPP: shifts
+// right by 1, 2, 4 and 8 lanes within each row of 16 (zero entering), then
+// the last lane of row 0 and 2 added to rows 1 and 3 (row_bcast:15) and that
+// of row 1 to rows 2 and 3 (row_bcast:31).
+template <uint32_t CTRL, uint32_t ROWS, typename T>
+__device__ __forceinline__ T dpp_or_zero(T v) {
+    if constexpr (sizeof(T) == 4) {
+        return (T)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+    } else {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROWS, 0xF, false);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xF, false);
+        return (T)(((uint64_t)hi << 32) | lo);
+    }
+}
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T v) {
-    const uint32_t lane = threadIdx.x & 63u;
-#pragma unroll
-    for (uint32_t off = 1; off < 64; off <<= 1) {
-        const T n = __shfl_up(v, off, 64);
-        if (lane >= off) v += n;
-    }
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte integers");
+    v += dpp_or_zero<0x111, 0xF>(v);   // row_shr:1
+    v += dpp_or_zero<0x112, 0xF>(v);   // row_shr:2
+    v += dpp_or_zero<0x114, 0xF>(v);   // row_shr:4
+    v += dpp_or_zero<0x118, 0xF>(v);   // row_shr:8
+    v += dpp_or_zero<0x142, 0xA>(v);   // row_bcast:15 into rows 1, 3
+    v += dpp_or_zero<0x143, 0xC>(v);   // row_bcast:31 into rows 2, 3
     return v;
 }
 
@@ -1006,7 +1020,7 @@ __device__ __forceinline__ void weight_block(const int32_t *E, uint32_t first, u
         w[1] += w[0]; w[2] += w[1]; w[3] += w[2];
         const uint64_t incl = wave_inclusive_scan(w[3]);
         uint64_t total;
-        const uint64_t off = carry + block_wave_offset(__shfl(incl, 63, 64), scratch, &total) + incl - w[3];
+        const uint64_t off = carry + block_wave_offset(lane_value(incl, 63), scratch, &total) + incl - w[3];
 #pragma unroll
         for (uint32_t v = 0; v < 4; ++v) w[v] += off;
         if (j + 4u <= last) {
@@ -1179,7 +1193,7 @@ __device__ __forceinline__ void weight_row_regs(const TileRegs &tr, uint32_t b, 
     w[1] += w[0]; w[2] += w[1]; w[3] += w[2];
     const uint64_t incl = wave_inclusive_scan(w[3]);
     uint64_t total;
-    const uint64_t off = carry + block_wave_offset(__shfl(incl, 63, 64), scratch, &total) + incl - w[3];
+    const uint64_t off = carry + block_wave_offset(lane_value(incl, 63), scratch, &total) + incl - w[3];
 #pragma unroll
     for (uint32_t r = 0; r < 4; ++r) w[r] += off;
     const uint32_t j = 4u * (b * blockDim.x + threadIdx.x);
@@ -1300,7 +1314,7 @@ __device__ void countfill_block(const SlotmapArgs &a, uint32_t b, uint64_t *scra
         const uint32_t sum = r[0] + r[1] + r[2] + r[3];
         const uint32_t incl = wave_inclusive_scan(sum);
         uint32_t total;
-        const uint32_t woff = block_wave_offset(__shfl(incl, 63, 64), reinterpret_cast<uint32_t *>(scratch), &total);
+        const uint32_t woff = block_wave_offset(lane_value(incl, 63), reinterpret_cast<uint32_t *>(scratch), &total);
         const uint64_t o0 = carry + woff + incl - sum;
         // Short runs of copies are written by their own lane, long ones
         // (strongly skewed weights) by the whole wave.
