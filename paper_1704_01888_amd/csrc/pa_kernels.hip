@@ -1375,6 +1375,8 @@ __device__ __forceinline__ void wave_aggregated_inc(uint32_t *h, uint32_t key, b
     if (active) atomicAdd(&h[key], 1u);
 }
 
+constexpr uint64_t SAMPLE_WINDOW = 128;
+
 __device__ __forceinline__ void sample_one(const SampleArgs &a, uint64_t kk) {
     const bool live = kk < a.n_new;
     uint32_t anc = 0;
@@ -1383,7 +1385,17 @@ __device__ __forceinline__ void sample_one(const SampleArgs &a, uint64_t kk) {
         const uint4 w = philox((uint32_t)kk, 0u, a.step, DOM_RESAMPLE << 28, a.key0, a.key1);
         const uint64_t x = ((uint64_t)w.y << 32) | (uint64_t)w.x;
         const uint64_t u = __umul64hi(x, S);
-        uint64_t lo = 0, hi = a.R_prev - 1;
+        // The cumulative weights are close to linear in j unless the weights
+        // are strongly skewed: the window of SAMPLE_WINDOW replicas either
+        // side of x R / 2^64 holds the answer when C_{lo-1} <= u < C_hi (both
+        // ends read in one round), and the search runs there; otherwise over
+        // all replicas.
+        const uint64_t n = a.R_prev, j0 = __umul64hi(x, n);
+        const uint64_t wlo = j0 > SAMPLE_WINDOW ? j0 - SAMPLE_WINDOW : 0;
+        const uint64_t whi = j0 + SAMPLE_WINDOW < n ? j0 + SAMPLE_WINDOW : n - 1;
+        const uint64_t c_lo = wlo ? a.C[wlo - 1] : 0ull, c_hi = a.C[whi];
+        const bool in_window = c_lo <= u && c_hi > u;
+        uint64_t lo = in_window ? wlo : 0, hi = in_window ? whi : n - 1;
         while (lo < hi) {
             const uint64_t mid = lo + ((hi - lo) >> 1);
             if (a.C[mid] > u) hi = mid; else lo = mid + 1;
