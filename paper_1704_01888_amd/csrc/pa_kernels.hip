@@ -935,7 +935,10 @@ __device__ HistBuild build_hist(const T *x, uint64_t n, int32_t shift, uint32_t 
         // one address serialise.
         const uint32_t C = nb * 9u <= cap ? 8u : nb * 5u <= cap ? 4u : nb * 3u <= cap ? 2u : 1u;
         uint32_t *folded = C > 1u ? lds + nb * C : lds;
-        for (uint32_t b = threadIdx.x; b < nb * C; b += blockDim.x) lds[b] = 0u;
+        const uint32_t nz = nb * C;
+        for (uint32_t b = threadIdx.x; b < nz / 4u; b += blockDim.x)
+            reinterpret_cast<uint4 *>(lds)[b] = make_uint4(0u, 0u, 0u, 0u);
+        if (threadIdx.x < nz % 4u) lds[nz - 1u - threadIdx.x] = 0u;
         __syncthreads();
         const uint32_t c = threadIdx.x & (C - 1u);
         for_each_tiled(x, n, [&](T e) { atomicAdd(&lds[(uint32_t)((int32_t)e + shift) * C + c], 1u); });
@@ -1068,7 +1071,7 @@ __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist
         if (a.has_next && h)
             acc += (double)h * exp(-(a.abs_dbeta_next * (double)abs((int32_t)(b + he.v.lo) - a.two_n - ref)));
     }
-    acc = wave_sum(acc);
+    acc = wave_allreduce(acc, [](double x, double y) { return x + y; });
     cnt = wave_allreduce(cnt, [](uint64_t x, uint64_t y) { return x + y; });
     if (lane == 0) { s_w[wave] = acc; scratch[wave] = cnt; }
     __syncthreads();
