@@ -100,6 +100,8 @@ uint32_t weight_table(double abs_dbeta, uint32_t Kb, uint32_t N, uint64_t *W) {
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+// Elements per copy-count buffer: R_cap rounded up to 64 (256 bytes).
+inline size_t counts_stride(uint64_t R_cap) { return (size_t)((R_cap + 63) & ~uint64_t(63)); }
 
 struct Plan {
     pa_run_desc desc;
@@ -237,7 +239,9 @@ pa_status build_plan(const pa_run_desc *d, Plan &p) {
     p.off_pop[1] = o; o += popb;
     p.off_E = o; o += align256(4 * p.R_cap);
     p.off_C = o; o += align256(8 * p.R_cap);
-    p.off_r = o; o += align256(4 * 2 * p.R_cap);   // copy counts, one buffer per step parity
+    // copy counts, one buffer per step parity, each starting 256-byte aligned
+    // (the kernels read and clear them in 16-byte pieces)
+    p.off_r = o; o += 4 * 2 * counts_stride(p.R_cap);
     p.off_anc = o; o += align256(4 * p.R_cap);
     p.off_counts = o; o += align256(4 * p.R_cap);
     p.off_hist = o; o += align256((size_t)4 * p.nbins * (p.hist_all ? K : 1));
@@ -489,7 +493,7 @@ hipError_t launch_tiled_sweeps(pa::TiledArgs a, uint32_t theta, uint8_t *x, hipS
 
 // Copy-count buffer of step parity `par`.
 uint32_t *counts_buf(pa_run_state *r, uint32_t par) {
-    return r->at<uint32_t>(r->plan.off_r) + (size_t)(par & 1u) * r->plan.R_cap;
+    return r->at<uint32_t>(r->plan.off_r) + (size_t)(par & 1u) * counts_stride(r->plan.R_cap);
 }
 
 // Records of the resampling into step i (draws from the R_prev replicas of
@@ -803,7 +807,7 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
     if ((st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_hist), hist_words, 0u, s), "fill")) ||
         (mhist_words &&
          (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_mhist), mhist_words, 0u, s), "fill"))) ||
-        (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_r), 2 * p.R_cap, 0u, s), "fill")) ||
+        (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_r), 2 * counts_stride(p.R_cap), 0u, s), "fill")) ||
         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_lnQ), 2 * (size_t)p.desc.K, 0u, s), "fill")) ||
         (p.tiled &&
          (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_bonds), p.R_cap, 0u, s), "fill"))) ||

@@ -1288,9 +1288,12 @@ __device__ void countfill_block(const SlotmapArgs &a, uint32_t b, uint64_t *scra
     const uint32_t n = (uint32_t)a.R_prev;   // R_prev < 2^32
     const uint32_t first = b * a.block, last = min(first + a.block, n);
     const uint64_t stride = (uint64_t)countfill_blocks(a) * a.block;
+    // (c0 is a multiple of the block, 4096, and r_clear 16-byte aligned)
     for (uint64_t c0 = first; c0 < a.clear_n; c0 += stride) {
-        const uint64_t c1 = min(c0 + a.block, a.clear_n);
-        for (uint64_t i = c0 + tid; i < c1; i += blockDim.x) a.r_clear[i] = 0u;
+        const uint64_t c1 = min(c0 + a.block, a.clear_n), n4 = (c1 - c0) / 4u;
+        for (uint64_t i = tid; i < n4; i += blockDim.x)
+            reinterpret_cast<uint4 *>(a.r_clear + c0)[i] = make_uint4(0u, 0u, 0u, 0u);
+        if (tid < (c1 - c0) % 4u) a.r_clear[c1 - 1u - tid] = 0u;
     }
     // the block's rows do not depend on the sum before it: the first row's
     // counts are loaded before that sum, so that the two reads overlap
