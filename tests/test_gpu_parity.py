@@ -71,6 +71,12 @@ FULL_CASES = [
     # beta up to 6: the dE = 4 threshold is zero (exact 64-bit threshold form)
     dict(L=16, q=4, R=300, beta=lin_beta(6.0, 6), theta=2, seed=14, resample=1),
     dict(L=12, q=3, R=200, beta=lin_beta(6.0, 4), theta=2, seed=15, resample=0),
+    # the draws' search: weights exp(-dbeta dE) with dbeta = 1 over an energy spread of
+    # about a hundred put the cumulative weights far from linear, so the window around
+    # x R / 2^64 fails its check and all replicas are searched; many small steps keep
+    # the weights even and the window holds
+    dict(L=8, q=10, R=4000, beta=lin_beta(4.0, 4), theta=2, seed=16, resample=1),
+    dict(L=8, q=10, R=5000, beta=lin_beta(1.6, 40), theta=2, seed=17, resample=0),
 ]
 
 
