@@ -868,11 +868,24 @@ __device__ __forceinline__ void for_each_tiled(const T *x, uint64_t n, F f) {
     static_assert(sizeof(T) == 4, "4-byte elements");
     constexpr uint32_t V = 32;
     const uint32_t tile = blockDim.x * V;
-    for (uint64_t base = 0; base < n; base += tile) {
+    uint64_t base = 0;
+    // whole tiles: every load unconditional
+    for (; base + tile <= n; base += tile) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(x + base) + threadIdx.x;
+        T v[V];
+#pragma unroll
+        for (uint32_t q = 0; q < V / 4; ++q) {
+            const uint4 w = src[q * blockDim.x];
+            v[4 * q] = (T)w.x; v[4 * q + 1] = (T)w.y; v[4 * q + 2] = (T)w.z; v[4 * q + 3] = (T)w.w;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < V; ++q) f(v[q]);
+    }
+    if (base < n) {
         const T *xb = x + base;
         T v[V];
         // element 4 (q blockDim + t) + r of the tile: row q, thread t
-        const uint32_t left = n - base < tile ? (uint32_t)(n - base) : tile;
+        const uint32_t left = (uint32_t)(n - base);
         const uint32_t m4 = left & ~3u;
         bool ok[V / 4];
 #pragma unroll
