@@ -8,7 +8,9 @@ each count-scan launch clears the other buffer over the extent the step before
 used, in strides of the launch's blocks. The cases: a population of several
 rows per block; a Poisson population fluctuating around one block (4096), so
 that the clearing runs past one stride; strongly skewed weights (long runs of
-copies in the slot map); a population of three rows per block. Bar as for
+copies in the slot map); a population of three rows per block; populations at
+the edges of one 32768-value read (the register-held weights and the bounded
+last tile). Bar as for
 every parity test:
 population sizes, histograms, copy numbers, ancestors, spins and digests
 bit-exact, ln Q and -beta F within 1e-12.
@@ -36,6 +38,14 @@ CASES = [
     dict(L=8, q=3, R=20000, beta=np.array([0.0, 0.5, 1.5, 3.0]), theta=1, seed=64, resample=0),
     # 600000 replicas: 49 blocks of three 4096-rows each
     dict(L=4, q=3, R=600000, beta=linear_betas(1.2, 2), theta=1, seed=65, resample=1),
+    # the edges of a one-round read (32 values per thread of 1024): 32768 replicas
+    # fill it exactly, with the weights taken from registers; 32769 is one whole
+    # read plus one value, the most the general path leaves to its bounded tail;
+    # 32766 and 32767 leave two and three values after the last 16-byte load
+    dict(L=4, q=3, R=32768, beta=linear_betas(1.2, 3), theta=1, seed=66, resample=1),
+    dict(L=4, q=3, R=32769, beta=linear_betas(1.2, 3), theta=1, seed=67, resample=1),
+    dict(L=4, q=4, R=32766, beta=linear_betas(1.2, 3), theta=1, seed=68, resample=1),
+    dict(L=4, q=4, R=32767, beta=linear_betas(1.2, 3), theta=1, seed=69, resample=1),
 ]
 
 
