@@ -733,10 +733,11 @@ __device__ __forceinline__ T lane_value(T v, int lane) {
     }
 }
 
-// op over the 64 lanes of a wave (all active; op associative and
-// commutative), wave-uniform: the DPP steps of wave_total, then the four row
-// results read from lanes 0, 16, 32 and 48.  No lane addresses, unlike
-// ds_bpermute shuffles.
+// op over the 64 lanes of a wave (all active; op commutative and
+// associative, or, for a floating-point sum, rounded in this fixed order),
+// wave-uniform: the DPP steps of wave_total, then the four row results read
+// from lanes 0, 16, 32 and 48.  No lane addresses, unlike ds_bpermute
+// shuffles.
 template <typename T, typename Op>
 __device__ __forceinline__ T wave_allreduce(T v, Op op) {
     v = op(v, dpp_move<0xB1>(v));
