@@ -1404,19 +1404,21 @@ __device__ __forceinline__ void sample_one(const SampleArgs &a, uint64_t kk) {
     const bool live = kk < a.n_new;
     uint32_t anc = 0;
     if (live) {
-        const uint64_t S = a.C[a.R_prev - 1];
         const uint4 w = philox((uint32_t)kk, 0u, a.step, DOM_RESAMPLE << 28, a.key0, a.key1);
         const uint64_t x = ((uint64_t)w.y << 32) | (uint64_t)w.x;
-        const uint64_t u = __umul64hi(x, S);
         // The cumulative weights are close to linear in j unless the weights
         // are strongly skewed: the window of SAMPLE_WINDOW replicas either
-        // side of x R / 2^64 holds the answer when C_{lo-1} <= u < C_hi (both
-        // ends read in one round), and the search runs there; otherwise over
-        // all replicas.
+        // side of x R / 2^64 holds the answer when C_{lo-1} <= u < C_hi, and
+        // the search runs there; otherwise over all replicas.  Both ends and
+        // S = C_{R-1} are read in one round (unconditionally, C_0 standing in
+        // for C_{-1} = 0).
         const uint64_t n = a.R_prev, j0 = __umul64hi(x, n);
         const uint64_t wlo = j0 > SAMPLE_WINDOW ? j0 - SAMPLE_WINDOW : 0;
         const uint64_t whi = j0 + SAMPLE_WINDOW < n ? j0 + SAMPLE_WINDOW : n - 1;
-        const uint64_t c_lo = wlo ? a.C[wlo - 1] : 0ull, c_hi = a.C[whi];
+        const uint64_t c_lo_read = a.C[wlo ? wlo - 1 : 0], c_hi = a.C[whi];
+        const uint64_t S = a.C[n - 1];
+        const uint64_t u = __umul64hi(x, S);
+        const uint64_t c_lo = wlo ? c_lo_read : 0ull;
         const bool in_window = c_lo <= u && c_hi > u;
         uint64_t lo = in_window ? wlo : 0, hi = in_window ? whi : n - 1;
         while (lo < hi) {
