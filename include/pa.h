@@ -35,6 +35,11 @@
  *     and the width is the distance between its outermost crossings of half
  *     the largest count, converted to e = E/N or m = M/N units.
  *
+ * Floating point: the device evaluates in FP64 only the ln Q_i terms and their
+ * running sum -beta_i F (eq. (2)); the population averages (eq. (4)-(5)) and
+ * the histogram widths are formed on the host from the exact integer sums and
+ * histogram counts the device produces.
+ *
  * Memory ownership: device memory belongs to the caller.  The library only
  * sub-allocates inside the workspace d_ws (device pointer, at least
  * pa_plan_info.workspace_bytes bytes, 256-byte aligned), which must stay
@@ -289,6 +294,34 @@ pa_status pa_width_maxima(const double *beta, const double *width, uint32_t K, u
                           double *w_max, double *T_max);
 pa_status pa_free_energy_crossing(const double *beta, const double *mbf_cool, const double *mbf_heat,
                                   uint32_t K, double *beta_x);
+
+/* ---- Instruction issue-rate probes (measurement of the sweep's ceiling) ----
+ *
+ * The sweep kernel is bound by the issue of 32-bit integer vector
+ * instructions, whose rates on gfx950 depend on the kind.  pa_issue_probe runs
+ * a stream of one kind (eight independent chains per lane, 32 waves per
+ * compute unit) on every compute unit of the context's device and returns the
+ * rate in lane-instructions per second (the fastest of three timed launches
+ * after a warm-up).  PA_PROBE_MIX is the sweep inner loop's mix of kinds per
+ * pair update (18 multiply-adds, 19 three-input bitops, 4 each of perm, xad
+ * and sad, 2 xor, 2 and, 2 compare-select pairs).  d_out is a device buffer of
+ * at least 4 * 256 * 8 * (compute units) bytes (one word per probe thread,
+ * overwritten); the launches are ordered on `stream` and the call waits for
+ * them. */
+enum {
+    PA_PROBE_XOR = 0,     /* v_xor_b32                               */
+    PA_PROBE_BITOP3 = 1,  /* v_bitop3_b32 (three-input bitwise op)   */
+    PA_PROBE_MAD64 = 2,   /* v_mad_u64_u32 (32x32 -> 64 multiply-add) */
+    PA_PROBE_PERM = 3,    /* v_perm_b32                              */
+    PA_PROBE_SAD = 4,     /* v_sad_u8                                */
+    PA_PROBE_XAD = 5,     /* v_xad_u32                               */
+    PA_PROBE_MULHI = 6,   /* v_mul_hi_u32                            */
+    PA_PROBE_CMPSEL = 7,  /* v_cmp_le_u32 to VCC + v_cndmask_b32     */
+    PA_PROBE_MIX = 8,     /* the sweep's mix, see above              */
+    PA_PROBE_KINDS = 9
+};
+pa_status pa_issue_probe(pa_ctx *ctx, uint32_t kind, void *d_out, uint64_t out_bytes, void *stream,
+                         double *lane_instr_per_s);
 
 const char *pa_status_str(pa_status s);
 const char *pa_last_error(void);

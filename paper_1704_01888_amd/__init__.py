@@ -32,8 +32,9 @@ EXPORTS = [
     "pa_run_read_slots", "pa_run_finish", "pa_status_str", "pa_last_error",
     "pa_plan_batch", "pa_run_batch",
     "pa_serve_start", "pa_serve_submit", "pa_serve_wait", "pa_serve_cancel", "pa_serve_stop",
-    "pa_width_maxima", "pa_free_energy_crossing",
+    "pa_width_maxima", "pa_free_energy_crossing", "pa_issue_probe",
 ]
+PROBE_KINDS = ("xor", "bitop3", "mad64", "perm", "sad", "xad", "mulhi", "cmpsel", "mix")
 PA_ERR_BUSY, PA_ERR_CANCELLED, PA_ERR_TIMEOUT = -6, -7, -8
 
 
@@ -126,6 +127,8 @@ def lib() -> ctypes.CDLL:
     L.pa_serve_stop.argtypes = [vp]
     L.pa_width_maxima.argtypes = [vp, vp, u32, vp, vp, vp]
     L.pa_free_energy_crossing.argtypes = [vp, vp, vp, u32, vp]
+    L.pa_issue_probe.argtypes = [vp, u32, vp, u64, vp, P(dbl)]
+    L.pa_issue_probe.restype = i32
     L.pa_status_str.argtypes = [i32]
     L.pa_status_str.restype = ctypes.c_char_p
     L.pa_last_error.argtypes = []
@@ -252,6 +255,18 @@ class Context:
         _check(lib().pa_autotune(self.handle, int(L), int(q), ctypes.c_void_p(ws.data_ptr()),
                                  ws.numel(), _stream_ptr(), _ptr(best), _ptr(rate)))
         return int(best[0]), float(rate[0])
+
+    def issue_probe(self, kind: str) -> float:
+        """Lane-instructions per second of a stream of one instruction kind
+        (PROBE_KINDS; pa_issue_probe) on this device."""
+        import torch
+        props = torch.cuda.get_device_properties(self.device)
+        out = _workspace(4 * 256 * 8 * props.multi_processor_count, self.device)
+        rate = ctypes.c_double(0.0)
+        _check(lib().pa_issue_probe(self.handle, PROBE_KINDS.index(kind),
+                                    ctypes.c_void_p(out.data_ptr()), out.numel(), _stream_ptr(),
+                                    ctypes.byref(rate)))
+        return float(rate.value)
 
     def set_graphs(self, on: bool):
         _check(lib().pa_ctx_set_graphs(self.handle, 1 if on else 0))

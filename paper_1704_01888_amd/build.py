@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpa.so")
-SOURCES = [os.path.join(CSRC, "pa_host.cpp"), os.path.join(CSRC, "pa_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "pa_host.cpp"), os.path.join(CSRC, "pa_kernels.hip"),
+           os.path.join(CSRC, "pa_probe.hip")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -45,7 +45,6 @@ struct PostArgs {
     double dbeta_next;        // beta_{i+1} - beta_i
     double abs_dbeta_next;    // |beta_{i+1} - beta_i|
     int64_t *E_sum;           // [K]
-    double *E_mean;           // [K]
     uint64_t *count;          // [K]   sum of the histogram (consistency check)
     double *lnQ;              // [K]
     double *mbF;              // [K]   -beta F
@@ -67,11 +66,10 @@ struct PostArgs {
     uint32_t *mhist;          // [N+1] M~ histogram of step i (output / work area)
     uint32_t q, N;
     int64_t *Mt_sum;          // [K]
-    double *M_mean;           // [K]
-    uint32_t widths;          // compute the FWHM of the histograms of step i
+    uint32_t widths;          // integer parts of the FWHM of the histograms of step i
     uint32_t bin_e, bin_m;    // levels per histogram bin (>= 1)
-    double *width_e;          // [K]
-    double *width_m;          // [K] (needs mhist)
+    uint64_t *fw_e;           // [K][8]: H, jl, jr, h(jl-1), h(jl), h(jr), h(jr+1), unused
+    uint64_t *fw_m;           // [K][8], M~ histogram (needs mhist)
 };
 
 struct SampleArgs {
@@ -162,6 +160,12 @@ hipError_t launch_post_batch(const PostArgs *runs, const uint32_t *pstart, uint3
 hipError_t launch_resample_batch(const SampleArgs *sruns, const uint32_t *start, uint32_t n,
                                  uint32_t blocks, const SlotmapArgs *mruns, const uint32_t *mstart,
                                  uint32_t mblocks, hipStream_t s);
+
+// Issue-rate probe of instruction kind `kind` (PA_PROBE_*): `blocks` workgroups
+// of probe_threads() threads, `iters` iterations; out[blocks * probe_threads()].
+hipError_t issue_probe(uint32_t kind, uint32_t blocks, uint32_t iters, uint32_t *out, hipStream_t s,
+                       double *lane_instr_per_s, double *ms);
+uint32_t probe_threads();
 
 // Lanes-per-replica candidates for L (0 if L has no fixed-shape kernel).
 uint32_t lane_candidates(uint32_t L, uint32_t *out /*[2]*/);

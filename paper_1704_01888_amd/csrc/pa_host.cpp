@@ -99,6 +99,21 @@ uint32_t weight_table(double abs_dbeta, uint32_t Kb, uint32_t N, uint64_t *W) {
     return D;
 }
 
+// Full width at half maximum (Sec. 4), in histogram levels, from the integer
+// part the device finds (H, jl, jr and the counts of bins jl-1, jl, jr, jr+1
+// in bins of B levels): the crossings of H/2 of the straight lines through
+// the counts at the bin indices jl-1, jl and jr, jr+1; zero for an empty
+// histogram.
+double fwhm_levels(const uint64_t *f, uint32_t B) {
+    const uint64_t H = f[0];
+    if (H == 0) return 0.0;
+    const double half = 0.5 * (double)H;
+    const double l0 = (double)f[3], l1 = (double)f[4], r0 = (double)f[5], r1 = (double)f[6];
+    const double xl = (double)((int64_t)f[1] - 1) + (half - l0) / (l1 - l0);
+    const double xr = (double)f[2] + (r0 - half) / (r0 - r1);
+    return (xr - xl) * (double)B;
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Elements per copy-count buffer: R_cap rounded up to 64 (256 bytes).
 inline size_t counts_stride(uint64_t R_cap) { return (size_t)((R_cap + 63) & ~uint64_t(63)); }
@@ -121,9 +136,9 @@ struct Plan {
     bool hist_all = false, mag = false, widths = false, digest = false;
     uint32_t bin_e = 1, bin_m = 1;
     // workspace layout
-    size_t off_pop[2], off_E, off_C, off_r, off_anc, off_counts, off_hist, off_Esum, off_Emean,
+    size_t off_pop[2], off_E, off_C, off_r, off_anc, off_counts, off_hist, off_Esum,
         off_count, off_lnQ, off_mbF, off_Eref, off_W, off_mhist, off_Mt, off_Mtsum,
-        off_Mmean, off_we, off_wm, off_bonds, off_cnt, off_pop_x, off_H, off_Hacc, off_digest, total;
+        off_fwe, off_fwm, off_bonds, off_cnt, off_pop_x, off_H, off_Hacc, off_digest, total;
     bool tiled = false;   // replicas beyond one workgroup's LDS: tiled half-sweeps in HBM
 };
 
@@ -246,7 +261,6 @@ pa_status build_plan(const pa_run_desc *d, Plan &p) {
     p.off_counts = o; o += align256(4 * p.R_cap);
     p.off_hist = o; o += align256((size_t)4 * p.nbins * (p.hist_all ? K : 1));
     p.off_Esum = o; o += align256(8 * (size_t)K);
-    p.off_Emean = o; o += align256(8 * (size_t)K);
     p.off_count = o; o += align256(8 * (size_t)K);
     p.off_lnQ = o; o += align256(8 * (size_t)K);
     p.off_mbF = o; o += align256(8 * (size_t)K);
@@ -255,9 +269,8 @@ pa_status build_plan(const pa_run_desc *d, Plan &p) {
     p.off_mhist = o; o += p.mag ? align256((size_t)4 * (p.N + 1) * (p.hist_all ? K : 1)) : 0;
     p.off_Mt = o; o += p.mag ? align256(4 * p.R_cap) : 0;
     p.off_Mtsum = o; o += p.mag ? align256(8 * (size_t)K) : 0;
-    p.off_Mmean = o; o += p.mag ? align256(8 * (size_t)K) : 0;
-    p.off_we = o; o += p.widths ? align256(8 * (size_t)K) : 0;
-    p.off_wm = o; o += (p.widths && p.mag) ? align256(8 * (size_t)K) : 0;
+    p.off_fwe = o; o += p.widths ? align256(64 * (size_t)K) : 0;
+    p.off_fwm = o; o += (p.widths && p.mag) ? align256(64 * (size_t)K) : 0;
     p.tiled = pa::tiled_path(d->L);
     p.off_bonds = o; o += p.tiled ? align256(4 * p.R_cap) : 0;
     p.off_cnt = o; o += (p.tiled && p.mag) ? align256((size_t)4 * p.R_cap * d->q) : 0;
@@ -282,7 +295,11 @@ struct pa_ctx {
     int device;
     int profiling;
     uint32_t lanes[pa::LANE_CHOICE_COUNT];   // chosen lanes per replica per lattice with choices (0 = default)
-    Server *server;
+    // The serving loop, shared with the pa_serve_* calls in flight: a call
+    // takes a reference under serve_mu, so that pa_serve_stop can drop the
+    // context's reference while waits still use the server.
+    std::shared_ptr<Server> server;
+    std::mutex serve_mu;
     int graphs;          // batched runs replay a captured HIP graph
     hipStream_t graph_stream;
     hipEvent_t ev_in, ev_out;
@@ -383,7 +400,6 @@ pa::PostArgs post_args(pa_run_state *r, uint32_t i) {
     const uint32_t tab = s.has_next ? p.table_of_step[i + 1] : 0;
     s.abs_dbeta_next = s.has_next ? p.abs_dbeta[tab] : 0.0;
     s.E_sum = r->at<int64_t>(p.off_Esum);
-    s.E_mean = r->at<double>(p.off_Emean);
     s.count = r->at<uint64_t>(p.off_count);
     s.lnQ = r->at<double>(p.off_lnQ);
     s.mbF = r->at<double>(p.off_mbF);
@@ -402,12 +418,11 @@ pa::PostArgs post_args(pa_run_state *r, uint32_t i) {
     s.q = p.desc.q;
     s.N = p.N;
     s.Mt_sum = p.mag ? r->at<int64_t>(p.off_Mtsum) : nullptr;
-    s.M_mean = p.mag ? r->at<double>(p.off_Mmean) : nullptr;
     s.widths = p.widths ? 1u : 0u;
     s.bin_e = p.bin_e;
     s.bin_m = p.bin_m;
-    s.width_e = p.widths ? r->at<double>(p.off_we) : nullptr;
-    s.width_m = (p.widths && p.mag) ? r->at<double>(p.off_wm) : nullptr;
+    s.fw_e = p.widths ? r->at<uint64_t>(p.off_fwe) : nullptr;
+    s.fw_m = (p.widths && p.mag) ? r->at<uint64_t>(p.off_fwm) : nullptr;
     return s;
 }
 
@@ -653,7 +668,6 @@ pa_status pa_ctx_create(int device, pa_ctx **out) {
     c->device = device;
     c->profiling = 0;
     for (auto &x : c->lanes) x = 0;
-    c->server = nullptr;
     c->graphs = 0;
     c->graph_stream = nullptr;
     c->ev_in = c->ev_out = nullptr;
@@ -663,7 +677,12 @@ pa_status pa_ctx_create(int device, pa_ctx **out) {
 
 void pa_ctx_destroy(pa_ctx *ctx) {
     if (!ctx) return;
-    if (ctx->server) pa_serve_stop(ctx);
+    bool serving;
+    {
+        std::lock_guard<std::mutex> lk(ctx->serve_mu);
+        serving = ctx->server != nullptr;
+    }
+    if (serving) pa_serve_stop(ctx);
     for (auto &g : ctx->graph_cache) (void)hipGraphExecDestroy(g.exec);
     if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
@@ -760,6 +779,24 @@ pa_status pa_autotune(pa_ctx *ctx, uint32_t L, uint32_t q, void *d_ws, uint64_t 
     if (best_lanes) *best_lanes = best_g;
     if (best_attempts_per_ns) *best_attempts_per_ns = best;
     return PA_OK;
+}
+
+pa_status pa_issue_probe(pa_ctx *ctx, uint32_t kind, void *d_out, uint64_t out_bytes, void *stream,
+                         double *lane_instr_per_s) {
+    if (!ctx || !d_out || !lane_instr_per_s || kind >= PA_PROBE_KINDS)
+        return fail(PA_ERR_INVALID, "bad probe arguments");
+    int cus = 0;
+    if (hipSetDevice(ctx->device) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
+        return fail(PA_ERR_DEVICE, "cannot query the compute units");
+    const uint32_t blocks = 8u * (uint32_t)cus;   // 32 waves per compute unit
+    if (out_bytes < (uint64_t)blocks * pa::probe_threads() * 4u)
+        return fail(PA_ERR_NOMEM, "probe output buffer too small");
+    const uint32_t iters = kind == PA_PROBE_MIX ? 8192u : 32768u;
+    double ms = 0;
+    return hip_check(nullptr, pa::issue_probe(kind, blocks, iters, static_cast<uint32_t *>(d_out),
+                                              static_cast<hipStream_t>(stream), lane_instr_per_s, &ms),
+                     "issue probe");
 }
 
 pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes,
@@ -970,21 +1007,44 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
             out->R_i[r->first_step] = r->R_first;
         }
         struct { void *dst; size_t off, bytes; } cp[] = {
-            {out->E_sum, p.off_Esum, 8 * (size_t)K},
-            {out->E_mean, p.off_Emean, 8 * (size_t)K},
             {out->lnQ, p.off_lnQ, 8 * (size_t)K},
             {out->minus_beta_F, p.off_mbF, 8 * (size_t)K},
             {p.hist_all ? out->hist : nullptr, p.off_hist, 4 * (size_t)K * p.nbins},
-            {p.mag ? out->Mt_sum : nullptr, p.off_Mtsum, 8 * (size_t)K},
-            {p.mag ? out->M_mean : nullptr, p.off_Mmean, 8 * (size_t)K},
             {(p.mag && p.hist_all) ? out->mhist : nullptr, p.off_mhist, 4 * (size_t)K * (p.N + 1)},
-            {p.widths ? out->width_e : nullptr, p.off_we, 8 * (size_t)K},
-            {(p.widths && p.mag) ? out->width_m : nullptr, p.off_wm, 8 * (size_t)K},
             {p.digest ? out->digest : nullptr, p.off_digest, 8 * (size_t)K},
         };
         for (auto &c : cp) {
             if (st || !c.dst) continue;
             st = hip_check(r, hipMemcpy(c.dst, r->ws + c.off, c.bytes, hipMemcpyDeviceToHost), "read");
+        }
+        // Population averages (eq. (4)-(5)) and widths (Sec. 4) on the host,
+        // from the exact integer sums and the integer parts of the widths.
+        std::vector<int64_t> esum(K), mtsum(p.mag ? K : 0);
+        std::vector<uint64_t> fwe(p.widths ? 8 * (size_t)K : 0), fwm(p.widths && p.mag ? 8 * (size_t)K : 0);
+        if (!st) st = hip_check(r, hipMemcpy(esum.data(), r->ws + p.off_Esum, 8 * (size_t)K, hipMemcpyDeviceToHost), "read");
+        if (!st && p.mag)
+            st = hip_check(r, hipMemcpy(mtsum.data(), r->ws + p.off_Mtsum, 8 * (size_t)K, hipMemcpyDeviceToHost), "read");
+        if (!st && p.widths)
+            st = hip_check(r, hipMemcpy(fwe.data(), r->ws + p.off_fwe, 8 * fwe.size(), hipMemcpyDeviceToHost), "read");
+        if (!st && p.widths && p.mag)
+            st = hip_check(r, hipMemcpy(fwm.data(), r->ws + p.off_fwm, 8 * fwm.size(), hipMemcpyDeviceToHost), "read");
+        if (!st) {
+            const double N = (double)p.N, q = (double)p.desc.q;
+            for (uint32_t i = 0; i < K; ++i) {
+                const uint64_t Ri = i == r->first_step ? r->R_first : p.R_sched[i];
+                const bool measured = i >= r->first_step && i <= r->step;
+                const double R = (double)Ri;
+                if (out->E_sum) out->E_sum[i] = measured ? esum[i] : 0;
+                if (out->E_mean) out->E_mean[i] = measured ? (double)esum[i] / R : 0.0;
+                if (p.mag && out->Mt_sum) out->Mt_sum[i] = measured ? mtsum[i] : 0;
+                if (p.mag && out->M_mean)
+                    out->M_mean[i] = measured ? (q * (double)mtsum[i] - N * R) / ((q - 1.0) * R) : 0.0;
+                if (p.widths && out->width_e)
+                    out->width_e[i] = measured ? fwhm_levels(&fwe[8 * (size_t)i], p.bin_e) / N : 0.0;
+                if (p.widths && p.mag && out->width_m)
+                    out->width_m[i] = measured ? (fwhm_levels(&fwm[8 * (size_t)i], p.bin_m) * q) / ((q - 1.0) * N)
+                                               : 0.0;
+            }
         }
         if (!st && out->lnQ) out->lnQ[0] = 0.0;
         if (!st && (out->kernel_ms || out->kernel_launches))
@@ -1510,29 +1570,42 @@ struct Server {
 
 extern "C" {
 
+// The context's server, or null; the reference keeps it alive for the call.
+static std::shared_ptr<Server> server_of(pa_ctx *ctx) {
+    std::lock_guard<std::mutex> lk(ctx->serve_mu);
+    return ctx->server;
+}
+
 pa_status pa_serve_start(pa_ctx *ctx, void *d_arena, uint64_t arena_bytes, uint32_t max_slots, void *stream) {
     if (!ctx || !d_arena || max_slots == 0 || ((uintptr_t)d_arena & 255u))
         return fail(PA_ERR_INVALID, "bad serving arguments");
+    std::lock_guard<std::mutex> lk(ctx->serve_mu);
     if (ctx->server) return fail(PA_ERR_BUSY, "a server is already running on this context");
-    Server *sv = new (std::nothrow) Server;
-    if (!sv) return fail(PA_ERR_NOMEM, "out of host memory");
+    std::shared_ptr<Server> sv;
+    try {
+        sv = std::make_shared<Server>();
+    } catch (const std::bad_alloc &) {
+        return fail(PA_ERR_NOMEM, "out of host memory");
+    }
     sv->ctx = ctx;
     sv->arena = static_cast<uint8_t *>(d_arena);
     sv->max_slots = max_slots;
     sv->desc_bytes = align256(step_desc_bytes(max_slots) * kStepsPerIteration);
-    if (arena_bytes <= sv->desc_bytes) { delete sv; return fail(PA_ERR_NOMEM, "arena too small"); }
+    if (arena_bytes <= sv->desc_bytes) return fail(PA_ERR_NOMEM, "arena too small");
     sv->run_bytes = (arena_bytes - sv->desc_bytes) & ~size_t(255);
     sv->alloc.reset(sv->run_bytes);
     sv->stream = static_cast<hipStream_t>(stream);
     sv->t0 = now_us();
-    ctx->server = sv;
-    sv->thread = std::thread([sv] { sv->loop(); });
+    Server *raw = sv.get();
+    sv->thread = std::thread([raw] { raw->loop(); });
+    ctx->server = std::move(sv);
     return PA_OK;
 }
 
 pa_status pa_serve_submit(pa_ctx *ctx, const pa_run_desc *desc, pa_result *out, uint64_t *ticket) {
-    if (!ctx || !ctx->server || !desc || !ticket) return fail(PA_ERR_INVALID, "no server or null argument");
-    Server *sv = ctx->server;
+    if (!ctx || !desc || !ticket) return fail(PA_ERR_INVALID, "null argument");
+    const std::shared_ptr<Server> sv = server_of(ctx);
+    if (!sv) return fail(PA_ERR_INVALID, "no server");
     auto q = std::make_shared<Request>();
     Plan p;
     pa_status st = build_plan(desc, p);
@@ -1559,30 +1632,36 @@ pa_status pa_serve_submit(pa_ctx *ctx, const pa_run_desc *desc, pa_result *out, 
 }
 
 pa_status pa_serve_wait(pa_ctx *ctx, uint64_t ticket, int64_t timeout_us, pa_timing *timing) {
-    if (!ctx || !ctx->server) return fail(PA_ERR_INVALID, "no server");
-    Server *sv = ctx->server;
+    if (!ctx) return fail(PA_ERR_INVALID, "null context");
+    const std::shared_ptr<Server> sv = server_of(ctx);
+    if (!sv) return fail(PA_ERR_INVALID, "no server");
     std::unique_lock<std::mutex> lk(sv->mu);
     auto it = sv->tickets.find(ticket);
     if (it == sv->tickets.end()) return fail(PA_ERR_INVALID, "unknown ticket");
-    auto q = it->second;
+    const std::shared_ptr<Request> q = it->second;
     auto ready = [&] { return q->state == ReqState::Done; };
     if (timeout_us < 0) sv->cv_done.wait(lk, ready);
     else if (!sv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
         return fail(PA_ERR_TIMEOUT, "request not finished");
+    // Another wait on the same ticket may have consumed it meanwhile.
+    auto again = sv->tickets.find(ticket);
+    if (again == sv->tickets.end() || again->second != q)
+        return fail(PA_ERR_INVALID, "ticket consumed by another wait");
+    sv->tickets.erase(again);
     if (timing) {
         timing->arrival_us = q->arrival_us;
         timing->admit_us = q->admit_us;
         timing->done_us = q->done_us;
         timing->attempts = q->attempts;
     }
-    sv->tickets.erase(it);
     if (q->status) return fail(q->status, q->message);
     return PA_OK;
 }
 
 pa_status pa_serve_cancel(pa_ctx *ctx, uint64_t ticket) {
-    if (!ctx || !ctx->server) return fail(PA_ERR_INVALID, "no server");
-    Server *sv = ctx->server;
+    if (!ctx) return fail(PA_ERR_INVALID, "null context");
+    const std::shared_ptr<Server> sv = server_of(ctx);
+    if (!sv) return fail(PA_ERR_INVALID, "no server");
     std::lock_guard<std::mutex> lk(sv->mu);
     auto it = sv->tickets.find(ticket);
     if (it == sv->tickets.end()) return fail(PA_ERR_INVALID, "unknown ticket");
@@ -1592,16 +1671,22 @@ pa_status pa_serve_cancel(pa_ctx *ctx, uint64_t ticket) {
 }
 
 pa_status pa_serve_stop(pa_ctx *ctx) {
-    if (!ctx || !ctx->server) return fail(PA_ERR_INVALID, "no server");
-    Server *sv = ctx->server;
+    if (!ctx) return fail(PA_ERR_INVALID, "null context");
+    std::shared_ptr<Server> sv;
+    {
+        std::lock_guard<std::mutex> lk(ctx->serve_mu);
+        sv = std::move(ctx->server);
+        ctx->server.reset();
+    }
+    if (!sv) return fail(PA_ERR_INVALID, "no server");
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->stopping = true;
         sv->cv_work.notify_one();
     }
     sv->thread.join();
-    ctx->server = nullptr;
-    delete sv;
+    // Waits still in flight hold their own references; the server is freed
+    // when the last of them returns.
     return PA_OK;
 }
 

@@ -832,29 +832,36 @@ __device__ __forceinline__ uint64_t bin_count(const HistView &v, uint32_t B, int
     return c;
 }
 
-// Full width at half maximum (Sec. 4) of the histogram in bins of B levels,
-// measured in levels: the histogram is the piecewise-linear curve through the
-// bin counts at the bin indices, zero beyond both ends, and the width is B
-// times the distance between its outermost crossings of H/2, H the largest
-// bin count.  Whole workgroup; the value is valid in thread 0.
-__device__ double hist_fwhm_levels(const HistView &v, uint32_t B, uint64_t *scratch) {
+// Integer part of the full width at half maximum (Sec. 4) of the histogram in
+// bins of B levels: H, the largest bin count; jl and jr, the outermost bins
+// whose count reaches H/2 (2 count >= H); and the counts of bins jl-1, jl, jr
+// and jr+1 (zero outside the histogram).  The width is the distance between
+// the crossings of H/2 of the straight lines through those counts at the bin
+// indices; that interpolation runs on the host.  Whole workgroup; thread 0
+// stores out[0..7) = H, jl, jr, h(jl-1), h(jl), h(jr), h(jr+1) (all zero for
+// an empty histogram).
+__device__ void hist_fwhm_ints(const HistView &v, uint32_t B, uint64_t *scratch, uint64_t *out) {
     const uint32_t j_lo = v.lo / B, j_hi = (v.lo + v.n - 1) / B;   // bins that meet the window
     uint64_t H = 0;
     for (uint32_t j = j_lo + threadIdx.x; j <= j_hi; j += blockDim.x) H = max(H, bin_count(v, B, j));
     H = block_reduce(H, [](uint64_t x, uint64_t y) { return x > y ? x : y; }, scratch);
-    if (H == 0) return 0.0;
     uint64_t jl = ~0ull, jr = 0;
     for (uint32_t j = j_lo + threadIdx.x; j <= j_hi; j += blockDim.x)
-        if (2 * bin_count(v, B, j) >= H) { jl = min(jl, (uint64_t)j); jr = max(jr, (uint64_t)j); }
+        if (H && 2 * bin_count(v, B, j) >= H) { jl = min(jl, (uint64_t)j); jr = max(jr, (uint64_t)j); }
     jl = block_reduce(jl, [](uint64_t x, uint64_t y) { return x < y ? x : y; }, scratch);
     jr = block_reduce(jr, [](uint64_t x, uint64_t y) { return x > y ? x : y; }, scratch);
-    if (threadIdx.x != 0) return 0.0;
-    const double half = 0.5 * (double)H;
-    const double l0 = (double)bin_count(v, B, (int64_t)jl - 1), l1 = (double)bin_count(v, B, jl);
-    const double r0 = (double)bin_count(v, B, jr), r1 = (double)bin_count(v, B, (int64_t)jr + 1);
-    const double xl = (double)((int64_t)jl - 1) + (half - l0) / (l1 - l0);
-    const double xr = (double)jr + (r0 - half) / (r0 - r1);
-    return (xr - xl) * (double)B;
+    if (threadIdx.x != 0) return;
+    if (H == 0) {
+        for (int k = 0; k < 7; ++k) out[k] = 0;
+        return;
+    }
+    out[0] = H;
+    out[1] = jl;
+    out[2] = jr;
+    out[3] = bin_count(v, B, (int64_t)jl - 1);
+    out[4] = bin_count(v, B, (int64_t)jl);
+    out[5] = bin_count(v, B, (int64_t)jr);
+    out[6] = bin_count(v, B, (int64_t)jr + 1);
 }
 
 // Calls f(x[j]) for j = 0 .. n-1 (4-byte elements, 16-byte aligned array), in
@@ -1054,9 +1061,11 @@ __device__ __forceinline__ void weight_block(const int32_t *E, uint32_t first, u
 }
 
 // ---------------------------------------------------------------------------
-// k_post(i), workgroup 0: population sums of eq. (4) and ln Q_{i+1} of Sec. 2
-// step 2 / eq. (2) from the energy histogram of step i, the magnetisation,
-// widths and digest.  Workgroups 1, 2, ...: if resampling follows, the integer
+// k_post(i), workgroup 0: the exact integer sums behind the population
+// averages of eq. (4) and ln Q_{i+1} of Sec. 2 step 2 / eq. (2) from the energy
+// histogram of step i, the magnetisation sum, the integer part of the widths
+// and the digest (the averages and the widths themselves are formed on the
+// host; FP64 on the device is the ln Q / -beta F chain only).  Workgroups 1, 2, ...: if resampling follows, the integer
 // weights W(|E_j - E_ref|) of step i+1 and their inclusive scan C, one block
 // of replicas each.
 // ---------------------------------------------------------------------------
@@ -1073,7 +1082,6 @@ __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist
     const int32_t ref = a.dbeta_next >= 0.0 ? he.mn : he.mx;   // E_ref of step i+1
     if (tid == 0) {
         a.E_sum[a.step] = he.sum;
-        a.E_mean[a.step] = (double)he.sum / (double)a.R_i;
         if (a.has_next) a.E_ref[a.step + 1] = ref;
     }
     // ln Q_{i+1} (Sec. 2 step 2, eq. (2)) from the histogram, and its count
@@ -1103,10 +1111,7 @@ __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist
     }
     __syncthreads();
     if (a.store_hist) store_hist(he.v, a.hist);
-    if (a.widths) {
-        const double we = hist_fwhm_levels(he.v, a.bin_e, scratch);
-        if (tid == 0) a.width_e[a.step] = we / (double)a.N;
-    }
+    if (a.widths) hist_fwhm_ints(he.v, a.bin_e, scratch, a.fw_e + 8 * (size_t)a.step);
     __syncthreads();
 
     if (a.H) {
@@ -1120,16 +1125,9 @@ __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist
     if (a.Mt) {
         // eq. (4)-(5): sum of M~ over the population, M-bar, the M~ histogram
         const HistBuild hm = build_hist(a.Mt, a.R_i, 0, a.N + 1, lds_hist, POST_LDS_BINS, a.mhist);
-        if (tid == 0) {
-            a.Mt_sum[a.step] = hm.sum;
-            a.M_mean[a.step] = ((double)a.q * (double)hm.sum - (double)a.N * (double)a.R_i) /
-                               ((double)(a.q - 1) * (double)a.R_i);
-        }
+        if (tid == 0) a.Mt_sum[a.step] = hm.sum;
         if (a.store_hist) store_hist(hm.v, a.mhist);
-        if (a.widths) {
-            const double wm = hist_fwhm_levels(hm.v, a.bin_m, scratch);
-            if (tid == 0) a.width_m[a.step] = (wm * (double)a.q) / ((double)(a.q - 1) * (double)a.N);
-        }
+        if (a.widths) hist_fwhm_ints(hm.v, a.bin_m, scratch, a.fw_m + 8 * (size_t)a.step);
         __syncthreads();
     }
 

@@ -221,30 +221,3 @@ def test_full_size_32x32_q10(ctx):
     the first steps at full size, sampled."""
     kw = dict(L=32, q=10, R=20000, beta=lin_beta(1.6, 400), theta=10, seed=2, resample=0)
     _sampled_full_size_step(ctx, kw, n_steps=3, n_samples=64, seed=1)
-
-
-def test_full_size_32x32_q10_whole_population_digests(ctx):
-    """The benchmark workload (32x32, q=10, R=2*10^4, Poisson, seed 2) at full
-    size: the digest of the whole population (every spin of every replica in
-    every slot) after each of the first 12 steps equals the oracle's, stepped
-    from the same initial population."""
-    kw = dict(L=32, q=10, R=20000, beta=lin_beta(1.6, 400), theta=10, seed=2, resample=0)
-    d = pa.Desc(outputs=pa.OUT_DIGEST, **kw)
-    od = oracle.Desc(**kw)
-    R_sched, _, Kb = oracle.plan(od)
-    run = pa.Run(ctx, d)
-    run.advance(12)
-    got = run.finish()["digest"]
-    spins = np.stack([oracle.init_replica(od, k) for k in range(kw["R"])])
-    E = np.array([oracle.energy(32, s) for s in spins], dtype=np.int32)
-    assert got[0] == oracle.digest(od, 0, spins)
-    for i in range(1, 13):
-        spins, E, _ = oracle.step(od, i, Kb, spins, E, int(R_sched[i]))
-        assert got[i] == oracle.digest(od, i, spins), f"step {i}"
-
-
-def test_full_size_128x128_q10(ctx):
-    """128x128, q=10, R=2*10^5, 500 steps to beta = 1.6, theta = 20, Poisson,
-    seed 4: one step at full size (6.6e10 spin-flip attempts), sampled."""
-    kw = dict(L=128, q=10, R=200000, beta=lin_beta(1.6, 500), theta=20, seed=4, resample=0)
-    _sampled_full_size_step(ctx, kw, n_steps=1, n_samples=12, seed=2)

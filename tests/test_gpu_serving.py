@@ -112,3 +112,43 @@ def test_cancel_timeout_and_stop(ctx):
     got, _ = sv2.wait(sv2.submit(queued))
     _same(got, pa.pa_run(ctx, queued))
     sv2.stop()
+
+
+def test_stop_while_waits_are_blocked(ctx):
+    """pa_serve_stop while other threads are blocked in pa_serve_wait on queued
+    tickets (one slot, a longer request running): stop returns, the running
+    request finishes, every queued wait returns PA_ERR_CANCELLED afterwards;
+    two waits on one ticket: one consumes it, the other gets PA_ERR_INVALID
+    (or the same cancellation when it consumed it first)."""
+    import ctypes
+    import threading
+    long_run = pa.Desc(64, 10, 50000, linear_betas(1.4, 200), 10, 31, resample=0)   # ~0.4 s
+    short = [pa.Desc(8, 5, 300, linear_betas(1.0, 10), 2, 40 + k, resample=1) for k in range(4)]
+    sv = pa.Server(ctx, arena_bytes=1 << 30, max_slots=1)
+    t_long = sv.submit(long_run)
+    t_q = [sv.submit(d) for d in short]
+    statuses = {}
+
+    def waiter(name, ticket):
+        tm = pa.Timing()
+        statuses[name] = pa.lib().pa_serve_wait(ctx.handle, ctypes.c_uint64(ticket), ctypes.c_int64(-1),
+                                                 ctypes.byref(tm))
+
+    threads = [threading.Thread(target=waiter, args=(f"q{k}", t)) for k, t in enumerate(t_q)]
+    threads.append(threading.Thread(target=waiter, args=("dup", t_q[0])))
+    for th in threads:
+        th.start()
+    time.sleep(0.05)
+    sv.stop()
+    for th in threads:
+        th.join(timeout=60)
+        assert not th.is_alive()
+    assert statuses["q1"] == statuses["q2"] == statuses["q3"] == pa.PA_ERR_CANCELLED
+    assert sorted([statuses["q0"], statuses["dup"]]) in (
+        sorted([pa.PA_ERR_CANCELLED, pa.PA_ERR_INVALID]), [pa.PA_ERR_CANCELLED] * 2)
+    # a new server can start on the same context after stop
+    sv2 = pa.Server(ctx, arena_bytes=1 << 28, max_slots=2)
+    got, _ = sv2.wait(sv2.submit(short[0]))
+    sv2.stop()
+    assert (got["R_i"] == pa.pa_run(ctx, short[0])["R_i"]).all()
+    del t_long
