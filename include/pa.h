@@ -92,10 +92,11 @@ enum {
 /* A PA run (Sec. 2): lattice L x L periodic (Sec. 3), q states, target
  * population R, inverse temperatures beta[0..K-1], theta sweeps per step. */
 typedef struct {
-    uint32_t L;          /* lattice side; this device path needs L % 4 == 0, 4 <= L <= 4096
-                            (L <= 256: one replica per workgroup in LDS; larger L: tiled
-                            half-sweeps with the replicas in HBM and a third population
-                            buffer in the workspace) */
+    uint32_t L;          /* lattice side, even, 2 <= L <= 4096 on this device path, and
+                            L <= 254 when L is not a multiple of 4 (L <= 256: replicas in
+                            LDS, one wave per replica byte by byte when L = 2 mod 4; larger
+                            L: tiled half-sweeps with the replicas in HBM and a third
+                            population buffer in the workspace) */
     uint32_t q;          /* 2 <= q <= 255                                               */
     uint64_t R;          /* 1 <= R <= 2^31                                              */
     uint32_t K;          /* number of temperatures, K >= 1                              */
@@ -234,6 +235,47 @@ pa_status pa_run_read_slots(pa_run_state *run, int previous, const uint32_t *slo
                             uint8_t *spins_out);
 pa_status pa_run_finish(pa_run_state *run, pa_result *out);
 
+/* Checkpoints.  A run's population at its current step, with -beta F of that
+ * step (eq. (2), accumulated so far) and the run description, in a binary file
+ * that a new run -- on this library or on any other implementation of the same
+ * conventions -- continues bit-identically (every random number is a function
+ * of logical indices; the weights, thresholds and population schedule follow
+ * from the description).  Results of the continued run are valid from the
+ * checkpoint's step on.
+ *
+ * File format (little-endian, 128-byte header, then beta, then the spins):
+ *   offset  type    field
+ *        0  char[8] magic "PACKPT01"
+ *        8  u32     header size, 128
+ *       12  u32     L        16  u32  q        20  u32  K
+ *       24  u64     R        32  u32  theta    36  i32  resample (pa_resample)
+ *       40  u64     seed     48  i32  init     52  u32  outputs
+ *       56  u32     bin_e    60  u32  bin_m
+ *       64  u32     step i of the population (0 <= i < K)
+ *       68  u32     zero
+ *       72  u64     R_i, replicas in the population
+ *       80  f64     -beta_i F_i
+ *       88  i64     sum of the energies of the population (eq. (3)), a check
+ *       96  zero up to byte 128
+ *      128  f64[K]  beta_0 .. beta_{K-1}
+ *  128+8K  u8[R_i][L*L]  spins 0..q-1, replica-major, row-major (slot order)
+ *
+ * pa_checkpoint: write the run's current state to `path` (waits for the run's
+ *   enqueued work).  PA_ERR_INVALID if the file cannot be written.
+ * pa_checkpoint_info: the description of a checkpoint (desc->beta points to
+ *   `beta` when beta_cap >= K, else NULL; PA_ERR_NOMEM if `beta` is given but
+ *   shorter than K, with desc->K set), its step and population size -- enough
+ *   to size the workspace with pa_plan before pa_resume.
+ * pa_resume: a new run in d_ws continued from the checkpoint (like
+ *   pa_run_begin followed by pa_run_load); PA_ERR_INVALID for a malformed or
+ *   truncated file or when the energies recomputed from the spins do not add up
+ *   to the stored sum. */
+pa_status pa_checkpoint(pa_run_state *run, const char *path);
+pa_status pa_checkpoint_info(const char *path, pa_run_desc *desc, double *beta, uint32_t beta_cap,
+                             uint32_t *step, uint64_t *R_cur);
+pa_status pa_resume(pa_ctx *ctx, const char *path, void *d_ws, uint64_t ws_bytes, void *stream,
+                    pa_run_state **out);
+
 /* Batched runs: n independent PA runs (any mix of L, q, R, K, theta, seeds,
  * resampling and init modes) advanced together, one set of segmented launches
  * per global step g for every run with K > g.  Results are identical to n
@@ -272,6 +314,16 @@ pa_status pa_serve_submit(pa_ctx *ctx, const pa_run_desc *desc, pa_result *out, 
 pa_status pa_serve_wait(pa_ctx *ctx, uint64_t ticket, int64_t timeout_us, pa_timing *timing);
 pa_status pa_serve_cancel(pa_ctx *ctx, uint64_t ticket);
 pa_status pa_serve_stop(pa_ctx *ctx);
+/* pa_serve_checkpoint: write the current state of a running ticket to `path`
+ * in the format of pa_checkpoint, at the next step boundary of the serving
+ * loop, and wait for it (the run goes on).  PA_ERR_BUSY for a ticket not
+ * admitted yet or with a checkpoint in progress, PA_ERR_INVALID for an unknown
+ * or finished ticket.  pa_serve_resume: submit a request that continues the run
+ * of a checkpoint file (its results are valid from the checkpoint's step on);
+ * otherwise as pa_serve_submit. */
+pa_status pa_serve_checkpoint(pa_ctx *ctx, uint64_t ticket, const char *path);
+pa_status pa_serve_resume(pa_ctx *ctx, const char *path, pa_result *out, uint64_t *ticket);
+
 
 /* ---- Analysis of run outputs (host only, no device work) -------------------
  *

@@ -59,6 +59,14 @@ class _Result(ctypes.Structure):
     ]
 
 
+class _Checkpoint(ctypes.Structure):
+    _fields_ = [
+        ("desc", _Desc), ("beta", ctypes.POINTER(ctypes.c_double)), ("step", ctypes.c_uint32),
+        ("R_cur", ctypes.c_uint64), ("minus_beta_F", ctypes.c_double), ("E_sum", ctypes.c_int64),
+        ("spins", ctypes.POINTER(ctypes.c_uint8)),
+    ]
+
+
 _lib = None
 
 
@@ -96,6 +104,10 @@ def lib():
         L.orc_crossing.argtypes = [vp, vp, vp, u32, vp]
         L.orc_run.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(_Result)]
         L.orc_step.argtypes = [ctypes.POINTER(_Desc), u32, u32, vp, vp, u64, u64, vp, vp, vp]
+        L.orc_run_from.argtypes = [ctypes.POINTER(_Desc), u32, u64, vp, dbl, ctypes.POINTER(_Result)]
+        L.orc_read_checkpoint.argtypes = [ctypes.c_char_p, ctypes.POINTER(_Checkpoint)]
+        L.orc_free_checkpoint.argtypes = [ctypes.POINTER(_Checkpoint)]
+        L.orc_free_checkpoint.restype = None
         _lib = L
     return _lib
 
@@ -261,9 +273,7 @@ def crossing(beta, f_cool, f_heat):
     return float(x[0])
 
 
-def run(d: Desc, hist=False, final=False, magnetisation=False, widths=False, digest=False):
-    """Whole PA run; returns a dict of numpy arrays."""
-    R_sched, R_cap, Kb = plan(d)
+def _result(d: Desc, R_final: int, hist, final, magnetisation, widths, digest):
     K, N = d.K, d.N
     out = {
         "R_i": np.zeros(K, dtype=np.uint64), "E_sum": np.zeros(K, dtype=np.int64),
@@ -292,16 +302,58 @@ def run(d: Desc, hist=False, final=False, magnetisation=False, widths=False, dig
         out["hist"] = np.zeros((K, 2 * N + 1), dtype=np.uint32)
         res.hist = _ptr(out["hist"])
     if final:
-        RK = int(R_sched[-1])
-        out["final_spins"] = np.zeros((RK, N), dtype=np.uint8)
-        out["final_E"] = np.zeros(RK, dtype=np.int32)
-        out["last_anc"] = np.zeros(RK, dtype=np.uint32)
+        out["final_spins"] = np.zeros((R_final, N), dtype=np.uint8)
+        out["final_E"] = np.zeros(R_final, dtype=np.int32)
+        out["last_anc"] = np.zeros(R_final, dtype=np.uint32)
         res.final_spins = _ptr(out["final_spins"])
         res.final_E = _ptr(out["final_E"])
         res.last_anc = _ptr(out["last_anc"])
+    return out, res
+
+
+def run(d: Desc, hist=False, final=False, magnetisation=False, widths=False, digest=False):
+    """Whole PA run; returns a dict of numpy arrays."""
+    R_sched, R_cap, Kb = plan(d)
+    out, res = _result(d, int(R_sched[-1]), hist, final, magnetisation, widths, digest)
     rc = lib().orc_run(ctypes.byref(d.c()), ctypes.byref(res))
     if rc:
         raise ValueError(f"orc_run failed: {rc}")
     out["n_threads"] = res.n_threads
     out["R_sched"], out["R_cap"], out["Kb"] = R_sched, R_cap, Kb
     return out
+
+
+def run_from(d: Desc, step: int, spins: np.ndarray, minus_beta_F: float, hist=False, final=False,
+             magnetisation=False, widths=False, digest=False):
+    """The run continued from population `spins` [R][N] at `step` with -beta F
+    there (orc_run_from); arrays filled from index `step` on."""
+    R_sched, R_cap, Kb = plan(d)
+    s = np.ascontiguousarray(spins, dtype=np.uint8)
+    out, res = _result(d, int(R_sched[-1]) if step + 1 < d.K else s.shape[0], hist, final,
+                       magnetisation, widths, digest)
+    rc = lib().orc_run_from(ctypes.byref(d.c()), int(step), s.shape[0], _ptr(s), float(minus_beta_F),
+                            ctypes.byref(res))
+    if rc:
+        raise ValueError(f"orc_run_from failed: {rc}")
+    out["n_threads"] = res.n_threads
+    return out
+
+
+def read_checkpoint(path):
+    """A checkpoint file of the GPU library (orc_read_checkpoint): its run
+    description (Desc), step, population size, -beta F, energy sum and spins."""
+    ck = _Checkpoint()
+    rc = lib().orc_read_checkpoint(os.fsencode(str(path)), ctypes.byref(ck))
+    if rc:
+        raise ValueError(f"orc_read_checkpoint failed: {rc}")
+    try:
+        dd = ck.desc
+        K, N = dd.K, dd.L * dd.L
+        beta = np.ctypeslib.as_array(ck.beta, shape=(K,)).copy()
+        spins = np.ctypeslib.as_array(ck.spins, shape=(ck.R_cur * N,)).copy().reshape(ck.R_cur, N)
+        desc = Desc(dd.L, dd.q, dd.R, beta, dd.theta, dd.seed, resample=dd.resample, init=dd.init,
+                    bin_e=dd.bin_e, bin_m=dd.bin_m)
+        return {"desc": desc, "step": int(ck.step), "R_cur": int(ck.R_cur),
+                "minus_beta_F": float(ck.minus_beta_F), "E_sum": int(ck.E_sum), "spins": spins}
+    finally:
+        lib().orc_free_checkpoint(ctypes.byref(ck))

@@ -22,6 +22,7 @@
 #include "pa_oracle.h"
 
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -574,10 +575,49 @@ static void observe(const orc_desc *d, uint32_t i, const uint8_t *spins, const i
     }
 }
 
-int orc_run(const orc_desc *d, orc_result *out)
+/* Steps i0+1 .. K-1 (steps 2-5 of the algorithm) from the population pop[0]
+ * of R_prev replicas with energies E[0] at step i0, whose -beta F is
+ * out->minus_beta_F[i0] and which has been observed.  pop and E hold two
+ * buffers of R_cap replicas each; anc and hist are work arrays. */
+static int run_steps(const orc_desc *d, uint32_t i0, uint64_t R_prev, const uint64_t *R_sched,
+                     uint32_t Kb, uint8_t *pop[2], int32_t *E[2], uint32_t *anc, uint32_t *hist,
+                     orc_result *out)
+{
+    uint32_t N = d->L * d->L;
+    int cur = 0;
+    for (uint32_t i = i0 + 1; i < d->K; ++i) {
+        double dbeta = d->beta[i] - d->beta[i - 1];
+        /* eq. (2): ln Q_i from the population at beta_{i-1}. */
+        memset(hist, 0, sizeof(uint32_t) * (2 * N + 1));
+        for (uint64_t k = 0; k < R_prev; ++k) hist[E[cur][k] + (int32_t)(2 * N)]++;
+        double lnQ = orc_lnQ(N, dbeta, hist, R_prev, NULL);
+        out->lnQ[i] = lnQ;
+        out->minus_beta_F[i] = out->minus_beta_F[i - 1] + lnQ;
+
+        uint64_t R_new = R_sched[i];
+        int rc = orc_step(d, i, Kb, pop[cur], E[cur], R_prev, R_new, pop[1 - cur], E[1 - cur], anc);
+        if (rc) return rc;
+        cur = 1 - cur;
+        R_prev = R_new;
+        observe(d, i, pop[cur], E[cur], R_prev, out);
+    }
+    if (out->final_spins) memcpy(out->final_spins, pop[cur], R_prev * N);
+    if (out->final_E) memcpy(out->final_E, E[cur], sizeof(int32_t) * R_prev);
+    if (out->last_anc) {
+        if (d->K > i0 + 1) memcpy(out->last_anc, anc, sizeof(uint32_t) * R_prev);
+        else for (uint64_t k = 0; k < R_prev; ++k) out->last_anc[k] = (uint32_t)k;
+    }
+    return ORC_OK;
+}
+
+/* Whole run (steps 1-5), or its continuation from a population at step i0
+ * (spins != NULL: R0 replicas, -beta F = mbF0). */
+static int run_from(const orc_desc *d, uint32_t i0, uint64_t R0, const uint8_t *spins, double mbF0,
+                    orc_result *out)
 {
     int rc = orc_validate(d);
     if (rc) return rc;
+    if (i0 >= d->K) return ORC_ERR_INVALID;
     uint32_t N = d->L * d->L;
     uint64_t *R_sched = (uint64_t *)malloc(sizeof(uint64_t) * d->K);
     if (!R_sched) return ORC_ERR_NOMEM;
@@ -585,6 +625,7 @@ int orc_run(const orc_desc *d, orc_result *out)
     uint32_t Kb;
     rc = orc_plan(d, R_sched, &R_cap, &Kb);
     if (rc) { free(R_sched); return rc; }
+    if (spins && (R0 == 0 || R0 > R_cap)) { free(R_sched); return ORC_ERR_INVALID; }
 
     uint8_t *pop[2];
     pop[0] = (uint8_t *)malloc(R_cap * N);
@@ -604,9 +645,9 @@ int orc_run(const orc_desc *d, orc_result *out)
     out->n_threads = 1;
 #endif
 
-    /* Step 1: R_0 = R replicas in equilibrium at beta_0. */
-    {
-        uint64_t R0 = d->R;
+    if (!spins) {
+        /* Step 1: R_0 = R replicas in equilibrium at beta_0. */
+        R0 = d->R;
         int64_t nk = (int64_t)R0;
 #pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < nk; ++k) {
@@ -621,35 +662,18 @@ int orc_run(const orc_desc *d, orc_result *out)
             out->minus_beta_F[0] = log((double)d->q) + 2.0 * (double)N * d->beta[0];
         else
             out->minus_beta_F[0] = (double)N * log((double)d->q);
+    } else {
+        /* A population at step i0 (a checkpoint): energies recomputed, observed
+         * at i0; its ln Q belongs to the step before and is reported as 0. */
+        memcpy(pop[0], spins, R0 * N);
+        int64_t nk = (int64_t)R0;
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < nk; ++k) E[0][k] = orc_energy(d->L, pop[0] + (uint64_t)k * N);
+        observe(d, i0, pop[0], E[0], R0, out);
+        out->lnQ[i0] = 0.0;
+        out->minus_beta_F[i0] = mbF0;
     }
-
-    /* Steps 2-5 for i = 1 .. K-1. */
-    uint64_t R_prev = d->R;
-    int cur = 0;
-    for (uint32_t i = 1; i < d->K; ++i) {
-        double dbeta = d->beta[i] - d->beta[i - 1];
-        /* eq. (2): ln Q_i from the population at beta_{i-1}. */
-        memset(hist, 0, sizeof(uint32_t) * (2 * N + 1));
-        for (uint64_t k = 0; k < R_prev; ++k) hist[E[cur][k] + (int32_t)(2 * N)]++;
-        double lnQ = orc_lnQ(N, dbeta, hist, R_prev, NULL);
-        out->lnQ[i] = lnQ;
-        out->minus_beta_F[i] = out->minus_beta_F[i - 1] + lnQ;
-
-        uint64_t R_new = R_sched[i];
-        rc = orc_step(d, i, Kb, pop[cur], E[cur], R_prev, R_new, pop[1 - cur], E[1 - cur], anc);
-        if (rc) goto done;
-        cur = 1 - cur;
-        R_prev = R_new;
-        observe(d, i, pop[cur], E[cur], R_prev, out);
-    }
-
-    if (out->final_spins) memcpy(out->final_spins, pop[cur], R_prev * N);
-    if (out->final_E) memcpy(out->final_E, E[cur], sizeof(int32_t) * R_prev);
-    if (out->last_anc) {
-        if (d->K > 1) memcpy(out->last_anc, anc, sizeof(uint32_t) * R_prev);
-        else for (uint64_t k = 0; k < R_prev; ++k) out->last_anc[k] = (uint32_t)k;
-    }
-    rc = ORC_OK;
+    rc = run_steps(d, i0, R0, R_sched, Kb, pop, E, anc, hist, out);
 done:
     free(R_sched);
     free(pop[0]);
@@ -659,4 +683,82 @@ done:
     free(anc);
     free(hist);
     return rc;
+}
+
+int orc_run(const orc_desc *d, orc_result *out)
+{
+    return run_from(d, 0, 0, NULL, 0.0, out);
+}
+
+int orc_run_from(const orc_desc *d, uint32_t step, uint64_t R_cur, const uint8_t *spins,
+                 double minus_beta_F, orc_result *out)
+{
+    if (!spins) return ORC_ERR_INVALID;
+    return run_from(d, step, R_cur, spins, minus_beta_F, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Checkpoint files of the GPU library (format stated in its C header): a    */
+/* 128-byte little-endian header, beta[K] as IEEE doubles, then the spins.   */
+/* Read here byte by byte from that statement, independently of the writer.  */
+/* ------------------------------------------------------------------------ */
+static uint64_t le_bytes(const unsigned char *b, int n)
+{
+    uint64_t v = 0;
+    for (int i = n - 1; i >= 0; --i) v = (v << 8) | b[i];
+    return v;
+}
+
+int orc_read_checkpoint(const char *path, orc_checkpoint *ck)
+{
+    memset(ck, 0, sizeof *ck);
+    FILE *f = fopen(path, "rb");
+    if (!f) return ORC_ERR_INVALID;
+    unsigned char h[128];
+    int rc = ORC_ERR_INVALID;
+    if (fread(h, 1, 128, f) != 128 || memcmp(h, "PACKPT01", 8) != 0 || le_bytes(h + 8, 4) != 128)
+        goto fail;
+    ck->desc.L = (uint32_t)le_bytes(h + 12, 4);
+    ck->desc.q = (uint32_t)le_bytes(h + 16, 4);
+    ck->desc.K = (uint32_t)le_bytes(h + 20, 4);
+    ck->desc.R = le_bytes(h + 24, 8);
+    ck->desc.theta = (uint32_t)le_bytes(h + 32, 4);
+    ck->desc.resample = (int32_t)(uint32_t)le_bytes(h + 36, 4);
+    ck->desc.seed = le_bytes(h + 40, 8);
+    ck->desc.init = (int32_t)(uint32_t)le_bytes(h + 48, 4);
+    ck->desc.bin_e = (uint32_t)le_bytes(h + 56, 4);
+    ck->desc.bin_m = (uint32_t)le_bytes(h + 60, 4);
+    ck->step = (uint32_t)le_bytes(h + 64, 4);
+    ck->R_cur = le_bytes(h + 72, 8);
+    uint64_t bits = le_bytes(h + 80, 8);
+    memcpy(&ck->minus_beta_F, &bits, 8);
+    ck->E_sum = (int64_t)le_bytes(h + 88, 8);
+    if (ck->desc.K == 0 || ck->step >= ck->desc.K || ck->R_cur == 0) goto fail;
+    ck->beta = (double *)malloc(sizeof(double) * ck->desc.K);
+    uint64_t bytes = ck->R_cur * (uint64_t)ck->desc.L * ck->desc.L;
+    ck->spins = (uint8_t *)malloc(bytes ? bytes : 1);
+    if (!ck->beta || !ck->spins) { rc = ORC_ERR_NOMEM; goto fail; }
+    for (uint32_t i = 0; i < ck->desc.K; ++i) {
+        unsigned char b[8];
+        if (fread(b, 1, 8, f) != 8) goto fail;
+        uint64_t v = le_bytes(b, 8);
+        memcpy(&ck->beta[i], &v, 8);
+    }
+    if (fread(ck->spins, 1, bytes, f) != bytes) goto fail;
+    ck->desc.beta = ck->beta;
+    if (orc_validate(&ck->desc)) goto fail;
+    fclose(f);
+    return ORC_OK;
+fail:
+    fclose(f);
+    orc_free_checkpoint(ck);
+    return rc;
+}
+
+void orc_free_checkpoint(orc_checkpoint *ck)
+{
+    free(ck->beta);
+    free(ck->spins);
+    ck->beta = NULL;
+    ck->spins = NULL;
 }

@@ -10,9 +10,11 @@
  * definition, the plan tables from their formulas, the update rule, the
  * resampler).
  *
- * Conventions (the paper is silent on them; see the readings table in the
- * design notes): spins are 0..q-1 (the paper's 1..q shifted down by one), the
- * lattice is L x L, periodic, row-major, site n = y*L + x.
+ * Conventions where the paper is silent: spins are 0..q-1 (the paper's 1..q
+ * shifted down by one), the lattice is L x L, periodic, row-major, site
+ * n = y*L + x; the other choices (random-number counters, update order,
+ * proposal, acceptance and resampling arithmetic) are stated at the functions
+ * that make them.
  *
  * Every function returns 0 on success and a negative code on invalid input.
  */
@@ -147,6 +149,28 @@ typedef struct {
 
 /* Whole run (steps 1-5 of the algorithm). */
 int orc_run(const orc_desc *d, orc_result *out);
+
+/* Continuation of a run from a population at step `step` (R_cur replicas,
+ * spins[R_cur][N], -beta F = minus_beta_F there): observes that population at
+ * `step` (ln Q reported as 0 there) and runs steps step+1 .. K-1; the result
+ * arrays are filled from index `step` on. */
+int orc_run_from(const orc_desc *d, uint32_t step, uint64_t R_cur, const uint8_t *spins,
+                 double minus_beta_F, orc_result *out);
+
+/* A checkpoint file of the GPU library (128-byte little-endian header with the
+ * run description, step, R_i, -beta F and energy sum; beta[K]; spins), read
+ * into owned arrays; orc_free_checkpoint releases them. */
+typedef struct {
+    orc_desc desc;         /* desc.beta points to beta                 */
+    double *beta;          /* [K]                                      */
+    uint32_t step;
+    uint64_t R_cur;
+    double minus_beta_F;
+    int64_t E_sum;
+    uint8_t *spins;        /* [R_cur][L*L]                             */
+} orc_checkpoint;
+int orc_read_checkpoint(const char *path, orc_checkpoint *ck);
+void orc_free_checkpoint(orc_checkpoint *ck);
 
 /* Stepwise: advance a population from step i-1 to step i.
  * spins_old[R_prev][N], E_old[R_prev] in; spins_new[R_new][N], E_new[R_new],

@@ -33,6 +33,7 @@ EXPORTS = [
     "pa_plan_batch", "pa_run_batch",
     "pa_serve_start", "pa_serve_submit", "pa_serve_wait", "pa_serve_cancel", "pa_serve_stop",
     "pa_width_maxima", "pa_free_energy_crossing", "pa_issue_probe",
+    "pa_checkpoint", "pa_checkpoint_info", "pa_resume", "pa_serve_checkpoint", "pa_serve_resume",
 ]
 PROBE_KINDS = ("xor", "bitop3", "mad64", "perm", "sad", "xad", "mulhi", "cmpsel", "mix")
 PA_ERR_BUSY, PA_ERR_CANCELLED, PA_ERR_TIMEOUT = -6, -7, -8
@@ -127,6 +128,14 @@ def lib() -> ctypes.CDLL:
     L.pa_serve_stop.argtypes = [vp]
     L.pa_width_maxima.argtypes = [vp, vp, u32, vp, vp, vp]
     L.pa_free_energy_crossing.argtypes = [vp, vp, vp, u32, vp]
+    L.pa_checkpoint.argtypes = [vp, ctypes.c_char_p]
+    L.pa_checkpoint_info.argtypes = [ctypes.c_char_p, P(RunDesc), vp, u32, P(u32), P(u64)]
+    L.pa_resume.argtypes = [vp, ctypes.c_char_p, vp, u64, vp, P(vp)]
+    L.pa_serve_checkpoint.argtypes = [vp, u64, ctypes.c_char_p]
+    L.pa_serve_resume.argtypes = [vp, ctypes.c_char_p, P(Result), P(u64)]
+    for name in ("pa_checkpoint", "pa_checkpoint_info", "pa_resume", "pa_serve_checkpoint",
+                 "pa_serve_resume"):
+        getattr(L, name).restype = i32
     L.pa_issue_probe.argtypes = [vp, u32, vp, u64, vp, P(dbl)]
     L.pa_issue_probe.restype = i32
     L.pa_status_str.argtypes = [i32]
@@ -405,25 +414,24 @@ class Run:
 
     def checkpoint(self, path):
         """Write the current step, population and -beta F with the run
-        description to `path` (numpy .npz, no pickled objects)."""
-        spins = self.read(E=False, anc=False, counts=False)["spins"]
-        step, mbf = self.free_energy()
-        d = self.desc
-        np.savez(path, step=step, spins=spins, minus_beta_F=mbf, L=d.L, q=d.q, R=d.R, beta=d.beta,
-                 theta=d.theta, seed=d.seed, resample=d.resample, init=d.init, outputs=d.outputs,
-                 bin_e=d.bin_e, bin_m=d.bin_m)
+        description to `path` (pa_checkpoint; the binary format of pa.h)."""
+        _check(lib().pa_checkpoint(self.handle, os.fsencode(str(path))))
 
     @classmethod
     def resume(cls, ctx: "Context", path, workspace=None) -> "Run":
-        """A run continued from a checkpoint file; it finishes bit-identically
-        to the run the checkpoint was taken from (results from the checkpoint
-        step on)."""
-        with np.load(path) as z:
-            desc = Desc(int(z["L"]), int(z["q"]), int(z["R"]), z["beta"], int(z["theta"]),
-                        int(z["seed"]), resample=int(z["resample"]), init=int(z["init"]),
-                        outputs=int(z["outputs"]), bin_e=int(z["bin_e"]), bin_m=int(z["bin_m"]))
-            run = cls(ctx, desc, workspace)
-            run.load(int(z["step"]), z["spins"], float(z["minus_beta_F"]))
+        """A run continued from a checkpoint file (pa_resume); it finishes
+        bit-identically to the run the checkpoint was taken from (results from
+        the checkpoint step on)."""
+        desc, _, _ = checkpoint_info(path)
+        run = cls.__new__(cls)
+        run.desc = desc
+        run.info = pa_plan(desc)
+        run.ws = workspace if workspace is not None else _workspace(run.info.workspace_bytes,
+                                                                    ctx.device)
+        h = ctypes.c_void_p()
+        _check(lib().pa_resume(ctx.handle, os.fsencode(str(path)), ctypes.c_void_p(run.ws.data_ptr()),
+                               run.ws.numel(), _stream_ptr(), ctypes.byref(h)))
+        run.handle = h
         return run
 
     def read_slots(self, slots, previous=False):
@@ -445,6 +453,20 @@ class Run:
                 lib().pa_run_finish(self.handle, None)
             except Exception:
                 pass
+
+
+def checkpoint_info(path):
+    """(Desc, step, R_cur) of a checkpoint file (pa_checkpoint_info)."""
+    d = RunDesc()
+    step, R_cur = ctypes.c_uint32(), ctypes.c_uint64()
+    _check(lib().pa_checkpoint_info(os.fsencode(str(path)), ctypes.byref(d), None, 0,
+                                    ctypes.byref(step), ctypes.byref(R_cur)))
+    beta = np.zeros(d.K)
+    _check(lib().pa_checkpoint_info(os.fsencode(str(path)), ctypes.byref(d), _ptr(beta), d.K, None,
+                                    None))
+    desc = Desc(d.L, d.q, d.R, beta, d.theta, d.seed, resample=d.resample, init=d.init,
+                outputs=d.outputs, bin_e=d.bin_e, bin_m=d.bin_m)
+    return desc, int(step.value), int(R_cur.value)
 
 
 def _desc_array(descs):
@@ -508,6 +530,20 @@ class Server:
 
     def cancel(self, ticket: int):
         _check(lib().pa_serve_cancel(self.ctx.handle, int(ticket)))
+
+    def checkpoint(self, ticket: int, path):
+        """Write a running ticket's state to `path` (pa_serve_checkpoint)."""
+        _check(lib().pa_serve_checkpoint(self.ctx.handle, int(ticket), os.fsencode(str(path))))
+
+    def resume(self, path) -> int:
+        """Submit a request continuing a checkpoint file (pa_serve_resume)."""
+        desc, _, _ = checkpoint_info(path)
+        out, res = _alloc_result(desc, pa_plan(desc))
+        t = ctypes.c_uint64(0)
+        _check(lib().pa_serve_resume(self.ctx.handle, os.fsencode(str(path)), ctypes.byref(res),
+                                     ctypes.byref(t)))
+        self._live[int(t.value)] = (out, res, desc)
+        return int(t.value)
 
     def stop(self):
         if self.running:

@@ -21,6 +21,7 @@
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -160,8 +161,9 @@ pa_status validate(const pa_run_desc *d) {
         return fail(PA_ERR_INVALID, "unknown output bits");
     if (d->bin_e > 2 * d->L * d->L + 1 || d->bin_m > d->L * d->L + 1)
         return fail(PA_ERR_INVALID, "histogram bin wider than the histogram");
-    if ((d->L & 3u) || d->L < 4 || d->L > 4096)
-        return fail(PA_ERR_UNSUPPORTED, "this device path needs L % 4 == 0 and 4 <= L <= 4096");
+    if (d->L > 4096 || ((d->L & 3u) && d->L > 254))
+        return fail(PA_ERR_UNSUPPORTED,
+                    "this device path needs L <= 4096, and L <= 254 when L is not a multiple of 4");
     return PA_OK;
 }
 
@@ -799,8 +801,14 @@ pa_status pa_issue_probe(pa_ctx *ctx, uint32_t kind, void *d_out, uint64_t out_b
                      "issue probe");
 }
 
-pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes,
-                       void *stream, pa_run_state **out) {
+}  // extern "C"
+
+namespace {
+
+// pa_run_begin, optionally without the initial population (a run that loads
+// a population right after, from a checkpoint).
+pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes, void *stream,
+                    bool initial, pa_run_state **out) {
     if (!ctx || !out) return fail(PA_ERR_INVALID, "null context or output");
     pa_run_state *r = new (std::nothrow) pa_run_state;
     if (!r) return fail(PA_ERR_NOMEM, "out of host memory");
@@ -870,8 +878,8 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
         const hipError_t e = pa::launch_tiled_init(ta, s);
         return e != hipSuccess ? e : pa::launch_tiled_measure(ta, s);
     };
-    if ((st = timed_launch(r, PA_KERNEL_INIT, "init kernel", init)) ||
-        (st = launch_post_for(r, 0))) {
+    if (initial && ((st = timed_launch(r, PA_KERNEL_INIT, "init kernel", init)) ||
+                    (st = launch_post_for(r, 0)))) {
         release_events(r, nullptr, nullptr);
         delete r; return st;
     }
@@ -879,6 +887,15 @@ pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_
     if ((st = hip_check(r, hipStreamSynchronize(s), "sync"))) { delete r; return st; }
     *out = r;
     return PA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pa_status pa_run_begin(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes,
+                       void *stream, pa_run_state **out) {
+    return begin_run(ctx, desc, d_ws, ws_bytes, stream, true, out);
 }
 
 pa_status pa_run_advance(pa_run_state *r, uint32_t n_steps) {
@@ -1066,6 +1083,180 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
     release_events(r, nullptr, nullptr);
     delete r;
     return st;
+}
+
+
+// ---------------------------------------------------------------------------
+// Checkpoints: a run's population at a step, with -beta F of that step and the
+// run description, in the binary format documented in pa.h.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr char kCkptMagic[8] = {'P', 'A', 'C', 'K', 'P', 'T', '0', '1'};
+constexpr uint32_t kCkptHeader = 128;
+
+struct Checkpoint {
+    pa_run_desc desc{};
+    std::vector<double> beta;
+    uint32_t step = 0;
+    uint64_t R_cur = 0;
+    double mbF = 0;
+    int64_t E_sum = 0;
+};
+
+template <typename T> void put(uint8_t *h, size_t off, T v) { std::memcpy(h + off, &v, sizeof v); }
+template <typename T> T get(const uint8_t *h, size_t off) { T v; std::memcpy(&v, h + off, sizeof v); return v; }
+
+pa_status write_checkpoint(pa_run_state *r, const char *path) {
+    if (!r || !path) return fail(PA_ERR_INVALID, "null run or path");
+    if (r->broken) return fail(PA_ERR_DEVICE, "run is unusable after a device error");
+    pa_status st = hip_check(r, hipStreamSynchronize(r->stream), "sync");
+    if (st) return st;
+    const Plan &p = r->plan;
+    std::vector<uint8_t> spins((size_t)r->R_cur * p.N);
+    double mbF = 0;
+    int64_t esum = 0;
+    if ((st = hip_check(r, hipMemcpy(spins.data(), r->ws + p.off_pop[r->cur], spins.size(), hipMemcpyDeviceToHost),
+                        "read")) ||
+        (st = hip_check(r, hipMemcpy(&mbF, r->at<double>(p.off_mbF) + r->step, 8, hipMemcpyDeviceToHost), "read")) ||
+        (st = hip_check(r, hipMemcpy(&esum, r->at<int64_t>(p.off_Esum) + r->step, 8, hipMemcpyDeviceToHost), "read")))
+        return st;
+    uint8_t h[kCkptHeader] = {};
+    std::memcpy(h, kCkptMagic, 8);
+    const pa_run_desc &d = p.desc;
+    put<uint32_t>(h, 8, kCkptHeader);
+    put<uint32_t>(h, 12, d.L);
+    put<uint32_t>(h, 16, d.q);
+    put<uint32_t>(h, 20, d.K);
+    put<uint64_t>(h, 24, d.R);
+    put<uint32_t>(h, 32, d.theta);
+    put<int32_t>(h, 36, d.resample);
+    put<uint64_t>(h, 40, d.seed);
+    put<int32_t>(h, 48, d.init);
+    put<uint32_t>(h, 52, d.outputs);
+    put<uint32_t>(h, 56, d.bin_e);
+    put<uint32_t>(h, 60, d.bin_m);
+    put<uint32_t>(h, 64, r->step);
+    put<uint64_t>(h, 72, r->R_cur);
+    put<double>(h, 80, mbF);
+    put<int64_t>(h, 88, esum);
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(PA_ERR_INVALID, std::string("cannot open ") + path + " for writing");
+    bool ok = std::fwrite(h, 1, kCkptHeader, f) == kCkptHeader &&
+              std::fwrite(p.beta.data(), 8, p.beta.size(), f) == p.beta.size() &&
+              std::fwrite(spins.data(), 1, spins.size(), f) == spins.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? PA_OK : fail(PA_ERR_INVALID, std::string("cannot write ") + path);
+}
+
+// Reads and checks the header and beta of a checkpoint; with `spins`, also
+// the population.
+pa_status read_checkpoint(const char *path, Checkpoint &c, std::vector<uint8_t> *spins) {
+    if (!path) return fail(PA_ERR_INVALID, "null path");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(PA_ERR_INVALID, std::string("cannot open ") + path);
+    std::unique_ptr<FILE, int (*)(FILE *)> guard(f, std::fclose);
+    uint8_t h[kCkptHeader];
+    if (std::fread(h, 1, kCkptHeader, f) != kCkptHeader || std::memcmp(h, kCkptMagic, 8) != 0 ||
+        get<uint32_t>(h, 8) != kCkptHeader)
+        return fail(PA_ERR_INVALID, "not a checkpoint file (magic or header size)");
+    pa_run_desc &d = c.desc;
+    d = pa_run_desc{};
+    d.L = get<uint32_t>(h, 12);
+    d.q = get<uint32_t>(h, 16);
+    d.K = get<uint32_t>(h, 20);
+    d.R = get<uint64_t>(h, 24);
+    d.theta = get<uint32_t>(h, 32);
+    d.resample = get<int32_t>(h, 36);
+    d.seed = get<uint64_t>(h, 40);
+    d.init = get<int32_t>(h, 48);
+    d.outputs = get<uint32_t>(h, 52);
+    d.bin_e = get<uint32_t>(h, 56);
+    d.bin_m = get<uint32_t>(h, 60);
+    c.step = get<uint32_t>(h, 64);
+    c.R_cur = get<uint64_t>(h, 72);
+    c.mbF = get<double>(h, 80);
+    c.E_sum = get<int64_t>(h, 88);
+    if (d.K == 0 || d.K > (1u << 27) || c.step >= d.K || d.L < 2 || d.L > 65536 || c.R_cur == 0 ||
+        c.R_cur > (1ull << 31))
+        return fail(PA_ERR_INVALID, "checkpoint header out of range");
+    c.beta.resize(d.K);
+    if (std::fread(c.beta.data(), 8, d.K, f) != d.K) return fail(PA_ERR_INVALID, "checkpoint truncated (beta)");
+    d.beta = c.beta.data();
+    const uint64_t bytes = c.R_cur * (uint64_t)d.L * d.L;
+    const long at = std::ftell(f);
+    if (at < 0 || std::fseek(f, 0, SEEK_END) != 0) return fail(PA_ERR_INVALID, "cannot size the checkpoint file");
+    const long end = std::ftell(f);
+    if (end < 0 || (uint64_t)end != (uint64_t)at + bytes)
+        return fail(PA_ERR_INVALID, "checkpoint file size does not match its header (truncated or extended)");
+    if (spins) {
+        spins->resize(bytes);
+        if (std::fseek(f, at, SEEK_SET) != 0 || std::fread(spins->data(), 1, bytes, f) != bytes)
+            return fail(PA_ERR_INVALID, "checkpoint truncated (spins)");
+    }
+    return PA_OK;
+}
+
+// A new run in the workspace continued from checkpoint c (population spins):
+// begun without an initial population, the population loaded at c.step, and
+// the energy sum the device recomputes checked against the stored one.
+pa_status resume_run(pa_ctx *ctx, const Checkpoint &c, const std::vector<uint8_t> &spins, void *d_ws,
+                     uint64_t ws_bytes, void *stream, pa_run_state **out) {
+    pa_run_state *r = nullptr;
+    pa_status st = begin_run(ctx, &c.desc, d_ws, ws_bytes, stream, false, &r);
+    if (st) return st;
+    if ((st = pa_run_load(r, c.step, c.R_cur, spins.data(), c.mbF))) {
+        const std::string msg = g_last_error;
+        pa_run_finish(r, nullptr);
+        return fail(st, msg);
+    }
+    int64_t esum = 0;
+    st = hip_check(r, hipMemcpy(&esum, r->at<int64_t>(r->plan.off_Esum) + c.step, 8, hipMemcpyDeviceToHost), "read");
+    if (!st && esum != c.E_sum) st = fail(PA_ERR_INVALID, "checkpoint energies do not match its population");
+    if (st) {
+        const std::string msg = g_last_error;
+        pa_run_finish(r, nullptr);
+        return fail(st, msg);
+    }
+    *out = r;
+    return PA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pa_status pa_checkpoint(pa_run_state *run, const char *path) { return write_checkpoint(run, path); }
+
+pa_status pa_checkpoint_info(const char *path, pa_run_desc *desc, double *beta, uint32_t beta_cap, uint32_t *step,
+                             uint64_t *R_cur) {
+    Checkpoint c;
+    pa_status st = read_checkpoint(path, c, nullptr);
+    if (st) return st;
+    if (desc) {
+        *desc = c.desc;
+        desc->beta = nullptr;
+    }
+    if (step) *step = c.step;
+    if (R_cur) *R_cur = c.R_cur;
+    if (beta) {
+        if (beta_cap < c.desc.K) return fail(PA_ERR_NOMEM, "beta buffer shorter than K");
+        std::memcpy(beta, c.beta.data(), 8 * (size_t)c.desc.K);
+        if (desc) desc->beta = beta;
+    }
+    return PA_OK;
+}
+
+pa_status pa_resume(pa_ctx *ctx, const char *path, void *d_ws, uint64_t ws_bytes, void *stream,
+                    pa_run_state **out) {
+    if (!ctx || !out) return fail(PA_ERR_INVALID, "null context or output");
+    Checkpoint c;
+    std::vector<uint8_t> spins;
+    pa_status st = read_checkpoint(path, c, &spins);
+    if (st) return st;
+    return resume_run(ctx, c, spins, d_ws, ws_bytes, stream, out);
 }
 
 }  // extern "C"
@@ -1440,6 +1631,15 @@ struct Request {
     pa_status status = PA_OK;
     std::string message;
     pa_run_state *run = nullptr;
+    // a checkpoint asked for by pa_serve_checkpoint: 0 none, 1 pending, 2 written
+    int ckpt_state = 0;
+    std::string ckpt_path;
+    pa_status ckpt_status = PA_OK;
+    std::string ckpt_msg;
+    // a request resumed from a checkpoint (pa_serve_resume)
+    bool resume = false;
+    Checkpoint from;
+    std::vector<uint8_t> from_spins;
 };
 
 }  // namespace
@@ -1506,8 +1706,11 @@ struct Server {
             }
             for (auto &q : admitted) {
                 pa_run_state *run = nullptr;
-                pa_status st = pa_run_begin(ctx, &q->desc, arena + desc_bytes + q->off, align256(q->bytes),
-                                            stream, &run);
+                pa_status st = q->resume ? resume_run(ctx, q->from, q->from_spins, arena + desc_bytes + q->off,
+                                                      align256(q->bytes), stream, &run)
+                                         : pa_run_begin(ctx, &q->desc, arena + desc_bytes + q->off,
+                                                        align256(q->bytes), stream, &run);
+                q->from_spins = std::vector<uint8_t>();   // loaded; release the host copy
                 std::lock_guard<std::mutex> lk(mu);
                 if (st) {
                     alloc.release(q->off, q->bytes);
@@ -1516,6 +1719,25 @@ struct Server {
                 }
                 q->run = run;
                 active.push_back(q);
+            }
+            // Checkpoints asked for since the last round (the runs are
+            // synchronised at a step boundary here), written outside the lock.
+            std::vector<std::shared_ptr<Request>> ckpts;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                for (auto &q : active)
+                    if (q->ckpt_state == 1) ckpts.push_back(q);
+            }
+            for (auto &q : ckpts) {
+                const pa_status cs = write_checkpoint(q->run, q->ckpt_path.c_str());
+                std::lock_guard<std::mutex> lk(mu);
+                q->ckpt_status = cs;
+                q->ckpt_msg = cs ? g_last_error : std::string();
+                q->ckpt_state = 2;
+            }
+            if (!ckpts.empty()) {
+                std::lock_guard<std::mutex> lk(mu);
+                cv_done.notify_all();
             }
             // Up to kStepsPerIteration global steps of every active run.
             std::vector<pa_run_state *> runs;
@@ -1560,6 +1782,11 @@ struct Server {
                 }
                 q->run = nullptr;
                 alloc.release(q->off, q->bytes);
+                if (q->ckpt_state == 1) {
+                    q->ckpt_status = PA_ERR_INVALID;
+                    q->ckpt_msg = "the request finished before its checkpoint";
+                    q->ckpt_state = 2;
+                }
                 finish(q, fs, fs ? (st ? msg : (q->cancel ? "cancelled while running" : g_last_error)) : "");
                 it = active.erase(it);
             }
@@ -1602,11 +1829,9 @@ pa_status pa_serve_start(pa_ctx *ctx, void *d_arena, uint64_t arena_bytes, uint3
     return PA_OK;
 }
 
-pa_status pa_serve_submit(pa_ctx *ctx, const pa_run_desc *desc, pa_result *out, uint64_t *ticket) {
-    if (!ctx || !desc || !ticket) return fail(PA_ERR_INVALID, "null argument");
-    const std::shared_ptr<Server> sv = server_of(ctx);
-    if (!sv) return fail(PA_ERR_INVALID, "no server");
-    auto q = std::make_shared<Request>();
+// Queue request q for run description desc (first step to run: step0 + 1).
+static pa_status enqueue(const std::shared_ptr<Server> &sv, const std::shared_ptr<Request> &q,
+                         const pa_run_desc *desc, uint32_t step0, pa_result *out, uint64_t *ticket) {
     Plan p;
     pa_status st = build_plan(desc, p);
     if (st) return st;
@@ -1615,10 +1840,11 @@ pa_status pa_serve_submit(pa_ctx *ctx, const pa_run_desc *desc, pa_result *out, 
     q->desc = *desc;
     q->beta.assign(desc->beta, desc->beta + desc->K);
     q->desc.beta = q->beta.data();
+    if (q->resume) q->from.desc.beta = q->from.beta.data();
     if (out) q->out = *out;
     q->bytes = p.total;
     double att = 0;
-    for (uint32_t i = 1; i < desc->K; ++i) att += (double)desc->theta * p.N * (double)p.R_sched[i];
+    for (uint32_t i = step0 + 1; i < desc->K; ++i) att += (double)desc->theta * p.N * (double)p.R_sched[i];
     q->attempts = (uint64_t)att;
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->stopping) return fail(PA_ERR_CANCELLED, "server stopping");
@@ -1628,6 +1854,44 @@ pa_status pa_serve_submit(pa_ctx *ctx, const pa_run_desc *desc, pa_result *out, 
     sv->queue.push_back(q);
     *ticket = q->ticket;
     sv->cv_work.notify_one();
+    return PA_OK;
+}
+
+pa_status pa_serve_submit(pa_ctx *ctx, const pa_run_desc *desc, pa_result *out, uint64_t *ticket) {
+    if (!ctx || !desc || !ticket) return fail(PA_ERR_INVALID, "null argument");
+    const std::shared_ptr<Server> sv = server_of(ctx);
+    if (!sv) return fail(PA_ERR_INVALID, "no server");
+    return enqueue(sv, std::make_shared<Request>(), desc, 0, out, ticket);
+}
+
+pa_status pa_serve_resume(pa_ctx *ctx, const char *path, pa_result *out, uint64_t *ticket) {
+    if (!ctx || !ticket) return fail(PA_ERR_INVALID, "null argument");
+    const std::shared_ptr<Server> sv = server_of(ctx);
+    if (!sv) return fail(PA_ERR_INVALID, "no server");
+    auto q = std::make_shared<Request>();
+    pa_status st = read_checkpoint(path, q->from, &q->from_spins);
+    if (st) return st;
+    q->resume = true;
+    return enqueue(sv, q, &q->from.desc, q->from.step, out, ticket);
+}
+
+pa_status pa_serve_checkpoint(pa_ctx *ctx, uint64_t ticket, const char *path) {
+    if (!ctx || !path) return fail(PA_ERR_INVALID, "null argument");
+    const std::shared_ptr<Server> sv = server_of(ctx);
+    if (!sv) return fail(PA_ERR_INVALID, "no server");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->tickets.find(ticket);
+    if (it == sv->tickets.end()) return fail(PA_ERR_INVALID, "unknown ticket");
+    const std::shared_ptr<Request> q = it->second;
+    if (q->state == ReqState::Queued) return fail(PA_ERR_BUSY, "request not admitted yet");
+    if (q->state == ReqState::Done) return fail(PA_ERR_INVALID, "request already finished");
+    if (q->ckpt_state != 0) return fail(PA_ERR_BUSY, "a checkpoint of this ticket is in progress");
+    q->ckpt_path = path;
+    q->ckpt_state = 1;
+    sv->cv_work.notify_one();
+    sv->cv_done.wait(lk, [&] { return q->ckpt_state == 2; });
+    q->ckpt_state = 0;
+    if (q->ckpt_status) return fail(q->ckpt_status, q->ckpt_msg);
     return PA_OK;
 }
 

@@ -702,6 +702,126 @@ __global__ void __launch_bounds__(1024) k_sweep_batch(const SweepArgs *runs, con
 }
 
 // ---------------------------------------------------------------------------
+// Lattices with L = 2 (mod 4): a row of L bytes is not a whole number of
+// dwords, and a row holds L/2 sites of each colour, an odd number, so the two
+// sites of one Philox block (the m-th and (m+1)-th colour-c sites in row-major
+// order, m even) can lie in consecutive rows.  One wave holds a replica in LDS
+// byte by byte, without halo rows: lane l updates the pairs p = l, l + 64, ...
+// of each half-sweep, site by site, with the same counters, thresholds and
+// update rule as the dword kernels (Sec. 2 step 3).  The population size N =
+// L^2 is a multiple of 4, so the gather, the initial spins, the digest and the
+// store still move whole dwords.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wrap_next(uint32_t v, uint32_t L) { return v + 1u == L ? 0u : v + 1u; }
+__device__ __forceinline__ uint32_t wrap_prev(uint32_t v, uint32_t L) { return v == 0u ? L - 1u : v - 1u; }
+
+// Metropolis update of site (y, x) of the replica s (L x L bytes).
+__device__ __forceinline__ void byte_site_update(uint8_t *s, uint32_t L, uint32_t y, uint32_t x,
+                                                 uint32_t w_prop, uint32_t w_acc, uint32_t qm1,
+                                                 const SweepArgs &a) {
+    const uint32_t row = y * L;
+    const uint32_t cur = s[row + x];
+    const uint32_t nb0 = s[row + wrap_prev(x, L)], nb1 = s[row + wrap_next(x, L)];
+    const uint32_t nb2 = s[wrap_prev(y, L) * L + x], nb3 = s[wrap_next(y, L) * L + x];
+    const uint32_t r = mulhi32(w_prop, qm1);
+    const uint32_t prop = r + (r >= cur ? 1u : 0u);
+    const int32_t dE = (int32_t)((nb0 == cur) + (nb1 == cur) + (nb2 == cur) + (nb3 == cur)) -
+                       (int32_t)((nb0 == prop) + (nb1 == prop) + (nb2 == prop) + (nb3 == prop));
+    // T[dE - 1] by selects: a run-time index into the arguments would go
+    // through scratch memory
+    const uint64_t T = dE == 1 ? a.T[0] : dE == 2 ? a.T[1] : dE == 3 ? a.T[2] : a.T[3];
+    if (dE <= 0 || (uint64_t)w_acc < T) s[row + x] = (uint8_t)prop;
+}
+
+__device__ __forceinline__ void sweep_bytes_body(const SweepArgs &a, uint32_t block) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t L = a.L, N = a.N, lane = threadIdx.x & 63u;
+    const uint32_t rpb = blockDim.x >> 6;                                  // one replica per wave
+    const uint64_t k64 = (uint64_t)block * rpb + (threadIdx.x >> 6);
+    if (k64 >= a.R_new) return;              // whole waves only; no workgroup barriers below
+    const uint32_t k = __builtin_amdgcn_readfirstlane((uint32_t)k64);
+    uint8_t *rep = smem + (size_t)(threadIdx.x >> 6) * ((N + 15u) & ~15u);
+    uint32_t *rep32 = reinterpret_cast<uint32_t *>(rep);
+    const uint32_t D = N >> 2;                                             // dwords per replica
+
+    if (a.mode == SWEEP_UPDATE) {
+        const uint32_t src = a.anc ? a.anc[k] : k;
+        const uint32_t *g = reinterpret_cast<const uint32_t *>(a.old_pop + (size_t)src * N);
+        for (uint32_t d = lane; d < D; d += 64u) rep32[d] = g[d];
+    } else if (a.mode == SWEEP_INIT_RANDOM) {
+        // site n takes word n mod 4 of Philox(n / 4, k, 0, INIT)
+        for (uint32_t d = lane; d < D; d += 64u) {
+            const uint4 w = philox(d, k, 0u, DOM_INIT << 28, a.key0, a.key1);
+            rep32[d] = mulhi32(w.x, a.q) | (mulhi32(w.y, a.q) << 8) | (mulhi32(w.z, a.q) << 16) |
+                       (mulhi32(w.w, a.q) << 24);
+        }
+    } else {
+        // eq. (6): all spins alpha, alpha uniform over the q states
+        const uint4 w = philox(0u, k, 0u, DOM_GROUND << 28, a.key0, a.key1);
+        const uint32_t alpha = mulhi32(w.x, a.q) * 0x01010101u;
+        for (uint32_t d = lane; d < D; d += 64u) rep32[d] = alpha;
+    }
+    wave_fence();
+
+    const uint32_t theta = a.mode == SWEEP_UPDATE ? a.theta : 0u;
+    const uint32_t half = L >> 1, qm1 = a.q - 1u;
+    for (uint32_t t = 0; t < theta; ++t) {
+        for (uint32_t c = 0; c < 2u; ++c) {
+            const uint32_t c3 = (DOM_SWEEP << 28) | (t << 1) | c;
+            for (uint32_t p = lane; p < D; p += 64u) {     // N/4 pairs of colour-c sites
+                const uint4 w = philox(p, k, a.step, c3, a.key0, a.key1);
+#pragma unroll
+                for (uint32_t h = 0; h < 2u; ++h) {
+                    const uint32_t m = 2u * p + h;
+                    const uint32_t y = m / half;
+                    const uint32_t x = 2u * (m - y * half) + ((y + c) & 1u);
+                    byte_site_update(rep, L, y, x, h ? w.z : w.x, h ? w.w : w.y, qm1, a);
+                }
+            }
+            wave_fence();
+        }
+    }
+
+    // energy (eq. (3)): bonds to the right and down neighbours
+    uint32_t bonds = 0;
+    for (uint32_t n = lane; n < N; n += 64u) {
+        const uint32_t y = n / L, x = n - y * L;
+        const uint32_t sv = rep[n];
+        bonds += (sv == rep[y * L + wrap_next(x, L)]) + (sv == rep[wrap_next(y, L) * L + x]);
+    }
+    bonds = wave_total(bonds);
+    // magnetisation (eq. (5)): the largest number of sites in one state
+    uint32_t mt = 0;
+    if (a.Mt_out) {
+        for (uint32_t st = 0; st < a.q; ++st) {
+            uint32_t cnt = 0;
+            for (uint32_t n = lane; n < N; n += 64u) cnt += rep[n] == st ? 1u : 0u;
+            mt = max(mt, wave_total(cnt));
+        }
+    }
+    uint64_t dig = 0;
+    if (a.H_out) {
+        for (uint32_t d = lane; d < D; d += 64u) dig += digest_term(d, k, a.step, rep32[d], a.key0, a.key1);
+        for (uint32_t off = 32; off > 0; off >>= 1) dig += __shfl_xor(dig, off, 64);
+    }
+    if (lane == 0) {
+        a.E_out[k] = -(int32_t)bonds;
+        if (a.Mt_out) a.Mt_out[k] = mt;
+        if (a.H_out) a.H_out[k] = dig;
+    }
+    uint32_t *dst = reinterpret_cast<uint32_t *>(a.new_pop + (size_t)k * N);
+    for (uint32_t d = lane; d < D; d += 64u) dst[d] = rep32[d];
+}
+
+__global__ void __launch_bounds__(256) k_sweep_bytes(SweepArgs a) { sweep_bytes_body(a, blockIdx.x); }
+
+__global__ void __launch_bounds__(256) k_sweep_bytes_batch(const SweepArgs *runs, const uint32_t *start,
+                                                           uint32_t n) {
+    const uint32_t r = segment_of(start, n, blockIdx.x);
+    sweep_bytes_body(runs[r], blockIdx.x - start[r]);
+}
+
+// ---------------------------------------------------------------------------
 // Workgroup helpers (1024 threads = 16 waves).  k_post and k_countfill, the
 // kernels they serve, always run workgroups of WG_THREADS, so the per-wave
 // partials are combined in unrolled loops whose LDS reads issue together.
@@ -1801,6 +1921,16 @@ uint32_t lane_candidates(uint32_t L, uint32_t *out) {
 
 void sweep_shape(uint32_t L, uint32_t lanes, uint32_t *G_out, uint32_t *waves_per_block) {
     uint32_t G = 0;
+    if (L & 3u) {
+        // byte kernel: one replica per wave, up to four per workgroup, as many
+        // as 64 KB of LDS hold (one for larger replicas)
+        const uint32_t bytes = ((L * L) + 15u) & ~15u;
+        uint32_t wpb = 4;
+        while (wpb > 1 && wpb * bytes > 65536u) --wpb;
+        *G_out = 64;
+        *waves_per_block = wpb;
+        return;
+    }
     if (lane_choice_index(L) >= 0) {
         uint32_t cand[2];
         const uint32_t n = lane_candidates(L, cand);
@@ -1839,6 +1969,7 @@ uint64_t replicas_per_block(uint32_t G, uint32_t waves_per_block) {
 size_t sweep_lds_bytes(uint32_t N, uint32_t G, uint32_t waves_per_block, uint32_t q_counters) {
     uint32_t L = 0;
     while (L * L < N) ++L;
+    if (L & 3u) return (size_t)waves_per_block * ((N + 15u) & ~15u);   // byte kernel
     const uint64_t rpb = replicas_per_block(G, waves_per_block);
     return pair_tab_off(sweep_lds_end(N, L, G, (uint32_t)rpb, q_counters)) + PAIR_TAB_BYTES;
 }
@@ -1877,15 +2008,19 @@ hipError_t launch_resample(const SampleArgs &a, const SlotmapArgs &m, hipStream_
     return hipGetLastError();
 }
 
-// Kernel class: lattice side, lanes per replica, q <= 128, 64-bit thresholds.
+// Kernel class: lattice side, lanes per replica, q <= 128, 64-bit thresholds;
+// bit 31 marks the byte kernel of L = 2 (mod 4).
+constexpr uint32_t CLASS_BYTES = 1u << 31;
 uint32_t sweep_class(uint32_t L, uint32_t q, bool t64, uint32_t G) {
+    if (L & 3u) return CLASS_BYTES | (L << 16);
     return (L << 16) | (G << 2) | ((q <= 128) ? 2u : 0u) | (t64 ? 1u : 0u);
 }
 
 // The instance for a class: fixed-shape when L is a power of two with a
 // candidate lane count and the 32-bit threshold form applies, else generic.
 void *sweep_kernel(uint32_t cls, bool batch) {
-    const uint32_t L = cls >> 16, G = (cls >> 2) & 0x3FFFu;
+    if (cls & CLASS_BYTES) return batch ? (void *)k_sweep_bytes_batch : (void *)k_sweep_bytes;
+    const uint32_t L = (cls >> 16) & 0x7FFFu, G = (cls >> 2) & 0x3FFFu;
     const bool qs = (cls & 2u) != 0, t64 = (cls & 1u) != 0;
 #define PA_INST(LV, GV)                                                                       \
     if (L == LV && G == GV)                                                                   \

@@ -139,3 +139,57 @@ def ising_lnZ_kaufman(m: int, n: int, K: float) -> float:
 def potts_q2_lnZ(L: int, beta: float) -> float:
     N = L * L
     return beta * N + ising_lnZ_kaufman(L, L, beta / 2)
+
+
+def one_sweep_matrix_L2(q: int, beta: float) -> tuple[np.ndarray, np.ndarray]:
+    """Exact transition matrix of one checkerboard Metropolis sweep on the
+    2 x 2 periodic lattice, and the energies of its q^4 configurations.
+
+    Configuration index a = s0 q^3 + s1 q^2 + s2 q + s3 with sites
+    0 = (0,0), 1 = (0,1), 2 = (1,0), 3 = (1,1) (row-major).  Colour 0 =
+    {0, 3}, colour 1 = {1, 2}; a half-sweep updates the sites of one colour,
+    each seeing only the other colour.  Each site's left and right neighbours
+    are the same site, as are its upper and lower ones, so each counts twice.
+    Per site: a proposal uniform over the q - 1 other states, accepted with
+    probability 1 when dE <= 0, else T(dE) / 2^32 with the integer threshold
+    T(dE) = floor(2^32 exp(-beta dE)) (w uniform over 2^32 words, accepted when
+    w < T).  The sweep is colour 0, then colour 1: P = P0 @ P1."""
+    confs = np.array(list(itertools.product(range(q), repeat=4)), dtype=np.int64)
+    nb = {0: (1, 2), 1: (0, 3), 2: (3, 0), 3: (2, 1)}   # (horizontal, vertical) neighbour
+
+    def energy(c):
+        return -sum(2 * int(c[n] == c[nb[n][0]]) + 2 * int(c[n] == c[nb[n][1]]) for n in range(4)) // 2
+
+    E = np.array([energy(c) for c in confs], dtype=np.int64)
+    acc = {d: (1.0 if d <= 0 else math.floor(math.ldexp(math.exp(-beta * d), 32)) / 2.0 ** 32)
+           for d in range(-8, 9)}
+
+    def site_kernel(c, n):
+        """Distribution of the new spin of site n given configuration c."""
+        s = int(c[n])
+        h, v = c[nb[n][0]], c[nb[n][1]]
+        neigh = (h, h, v, v)
+        p = np.zeros(q)
+        stay = 1.0
+        for t in range(q):
+            if t == s:
+                continue
+            dE = sum(int(x == s) for x in neigh) - sum(int(x == t) for x in neigh)
+            pt = acc[dE] / (q - 1)
+            p[t] = pt
+            stay -= pt
+        p[s] += stay
+        return p
+
+    def half_matrix(sites):
+        M = np.zeros((len(confs), len(confs)))
+        for a, c in enumerate(confs):
+            pa_, pb_ = site_kernel(c, sites[0]), site_kernel(c, sites[1])
+            for ta in range(q):
+                for tb in range(q):
+                    d = c.copy()
+                    d[sites[0]], d[sites[1]] = ta, tb
+                    M[a, int(d[0] * q ** 3 + d[1] * q ** 2 + d[2] * q + d[3])] += pa_[ta] * pb_[tb]
+        return M
+
+    return half_matrix((0, 3)) @ half_matrix((1, 2)), E

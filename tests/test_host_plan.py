@@ -81,7 +81,7 @@ def test_validation():
         (dict(good, beta=[0.0, float("inf")]), pa.PA_ERR_INVALID),
         (dict(good, beta=[0.0, -1.0]), pa.PA_ERR_INVALID),
         (dict(good, theta=2**27), pa.PA_ERR_INVALID),
-        (dict(good, L=6), pa.PA_ERR_UNSUPPORTED),
+        (dict(good, L=1), pa.PA_ERR_INVALID),
         (dict(good, L=4100), pa.PA_ERR_UNSUPPORTED),
         (dict(good, L=258), pa.PA_ERR_UNSUPPORTED),
         (dict(good, outputs=32), pa.PA_ERR_INVALID),
@@ -134,3 +134,17 @@ def test_large_lattices_plan_compact_tables():
     assert pop <= info.workspace_bytes < pop + 200 * 2**20
     info = pa.pa_plan(pa.Desc(L=260, q=10, R=100, beta=beta, theta=1, seed=1))
     assert info.workspace_bytes < 2 * info.R_cap * 260 * 260 + 20 * 2**20
+
+
+def test_lattice_sides_accepted_and_rejected():
+    """Even L from 2 up: multiples of 4 up to 4096 and L = 2 (mod 4) up to 254
+    run on the device; odd L is invalid for the checkerboard update (Sec. 3
+    lattice, the update needs two colours)."""
+    base = dict(q=4, R=10, beta=np.array([0.0, 0.5, 1.0]), theta=1, seed=1)
+    for L in (2, 4, 6, 10, 18, 254, 256, 4096):
+        assert pa.pa_plan(pa.Desc(L=L, **base)).workspace_bytes > 0
+    for L, status in ((3, pa.PA_ERR_INVALID), (7, pa.PA_ERR_INVALID), (258, pa.PA_ERR_UNSUPPORTED),
+                      (4098, pa.PA_ERR_UNSUPPORTED)):
+        with pytest.raises(pa.PAError) as e:
+            pa.pa_plan(pa.Desc(L=L, **base))
+        assert e.value.status == status, L

@@ -172,6 +172,67 @@ def test_stationary_distribution_L2():
     assert stats.chisquare(counts, p * R).pvalue > 1e-4
 
 
+@pytest.mark.parametrize("q", [2, 3])
+@pytest.mark.parametrize("beta", [0.3, 0.7, 1.5])
+def test_one_sweep_matrix_leaves_boltzmann_stationary(q, beta):
+    """The exact one-sweep transition matrix of the 2 x 2 lattice built from the
+    proposal and acceptance rule (independently of the oracle) is stochastic
+    and leaves exp(-beta E) / Z stationary to 1e-9: the only departure from
+    detailed balance is the flooring of the thresholds to multiples of 2^-32."""
+    P, E = exact.one_sweep_matrix_L2(q, beta)
+    assert np.abs(P.sum(axis=1) - 1.0).max() < 1e-12
+    pi = np.exp(-beta * E)
+    pi /= pi.sum()
+    assert np.abs(pi @ P - pi).max() < 1e-9
+
+
+def one_sweep_transition_counts(sweep, q, n_slots):
+    """Counts [q^4, q^4] of (start, end) configurations of one sweep of the
+    2 x 2 lattice, every start configuration taken n_slots times; sweep(k,
+    spins) returns the swept spins of slot k."""
+    confs = np.array([[a // q ** 3, (a // q ** 2) % q, (a // q) % q, a % q] for a in range(q ** 4)],
+                     np.uint8)
+    counts = np.zeros((q ** 4, q ** 4), np.int64)
+    k = 0
+    for a, c in enumerate(confs):
+        for _ in range(n_slots):
+            s = sweep(k, c)
+            counts[a, int(s[0]) * q ** 3 + int(s[1]) * q ** 2 + int(s[2]) * q + int(s[3])] += 1
+            k += 1
+    return counts
+
+
+def transitions_match(counts, P):
+    """Chi-square of all rows against the exact matrix (cells with an expected
+    count of at least 5; the rest of each row pooled into one cell)."""
+    chi2, dof = 0.0, 0
+    for a in range(P.shape[0]):
+        n = counts[a].sum()
+        e = P[a] * n
+        big = e >= 5
+        obs = list(counts[a][big]) + [counts[a][~big].sum()]
+        exp_ = list(e[big]) + [e[~big].sum()]
+        if exp_[-1] < 1e-12:
+            obs, exp_ = obs[:-1], exp_[:-1]
+            assert counts[a][~big].sum() == 0
+        chi2 += sum((o - x) ** 2 / x for o, x in zip(obs, exp_))
+        dof += len(obs) - 1
+    return stats.chi2.sf(chi2, dof)
+
+
+def test_oracle_one_sweep_follows_the_exact_matrix_L2():
+    """The oracle's sweep of the 2 x 2, q = 3 lattice, started 300 times from
+    each of the 81 configurations (different slots, so different random
+    words), lands on the configurations with the exact matrix's
+    probabilities."""
+    q, beta = 3, 0.7
+    d = oracle.Desc(2, q, 1, np.array([0.0, beta]), 1, seed=77, resample=oracle.RESAMPLE_NONE)
+    T = oracle.thresholds(beta)
+    counts = one_sweep_transition_counts(lambda k, c: oracle.one_sweep(d, 1, 0, k, T, c), q, 300)
+    P, _ = exact.one_sweep_matrix_L2(q, beta)
+    assert transitions_match(counts, P) > 1e-4
+
+
 def test_mcmc_mean_energy_L4_q3():
     """Metropolis alone (no resampling) at fixed beta on 4 x 4, q = 3 reaches
     the exact <E> of the transfer-matrix density of states."""
