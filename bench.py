@@ -50,9 +50,11 @@ INT_OPS_PEAK = 256 * 128 * 2.4e9
 # select -- 35-45 by the plain count, 40 taken as the figure.
 ALG_OPS_PER_ATTEMPT = 40
 
-# HBM bytes per sweep launch at 128x128, R = 2e5 (rocprofv3 FETCH_SIZE and
-# WRITE_SIZE scaled by the plain-copy calibration); None until measured.
-SWEEP_TRAFFIC_BYTES = None
+# HBM bytes per sweep launch at 128x128, R = 2e5: rocprofv3 FETCH_SIZE x 2.00
+# + WRITE_SIZE x 1.00 (the factors a plain 256 MiB copy gives), average of the
+# step launches 1-3: (2 x 1603274 + 3200009) KiB; 2 R_i N = 6.55e9 bytes are
+# algorithmic (gather + store).
+SWEEP_TRAFFIC_BYTES = (2.0 * 1603274 + 3200009) * 1024
 
 CFG3 = dict(L=128, q=10, R=200000, K=501, beta_max=1.6, theta=20, seed=4)
 CFG1 = dict(L=32, q=10, R=20000, K=401, beta_max=1.6, theta=10, seed=2)
@@ -181,8 +183,9 @@ def whole_runs(pa, torch, ctx, w, reps=3):
 
 
 def batched_vs_plain(pa, torch, ctx, runs, reps=1):
-    """The same runs as separate pa_run calls and as one pa_run_batch (eager
-    launches and a replayed HIP graph)."""
+    """The same runs as separate pa_run calls and as one pa_run_batch:
+    segmented launches (the default), team launches for the runs that
+    qualify, and the segmented step sequence replayed as a HIP graph."""
     descs = [pa.Desc(**r) for r in runs]
     att = sum(float(r["theta"]) * r["L"] ** 2 * float(np.sum(pa.pa_plan_tables(d)[1][1:]))
               for r, d in zip(runs, descs))
@@ -203,6 +206,12 @@ def batched_vs_plain(pa, torch, ctx, runs, reps=1):
 
     t_plain = timed(lambda: [pa.pa_run(ctx, d, workspace=ws_p) for d in descs])
     t_batch = timed(lambda: pa.pa_run_batch(ctx, descs, workspace=ws_b))
+    ctx.set_batch_mode(pa.BATCH_TEAM)
+    pa.pa_run_batch(ctx, descs, workspace=ws_b)
+    torch.cuda.synchronize()
+    t_team = timed(lambda: pa.pa_run_batch(ctx, descs, workspace=ws_b))
+    team_runs, team_launches = ctx.batch_info()
+    ctx.set_batch_mode(pa.BATCH_SEGMENTED)
     ctx.set_graphs(True)
     pa.pa_run_batch(ctx, descs, workspace=ws_b)        # capture
     torch.cuda.synchronize()
@@ -212,8 +221,10 @@ def batched_vs_plain(pa, torch, ctx, runs, reps=1):
     return {"runs": len(runs), "attempts": att,
             "plain_attempts_per_ns": att / t_plain / 1e9, "plain_ms": t_plain * 1e3,
             "batched_attempts_per_ns": att / t_batch / 1e9, "batched_ms": t_batch * 1e3,
+            "team_attempts_per_ns": att / t_team / 1e9, "team_ms": t_team * 1e3,
+            "team_runs": team_runs, "team_launches": team_launches,
             "graph_attempts_per_ns": att / t_graph / 1e9, "graph_ms": t_graph * 1e3,
-            "speedup": t_plain / min(t_batch, t_graph)}
+            "speedup": t_plain / min(t_batch, t_team, t_graph)}
 
 
 def serving(pa, torch, ctx, n_requests, capacity_attempts_per_ns, rho=0.8,

@@ -138,7 +138,9 @@ typedef struct {
                                 r = (w1 << 32 | w0) | 1 with w = Philox(n, k, i, 5 << 28);
                                 equal populations in equal slots give equal digests, and any
                                 single changed dword changes the digest              */
-    uint8_t  *final_spins;   /* [R_{K-1}][N]; NULL unless PA_OUT_FINAL              */
+    uint8_t  *final_spins;   /* [R_{K-1}][N]; NULL unless PA_OUT_FINAL; the final_* and
+                                last_anc buffers are written only by a run that has
+                                reached its last temperature                          */
     int32_t  *final_E;       /* [R_{K-1}];     NULL unless PA_OUT_FINAL              */
     uint32_t *last_anc;      /* [R_{K-1}] ancestors of the last resampling (identity if K == 1) */
     double   *kernel_ms;     /* [PA_KERNEL_KINDS] summed HIP-event time per kernel kind, or NULL;
@@ -287,6 +289,26 @@ pa_status pa_plan_batch(const pa_run_desc *descs, uint32_t n, uint64_t *workspac
  * stream by events) and replays it for later calls with the same
  * descriptions, workspace and kernel shapes (up to 8 cached graphs). */
 pa_status pa_ctx_set_graphs(pa_ctx *ctx, int enable);
+/* Batch modes.  PA_BATCH_SEGMENTED (the default): the launches above, one
+ * set per global step.  PA_BATCH_TEAM: the runs whose every remaining step
+ * fits one workgroup's sweep class, with populations up to 8192 replicas and
+ * no 64-bit thresholds, go through all their steps in one cooperative launch
+ * per sweep class -- each run a team of workgroups that meet at one
+ * device-wide barrier per step: every sweeping workgroup redoes the
+ * resampling of eq. (1) from the energies in its LDS and then claims blocks
+ * of replicas to sweep; the statistics of Sec. 4 run in a workgroup of their
+ * own, one step behind.  Other runs take the segmented launches (graphs on:
+ * all of them).  Results are identical in both modes. */
+enum { PA_BATCH_TEAM = 0, PA_BATCH_SEGMENTED = 1 };
+pa_status pa_ctx_set_batch_mode(pa_ctx *ctx, int mode);
+/* How the last pa_run_batch on ctx went: the runs it finished in team
+ * launches and the number of those launches (either may be NULL). */
+pa_status pa_ctx_batch_info(pa_ctx *ctx, uint32_t *team_runs, uint32_t *team_launches);
+/* Stops the pa_run_batch running on ctx (callable from any thread): a team
+ * launch leaves its barrier waits and the call returns PA_ERR_CANCELLED; the
+ * runs' results are then undefined, the context stays usable.  A barrier wait
+ * that lasts longer than 10 s ends the same way with PA_ERR_DEVICE. */
+pa_status pa_ctx_abort_batch(pa_ctx *ctx);
 pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_t n, void *d_ws,
                        uint64_t ws_bytes, void *stream, pa_result *outs);
 

@@ -26,7 +26,8 @@ KERNEL_NAMES = ("init", "sweep", "post", "resample")
 EXPORTS = [
     "pa_plan", "pa_plan_tables", "pa_weight_table", "pa_ctx_create", "pa_ctx_destroy",
     "pa_ctx_set_profiling", "pa_ctx_set_lanes", "pa_ctx_get_lanes", "pa_autotune",
-    "pa_ctx_set_graphs",
+    "pa_ctx_set_graphs", "pa_ctx_set_batch_mode", "pa_ctx_abort_batch",
+    "pa_ctx_batch_info",
     "pa_run", "pa_run_begin", "pa_run_advance", "pa_run_sync", "pa_run_read", "pa_run_load",
     "pa_run_read_free_energy",
     "pa_run_read_slots", "pa_run_finish", "pa_status_str", "pa_last_error",
@@ -37,6 +38,7 @@ EXPORTS = [
 ]
 PROBE_KINDS = ("xor", "bitop3", "mad64", "perm", "sad", "xad", "mulhi", "cmpsel", "mix")
 PA_ERR_BUSY, PA_ERR_CANCELLED, PA_ERR_TIMEOUT = -6, -7, -8
+BATCH_TEAM, BATCH_SEGMENTED = 0, 1
 
 
 class PAError(RuntimeError):
@@ -110,6 +112,12 @@ def lib() -> ctypes.CDLL:
     L.pa_autotune.restype = i32
     L.pa_ctx_set_graphs.argtypes = [vp, ctypes.c_int]
     L.pa_ctx_set_graphs.restype = i32
+    L.pa_ctx_set_batch_mode.argtypes = [vp, ctypes.c_int]
+    L.pa_ctx_set_batch_mode.restype = i32
+    L.pa_ctx_abort_batch.argtypes = [vp]
+    L.pa_ctx_batch_info.argtypes = [vp, vp, vp]
+    L.pa_ctx_batch_info.restype = i32
+    L.pa_ctx_abort_batch.restype = i32
     L.pa_run.argtypes = [vp, P(RunDesc), vp, u64, vp, P(Result)]
     L.pa_run_begin.argtypes = [vp, P(RunDesc), vp, u64, vp, P(vp)]
     L.pa_run_advance.argtypes = [vp, u32]
@@ -279,6 +287,20 @@ class Context:
 
     def set_graphs(self, on: bool):
         _check(lib().pa_ctx_set_graphs(self.handle, 1 if on else 0))
+
+    def set_batch_mode(self, mode: int):
+        """BATCH_SEGMENTED (default) or BATCH_TEAM for later pa_run_batch calls."""
+        _check(lib().pa_ctx_set_batch_mode(self.handle, int(mode)))
+
+    def batch_info(self):
+        """(runs finished in team launches, team launches) of the last batch."""
+        a, b = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().pa_ctx_batch_info(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
+    def abort_batch(self):
+        """Stop the pa_run_batch running on this context (from another thread)."""
+        _check(lib().pa_ctx_abort_batch(self.handle))
 
     def set_profiling(self, on: bool):
         _check(lib().pa_ctx_set_profiling(self.handle, 1 if on else 0))

@@ -167,6 +167,54 @@ hipError_t issue_probe(uint32_t kind, uint32_t blocks, uint32_t iters, uint32_t 
                        double *lane_instr_per_s, double *ms);
 uint32_t probe_threads();
 
+// Team kernel: small runs of one sweep class through all their steps in one
+// cooperative launch (see k_team).  Per run and step i (first step of the
+// launch i0 + 1): the resampling into i, the sweeps of i, the statistics of
+// i - 1 (statistics of step i0 were formed before the launch).
+struct TeamStep {
+    SweepArgs w;              // sweeps of step i (each workgroup gathers from its own LDS
+                              // ancestors and sweeps its own range of slots)
+    PostArgs p;               // statistics of step i-1 (used when stats != 0)
+    const int32_t *E_prev;    // [R_prev] energies of step i-1
+    uint32_t *anc_out;        // [R_new] ancestors of the new slots
+    uint32_t *counts_out;     // [R_prev] copy numbers
+    uint64_t R_prev, n_new;
+    const uint64_t *W;        // integer weights of step i, zero from D on
+    uint32_t D;
+    uint64_t w_const;         // nonzero: every weight equals it (dbeta = 0)
+    uint32_t ref_max;         // E_ref = largest energy (dbeta < 0), else the smallest
+    uint32_t resample;        // 0: resampling off (slot k keeps replica k)
+    uint32_t stats;           // statistics of step i-1 due in this launch
+    uint32_t step, key0, key1;
+};
+struct TeamRun {
+    uint32_t team0, team;     // first workgroup of the run's team, workgroups (>= 2)
+    uint32_t rec0, n_steps;   // its TeamStep records
+    uint32_t *barrier;        // the team's barrier counter (own 256 bytes, zero at launch)
+    uint32_t *claims;         // [n_steps] sweep blocks claimed per step (zero at launch)
+    PostArgs last;            // statistics of the last step, after the last sweeps
+    uint32_t last_stats;
+};
+struct TeamCtl {
+    uint32_t *abort;          // host-visible word: nonzero makes every barrier wait end
+    uint64_t timeout_ticks;   // bound of one barrier wait (100 MHz real-time counter)
+    uint32_t r_max;           // largest R_prev of the launch
+    uint32_t anc_bytes;       // LDS for the ancestors of every new slot (16-byte multiple)
+    uint32_t work_bytes;      // LDS after them: resampling, sweep groups or statistics
+    uint32_t sub_lds;         // LDS of one sweep group (16-byte multiple)
+};
+// Kernel of a class for the team launch (null if the class has none), and its
+// launch; team workgroups have 1024 threads.
+void *team_kernel(uint32_t cls);
+uint32_t team_threads();
+// Workgroups of the team kernel of a class that fit the device at once with
+// `lds` bytes of dynamic LDS each (0 if none).
+uint32_t team_capacity(uint32_t cls, size_t lds, int device);
+// Dynamic LDS of the statistics' histogram window (k_post).
+constexpr size_t POST_LDS_BYTES = 14336 * 4;
+hipError_t launch_team(uint32_t cls, const TeamRun *runs, uint32_t n_runs, const TeamStep *steps,
+                       const TeamCtl &ctl, uint32_t blocks, size_t lds, hipStream_t s);
+
 // Lanes-per-replica candidates for L (0 if L has no fixed-shape kernel).
 uint32_t lane_candidates(uint32_t L, uint32_t *out /*[2]*/);
 // Lanes per replica (log2) and waves per block for a lattice side L; `lanes`

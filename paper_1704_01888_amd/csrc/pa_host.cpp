@@ -13,6 +13,7 @@
 #include "pa_device.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -139,7 +140,8 @@ struct Plan {
     // workspace layout
     size_t off_pop[2], off_E, off_C, off_r, off_anc, off_counts, off_hist, off_Esum,
         off_count, off_lnQ, off_mbF, off_Eref, off_W, off_mhist, off_Mt, off_Mtsum,
-        off_fwe, off_fwm, off_bonds, off_cnt, off_pop_x, off_H, off_Hacc, off_digest, total;
+        off_fwe, off_fwm, off_bonds, off_cnt, off_pop_x, off_H, off_Hacc, off_digest, off_E2, off_Mt2, off_H2,
+        off_steps, steps_bytes, total;
     bool tiled = false;   // replicas beyond one workgroup's LDS: tiled half-sweeps in HBM
 };
 
@@ -262,24 +264,33 @@ pa_status build_plan(const pa_run_desc *d, Plan &p) {
     p.off_anc = o; o += align256(4 * p.R_cap);
     p.off_counts = o; o += align256(4 * p.R_cap);
     p.off_hist = o; o += align256((size_t)4 * p.nbins * (p.hist_all ? K : 1));
+    // the per-step results, one block (read back in one copy)
+    p.off_steps = o;
     p.off_Esum = o; o += align256(8 * (size_t)K);
     p.off_count = o; o += align256(8 * (size_t)K);
     p.off_lnQ = o; o += align256(8 * (size_t)K);
     p.off_mbF = o; o += align256(8 * (size_t)K);
+    p.off_Mtsum = o; o += p.mag ? align256(8 * (size_t)K) : 0;
+    p.off_fwe = o; o += p.widths ? align256(64 * (size_t)K) : 0;
+    p.off_fwm = o; o += (p.widths && p.mag) ? align256(64 * (size_t)K) : 0;
+    p.off_digest = o; o += p.digest ? align256(8 * (size_t)K) : 0;
+    p.steps_bytes = o - p.off_steps;
     p.off_Eref = o; o += align256(4 * (size_t)K);
     p.off_W = o; o += align256((size_t)8 * p.W.size());
     p.off_mhist = o; o += p.mag ? align256((size_t)4 * (p.N + 1) * (p.hist_all ? K : 1)) : 0;
     p.off_Mt = o; o += p.mag ? align256(4 * p.R_cap) : 0;
-    p.off_Mtsum = o; o += p.mag ? align256(8 * (size_t)K) : 0;
-    p.off_fwe = o; o += p.widths ? align256(64 * (size_t)K) : 0;
-    p.off_fwm = o; o += (p.widths && p.mag) ? align256(64 * (size_t)K) : 0;
     p.tiled = pa::tiled_path(d->L);
     p.off_bonds = o; o += p.tiled ? align256(4 * p.R_cap) : 0;
     p.off_cnt = o; o += (p.tiled && p.mag) ? align256((size_t)4 * p.R_cap * d->q) : 0;
     p.off_pop_x = o; o += p.tiled ? popb : 0;   // third population buffer of the tiled sweeps
     p.off_H = o; o += p.digest ? align256(8 * p.R_cap) : 0;
     p.off_Hacc = o; o += (p.digest && p.tiled) ? align256(8 * p.R_cap) : 0;
-    p.off_digest = o; o += p.digest ? align256(8 * (size_t)K) : 0;
+    // second energy, M~ and digest-term buffers: the team launch alternates
+    // them by step (the statistics of one step and the sweeps of the next run
+    // at the same time)
+    p.off_E2 = o; o += p.tiled ? 0 : align256(4 * p.R_cap);
+    p.off_Mt2 = o; o += (!p.tiled && p.mag) ? align256(4 * p.R_cap) : 0;
+    p.off_H2 = o; o += (!p.tiled && p.digest) ? align256(8 * p.R_cap) : 0;
     p.total = o;
     return PA_OK;
 }
@@ -303,10 +314,35 @@ struct pa_ctx {
     std::shared_ptr<Server> server;
     std::mutex serve_mu;
     int graphs;          // batched runs replay a captured HIP graph
+    int batch_mode;      // PA_BATCH_SEGMENTED (default) or PA_BATCH_TEAM
+    uint32_t *team_abort;   // pinned host word read by the team launches' barrier waits
+    std::atomic<int> abort_requested;
+    uint32_t team_runs, team_launches;   // of the last pa_run_batch
+    // pa_run_batch calls on a context take turns; their descriptor records
+    // go up from pinned host memory (asynchronous copies)
+    std::mutex batch_mu;
+    uint8_t *staging;
+    size_t staging_bytes;
     hipStream_t graph_stream;
     hipEvent_t ev_in, ev_out;
     std::deque<GraphCache> graph_cache;
 };
+
+// Pinned host memory of at least `bytes` for the batch's uploads (the
+// caller holds batch_mu, and the previous batch has synchronised its stream).
+static uint8_t *ctx_staging(pa_ctx *c, size_t bytes) {
+    if (bytes > c->staging_bytes) {
+        if (c->staging) (void)hipHostFree(c->staging);
+        c->staging = nullptr;
+        c->staging_bytes = 0;
+        void *h = nullptr;
+        const size_t want = std::max(bytes, size_t(1) << 20);
+        if (hipHostMalloc(&h, want, hipHostMallocDefault) != hipSuccess || !h) return nullptr;
+        c->staging = static_cast<uint8_t *>(h);
+        c->staging_bytes = want;
+    }
+    return c->staging;
+}
 
 static uint32_t ctx_lanes(const pa_ctx *c, uint32_t L) {
     const int i = pa::lane_choice_index(L);
@@ -665,12 +701,27 @@ pa_status pa_ctx_create(int device, pa_ctx **out) {
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess || device < 0 || device >= n)
         return fail(PA_ERR_DEVICE, "no such HIP device");
+    // the abort word of the team launches: pinned, coherent host memory the
+    // kernels poll while they wait at a barrier
+    void *abort_word = nullptr;
+    if (hipHostMalloc(&abort_word, 256, hipHostMallocCoherent) != hipSuccess || !abort_word)
+        return fail(PA_ERR_DEVICE, "cannot allocate the abort word");
+    *static_cast<volatile uint32_t *>(abort_word) = 0u;
     pa_ctx *c = new (std::nothrow) pa_ctx;
-    if (!c) return fail(PA_ERR_NOMEM, "out of host memory");
+    if (!c) {
+        (void)hipHostFree(abort_word);
+        return fail(PA_ERR_NOMEM, "out of host memory");
+    }
     c->device = device;
     c->profiling = 0;
     for (auto &x : c->lanes) x = 0;
     c->graphs = 0;
+    c->batch_mode = PA_BATCH_SEGMENTED;
+    c->team_abort = static_cast<uint32_t *>(abort_word);
+    c->abort_requested = 0;
+    c->team_runs = c->team_launches = 0;
+    c->staging = nullptr;
+    c->staging_bytes = 0;
     c->graph_stream = nullptr;
     c->ev_in = c->ev_out = nullptr;
     *out = c;
@@ -689,6 +740,8 @@ void pa_ctx_destroy(pa_ctx *ctx) {
     if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->team_abort) (void)hipHostFree(ctx->team_abort);
+    if (ctx->staging) (void)hipHostFree(ctx->staging);
     delete ctx;
 }
 
@@ -702,6 +755,26 @@ pa_status pa_ctx_set_graphs(pa_ctx *ctx, int enable) {
             return fail(PA_ERR_DEVICE, "cannot create the graph stream");
     }
     ctx->graphs = enable ? 1 : 0;
+    return PA_OK;
+}
+
+pa_status pa_ctx_set_batch_mode(pa_ctx *ctx, int mode) {
+    if (!ctx || (mode != PA_BATCH_TEAM && mode != PA_BATCH_SEGMENTED)) return fail(PA_ERR_INVALID, "bad batch mode");
+    ctx->batch_mode = mode;
+    return PA_OK;
+}
+
+pa_status pa_ctx_batch_info(pa_ctx *ctx, uint32_t *team_runs, uint32_t *team_launches) {
+    if (!ctx) return fail(PA_ERR_INVALID, "null context");
+    if (team_runs) *team_runs = ctx->team_runs;
+    if (team_launches) *team_launches = ctx->team_launches;
+    return PA_OK;
+}
+
+pa_status pa_ctx_abort_batch(pa_ctx *ctx) {
+    if (!ctx) return fail(PA_ERR_INVALID, "null context");
+    ctx->abort_requested = 1;
+    __atomic_store_n(ctx->team_abort, 1u, __ATOMIC_SEQ_CST);
     return PA_OK;
 }
 
@@ -807,8 +880,11 @@ namespace {
 
 // pa_run_begin, optionally without the initial population (a run that loads
 // a population right after, from a checkpoint).
+// With `wait`, returns once the uploads and launches are done; otherwise the
+// caller synchronises the stream before freeing the run (its plan holds the
+// uploaded host tables).
 pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes, void *stream,
-                    bool initial, pa_run_state **out) {
+                    bool initial, pa_run_state **out, bool wait = true) {
     if (!ctx || !out) return fail(PA_ERR_INVALID, "null context or output");
     pa_run_state *r = new (std::nothrow) pa_run_state;
     if (!r) return fail(PA_ERR_NOMEM, "out of host memory");
@@ -842,10 +918,17 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
 
     // Tables and initial state.
     hipStream_t s = r->stream;
+    // on an error after the first upload: let the stream drain before the
+    // run (and the host tables the copies read) goes
+    auto drop = [&](pa_status e) {
+        (void)hipStreamSynchronize(s);
+        delete r;
+        return e;
+    };
     if (!p.W.empty() &&
         (st = hip_check(r, hipMemcpyAsync(r->ws + p.off_W, p.W.data(), 8 * p.W.size(),
                                           hipMemcpyHostToDevice, s), "upload W"))) {
-        delete r; return st;
+        return drop(st);
     }
     const size_t hist_words = (size_t)p.nbins * (p.hist_all ? p.desc.K : 1);
     const size_t mhist_words = p.mag ? (size_t)(p.N + 1) * (p.hist_all ? p.desc.K : 1) : 0;
@@ -860,7 +943,7 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
          (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_cnt), p.R_cap * p.desc.q, 0u, s), "fill"))) ||
         (p.tiled && p.digest &&
          (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_Hacc), 2 * p.R_cap, 0u, s), "fill")))) {
-        delete r; return st;
+        return drop(st);
     }
     // ln Z at beta_0: N ln q (Z = q^N at beta = 0, Sec. 6) or, for ground
     // states, ln q + 2N beta_0 (eq. (7)-(8), E_0 = -2N).
@@ -868,7 +951,7 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
                   ? std::log((double)p.desc.q) + 2.0 * (double)p.N * p.beta[0]
                   : (double)p.N * std::log((double)p.desc.q);
     if ((st = hip_check(r, hipMemcpyAsync(r->ws + p.off_mbF, &r->mbF0, 8, hipMemcpyHostToDevice, s), "upload"))) {
-        delete r; return st;
+        return drop(st);
     }
     const uint32_t mode = p.desc.init == PA_INIT_GROUND ? pa::SWEEP_INIT_GROUND : pa::SWEEP_INIT_RANDOM;
     pa::SweepArgs a = sweep_args(r, 0, mode, nullptr, nullptr, r->at<uint8_t>(p.off_pop[0]), 0);
@@ -881,10 +964,10 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
     if (initial && ((st = timed_launch(r, PA_KERNEL_INIT, "init kernel", init)) ||
                     (st = launch_post_for(r, 0)))) {
         release_events(r, nullptr, nullptr);
-        delete r; return st;
+        return drop(st);
     }
-    // The uploads read host memory owned by the run; make sure they are done.
-    if ((st = hip_check(r, hipStreamSynchronize(s), "sync"))) { delete r; return st; }
+    // The uploads read host memory owned by the run.
+    if (wait && (st = hip_check(r, hipStreamSynchronize(s), "sync"))) { delete r; return st; }
     *out = r;
     return PA_OK;
 }
@@ -1014,8 +1097,12 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
     const Plan &p = r->plan;
     const uint32_t K = p.desc.K;
     if (!st && out) {
+        // the per-step block in one copy
+        std::vector<uint8_t> blk(p.steps_bytes);
+        st = hip_check(r, hipMemcpy(blk.data(), r->ws + p.off_steps, p.steps_bytes, hipMemcpyDeviceToHost), "read");
+        auto field = [&](size_t off) { return blk.data() + (off - p.off_steps); };
         std::vector<uint64_t> count(K);
-        if (!st) st = hip_check(r, hipMemcpy(count.data(), r->ws + p.off_count, 8 * (size_t)K, hipMemcpyDeviceToHost), "read");
+        if (!st) std::memcpy(count.data(), field(p.off_count), 8 * (size_t)K);
         for (uint32_t i = r->first_step; !st && i <= r->step; ++i)
             if (count[i] != (i == r->first_step ? r->R_first : p.R_sched[i]))
                 st = fail(PA_ERR_DEVICE, "population histogram does not add up to R_i");
@@ -1023,12 +1110,14 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
             for (uint32_t i = 0; i < K; ++i) out->R_i[i] = p.R_sched[i];
             out->R_i[r->first_step] = r->R_first;
         }
+        if (!st) {
+            if (out->lnQ) std::memcpy(out->lnQ, field(p.off_lnQ), 8 * (size_t)K);
+            if (out->minus_beta_F) std::memcpy(out->minus_beta_F, field(p.off_mbF), 8 * (size_t)K);
+            if (p.digest && out->digest) std::memcpy(out->digest, field(p.off_digest), 8 * (size_t)K);
+        }
         struct { void *dst; size_t off, bytes; } cp[] = {
-            {out->lnQ, p.off_lnQ, 8 * (size_t)K},
-            {out->minus_beta_F, p.off_mbF, 8 * (size_t)K},
             {p.hist_all ? out->hist : nullptr, p.off_hist, 4 * (size_t)K * p.nbins},
             {(p.mag && p.hist_all) ? out->mhist : nullptr, p.off_mhist, 4 * (size_t)K * (p.N + 1)},
-            {p.digest ? out->digest : nullptr, p.off_digest, 8 * (size_t)K},
         };
         for (auto &c : cp) {
             if (st || !c.dst) continue;
@@ -1038,13 +1127,12 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
         // from the exact integer sums and the integer parts of the widths.
         std::vector<int64_t> esum(K), mtsum(p.mag ? K : 0);
         std::vector<uint64_t> fwe(p.widths ? 8 * (size_t)K : 0), fwm(p.widths && p.mag ? 8 * (size_t)K : 0);
-        if (!st) st = hip_check(r, hipMemcpy(esum.data(), r->ws + p.off_Esum, 8 * (size_t)K, hipMemcpyDeviceToHost), "read");
-        if (!st && p.mag)
-            st = hip_check(r, hipMemcpy(mtsum.data(), r->ws + p.off_Mtsum, 8 * (size_t)K, hipMemcpyDeviceToHost), "read");
-        if (!st && p.widths)
-            st = hip_check(r, hipMemcpy(fwe.data(), r->ws + p.off_fwe, 8 * fwe.size(), hipMemcpyDeviceToHost), "read");
-        if (!st && p.widths && p.mag)
-            st = hip_check(r, hipMemcpy(fwm.data(), r->ws + p.off_fwm, 8 * fwm.size(), hipMemcpyDeviceToHost), "read");
+        if (!st) {
+            std::memcpy(esum.data(), field(p.off_Esum), 8 * (size_t)K);
+            if (p.mag) std::memcpy(mtsum.data(), field(p.off_Mtsum), 8 * (size_t)K);
+            if (p.widths) std::memcpy(fwe.data(), field(p.off_fwe), 8 * fwe.size());
+            if (p.widths && p.mag) std::memcpy(fwm.data(), field(p.off_fwm), 8 * fwm.size());
+        }
         if (!st) {
             const double N = (double)p.N, q = (double)p.desc.q;
             for (uint32_t i = 0; i < K; ++i) {
@@ -1066,7 +1154,9 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
         if (!st && out->lnQ) out->lnQ[0] = 0.0;
         if (!st && (out->kernel_ms || out->kernel_launches))
             release_events(r, out->kernel_ms, out->kernel_launches);
-        if (!st && (p.desc.outputs & PA_OUT_FINAL)) {
+        // the final population, only for a run that reached its last temperature
+        // (the buffers are sized for R_{K-1})
+        if (!st && (p.desc.outputs & PA_OUT_FINAL) && r->step + 1 == K) {
             if (out->final_spins)
                 st = hip_check(r, hipMemcpy(out->final_spins, r->ws + p.off_pop[r->cur], (size_t)r->R_cur * p.N, hipMemcpyDeviceToHost), "read");
             if (!st && out->final_E)
@@ -1426,9 +1516,21 @@ pa_status launch_step(const StepLaunch &L, const uint8_t *dtab, hipStream_t s) {
 struct BatchLayout {
     std::vector<Plan> plans;
     std::vector<size_t> run_off;
-    size_t desc_off = 0, desc_bytes = 0, total = 0;
+    size_t desc_off = 0, desc_bytes = 0, team_off = 0, team_bytes = 0, total = 0;
     uint32_t max_K = 0;
 };
+
+// Device bytes of the team launches' records for runs with these plans: one
+// TeamStep per step after the first, one TeamRun, a 256-byte barrier counter
+// and the per-step claim counters per run.
+size_t team_record_bytes(const std::vector<Plan> &plans) {
+    size_t steps = 0, counters = 0;
+    for (const Plan &p : plans) {
+        steps += p.desc.K;
+        counters += 256 + align256(4 * (size_t)p.desc.K);
+    }
+    return align256(steps * sizeof(pa::TeamStep)) + align256(plans.size() * sizeof(pa::TeamRun)) + counters;
+}
 
 pa_status batch_layout(const pa_run_desc *descs, uint32_t n, BatchLayout &b) {
     if (!descs || n == 0) return fail(PA_ERR_INVALID, "empty batch");
@@ -1444,7 +1546,227 @@ pa_status batch_layout(const pa_run_desc *descs, uint32_t n, BatchLayout &b) {
     }
     b.desc_off = o;
     b.desc_bytes = step_desc_bytes(n) * (b.max_K > 1 ? b.max_K - 1 : 1);
-    b.total = o + b.desc_bytes;
+    b.team_off = align256(o + b.desc_bytes);
+    b.team_bytes = team_record_bytes(b.plans);
+    b.total = b.team_off + b.team_bytes;
+    return PA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Team launches (k_team): runs of one sweep class with small populations go
+// through all their remaining steps in one cooperative launch; each run owns a
+// team of workgroups (one for the statistics, the rest for resampling and
+// sweeps) that meet at one barrier per step.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kTeamRMax = 8192;              // largest population in a team launch
+constexpr uint64_t kTeamTimeoutTicks = 1000000000ull;   // 10 s of the 100 MHz counter
+
+// The class of a run's sweeps if every step of it can go to a team launch,
+// else 0 (tiled, byte-kernel or 64-bit-threshold steps, a population above
+// kTeamRMax, or no team kernel for the class).
+uint32_t team_class(const pa_run_state *r) {
+    const Plan &p = r->plan;
+    if (p.tiled || p.R_cap > kTeamRMax || r->step + 1 >= p.desc.K) return 0;
+    for (uint32_t i = r->step + 1; i < p.desc.K; ++i)
+        if (p.T[(size_t)i * 4 + 3] == 0) return 0;
+    const uint32_t cls = pa::sweep_class(p.desc.L, p.desc.q, false, r->G);
+    return pa::team_kernel(cls) ? cls : 0u;
+}
+
+// The buffers of step i in a team launch ending at step K-1: the last step
+// writes the run's main energy, M~ and digest-term buffers.
+struct TeamBufs { int32_t *E; uint32_t *Mt; uint64_t *H; };
+TeamBufs team_bufs(pa_run_state *r, uint32_t i) {
+    const Plan &p = r->plan;
+    const bool alt = ((p.desc.K - 1 - i) & 1u) != 0;
+    return {r->at<int32_t>(alt ? p.off_E2 : p.off_E),
+            p.mag ? r->at<uint32_t>(alt ? p.off_Mt2 : p.off_Mt) : nullptr,
+            p.digest ? r->at<uint64_t>(alt ? p.off_H2 : p.off_H) : nullptr};
+}
+
+// Statistics of step i (R_cur replicas) reading the team buffers of step i.
+pa::PostArgs team_post(pa_run_state *r, uint32_t i) {
+    pa::PostArgs a = post_args(r, i);
+    const TeamBufs b = team_bufs(r, i);
+    a.E = b.E;
+    a.Mt = b.Mt;
+    a.H = b.H;
+    a.do_weights = 0;
+    return a;
+}
+
+// The records of run r's remaining steps; advances its host state to the
+// last step.
+void team_records(pa_run_state *r, std::vector<pa::TeamStep> &recs, pa::TeamRun &tr) {
+    const Plan &p = r->plan;
+    const uint32_t K = p.desc.K, i0 = r->step;
+    tr.rec0 = (uint32_t)recs.size();
+    tr.n_steps = K - 1 - i0;
+    for (uint32_t i = i0 + 1; i < K; ++i) {
+        pa::TeamStep t{};
+        const uint64_t R_prev = r->R_cur, R_new = p.R_sched[i];
+        t.stats = i - 1 > i0 ? 1u : 0u;
+        if (t.stats) t.p = team_post(r, i - 1);         // r->R_cur is R_{i-1} here
+        const TeamBufs prev = team_bufs(r, i - 1), cur = team_bufs(r, i);
+        t.E_prev = prev.E;
+        t.R_prev = R_prev;
+        t.n_new = R_new;
+        t.resample = p.desc.resample != PA_RESAMPLE_NONE ? 1u : 0u;
+        const uint32_t tab = p.table_of_step[i];
+        t.W = r->at<uint64_t>(p.off_W) + p.W_off[tab];
+        t.D = p.D[tab];
+        t.w_const = p.abs_dbeta[tab] == 0.0 ? (1ull << p.Kb) : 0ull;
+        t.ref_max = p.dbeta[i] < 0.0 ? 1u : 0u;
+        t.anc_out = r->at<uint32_t>(p.off_anc);
+        t.counts_out = r->at<uint32_t>(p.off_counts);
+        t.step = i;
+        t.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
+        t.key1 = (uint32_t)(p.desc.seed >> 32);
+        r->R_prev = R_prev;
+        r->R_cur = R_new;
+        t.w = sweep_args(r, i, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[r->cur]), nullptr,
+                         r->at<uint8_t>(p.off_pop[1 - r->cur]), p.desc.theta);
+        t.w.E_out = cur.E;
+        t.w.Mt_out = cur.Mt;
+        t.w.H_out = cur.H;
+        recs.push_back(t);
+        r->cur = 1 - r->cur;
+        r->step = i;
+    }
+    tr.last = team_post(r, K - 1);
+    tr.last_stats = 1;
+}
+
+pa_status run_team_launch(pa_ctx *ctx, uint32_t cls, std::vector<pa_run_state *> &group, uint8_t *dtab,
+                          size_t dtab_bytes, hipStream_t s) {
+    const uint32_t n = (uint32_t)group.size();
+    pa_status st;
+    // shape of the class: sweep groups of 64 * waves_per_block threads
+    const pa_run_state *r0 = group[0];
+    const uint32_t BS = 64u * r0->wpb, SUB = pa::team_threads() / BS;
+    const uint32_t rpb = (uint32_t)pa::replicas_per_block(r0->G, r0->wpb);
+    size_t sub_lds = 0;
+    uint64_t r_max = 1;
+    uint32_t n_max = 1;
+    std::vector<uint32_t> useful(n), sweepers(n);
+    std::vector<double> cost(n);
+    for (uint32_t k = 0; k < n; ++k) {
+        const pa_run_state *r = group[k];
+        const Plan &p = r->plan;
+        sub_lds = std::max(sub_lds, (pa::sweep_lds_bytes(p.N, r->G, r->wpb, p.mag ? p.desc.q : 0u) + 15) & ~size_t(15));
+        r_max = std::max(r_max, p.R_cap);
+        n_max = std::max(n_max, p.N);
+        // sweep workgroups beyond one claim of SUB blocks each would only
+        // repeat the resampling
+        const uint64_t blocks = (p.R_cap + rpb - 1) / rpb;
+        useful[k] = (uint32_t)((blocks + SUB - 1) / SUB);
+        // site updates (and the gather) of the run's remaining steps
+        cost[k] = (double)p.N * (p.desc.theta + 1.0) * (double)p.R_cap * (double)(p.desc.K - 1 - r->step);
+    }
+    // LDS: the ancestors of every new slot, then a work area for the
+    // resampling's counts and weights, the sweep groups, or the statistics'
+    // energy and M~ histograms, in turn
+    const size_t anc_bytes = (4 * r_max + 15) & ~uint64_t(15);
+    const size_t work = (std::max({anc_bytes + 8 * r_max, SUB * sub_lds, 4 * (2 * (size_t)n_max + 1)}) + 15) & ~size_t(15);
+    const size_t lds = anc_bytes + work;
+    if (lds > pa::max_lds_per_block(ctx->device)) return fail(PA_ERR_UNSUPPORTED, "team launch exceeds the LDS");
+    const uint32_t cap = pa::team_capacity(cls, lds, ctx->device);
+    if (cap < 2 * n) return fail(PA_ERR_UNSUPPORTED, "team launch does not fit the device");
+    // teams: one statistics workgroup each, and the resident workgroups left
+    // shared out as sweep workgroups in proportion to the runs' work, none
+    // beyond its useful number and at least one
+    uint32_t avail = cap - n;
+    std::vector<bool> fixed(n, false);
+    for (bool again = true; again;) {
+        again = false;
+        double total = 0;
+        for (uint32_t k = 0; k < n; ++k)
+            if (!fixed[k]) total += cost[k];
+        for (uint32_t k = 0; k < n && !again; ++k)
+            if (!fixed[k] && (total <= 0 || (double)avail * cost[k] / total >= useful[k])) {
+                sweepers[k] = useful[k];
+                avail -= std::min(avail, useful[k]);
+                fixed[k] = again = true;
+            }
+        if (!again)
+            for (uint32_t k = 0; k < n; ++k)
+                if (!fixed[k]) sweepers[k] = std::max<uint32_t>(1, (uint32_t)((double)avail * cost[k] / total));
+    }
+    uint32_t team_total = n;
+    for (uint32_t k = 0; k < n; ++k) team_total += sweepers[k];
+    while (team_total > cap) {   // the floor of one each may overshoot: trim the largest
+        uint32_t big = 0;
+        for (uint32_t k = 1; k < n; ++k)
+            if (sweepers[k] > sweepers[big]) big = k;
+        if (sweepers[big] <= 1) return fail(PA_ERR_UNSUPPORTED, "team launch does not fit the device");
+        --sweepers[big];
+        --team_total;
+    }
+    // records
+    std::vector<pa::TeamStep> recs;
+    std::vector<pa::TeamRun> truns(n);
+    uint32_t team0 = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+        pa_run_state *r = group[k];
+        const Plan &p = r->plan;
+        // the population of the first step must sit in the buffers that step
+        // reads (step i0 alternates with the last step's parity)
+        const TeamBufs b0 = team_bufs(r, r->step);
+        if (b0.E != r->at<int32_t>(p.off_E)) {
+            if ((st = hip_check(r, hipMemcpyAsync(b0.E, r->at<int32_t>(p.off_E), 4 * r->R_cur, hipMemcpyDeviceToDevice, s),
+                                "copy energies")) ||
+                (b0.Mt && (st = hip_check(r, hipMemcpyAsync(b0.Mt, r->at<uint32_t>(p.off_Mt), 4 * r->R_cur,
+                                                             hipMemcpyDeviceToDevice, s), "copy M~"))) ||
+                (b0.H && (st = hip_check(r, hipMemcpyAsync(b0.H, r->at<uint64_t>(p.off_H), 8 * r->R_cur,
+                                                            hipMemcpyDeviceToDevice, s), "copy digest terms"))))
+                return st;
+        }
+        truns[k].team0 = team0;
+        truns[k].team = 1 + sweepers[k];
+        team0 += truns[k].team;
+        team_records(r, recs, truns[k]);
+    }
+    const size_t steps_bytes = align256(recs.size() * sizeof(pa::TeamStep));
+    const size_t runs_bytes = align256(n * sizeof(pa::TeamRun));
+    // per run: a 256-byte barrier counter, then its claim counters
+    size_t counter_bytes = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+        truns[k].barrier = reinterpret_cast<uint32_t *>(dtab + steps_bytes + runs_bytes + counter_bytes);
+        truns[k].claims = truns[k].barrier + 64;
+        counter_bytes += 256 + align256(4 * (size_t)truns[k].n_steps);
+    }
+    if (steps_bytes + runs_bytes + counter_bytes > dtab_bytes)
+        return fail(PA_ERR_DEVICE, "team record table overflow");
+    uint32_t *barriers = reinterpret_cast<uint32_t *>(dtab + steps_bytes + runs_bytes);
+    uint8_t *stage = ctx_staging(ctx, steps_bytes + runs_bytes);
+    if (!stage) return fail(PA_ERR_DEVICE, "cannot allocate pinned staging memory");
+    std::memcpy(stage, recs.data(), recs.size() * sizeof(pa::TeamStep));
+    std::memcpy(stage + steps_bytes, truns.data(), n * sizeof(pa::TeamRun));
+    if ((st = hip_check(nullptr, hipMemcpyAsync(dtab, stage, steps_bytes + runs_bytes, hipMemcpyHostToDevice, s),
+                        "upload team records")) ||
+        (st = hip_check(nullptr, pa::launch_fill_u32(barriers, counter_bytes / 4, 0u, s), "clear counters")))
+        return st;
+    pa::TeamCtl ctl{};
+    ctl.abort = ctx->team_abort;
+    ctl.timeout_ticks = kTeamTimeoutTicks;
+    ctl.r_max = (uint32_t)r_max;
+    ctl.anc_bytes = (uint32_t)anc_bytes;
+    ctl.work_bytes = (uint32_t)work;
+    ctl.sub_lds = (uint32_t)sub_lds;
+    // the uploads above read host memory; the abort word is reset once the
+    // stream has drained
+    if ((st = hip_check(nullptr, hipStreamSynchronize(s), "sync"))) return st;
+    if (ctx->abort_requested) return fail(PA_ERR_CANCELLED, "batch aborted");
+    __atomic_store_n(ctx->team_abort, 0u, __ATOMIC_SEQ_CST);
+    if (ctx->abort_requested) __atomic_store_n(ctx->team_abort, 1u, __ATOMIC_SEQ_CST);
+    if ((st = hip_check(nullptr, pa::launch_team(cls, reinterpret_cast<const pa::TeamRun *>(dtab + steps_bytes), n,
+                                                 reinterpret_cast<const pa::TeamStep *>(dtab), ctl, team0, lds, s),
+                        "team launch")) ||
+        (st = hip_check(nullptr, hipStreamSynchronize(s), "sync")))
+        return st;
+    const uint32_t ab = __atomic_load_n(ctx->team_abort, __ATOMIC_SEQ_CST);
+    if (ab == 1u) return fail(PA_ERR_CANCELLED, "batch aborted");
+    if (ab) return fail(PA_ERR_DEVICE, "a team barrier wait timed out");
     return PA_OK;
 }
 
@@ -1462,6 +1784,7 @@ extern "C" pa_status pa_plan_batch(const pa_run_desc *descs, uint32_t n, uint64_
 extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_t n, void *d_ws,
                                   uint64_t ws_bytes, void *stream, pa_result *outs) {
     if (!ctx) return fail(PA_ERR_INVALID, "null context");
+    std::lock_guard<std::mutex> lk(ctx->batch_mu);
     BatchLayout b;
     pa_status st = batch_layout(descs, n, b);
     if (st) return st;
@@ -1476,25 +1799,53 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
             if (r) pa_run_finish(r, nullptr);
         return fail(code, msg);
     };
+    ctx->abort_requested = 0;
+    ctx->team_runs = ctx->team_launches = 0;
     for (uint32_t r = 0; r < n; ++r) {
-        st = pa_run_begin(ctx, &descs[r], ws + b.run_off[r], align256(b.plans[r].total), stream, &runs[r]);
+        st = begin_run(ctx, &descs[r], ws + b.run_off[r], align256(b.plans[r].total), stream, true, &runs[r],
+                       /*wait=*/false);
         if (st) return cleanup(fail(st, "run " + std::to_string(r) + ": " + g_last_error));
     }
-    // Every global step's records, built up front (all sizes are in the plans).
+    // Team launches first, one per sweep class, for the runs that qualify;
+    // they finish those runs.
+    std::vector<bool> finished(n, false);
+    if (ctx->batch_mode == PA_BATCH_TEAM && !ctx->graphs) {
+        std::map<uint32_t, std::vector<uint32_t>> by_class;
+        for (uint32_t r = 0; r < n; ++r)
+            if (const uint32_t cls = team_class(runs[r])) by_class[cls].push_back(r);
+        for (auto &kv : by_class) {
+            std::vector<pa_run_state *> group;
+            for (uint32_t r : kv.second) group.push_back(runs[r]);
+            st = run_team_launch(ctx, kv.first, group, ws + b.team_off, b.team_bytes, s);
+            if (st == PA_ERR_UNSUPPORTED) continue;      // too large for one launch: segmented below
+            if (st) return cleanup(st);
+            for (uint32_t r : kv.second) finished[r] = true;
+            ctx->team_runs += (uint32_t)kv.second.size();
+            ++ctx->team_launches;
+        }
+    }
+    // Every global step's records for the other runs, built up front (all
+    // sizes are in the plans).
     std::vector<uint8_t> blob;
     std::vector<StepLaunch> steps;
     size_t cursor = 0;
     for (uint32_t g = 1; g < b.max_K; ++g) {
         std::vector<pa_run_state *> active;
-        for (auto *r : runs)
-            if (g < r->plan.desc.K) active.push_back(r);
+        for (uint32_t r = 0; r < n; ++r)
+            if (!finished[r] && g < runs[r]->plan.desc.K) active.push_back(runs[r]);
+        if (active.empty()) break;
         steps.push_back(build_step(active, blob, cursor));
     }
     if (cursor > b.desc_bytes) return cleanup(fail(PA_ERR_DEVICE, "descriptor table overflow"));
     uint8_t *dtab = ws + b.desc_off;
-    if (cursor && (st = hip_check(nullptr, hipMemcpyAsync(dtab, blob.data(), cursor, hipMemcpyHostToDevice, s),
-                                  "upload descriptors")))
-        return cleanup(st);
+    if (cursor) {
+        uint8_t *stage = ctx_staging(ctx, cursor);
+        if (!stage) return cleanup(fail(PA_ERR_DEVICE, "cannot allocate pinned staging memory"));
+        std::memcpy(stage, blob.data(), cursor);
+        if ((st = hip_check(nullptr, hipMemcpyAsync(dtab, stage, cursor, hipMemcpyHostToDevice, s),
+                            "upload descriptors")))
+            return cleanup(st);
+    }
     if (ctx->graphs) {
         // Replay (capturing first if needed) the step sequence as one graph on
         // the context's stream, ordered after everything on the caller's stream.
@@ -1532,8 +1883,10 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
             (st = hip_check(nullptr, hipStreamWaitEvent(s, ctx->ev_out, 0), "wait")))
             return cleanup(st);
     } else {
-        for (const StepLaunch &L : steps)
+        for (const StepLaunch &L : steps) {
+            if (ctx->abort_requested) return cleanup(fail(PA_ERR_CANCELLED, "batch aborted"));
             if ((st = launch_step(L, dtab, s))) return cleanup(st);
+        }
     }
     if ((st = hip_check(nullptr, hipStreamSynchronize(s), "sync"))) return cleanup(st);
     pa_status first = PA_OK;

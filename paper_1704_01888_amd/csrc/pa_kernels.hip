@@ -160,15 +160,16 @@ __host__ __device__ inline uint32_t tiled_lds_end(uint32_t rows, uint32_t halves
 }
 
 template <bool T64>
-__device__ __forceinline__ void load_thresholds(uint8_t *smem, uint32_t tab, const uint64_t *T) {
+__device__ __forceinline__ void load_thresholds(uint8_t *smem, uint32_t tab, const uint64_t *T, uint32_t tid,
+                                                uint32_t nthreads) {
     if (T64) {
-        if (threadIdx.x < 9) {
-            const int dE = (int)threadIdx.x - 4;
-            reinterpret_cast<uint64_t *>(smem)[threadIdx.x] = dE <= 0 ? (1ull << 32) : T[dE - 1];
+        if (tid < 9) {
+            const int dE = (int)tid - 4;
+            reinterpret_cast<uint64_t *>(smem)[tid] = dE <= 0 ? (1ull << 32) : T[dE - 1];
         }
         return;
     }
-    for (uint32_t t = threadIdx.x; t < 81u; t += blockDim.x) {
+    for (uint32_t t = tid; t < 81u; t += nthreads) {
         const uint32_t i0 = t % 9u, i1 = t / 9u;
         const uint32_t a = i0 <= 4u ? 0xFFFFFFFFu : (uint32_t)(T[i0 - 5u] - 1u);
         const uint32_t b = i1 <= 4u ? 0xFFFFFFFFu : (uint32_t)(T[i1 - 5u] - 1u);
@@ -502,10 +503,16 @@ __device__ __forceinline__ uint32_t wave_total(uint32_t v) {
 }
 
 // One workgroup `block` of the sweep launch of one run (a): gather or create
-// its replicas in LDS, theta sweeps, energies (and M~), store.
-template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64>
-__device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
-    extern __shared__ __align__(16) uint8_t smem[];
+// its replicas in LDS, theta sweeps, energies (and M~), store.  The workgroup
+// is the nthreads threads tid = 0 .. nthreads-1 with the LDS at smem: a whole
+// workgroup of k_sweep, or, in the persistent batched kernel, one of several
+// such groups of waves that share a larger workgroup (PERSIST: every group
+// runs the whole body, idle ones without storing, so that all groups meet the
+// same workgroup barriers).
+template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64, bool PERSIST = false>
+__device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block, uint8_t *smem, uint32_t tid,
+                                           uint32_t nthreads, const uint32_t *anc, uint32_t anc_first,
+                                           uint32_t R_new) {
     // Lanes per replica G: a divisor of 64 (one or several replicas per wave),
     // a multiple of 64 (one replica per block of G/64 waves), or neither
     // (replicas span wave boundaries, several per block: "spanning").  Every
@@ -513,35 +520,36 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
     const uint32_t G = GT ? GT : a.G;
     const bool multiwave = G > 64 && G % 64u == 0;               // one replica per block
     const bool span = 64u % G != 0 && !multiwave;
-    if (threadIdx.x == 32) reinterpret_cast<uint32_t *>(smem)[24] = 0u;   // energy sum (multi-wave)
-    if (threadIdx.x == 33) reinterpret_cast<uint64_t *>(smem)[13] = 0ull; // digest sum (multi-wave)
+    if (tid == 32) reinterpret_cast<uint32_t *>(smem)[24] = 0u;   // energy sum (multi-wave)
+    if (tid == 33) reinterpret_cast<uint64_t *>(smem)[13] = 0ull; // digest sum (multi-wave)
     if (a.Mt_out && multiwave) {   // per-state counters of a multi-wave replica, after its rows
         uint32_t *mcnt = reinterpret_cast<uint32_t *>(smem + LDS_HDR + a.N + 2 * a.L);
-        for (uint32_t t = threadIdx.x; t < a.q; t += blockDim.x) mcnt[t] = 0u;
+        for (uint32_t t = tid; t < a.q; t += nthreads) mcnt[t] = 0u;
     }
     if (span) {       // sums of spanning replicas, after all rows
-        const uint32_t nr = blockDim.x / G;
+        const uint32_t nr = nthreads / G;
         uint8_t *acc = smem + LDS_HDR + (size_t)nr * (a.N + 2 * a.L);
         const uint32_t words = nr * (3u + (a.Mt_out ? a.q : 0u));
-        for (uint32_t t = threadIdx.x; t < words; t += blockDim.x) reinterpret_cast<uint32_t *>(acc)[t] = 0u;
+        for (uint32_t t = tid; t < words; t += nthreads) reinterpret_cast<uint32_t *>(acc)[t] = 0u;
     }
     const bool barrier = multiwave || span;
-    const uint32_t wave = threadIdx.x >> 6;
-    const uint32_t g = multiwave ? threadIdx.x : threadIdx.x % G;
+    const uint32_t wave = tid >> 6;
+    const uint32_t g = multiwave ? tid : tid % G;
     const uint32_t rpb = multiwave ? 1u : (64u * a.waves_per_block) / G;   // replicas per block
 
     // the pair threshold table after rows and sums (the host sizes the LDS alike)
     const uint32_t tab = pair_tab_off(sweep_lds_end(a.N, a.L, G, rpb, a.Mt_out ? a.q : 0u));
-    load_thresholds<T64>(smem, tab, a.T);
+    load_thresholds<T64>(smem, tab, a.T, tid, nthreads);
     __syncthreads();
     const Thresholds<T64> thr{smem, tab};
-    const uint32_t rep = multiwave ? 0u : threadIdx.x / G;                 // replica within block
+    const uint32_t rep = multiwave ? 0u : tid / G;                         // replica within block
     const uint64_t k64 = (uint64_t)block * rpb + rep;
-    // idle waves leave; with barriers only a whole idle block may
+    // idle waves leave; with barriers only a whole idle block may (and in the
+    // persistent kernel none)
     const uint64_t first_idle = multiwave ? (uint64_t)block
                                           : (uint64_t)block * rpb + (span ? 0u : (wave * 64u) / G);
-    if (first_idle >= a.R_new) return;
-    const bool live = k64 < a.R_new;
+    if (!PERSIST && first_idle >= R_new) return;
+    const bool live = k64 < R_new;
     // wave-uniform when a wave holds (part of) one replica only
     const uint32_t k = G % 64u == 0 ? __builtin_amdgcn_readfirstlane((uint32_t)k64) : (uint32_t)k64;
 
@@ -554,7 +562,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
 
     // ---- load or create the replica in LDS -----------------------------
     if (a.mode == SWEEP_UPDATE) {
-        const uint32_t src = live ? (a.anc ? a.anc[k] : k) : 0u;
+        const uint32_t src = live ? (anc ? anc[k - anc_first] : k) : 0u;
         const uint4 *gsrc = reinterpret_cast<const uint4 *>(a.old_pop + (size_t)src * N);
         uint4 *ldst = reinterpret_cast<uint4 *>(rep_lds + L);
         lane_stride<LT * LT / 16, GT>(g, N / 16u, G, [&](uint32_t o) {
@@ -611,7 +619,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         else for (uint32_t off = G >> 1; off > 0; off >>= 1) bonds += __shfl_xor(bonds, off, 64);
         if (multiwave) {
             uint32_t *sum = reinterpret_cast<uint32_t *>(smem) + 24;
-            if ((threadIdx.x & 63u) == 0) atomicAdd(sum, bonds);
+            if ((tid & 63u) == 0) atomicAdd(sum, bonds);
             __syncthreads();
             bonds = *sum;
         }
@@ -631,7 +639,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
             if (G % 64u == 0) c = wave_total(c);
             else for (uint32_t off = G >> 1; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
             if (!multiwave) mt = max(mt, c);
-            else if ((threadIdx.x & 63u) == 0) atomicAdd(&mcnt[st], c);
+            else if ((tid & 63u) == 0) atomicAdd(&mcnt[st], c);
         }
         if (multiwave || span) {
             __syncthreads();
@@ -652,7 +660,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
         }
         if (multiwave) {
             unsigned long long *sum = reinterpret_cast<unsigned long long *>(smem) + 13;
-            if ((threadIdx.x & 63u) == 0) atomicAdd(sum, (unsigned long long)dig);
+            if ((tid & 63u) == 0) atomicAdd(sum, (unsigned long long)dig);
             __syncthreads();
             dig = *sum;
         }
@@ -677,7 +685,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a, uint32_t block) {
 
 template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64>
 __global__ void __launch_bounds__(1024) k_sweep(SweepArgs a) {
-    sweep_body<LT, GT, QSMALL, T64>(a, blockIdx.x);
+    extern __shared__ __align__(16) uint8_t smem[];
+    sweep_body<LT, GT, QSMALL, T64>(a, blockIdx.x, smem, threadIdx.x, blockDim.x, a.anc, 0u, a.R_new);
 }
 
 // Index of the segment holding `block`: start[r] <= block < start[r + 1].
@@ -698,7 +707,8 @@ __global__ void __launch_bounds__(1024) k_sweep_batch(const SweepArgs *runs, con
     const uint32_t r = segment_of(start, n, blockIdx.x);
     // by reference: a local copy would go to scratch memory (T[] is indexed at run time)
     const SweepArgs &a = runs[r];
-    sweep_body<LT, GT, QSMALL, T64>(a, blockIdx.x - start[r]);
+    extern __shared__ __align__(16) uint8_t smem[];
+    sweep_body<LT, GT, QSMALL, T64>(a, blockIdx.x - start[r], smem, threadIdx.x, blockDim.x, a.anc, 0u, a.R_new);
 }
 
 // ---------------------------------------------------------------------------
@@ -899,16 +909,25 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
     return v;
 }
 
+// Loops over the 16 wave partials of a workgroup: unrolled, so that their LDS
+// reads issue together, or (LEAN) rolled, holding one partial at a time, for
+// kernels that must keep few registers.  The results are the same.
+template <bool LEAN>
+__device__ __forceinline__ uint32_t wave_partials() {
+    return LEAN ? (blockDim.x >> 6) : WG_WAVES;
+}
+
 // Exclusive offset of this wave's total among the waves of the block (in wave
 // order); *total receives the block sum.  scratch holds blockDim/64 entries.
-template <typename T>
+template <bool LEAN = false, typename T>
 __device__ __forceinline__ T block_wave_offset(T wave_total, T *scratch, T *total) {
     const uint32_t wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63u) == 0) scratch[wave] = wave_total;
     __syncthreads();
     T off = T(0), tot = T(0);
+    const uint32_t nw = wave_partials<LEAN>();
 #pragma unroll
-    for (uint32_t w = 0; w < WG_WAVES; ++w) {
+    for (uint32_t w = 0; w < nw; ++w) {
         const T x = scratch[w];
         off += w < wave ? x : T(0);
         tot += x;
@@ -920,15 +939,16 @@ __device__ __forceinline__ T block_wave_offset(T wave_total, T *scratch, T *tota
 
 // Block-wide reduction with `op`; every thread receives the result.
 // scratch holds blockDim/64 entries.
-template <typename T, typename Op>
+template <bool LEAN = false, typename T, typename Op>
 __device__ __forceinline__ T block_reduce(T v, Op op, T *scratch) {
     v = wave_allreduce(v, op);
     __syncthreads();
     if ((threadIdx.x & 63u) == 0) scratch[threadIdx.x >> 6] = v;
     __syncthreads();
     T r = scratch[0];
+    const uint32_t nw = wave_partials<LEAN>();
 #pragma unroll
-    for (uint32_t w = 1; w < WG_WAVES; ++w) r = op(r, scratch[w]);
+    for (uint32_t w = 1; w < nw; ++w) r = op(r, scratch[w]);
     return r;
 }
 
@@ -960,16 +980,17 @@ __device__ __forceinline__ uint64_t bin_count(const HistView &v, uint32_t B, int
 // indices; that interpolation runs on the host.  Whole workgroup; thread 0
 // stores out[0..7) = H, jl, jr, h(jl-1), h(jl), h(jr), h(jr+1) (all zero for
 // an empty histogram).
+template <bool LEAN = false>
 __device__ void hist_fwhm_ints(const HistView &v, uint32_t B, uint64_t *scratch, uint64_t *out) {
     const uint32_t j_lo = v.lo / B, j_hi = (v.lo + v.n - 1) / B;   // bins that meet the window
     uint64_t H = 0;
     for (uint32_t j = j_lo + threadIdx.x; j <= j_hi; j += blockDim.x) H = max(H, bin_count(v, B, j));
-    H = block_reduce(H, [](uint64_t x, uint64_t y) { return x > y ? x : y; }, scratch);
+    H = block_reduce<LEAN>(H, [](uint64_t x, uint64_t y) { return x > y ? x : y; }, scratch);
     uint64_t jl = ~0ull, jr = 0;
     for (uint32_t j = j_lo + threadIdx.x; j <= j_hi; j += blockDim.x)
         if (H && 2 * bin_count(v, B, j) >= H) { jl = min(jl, (uint64_t)j); jr = max(jr, (uint64_t)j); }
-    jl = block_reduce(jl, [](uint64_t x, uint64_t y) { return x < y ? x : y; }, scratch);
-    jr = block_reduce(jr, [](uint64_t x, uint64_t y) { return x > y ? x : y; }, scratch);
+    jl = block_reduce<LEAN>(jl, [](uint64_t x, uint64_t y) { return x < y ? x : y; }, scratch);
+    jr = block_reduce<LEAN>(jr, [](uint64_t x, uint64_t y) { return x > y ? x : y; }, scratch);
     if (threadIdx.x != 0) return;
     if (H == 0) {
         for (int k = 0; k < 7; ++k) out[k] = 0;
@@ -1039,6 +1060,7 @@ __device__ __forceinline__ void for_each_tiled(const T *x, uint64_t n, F f) {
 // Sum, minimum and maximum over the workgroup; every thread receives them.
 struct SumMinMax { int64_t sum; int32_t mn, mx; };
 
+template <bool LEAN = false>
 __device__ SumMinMax block_sum_min_max(int64_t sum, int32_t mn, int32_t mx) {
     __shared__ int64_t s_sum[WG_WAVES];
     __shared__ int32_t s_mn[WG_WAVES], s_mx[WG_WAVES];
@@ -1049,8 +1071,9 @@ __device__ SumMinMax block_sum_min_max(int64_t sum, int32_t mn, int32_t mx) {
     if ((threadIdx.x & 63u) == 0) { s_sum[threadIdx.x >> 6] = sum; s_mn[threadIdx.x >> 6] = mn; s_mx[threadIdx.x >> 6] = mx; }
     __syncthreads();
     SumMinMax r{s_sum[0], s_mn[0], s_mx[0]};
+    const uint32_t nw = wave_partials<LEAN>();
 #pragma unroll
-    for (uint32_t w = 1; w < WG_WAVES; ++w) {
+    for (uint32_t w = 1; w < nw; ++w) {
         r.sum += s_sum[w]; r.mn = min(r.mn, s_mn[w]); r.mx = max(r.mx, s_mx[w]);
     }
     return r;
@@ -1064,7 +1087,7 @@ __device__ SumMinMax block_sum_min_max(int64_t sum, int32_t mn, int32_t mx) {
 // atomics.  sum (of x, not shifted), mn and mx are valid in every thread.
 struct HistBuild { HistView v; int64_t sum; int32_t mn, mx; };
 
-template <typename T>
+template <uint32_t V = 32, bool LEAN = false, typename T>
 __device__ HistBuild build_hist(const T *x, uint64_t n, int32_t shift, uint32_t nb, uint32_t *lds,
                                 uint32_t cap, uint32_t *out) {
     HistBuild r;
@@ -1082,7 +1105,7 @@ __device__ HistBuild build_hist(const T *x, uint64_t n, int32_t shift, uint32_t 
         if (threadIdx.x < nz % 4u) lds[nz - 1u - threadIdx.x] = 0u;
         __syncthreads();
         const uint32_t c = threadIdx.x & (C - 1u);
-        for_each_tiled(x, n, [&](T e) { atomicAdd(&lds[(uint32_t)((int32_t)e + shift) * C + c], 1u); });
+        for_each_tiled<V>(x, n, [&](T e) { atomicAdd(&lds[(uint32_t)((int32_t)e + shift) * C + c], 1u); });
         __syncthreads();
         int64_t sum = 0;
         int32_t mn = 0x7fffffff, mx = (int32_t)0x80000000;
@@ -1095,28 +1118,28 @@ __device__ HistBuild build_hist(const T *x, uint64_t n, int32_t shift, uint32_t 
                 sum += (int64_t)h * e; mn = min(mn, e); mx = max(mx, e);
             }
         }
-        const SumMinMax t = block_sum_min_max(sum, mn, mx);   // synchronises the workgroup first
+        const SumMinMax t = block_sum_min_max<LEAN>(sum, mn, mx);   // synchronises the workgroup first
         r.sum = t.sum; r.mn = t.mn; r.mx = t.mx;
         r.v = HistView{folded, 0u, nb, nb};
         return r;
     }
     int64_t sum = 0;
     int32_t mn = 0x7fffffff, mx = (int32_t)0x80000000;
-    for_each_tiled(x, n, [&](T v) { const int32_t e = (int32_t)v; sum += e; mn = min(mn, e); mx = max(mx, e); });
-    const SumMinMax t = block_sum_min_max(sum, mn, mx);
+    for_each_tiled<V>(x, n, [&](T v) { const int32_t e = (int32_t)v; sum += e; mn = min(mn, e); mx = max(mx, e); });
+    const SumMinMax t = block_sum_min_max<LEAN>(sum, mn, mx);
     r.sum = t.sum; r.mn = t.mn; r.mx = t.mx;
     const uint32_t lo = (uint32_t)(r.mn + shift), width = (uint32_t)(r.mx - r.mn) + 1u;
     if (width <= cap) {
         for (uint32_t b = threadIdx.x; b < width; b += blockDim.x) lds[b] = 0u;
         __syncthreads();
-        for_each_tiled(x, n, [&](T e) { atomicAdd(&lds[(uint32_t)((int32_t)e + shift) - lo], 1u); });
+        for_each_tiled<V>(x, n, [&](T e) { atomicAdd(&lds[(uint32_t)((int32_t)e + shift) - lo], 1u); });
         __syncthreads();
         r.v = HistView{lds, lo, width, nb};
     } else {
         for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) out[b] = 0u;
         __threadfence();
         __syncthreads();
-        for_each_tiled(x, n, [&](T e) { atomicAdd(&out[(uint32_t)((int32_t)e + shift)], 1u); });
+        for_each_tiled<V>(x, n, [&](T e) { atomicAdd(&out[(uint32_t)((int32_t)e + shift)], 1u); });
         __threadfence();
         __syncthreads();
         r.v = HistView{out, 0u, nb, nb};
@@ -1189,7 +1212,11 @@ __device__ __forceinline__ void weight_block(const int32_t *E, uint32_t first, u
 // weights W(|E_j - E_ref|) of step i+1 and their inclusive scan C, one block
 // of replicas each.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist, uint64_t *scratch) {
+// V: values per thread and load round of the population passes (the team
+// kernel's smaller populations take fewer, and fewer registers).
+template <uint32_t V = 32, bool LEAN = false>
+__device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist, uint64_t *scratch,
+                                           uint32_t lds_cap = POST_LDS_BINS) {
     __shared__ double s_w[WG_WAVES];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const uint32_t nb = a.nbins;
@@ -1198,7 +1225,7 @@ __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist
     const double mbF_i = (tid == 0 && a.has_next) ? a.mbF[a.step] : 0.0;
 
     // eq. (4) sums and the energy histogram h[E + 2N] of step i
-    const HistBuild he = build_hist(a.E, a.R_i, a.two_n, nb, lds_hist, POST_LDS_BINS, a.hist);
+    const HistBuild he = build_hist<V, LEAN>(a.E, a.R_i, a.two_n, nb, lds_hist, lds_cap, a.hist);
     const int32_t ref = a.dbeta_next >= 0.0 ? he.mn : he.mx;   // E_ref of step i+1
     if (tid == 0) {
         a.E_sum[a.step] = he.sum;
@@ -1220,8 +1247,9 @@ __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist
     if (tid == 0) {
         double S = 0.0;
         uint64_t C = 0;
+        const uint32_t nw = wave_partials<LEAN>();
 #pragma unroll
-        for (uint32_t w = 0; w < WG_WAVES; ++w) { S += s_w[w]; C += scratch[w]; }
+        for (uint32_t w = 0; w < nw; ++w) { S += s_w[w]; C += scratch[w]; }
         a.count[a.step] = C;
         if (a.has_next) {
             const double lnq = -a.dbeta_next * (double)ref + log(S) - log((double)a.R_i);
@@ -1231,23 +1259,23 @@ __device__ __forceinline__ void post_stats(const PostArgs &a, uint32_t *lds_hist
     }
     __syncthreads();
     if (a.store_hist) store_hist(he.v, a.hist);
-    if (a.widths) hist_fwhm_ints(he.v, a.bin_e, scratch, a.fw_e + 8 * (size_t)a.step);
+    if (a.widths) hist_fwhm_ints<LEAN>(he.v, a.bin_e, scratch, a.fw_e + 8 * (size_t)a.step);
     __syncthreads();
 
     if (a.H) {
         // digest of the population: the sum of the replicas' terms
         uint64_t dsum = 0;
         for (uint64_t j = tid; j < a.R_i; j += blockDim.x) dsum += a.H[j];
-        dsum = block_reduce(dsum, [](uint64_t x, uint64_t y) { return x + y; }, scratch);
+        dsum = block_reduce<LEAN>(dsum, [](uint64_t x, uint64_t y) { return x + y; }, scratch);
         if (tid == 0) a.digest[a.step] = dsum;
         __syncthreads();
     }
     if (a.Mt) {
         // eq. (4)-(5): sum of M~ over the population, M-bar, the M~ histogram
-        const HistBuild hm = build_hist(a.Mt, a.R_i, 0, a.N + 1, lds_hist, POST_LDS_BINS, a.mhist);
+        const HistBuild hm = build_hist<V, LEAN>(a.Mt, a.R_i, 0, a.N + 1, lds_hist, lds_cap, a.mhist);
         if (tid == 0) a.Mt_sum[a.step] = hm.sum;
         if (a.store_hist) store_hist(hm.v, a.mhist);
-        if (a.widths) hist_fwhm_ints(hm.v, a.bin_m, scratch, a.fw_m + 8 * (size_t)a.step);
+        if (a.widths) hist_fwhm_ints<LEAN>(hm.v, a.bin_m, scratch, a.fw_m + 8 * (size_t)a.step);
         __syncthreads();
     }
 
@@ -1634,7 +1662,7 @@ __global__ void __launch_bounds__(256) k_tiled_half(TiledArgs a) {
     uint32_t k, tile;
     tile_of(a.tiles, k, tile);
     const uint32_t tab = pair_tab_off(tiled_lds_end(a.rows, a.halves, a.L, blockDim.x, false));
-    load_thresholds<T64>(smem, tab, a.T);
+    load_thresholds<T64>(smem, tab, a.T, threadIdx.x, blockDim.x);
     const uint32_t L = a.L, DPR = L >> 2, S = a.halves;
     const uint32_t y0 = tile * a.rows, n = min(a.rows, L - y0), nl = n + 2 * S;
     uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem + LDS_HDR);
@@ -1690,7 +1718,7 @@ __global__ void __launch_bounds__(NTT) k_tiled_fixed(TiledArgs a) {
     uint32_t k, tile;
     tile_of(a.tiles, k, tile);
     const uint32_t tab = pair_tab_off(tiled_lds_end(a.rows, a.halves, L, NT, true));
-    load_thresholds<T64>(smem, tab, a.T);
+    load_thresholds<T64>(smem, tab, a.T, threadIdx.x, blockDim.x);
     const uint32_t S = a.halves, y0 = tile * a.rows, n = a.rows, nl = n + 2 * S;
     uint32_t *lds32 = reinterpret_cast<uint32_t *>(smem + LDS_HDR);
     const uint32_t src = a.anc ? a.anc[k] : k;
@@ -1878,6 +1906,224 @@ __global__ void k_tiled_finalize(TiledArgs a) {
         }
         if (a.Mt_out) a.Mt_out[k] = m;
     }
+}
+
+
+// ---------------------------------------------------------------------------
+// Team kernel (k_team): small runs of one sweep class advanced through all
+// their steps in one cooperative launch.  Each run owns a team of workgroups
+// of 1024 threads.  Per step i, workgroup 0 of the team forms the statistics of
+// step i-1 (the k_post statistics: histogram, sums, ln Q_i, -beta F_i, digest),
+// while every other workgroup repeats the whole resampling into step i in its
+// LDS from the energies of step i-1 (E_ref, the integer weights and their
+// scan, the draws, the copy numbers and their scan: the same integer results as
+// k_post, k_sample and k_countfill, since the arithmetic is exact) and then
+// sweeps its own contiguous range of new slots, gathering each replica from its
+// ancestor.  One team barrier per step separates the steps: energies, digest
+// terms and M~ alternate between two buffers by step, so the statistics of
+// step i-1 and the sweeps of step i never touch the same buffer.
+//
+// Barrier: every thread waits for its own stores, the workgroup meets, one
+// thread adds to the team counter with agent-scope release and waits for the
+// team's count with agent-scope acquire.  The wait is bounded: it ends when
+// the host sets the abort word (pinned host memory) or after timeout_ticks of
+// the 100 MHz real-time counter, after which it sets the abort word itself, so
+// every workgroup leaves normally.
+// ---------------------------------------------------------------------------
+constexpr uint32_t TEAM_THREADS = 1024;
+static_assert(POST_LDS_BINS * 4u <= 65536u, "the statistics' LDS window fits a team workgroup's work area");
+
+__device__ bool team_barrier(uint32_t *ctr, uint32_t target, const TeamCtl &ctl, uint32_t *s_ok) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t ok = 1, spins = 0;
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if ((++spins & 63u) == 0) {
+                if (__hip_atomic_load(ctl.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) { ok = 0; break; }
+                if (__builtin_amdgcn_s_memrealtime() - t0 > ctl.timeout_ticks) {
+                    __hip_atomic_store(ctl.abort, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// The resampling into step `st.step` (Sec. 2 step 2, eq. (1)) in LDS: the
+// ancestor of every new slot in ancL[0 .. n_new).  Work areas: E and then the
+// copy numbers in ru[R_prev], the cumulative weights and then the offsets in
+// C[R_prev].  With `write_out` the ancestors also go to st.anc_out and the
+// copy numbers to st.counts_out.
+__device__ __attribute__((noinline)) void team_resample(const TeamStep &st, uint32_t *ancL, uint32_t *ru, uint64_t *C,
+                                                        uint64_t *scratch, bool write_out) {
+    const uint32_t tid = threadIdx.x, n = (uint32_t)st.R_prev;
+    if (!st.resample) {
+        for (uint32_t k = tid; k < (uint32_t)st.n_new; k += blockDim.x) {
+            ancL[k] = k;
+            if (write_out) st.anc_out[k] = k;
+        }
+        __syncthreads();
+        return;
+    }
+    // E_ref: the smallest energy (the largest when dbeta < 0)
+    int32_t mn = 0x7fffffff, mx = (int32_t)0x80000000;
+    for (uint32_t j = tid; j < n; j += blockDim.x) {
+        const int32_t e = st.E_prev[j];
+        reinterpret_cast<int32_t *>(ru)[j] = e;
+        mn = min(mn, e);
+        mx = max(mx, e);
+    }
+    const SumMinMax t = block_sum_min_max<true>(0, mn, mx);
+    const int32_t ref = st.ref_max ? t.mx : t.mn;
+    // C_j = sum_{j' <= j} W(|E_j' - E_ref|), rows of 4 per thread
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < n; base += blockDim.x * 4u) {
+        const uint32_t j = base + tid * 4u;
+        uint64_t w[4];
+#pragma unroll
+        for (uint32_t v = 0; v < 4; ++v) {
+            uint64_t x = 0;
+            if (j + v < n) {
+                const uint32_t d = (uint32_t)abs(reinterpret_cast<const int32_t *>(ru)[j + v] - ref);
+                x = st.w_const ? st.w_const : (d < st.D ? st.W[d] : 0ull);
+            }
+            w[v] = x;
+        }
+        w[1] += w[0]; w[2] += w[1]; w[3] += w[2];
+        const uint64_t incl = wave_inclusive_scan(w[3]);
+        uint64_t total;
+        const uint64_t off = carry + block_wave_offset<true>(lane_value(incl, 63), scratch, &total) + incl - w[3];
+#pragma unroll
+        for (uint32_t v = 0; v < 4; ++v)
+            if (j + v < n) C[j + v] = w[v] + off;
+        carry += total;
+    }
+    __syncthreads();
+    // the draws: u = floor(x S / 2^64), ancestor = first j with C_j > u
+    const uint64_t S = C[n - 1];
+    for (uint32_t j = tid; j < n; j += blockDim.x) ru[j] = 0u;
+    __syncthreads();
+    for (uint64_t kk = tid; kk < st.n_new; kk += blockDim.x) {
+        const uint4 w = philox((uint32_t)kk, 0u, st.step, DOM_RESAMPLE << 28, st.key0, st.key1);
+        const uint64_t x = ((uint64_t)w.y << 32) | (uint64_t)w.x;
+        const uint64_t u = __umul64hi(x, S);
+        uint32_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const uint32_t mid = lo + ((hi - lo) >> 1);
+            if (C[mid] > u) hi = mid; else lo = mid + 1;
+        }
+        atomicAdd(&ru[lo], 1u);
+    }
+    __syncthreads();
+    // offsets o_j = sum_{j' < j} r_j' (in the C area), the copy numbers kept
+    uint32_t *o = reinterpret_cast<uint32_t *>(C);
+    uint64_t ocarry = 0;
+    for (uint32_t base = 0; base < n; base += blockDim.x * 4u) {
+        const uint32_t j = base + tid * 4u;
+        uint32_t r[4];
+#pragma unroll
+        for (uint32_t v = 0; v < 4; ++v) r[v] = j + v < n ? ru[j + v] : 0u;
+        const uint32_t sum = r[0] + r[1] + r[2] + r[3];
+        const uint32_t incl = wave_inclusive_scan(sum);
+        uint32_t total;
+        const uint32_t woff = block_wave_offset<true>(lane_value(incl, 63), reinterpret_cast<uint32_t *>(scratch), &total);
+        uint32_t at = (uint32_t)ocarry + woff + incl - sum;
+#pragma unroll
+        for (uint32_t v = 0; v < 4; ++v) {
+            if (j + v < n) o[j + v] = at;
+            at += r[v];
+        }
+        ocarry += total;
+    }
+    __syncthreads();
+    // the copies of ancestor j fill slots o_j .. o_j + r_j - 1
+    for (uint32_t j = tid; j < n; j += blockDim.x) {
+        const uint32_t r = ru[j], b = o[j];
+        for (uint32_t k = b; k < b + r; ++k) ancL[k] = j;
+        if (write_out) {
+            st.counts_out[j] = r;
+            for (uint32_t k = b; k < b + r; ++k) st.anc_out[k] = j;
+        }
+    }
+    __syncthreads();
+}
+
+// The statistics of a step, called (not inlined) from the team kernel so that
+// their registers do not add to the sweep's.
+__device__ __attribute__((noinline)) void team_stats(const PostArgs &a, uint32_t *lds, uint64_t *scratch,
+                                                     uint32_t lds_cap) {
+    post_stats<8, true>(a, lds, scratch, lds_cap);
+}
+
+template <uint32_t LT, uint32_t GT, bool QSMALL, bool T64>
+__global__ void __launch_bounds__(TEAM_THREADS)
+k_team(const TeamRun *runs, uint32_t n_runs, const TeamStep *steps, TeamCtl ctl) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t s_ok, s_next;
+    __shared__ uint64_t scratch[17];
+    // the run: runs are sorted by their first workgroup
+    uint32_t lo = 0, hi = n_runs - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (runs[mid].team0 <= blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    const TeamRun &tr = runs[__builtin_amdgcn_readfirstlane(lo)];
+    const uint32_t w = blockIdx.x - tr.team0;       // 0: statistics, 1 .. team-1: sweeps
+    if (w >= tr.team) return;                        // (not reached: the grid is the teams)
+    // LDS: the ancestors of the new slots, then one area used in turn by the
+    // resampling (ru, C), the sweep groups and the statistics
+    uint32_t *ancL = reinterpret_cast<uint32_t *>(smem);
+    uint8_t *work = smem + ctl.anc_bytes;
+    uint32_t *ru = reinterpret_cast<uint32_t *>(work);
+    uint64_t *C = reinterpret_cast<uint64_t *>(work + ((4u * ctl.r_max + 15u) & ~15u));
+    const uint32_t lds_cap = ctl.work_bytes / 4u;
+    // sweep groups: a k_sweep workgroup's worth of waves each (64 * waves_per_block
+    // threads, which divides 1024 for the classes of this kernel)
+    const uint32_t BS = 64u * steps[tr.rec0].w.waves_per_block;
+    const uint32_t SUB = TEAM_THREADS / BS;
+    const uint32_t rpb = GT > 64u ? 1u : BS / GT;                 // replicas per group
+    const uint32_t sub = threadIdx.x / BS, stid = threadIdx.x % BS;
+    uint32_t gen = 0;
+    for (uint32_t s = 0; s < tr.n_steps; ++s) {
+        const TeamStep &st = steps[tr.rec0 + s];
+        if (s > 0 && !team_barrier(tr.barrier, ++gen * tr.team, ctl, &s_ok)) return;
+        if (w == 0) {
+            if (st.stats) team_stats(st.p, reinterpret_cast<uint32_t *>(work), scratch, lds_cap);
+            continue;
+        }
+        // Sweep blocks are taken SUB at a time from the step's counter, so
+        // that workgroups which run faster (alone on their compute unit, or
+        // first in its issue order) take more of them.  The next claim is
+        // in flight while the current blocks are swept.
+        uint32_t *claim = tr.claims + s;
+        const uint32_t nblocks = (uint32_t)((st.w.R_new + rpb - 1) / rpb);
+        uint32_t next = 0;
+        if (threadIdx.x == 0) next = __hip_atomic_fetch_add(claim, SUB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        team_resample(st, ancL, ru, C, scratch, w == 1);
+        if (threadIdx.x == 0) s_next = next;
+        __syncthreads();
+        uint32_t b = s_next;
+        while (b < nblocks) {
+            if (threadIdx.x == 0) next = __hip_atomic_fetch_add(claim, SUB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sweep_body<LT, GT, QSMALL, T64, true>(st.w, b + sub, work + (size_t)sub * ctl.sub_lds, stid, BS,
+                                                  ancL, 0u, (uint32_t)st.w.R_new);
+            __syncthreads();                     // every group is done with its LDS and s_next
+            if (threadIdx.x == 0) s_next = next;
+            __syncthreads();
+            b = s_next;
+        }
+    }
+    if (!team_barrier(tr.barrier, ++gen * tr.team, ctl, &s_ok)) return;
+    if (w == 0 && tr.last_stats) team_stats(tr.last, reinterpret_cast<uint32_t *>(work), scratch, lds_cap);
 }
 
 }  // namespace
@@ -2076,6 +2322,46 @@ hipError_t launch_resample_batch(const SampleArgs *sruns, const uint32_t *start,
     if (blocks) hipLaunchKernelGGL(k_sample_batch, dim3(blocks), dim3(256), 0, s, sruns, start, n);
     hipLaunchKernelGGL(k_countfill_batch, dim3(mblocks), dim3(WG_THREADS), 0, s, mruns, mstart, n);
     return hipGetLastError();
+}
+
+// Team kernels: the classes whose k_sweep workgroup (64 * waves_per_block
+// threads) divides 1024, with the 32-bit threshold form.
+void *team_kernel(uint32_t cls) {
+    if (cls & (CLASS_BYTES | 1u)) return nullptr;
+    const uint32_t L = (cls >> 16) & 0x7FFFu, G = (cls >> 2) & 0x3FFFu;
+    const bool qs = (cls & 2u) != 0;
+#define PA_TEAM(LV, GV) \
+    if (L == LV && G == GV) return qs ? (void *)k_team<LV, GV, true, false> : (void *)k_team<LV, GV, false, false>;
+    PA_TEAM(8, 16) PA_TEAM(16, 64) PA_TEAM(32, 256) PA_TEAM(64, 512)
+#undef PA_TEAM
+    return nullptr;
+}
+
+uint32_t team_threads() { return TEAM_THREADS; }
+
+uint32_t team_capacity(uint32_t cls, size_t lds, int device) {
+    void *k = team_kernel(cls);
+    int occ = 0, cus = 0;
+    if (!k) return 0;
+    if (lds > 65536 && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, TEAM_THREADS, lds) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    return (uint32_t)(occ > 0 ? occ : 0) * (uint32_t)cus;
+}
+
+hipError_t launch_team(uint32_t cls, const TeamRun *runs, uint32_t n_runs, const TeamStep *steps,
+                       const TeamCtl &ctl, uint32_t blocks, size_t lds, hipStream_t s) {
+    void *k = team_kernel(cls);
+    if (!k || blocks == 0) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    TeamCtl c = ctl;
+    void *args[] = {(void *)&runs, (void *)&n_runs, (void *)&steps, (void *)&c};
+    return hipLaunchCooperativeKernel(k, dim3(blocks), dim3(TEAM_THREADS), args, (unsigned)lds, s);
 }
 
 bool tiled_path(uint32_t L) { return L > 256; }
