@@ -198,11 +198,15 @@ def batched_vs_plain(pa, torch, ctx, runs, reps=1):
     torch.cuda.synchronize()
 
     def timed(fn):
-        t0 = time.perf_counter()
+        # the median of reps timed calls (a rare host-side stall of tens of
+        # milliseconds would otherwise dominate a mean of a few short calls)
+        ts = []
         for _ in range(reps):
+            t0 = time.perf_counter()
             fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / reps
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
 
     t_plain = timed(lambda: [pa.pa_run(ctx, d, workspace=ws_p) for d in descs])
     t_batch = timed(lambda: pa.pa_run_batch(ctx, descs, workspace=ws_b))
@@ -424,7 +428,7 @@ def main():
         print("batched lines", file=sys.stderr, flush=True)
         result["batched"] = {
             "20 runs of 8x8 q=8 R=1000, 200 steps, theta=10, multinomial":
-                batched_vs_plain(pa, torch, ctx, workloads.small_runs(20), reps=3),
+                batched_vs_plain(pa, torch, ctx, workloads.small_runs(20), reps=5),
             "20 runs L in {16..64}, q in {5..20}, R in [1e4,1e5], 300 steps, theta=10, Poisson":
                 batched_vs_plain(pa, torch, ctx, workloads.mixed_runs(20), reps=1),
         }
