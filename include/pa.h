@@ -204,6 +204,18 @@ pa_status pa_autotune(pa_ctx *ctx, uint32_t L, uint32_t q, void *d_ws, uint64_t 
 pa_status pa_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes,
                  void *stream, pa_result *out);
 
+/* Allocation-free form of pa_run, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops that forbid allocation):
+ * the workspace is a device array of PA_STATIC_SCRATCH_BYTES that the library
+ * holds on every GPU it runs on until the process ends, so the call makes no
+ * device allocation.  PA_ERR_NOMEM if the run's pa_plan workspace_bytes exceed
+ * it.  Every call on one GPU uses that GPU's array, which keeps the previous
+ * call's contents (a run clears what must start at zero): calls that overlap
+ * on one GPU, from any thread or context, race.  Per-kernel timing
+ * (pa_ctx_set_profiling) is not recorded by this call. */
+#define PA_STATIC_SCRATCH_BYTES (64ull << 20)
+pa_status pa_run_static(pa_ctx *ctx, const pa_run_desc *desc, void *stream, pa_result *out);
+
 /* Stepwise form of pa_run.
  * pa_run_begin: plan, upload tables, create the initial population (step 0).
  * pa_run_advance: enqueue the next n steps (resampling + theta sweeps + stats).

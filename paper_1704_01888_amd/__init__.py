@@ -35,7 +35,9 @@ EXPORTS = [
     "pa_serve_start", "pa_serve_submit", "pa_serve_wait", "pa_serve_cancel", "pa_serve_stop",
     "pa_width_maxima", "pa_free_energy_crossing", "pa_issue_probe",
     "pa_checkpoint", "pa_checkpoint_info", "pa_resume", "pa_serve_checkpoint", "pa_serve_resume",
+    "pa_run_static",
 ]
+STATIC_SCRATCH_BYTES = 64 << 20
 PROBE_KINDS = ("xor", "bitop3", "mad64", "perm", "sad", "xad", "mulhi", "cmpsel", "mix")
 PA_ERR_BUSY, PA_ERR_CANCELLED, PA_ERR_TIMEOUT = -6, -7, -8
 BATCH_TEAM, BATCH_SEGMENTED = 0, 1
@@ -136,6 +138,8 @@ def lib() -> ctypes.CDLL:
     L.pa_serve_stop.argtypes = [vp]
     L.pa_width_maxima.argtypes = [vp, vp, u32, vp, vp, vp]
     L.pa_free_energy_crossing.argtypes = [vp, vp, vp, u32, vp]
+    L.pa_run_static.argtypes = [vp, P(RunDesc), vp, P(Result)]
+    L.pa_run_static.restype = i32
     L.pa_checkpoint.argtypes = [vp, ctypes.c_char_p]
     L.pa_checkpoint_info.argtypes = [ctypes.c_char_p, P(RunDesc), vp, u32, P(u32), P(u64)]
     L.pa_resume.argtypes = [vp, ctypes.c_char_p, vp, u64, vp, P(vp)]
@@ -378,6 +382,14 @@ def pa_run(ctx: Context, desc: Desc, workspace=None):
     out, res = _alloc_result(desc, info)
     _check(lib().pa_run(ctx.handle, ctypes.byref(desc.c()), ctypes.c_void_p(ws.data_ptr()),
                         ws.numel(), _stream_ptr(), ctypes.byref(res)))
+    return out
+
+
+def pa_run_static(ctx: Context, desc: Desc):
+    """Whole run in the library's fixed device workspace (pa_run_static: no
+    device allocation by the call); returns a dict of numpy arrays."""
+    out, res = _alloc_result(desc, pa_plan(desc))
+    _check(lib().pa_run_static(ctx.handle, ctypes.byref(desc.c()), _stream_ptr(), ctypes.byref(res)))
     return out
 
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpa.so")
 SOURCES = [os.path.join(CSRC, "pa_host.cpp"), os.path.join(CSRC, "pa_kernels.hip"),
-           os.path.join(CSRC, "pa_probe.hip")]
+           os.path.join(CSRC, "pa_probe.hip"), os.path.join(CSRC, "pa_static.hip")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

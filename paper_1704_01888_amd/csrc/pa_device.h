@@ -226,6 +226,9 @@ uint64_t replicas_per_block(uint32_t G, uint32_t waves_per_block);
 // index of L in the table of lattices with lane choices (-1: none), and its size
 int lane_choice_index(uint32_t L);
 constexpr int LANE_CHOICE_COUNT = 13;
+// Device address of the fixed workspace array of pa_run_static on `device`
+// (the current device), looked up once per device; null on failure.
+void *static_scratch(int device, hipError_t *err);
 // Largest dynamic LDS a workgroup may use on the current device.
 size_t max_lds_per_block(int device);
 

@@ -701,6 +701,14 @@ pa_status pa_ctx_create(int device, pa_ctx **out) {
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess || device < 0 || device >= n)
         return fail(PA_ERR_DEVICE, "no such HIP device");
+    // the fixed workspace of pa_run_static: its device address on this device,
+    // looked up with the device current
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    hipError_t se = hipSetDevice(device);
+    if (se == hipSuccess) (void)pa::static_scratch(device, &se);
+    (void)hipSetDevice(prev);
+    if (se != hipSuccess) return fail(PA_ERR_DEVICE, std::string("static workspace: ") + hipGetErrorString(se));
     // the abort word of the team launches: pinned, coherent host memory the
     // kernels poll while they wait at a barrier
     void *abort_word = nullptr;
@@ -1896,6 +1904,25 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
         if (sr && !first) first = sr;
     }
     return first;
+}
+
+extern "C" pa_status pa_run_static(pa_ctx *ctx, const pa_run_desc *desc, void *stream, pa_result *out) {
+    if (!ctx || !desc) return fail(PA_ERR_INVALID, "null context or description");
+    pa_plan_info info;
+    pa_status st = pa_plan(desc, &info);
+    if (st) return st;
+    if (info.workspace_bytes > PA_STATIC_SCRATCH_BYTES)
+        return fail(PA_ERR_NOMEM, "the run's workspace exceeds the fixed workspace of pa_run_static (" +
+                                      std::to_string(info.workspace_bytes) + " > " +
+                                      std::to_string(PA_STATIC_SCRATCH_BYTES) + " bytes)");
+    hipError_t e = hipSuccess;
+    void *ws = pa::static_scratch(ctx->device, &e);
+    if (!ws) return fail(PA_ERR_DEVICE, std::string("static workspace: ") + hipGetErrorString(e));
+    const int prof = ctx->profiling;   // no timing events: they would be created per launch
+    ctx->profiling = 0;
+    st = pa_run(ctx, desc, ws, PA_STATIC_SCRATCH_BYTES, stream, out);
+    ctx->profiling = prof;
+    return st;
 }
 
 extern "C" pa_status pa_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes, void *stream,
