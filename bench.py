@@ -315,6 +315,11 @@ def main():
                          "known size for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--profile-steps", type=int, default=0, metavar="S",
                     help="only the headline run's initial population and S steps, for profiling")
+    ap.add_argument("--profile-run", default="", metavar="L:R:K:THETA",
+                    help="only whole runs of an LxL, q=10 lattice with R replicas, K temperatures "
+                         "to beta = 1.6 and THETA sweeps per step (Poisson, seed 2, per-step "
+                         "histograms), for profiling")
+    ap.add_argument("--profile-reps", type=int, default=1, help="repetitions of --profile-run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -339,6 +344,21 @@ def main():
     ctx = pa.Context(0)
     if args.issue_probe:
         print(json.dumps(issue_ceiling(ctx, pa.LIB_PATH)), flush=True)
+        return
+
+    if args.profile_run:
+        L, R, K, theta = (int(x) for x in args.profile_run.split(":"))
+        w = dict(L=L, q=10, R=R, K=K, beta_max=1.6, theta=theta, seed=2)
+        d = linear_desc(pa, w, outputs=pa.OUT_HIST)
+        ws = torch.empty(int(pa.pa_plan(d).workspace_bytes), dtype=torch.uint8, device="cuda:0")
+        t0 = time.perf_counter()
+        att = 0.0
+        for _ in range(args.profile_reps):
+            out = pa.pa_run(ctx, d, workspace=ws)
+            att += attempts_of(out["R_i"][1:], theta, L * L)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"profiled_run": w, "reps": args.profile_reps, "attempts_per_ns": att / dt / 1e9}))
         return
 
     desc = linear_desc(pa, CFG3)
