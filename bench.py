@@ -341,7 +341,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     pa.lib()
-    ctx = pa.Context(0)
+    # the profiling modes sweep with the default shapes, the others with the
+    # package's tuned shapes (as any Context does)
+    ctx = pa.Context(0, tune_cache=not (args.profile_run or args.profile_steps))
     if args.issue_probe:
         print(json.dumps(issue_ceiling(ctx, pa.LIB_PATH)), flush=True)
         return

@@ -199,6 +199,43 @@ pa_status pa_ctx_get_lanes(pa_ctx *ctx, uint32_t L, uint32_t *lanes, uint32_t *c
 pa_status pa_autotune(pa_ctx *ctx, uint32_t L, uint32_t q, void *d_ws, uint64_t ws_bytes, void *stream,
                       uint32_t *best_lanes, double *best_attempts_per_ns);
 
+/* Tuned sweep shapes.  An entry gives, for lattice side L, a q class (q_large:
+ * q above 128, the other form of the neighbour comparison) and a population
+ * class (r_class: R_cap below 2^11, 2^14, 2^17, or above), the lanes per
+ * replica and the waves per workgroup of the sweep kernel.  Later runs on the
+ * context whose description falls in an entry's class sweep with its shape --
+ * pa_run, pa_run_batch and the serving loop alike -- unless pa_ctx_set_lanes
+ * fixed a lane count for L; results do not depend on the shape.  Lattices on
+ * the tiled path (L > 256) have no shape.
+ * pa_tune: times every shape of L (each lane count with a kernel for L; for
+ *   each, the waves per workgroup that fit 1024 threads, 256 for L = 2 mod 4,
+ *   and the LDS) on a synthetic run of R replicas (K = 3, theta = 10) in the
+ *   caller's workspace (at least pa_plan's size for that run), keeps the
+ *   fastest as the entry of (L, q, R)'s class and returns it with its rate;
+ *   `timed` (may be NULL) receives up to timed_cap of the shapes with their
+ *   rates, *n_timed the number of shapes timed.  Calls on the context must
+ *   not overlap it.
+ * pa_tune_set: installs an entry (PA_ERR_INVALID if it is not a shape of L).
+ * pa_tune_get: the shape later runs of (L, q, R) will use (the entry, or the
+ *   default with attempts_per_ns 0).
+ * pa_tune_save / pa_tune_load: the context's entries as a text file, one JSON
+ *   object per line with the keys arch, L, q_large, r_class, lanes,
+ *   waves_per_block and attempts_per_ns; loading keeps the lines of this
+ *   device's architecture (e.g. "gfx950") and refuses a file with a malformed
+ *   line or a shape its lattice side does not have (nothing is installed
+ *   then). */
+typedef struct {
+    uint32_t L, q_large, r_class;      /* the class */
+    uint32_t lanes, waves_per_block;   /* its shape */
+    double attempts_per_ns;            /* measured sweep rate (0 if not measured) */
+} pa_tune_entry;
+pa_status pa_tune(pa_ctx *ctx, uint32_t L, uint32_t q, uint64_t R, void *d_ws, uint64_t ws_bytes, void *stream,
+                  pa_tune_entry *best, pa_tune_entry *timed, uint32_t timed_cap, uint32_t *n_timed);
+pa_status pa_tune_set(pa_ctx *ctx, const pa_tune_entry *entry);
+pa_status pa_tune_get(pa_ctx *ctx, uint32_t L, uint32_t q, uint64_t R, pa_tune_entry *entry);
+pa_status pa_tune_save(pa_ctx *ctx, const char *path);
+pa_status pa_tune_load(pa_ctx *ctx, const char *path, uint32_t *n_loaded);
+
 /* Whole run, steps 1-5 of Sec. 2, enqueued on `stream`; returns when the
  * results are in `out`. */
 pa_status pa_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes,

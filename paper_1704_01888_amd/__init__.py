@@ -27,7 +27,7 @@ EXPORTS = [
     "pa_plan", "pa_plan_tables", "pa_weight_table", "pa_ctx_create", "pa_ctx_destroy",
     "pa_ctx_set_profiling", "pa_ctx_set_lanes", "pa_ctx_get_lanes", "pa_autotune",
     "pa_ctx_set_graphs", "pa_ctx_set_batch_mode", "pa_ctx_abort_batch",
-    "pa_ctx_batch_info",
+    "pa_ctx_batch_info", "pa_tune", "pa_tune_set", "pa_tune_get", "pa_tune_save", "pa_tune_load",
     "pa_run", "pa_run_begin", "pa_run_advance", "pa_run_sync", "pa_run_read", "pa_run_load",
     "pa_run_read_free_energy",
     "pa_run_read_slots", "pa_run_finish", "pa_status_str", "pa_last_error",
@@ -76,6 +76,15 @@ class Timing(ctypes.Structure):
                 ("done_us", ctypes.c_double), ("attempts", ctypes.c_uint64)]
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("q_large", ctypes.c_uint32), ("r_class", ctypes.c_uint32),
+                ("lanes", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
+                ("attempts_per_ns", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [
         ("R_cap", ctypes.c_uint64), ("R_final", ctypes.c_uint64),
@@ -112,6 +121,16 @@ def lib() -> ctypes.CDLL:
     L.pa_ctx_get_lanes.restype = i32
     L.pa_autotune.argtypes = [vp, u32, u32, vp, u64, vp, vp, vp]
     L.pa_autotune.restype = i32
+    L.pa_tune.argtypes = [vp, u32, u32, u64, vp, u64, vp, P(TuneEntry), vp, u32, vp]
+    L.pa_tune.restype = i32
+    L.pa_tune_set.argtypes = [vp, P(TuneEntry)]
+    L.pa_tune_set.restype = i32
+    L.pa_tune_get.argtypes = [vp, u32, u32, u64, P(TuneEntry)]
+    L.pa_tune_get.restype = i32
+    L.pa_tune_save.argtypes = [vp, ctypes.c_char_p]
+    L.pa_tune_save.restype = i32
+    L.pa_tune_load.argtypes = [vp, ctypes.c_char_p, vp]
+    L.pa_tune_load.restype = i32
     L.pa_ctx_set_graphs.argtypes = [vp, ctypes.c_int]
     L.pa_ctx_set_graphs.restype = i32
     L.pa_ctx_set_batch_mode.argtypes = [vp, ctypes.c_int]
@@ -245,10 +264,18 @@ def free_energy_crossing(beta, mbf_cool, mbf_heat) -> float:
     return float(x[0])
 
 
-class Context:
-    """A device handle (``pa_ctx``) on torch's current HIP device."""
+def tune_cache_path(device: int = 0) -> str:
+    """The cache of tuned sweep shapes shipped with the package (one file for
+    every architecture; pa_tune_load keeps the lines of the device's)."""
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.jsonl")
 
-    def __init__(self, device: int | None = None):
+
+class Context:
+    """A device handle (``pa_ctx``) on torch's current HIP device.  With
+    tune_cache (the default) the tuned sweep shapes of tune_cache_path() are
+    loaded, so that every run on the context uses them."""
+
+    def __init__(self, device: int | None = None, tune_cache: bool = True):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible to torch")
@@ -256,6 +283,8 @@ class Context:
         h = ctypes.c_void_p()
         _check(lib().pa_ctx_create(self.device, ctypes.byref(h)))
         self.handle = h
+        if tune_cache and os.path.exists(tune_cache_path(self.device)):
+            self.tune_load(tune_cache_path(self.device))
 
     def set_lanes(self, L: int, lanes: int):
         _check(lib().pa_ctx_set_lanes(self.handle, int(L), int(lanes)))
@@ -276,6 +305,41 @@ class Context:
         _check(lib().pa_autotune(self.handle, int(L), int(q), ctypes.c_void_p(ws.data_ptr()),
                                  ws.numel(), _stream_ptr(), _ptr(best), _ptr(rate)))
         return int(best[0]), float(rate[0])
+
+    def tune(self, L: int, q: int, R: int, workspace=None) -> dict:
+        """Time every sweep shape of L on R replicas (pa_tune); the fastest
+        becomes the entry of the (L, q, R) class and is returned, with every
+        shape's rate under "timed"."""
+        d = Desc(L=int(L), q=int(q), R=int(R), beta=np.array([0.0, 0.5, 1.0]), theta=10, seed=12345,
+                 resample=RESAMPLE_MULTINOMIAL)
+        ws = workspace if workspace is not None else _workspace(pa_plan(d).workspace_bytes, self.device)
+        e = TuneEntry()
+        timed = (TuneEntry * 64)()
+        n = ctypes.c_uint32(0)
+        _check(lib().pa_tune(self.handle, int(L), int(q), int(R), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                             _stream_ptr(), ctypes.byref(e), timed, 64, ctypes.byref(n)))
+        out = e.as_dict()
+        out["timed"] = [timed[i].as_dict() for i in range(min(n.value, 64))]
+        return out
+
+    def tune_set(self, L: int, q_large: int, r_class: int, lanes: int, waves_per_block: int):
+        """Install a tuned shape for a class (pa_tune_set)."""
+        e = TuneEntry(int(L), int(q_large), int(r_class), int(lanes), int(waves_per_block), 0.0)
+        _check(lib().pa_tune_set(self.handle, ctypes.byref(e)))
+
+    def tune_get(self, L: int, q: int, R: int) -> dict:
+        """The sweep shape later runs of (L, q, R) use (pa_tune_get)."""
+        e = TuneEntry()
+        _check(lib().pa_tune_get(self.handle, int(L), int(q), int(R), ctypes.byref(e)))
+        return e.as_dict()
+
+    def tune_save(self, path):
+        _check(lib().pa_tune_save(self.handle, os.fsencode(str(path))))
+
+    def tune_load(self, path) -> int:
+        n = ctypes.c_uint32(0)
+        _check(lib().pa_tune_load(self.handle, os.fsencode(str(path)), ctypes.byref(n)))
+        return int(n.value)
 
     def issue_probe(self, kind: str) -> float:
         """Lane-instructions per second of a stream of one instruction kind

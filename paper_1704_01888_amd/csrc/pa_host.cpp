@@ -23,6 +23,7 @@
 #include <mutex>
 #include <thread>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -318,6 +319,12 @@ struct pa_ctx {
     uint32_t *team_abort;   // pinned host word read by the team launches' barrier waits
     std::atomic<int> abort_requested;
     uint32_t team_runs, team_launches;   // of the last pa_run_batch
+    // tuned sweep shapes by (L, q above 128, population class); guarded by
+    // tune_mu (the serving thread reads them too); tune_gen counts changes
+    std::mutex tune_mu;
+    std::map<uint64_t, pa_tune_entry> tune;
+    uint64_t tune_gen;
+    uint32_t tune_try_G, tune_try_wpb;   // the shape pa_tune is timing (0: none)
     // pa_run_batch calls on a context take turns; their descriptor records
     // go up from pinned host memory (asynchronous copies)
     std::mutex batch_mu;
@@ -342,6 +349,14 @@ static uint8_t *ctx_staging(pa_ctx *c, size_t bytes) {
         c->staging_bytes = want;
     }
     return c->staging;
+}
+
+// Population classes of the tuned shapes: R_cap below 2^11, 2^14, 2^17, or above.
+static uint32_t r_class_of(uint64_t R_cap) {
+    return R_cap < (1ull << 11) ? 0u : R_cap < (1ull << 14) ? 1u : R_cap < (1ull << 17) ? 2u : 3u;
+}
+static uint64_t tune_key(uint32_t L, uint32_t q_large, uint32_t r_class) {
+    return ((uint64_t)L << 8) | ((uint64_t)(q_large != 0) << 4) | r_class;
 }
 
 static uint32_t ctx_lanes(const pa_ctx *c, uint32_t L) {
@@ -730,6 +745,8 @@ pa_status pa_ctx_create(int device, pa_ctx **out) {
     c->team_runs = c->team_launches = 0;
     c->staging = nullptr;
     c->staging_bytes = 0;
+    c->tune_gen = 0;
+    c->tune_try_G = c->tune_try_wpb = 0;
     c->graph_stream = nullptr;
     c->ev_in = c->ev_out = nullptr;
     *out = c;
@@ -864,6 +881,232 @@ pa_status pa_autotune(pa_ctx *ctx, uint32_t L, uint32_t q, void *d_ws, uint64_t 
     return PA_OK;
 }
 
+// The sweep shapes a tuned entry may take for lattice side L: every lane
+// count with a kernel for L, and for each the waves per workgroup that keep a
+// workgroup within 1024 threads (256 for the byte kernel) and the LDS.
+static std::vector<std::pair<uint32_t, uint32_t>> tune_candidates(uint32_t L, int device) {
+    std::vector<std::pair<uint32_t, uint32_t>> out;
+    if (pa::tiled_path(L)) return out;
+    const uint32_t N = L * L;
+    const size_t lds_max = pa::max_lds_per_block(device);
+    auto add = [&](uint32_t G, uint32_t w) {
+        if (pa::sweep_lds_bytes(N, G, w, 0u) <= lds_max) out.push_back({G, w});
+    };
+    if (L & 3u) {                                        // byte kernel: one replica per wave
+        for (uint32_t w = 1; w <= 4; w *= 2) add(64, w);
+        return out;
+    }
+    uint32_t cand[2];
+    uint32_t nc = pa::lane_candidates(L, cand);
+    if (nc == 0) {                                       // the generic kernel's one lane count
+        uint32_t G, w;
+        pa::sweep_shape(L, 0, &G, &w);
+        cand[0] = G;
+        nc = 1;
+    }
+    for (uint32_t c = 0; c < nc; ++c) {
+        const uint32_t G = cand[c];
+        if (G > 64 && G % 64 == 0) {
+            add(G, G / 64);                              // one replica per workgroup
+        } else if (64 % G != 0) {
+            uint32_t w0 = 1;                             // replicas spanning waves
+            while ((64 * w0) % G != 0) ++w0;
+            for (uint32_t w = w0; 64 * w <= 1024; w += w0) add(G, w);
+        } else {
+            for (uint32_t w = 1; w <= 16; w *= 2) add(G, w);
+        }
+    }
+    return out;
+}
+
+static pa_status tune_check(pa_ctx *ctx, const pa_tune_entry *e) {
+    for (const auto &c : tune_candidates(e->L, ctx->device))
+        if (c.first == e->lanes && c.second == e->waves_per_block) return PA_OK;
+    return fail(PA_ERR_INVALID, "not a sweep shape of this lattice side");
+}
+
+pa_status pa_tune_set(pa_ctx *ctx, const pa_tune_entry *e) {
+    if (!ctx || !e || e->r_class > 3) return fail(PA_ERR_INVALID, "bad tuned entry");
+    pa_status st = tune_check(ctx, e);
+    if (st) return st;
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    ctx->tune[tune_key(e->L, e->q_large, e->r_class)] = *e;
+    ++ctx->tune_gen;
+    return PA_OK;
+}
+
+pa_status pa_tune_get(pa_ctx *ctx, uint32_t L, uint32_t q, uint64_t R, pa_tune_entry *e) {
+    if (!ctx || !e) return fail(PA_ERR_INVALID, "null argument");
+    pa_tune_entry t{};
+    t.L = L;
+    t.q_large = q > 128 ? 1u : 0u;
+    t.r_class = r_class_of(R);
+    if (pa::tiled_path(L)) return fail(PA_ERR_INVALID, "the tiled path has no sweep shape");
+    pa::sweep_shape(L, ctx_lanes(ctx, L), &t.lanes, &t.waves_per_block);
+    if (ctx_lanes(ctx, L) == 0) {
+        std::lock_guard<std::mutex> lk(ctx->tune_mu);
+        auto it = ctx->tune.find(tune_key(t.L, t.q_large, t.r_class));
+        if (it != ctx->tune.end()) t = it->second;
+    }
+    *e = t;
+    return PA_OK;
+}
+
+pa_status pa_tune(pa_ctx *ctx, uint32_t L, uint32_t q, uint64_t R, void *d_ws, uint64_t ws_bytes, void *stream,
+                  pa_tune_entry *best, pa_tune_entry *timed, uint32_t timed_cap, uint32_t *n_timed) {
+    if (!ctx || !best) return fail(PA_ERR_INVALID, "null argument");
+    const auto cands = tune_candidates(L, ctx->device);
+    if (cands.empty()) return fail(PA_ERR_INVALID, "no sweep shapes for this lattice side");
+    const double beta[3] = {0.0, 0.5, 1.0};
+    pa_run_desc d{};
+    d.L = L; d.q = q; d.R = R; d.K = 3; d.beta = beta; d.theta = 10; d.seed = 12345;
+    d.resample = PA_RESAMPLE_MULTINOMIAL; d.init = PA_INIT_RANDOM; d.outputs = 0;
+    pa_plan_info info;
+    pa_status st = pa_plan(&d, &info);
+    if (st) return st;
+    if (info.workspace_bytes > ws_bytes) return fail(PA_ERR_NOMEM, "workspace too small for tuning");
+    const int saved_prof = ctx->profiling;
+    pa_tune_entry b{};
+    b.L = L;
+    b.q_large = q > 128 ? 1u : 0u;
+    b.r_class = r_class_of(R);
+    b.attempts_per_ns = -1.0;
+    uint32_t nt = 0;
+    for (const auto &c : cands) {
+        ctx->tune_try_G = c.first;
+        ctx->tune_try_wpb = c.second;
+        pa_result res{};
+        double kms[PA_KERNEL_KINDS];
+        uint64_t kn[PA_KERNEL_KINDS];
+        res.kernel_ms = kms;
+        res.kernel_launches = kn;
+        ctx->profiling = 0;
+        st = pa_run(ctx, &d, d_ws, ws_bytes, stream, nullptr);   // warm-up
+        ctx->profiling = 1;
+        if (!st) st = pa_run(ctx, &d, d_ws, ws_bytes, stream, &res);
+        ctx->profiling = saved_prof;
+        if (st) break;
+        const double rate = (double)d.theta * (double)L * L * (double)(2 * R) / (kms[PA_KERNEL_SWEEP] * 1e6);
+        if (timed && nt < timed_cap) {
+            timed[nt] = b;
+            timed[nt].lanes = c.first;
+            timed[nt].waves_per_block = c.second;
+            timed[nt].attempts_per_ns = rate;
+        }
+        ++nt;
+        if (rate > b.attempts_per_ns) {
+            b.lanes = c.first;
+            b.waves_per_block = c.second;
+            b.attempts_per_ns = rate;
+        }
+    }
+    ctx->tune_try_G = ctx->tune_try_wpb = 0;
+    if (st) return st;
+    if (n_timed) *n_timed = nt;
+    {
+        std::lock_guard<std::mutex> lk(ctx->tune_mu);
+        ctx->tune[tune_key(b.L, b.q_large, b.r_class)] = b;
+        ++ctx->tune_gen;
+    }
+    *best = b;
+    return PA_OK;
+}
+
+// The device's architecture name (gfx950, without target features).
+static std::string ctx_arch(pa_ctx *ctx) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+pa_status pa_tune_save(pa_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(PA_ERR_INVALID, "null argument");
+    const std::string arch = ctx_arch(ctx);
+    std::vector<pa_tune_entry> all;
+    {
+        std::lock_guard<std::mutex> lk(ctx->tune_mu);
+        for (const auto &kv : ctx->tune) all.push_back(kv.second);
+    }
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(PA_ERR_INVALID, std::string("cannot write ") + path);
+    for (const auto &e : all)
+        std::fprintf(f,
+                     "{\"arch\": \"%s\", \"L\": %u, \"q_large\": %u, \"r_class\": %u, \"lanes\": %u, "
+                     "\"waves_per_block\": %u, \"attempts_per_ns\": %.3f}\n",
+                     arch.c_str(), e.L, e.q_large, e.r_class, e.lanes, e.waves_per_block, e.attempts_per_ns);
+    const bool ok = std::fclose(f) == 0;
+    return ok ? PA_OK : fail(PA_ERR_INVALID, std::string("cannot write ") + path);
+}
+
+// The value after "key": on a line of the cache file.
+static bool json_field(const std::string &line, const char *key, std::string *out) {
+    const std::string k = std::string("\"") + key + "\"";
+    size_t i = line.find(k);
+    if (i == std::string::npos) return false;
+    i = line.find(':', i + k.size());
+    if (i == std::string::npos) return false;
+    ++i;
+    while (i < line.size() && line[i] == ' ') ++i;
+    size_t j = i;
+    if (j < line.size() && line[j] == '"') {
+        const size_t e = line.find('"', j + 1);
+        if (e == std::string::npos) return false;
+        *out = line.substr(j + 1, e - j - 1);
+        return true;
+    }
+    while (j < line.size() && line[j] != ',' && line[j] != '}') ++j;
+    *out = line.substr(i, j - i);
+    return !out->empty();
+}
+
+pa_status pa_tune_load(pa_ctx *ctx, const char *path, uint32_t *n_loaded) {
+    if (!ctx || !path) return fail(PA_ERR_INVALID, "null argument");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(PA_ERR_INVALID, std::string("cannot read ") + path);
+    const std::string arch = ctx_arch(ctx);
+    std::vector<pa_tune_entry> got;
+    char buf[512];
+    pa_status st = PA_OK;
+    unsigned line_no = 0;
+    while (!st && std::fgets(buf, sizeof buf, f)) {
+        ++line_no;
+        const std::string line(buf);
+        if (line.find_first_not_of(" \t\r\n") == std::string::npos) continue;
+        std::string a, v[6];
+        const char *keys[6] = {"L", "q_large", "r_class", "lanes", "waves_per_block", "attempts_per_ns"};
+        bool ok = json_field(line, "arch", &a);
+        for (int k = 0; k < 6 && ok; ++k) ok = json_field(line, keys[k], &v[k]);
+        if (!ok) {
+            st = fail(PA_ERR_INVALID, std::string(path) + ": malformed line " + std::to_string(line_no));
+            break;
+        }
+        if (a != arch) continue;                      // tuned on another architecture
+        pa_tune_entry e{};
+        e.L = (uint32_t)std::strtoul(v[0].c_str(), nullptr, 10);
+        e.q_large = (uint32_t)std::strtoul(v[1].c_str(), nullptr, 10);
+        e.r_class = (uint32_t)std::strtoul(v[2].c_str(), nullptr, 10);
+        e.lanes = (uint32_t)std::strtoul(v[3].c_str(), nullptr, 10);
+        e.waves_per_block = (uint32_t)std::strtoul(v[4].c_str(), nullptr, 10);
+        e.attempts_per_ns = std::strtod(v[5].c_str(), nullptr);
+        if (e.r_class > 3 || (st = tune_check(ctx, &e)))
+            st = fail(PA_ERR_INVALID, std::string(path) + ": line " + std::to_string(line_no) +
+                                          " is not a sweep shape of its lattice side");
+        else
+            got.push_back(e);
+    }
+    std::fclose(f);
+    if (st) return st;
+    {
+        std::lock_guard<std::mutex> lk(ctx->tune_mu);
+        for (const auto &e : got) ctx->tune[tune_key(e.L, e.q_large, e.r_class)] = e;
+        ++ctx->tune_gen;
+    }
+    if (n_loaded) *n_loaded = (uint32_t)got.size();
+    return PA_OK;
+}
+
 pa_status pa_issue_probe(pa_ctx *ctx, uint32_t kind, void *d_out, uint64_t out_bytes, void *stream,
                          double *lane_instr_per_s) {
     if (!ctx || !d_out || !lane_instr_per_s || kind >= PA_PROBE_KINDS)
@@ -916,7 +1159,27 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
     r->broken = false;
     r->G = 0;
     r->wpb = 0;
-    if (!p.tiled) pa::sweep_shape(p.desc.L, ctx_lanes(ctx, p.desc.L), &r->G, &r->wpb);
+    if (!p.tiled) {
+        // a lane count set on the context, else the tuned shape of this
+        // class, else the default
+        pa::sweep_shape(p.desc.L, ctx_lanes(ctx, p.desc.L), &r->G, &r->wpb);
+        uint32_t tG = 0, tw = 0;
+        if (ctx->tune_try_G) {
+            tG = ctx->tune_try_G;
+            tw = ctx->tune_try_wpb;
+        } else if (ctx_lanes(ctx, p.desc.L) == 0) {
+            std::lock_guard<std::mutex> lk(ctx->tune_mu);
+            auto it = ctx->tune.find(tune_key(p.desc.L, p.desc.q > 128, r_class_of(p.R_cap)));
+            if (it != ctx->tune.end()) {
+                tG = it->second.lanes;
+                tw = it->second.waves_per_block;
+            }
+        }
+        if (tG && pa::sweep_lds_bytes(p.N, tG, tw, p.mag ? p.desc.q : 0u) <= pa::max_lds_per_block(ctx->device)) {
+            r->G = tG;
+            r->wpb = tw;
+        }
+    }
     if (!p.tiled && pa::sweep_lds_bytes(p.N, r->G, r->wpb, p.mag ? p.desc.q : 0u) >
                         pa::max_lds_per_block(ctx->device)) {
         delete r;
@@ -1458,13 +1721,17 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
     std::memcpy(blob.data() + L.slot_off, sm.data(), sm.size() * sizeof(pa::SlotmapArgs));
     std::memcpy(blob.data() + L.slot_start_off, mstart.data(), mstart.size() * 4);
     // sweep groups: runs of one kernel class contiguous in the table
-    std::stable_sort(sw.begin(), sw.end(), [](const SW &x, const SW &y) { return x.cls < y.cls; });
+    // (a class's runs may differ in waves per workgroup when tuned shapes
+    // apply: a launch takes one block size)
+    std::stable_sort(sw.begin(), sw.end(), [](const SW &x, const SW &y) {
+        return x.cls != y.cls ? x.cls < y.cls : x.threads < y.threads;
+    });
     L.sweep_off = take(n * sizeof(pa::SweepArgs));
     L.sweep_start_off = take(2 * (n + 1) * 4 + 4 * n);
     std::vector<uint32_t> starts;
     for (size_t k = 0; k < sw.size();) {
         StepLaunch::Group G{sw[k].cls, (uint32_t)starts.size(), 0, 0, sw[k].threads, sw[k].lds};
-        while (k < sw.size() && sw[k].cls == G.cls) {
+        while (k < sw.size() && sw[k].cls == G.cls && sw[k].threads == G.threads) {
             G.lds = std::max(G.lds, sw[k].lds);   // runs of one class may differ in q and outputs
             starts.push_back(G.blocks);
             G.blocks += sw[k].blocks;
@@ -1818,13 +2085,13 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
     // they finish those runs.
     std::vector<bool> finished(n, false);
     if (ctx->batch_mode == PA_BATCH_TEAM && !ctx->graphs) {
-        std::map<uint32_t, std::vector<uint32_t>> by_class;
+        std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>> by_class;   // (class, waves per group)
         for (uint32_t r = 0; r < n; ++r)
-            if (const uint32_t cls = team_class(runs[r])) by_class[cls].push_back(r);
+            if (const uint32_t cls = team_class(runs[r])) by_class[{cls, runs[r]->wpb}].push_back(r);
         for (auto &kv : by_class) {
             std::vector<pa_run_state *> group;
             for (uint32_t r : kv.second) group.push_back(runs[r]);
-            st = run_team_launch(ctx, kv.first, group, ws + b.team_off, b.team_bytes, s);
+            st = run_team_launch(ctx, kv.first.first, group, ws + b.team_off, b.team_bytes, s);
             if (st == PA_ERR_UNSUPPORTED) continue;      // too large for one launch: segmented below
             if (st) return cleanup(st);
             for (uint32_t r : kv.second) finished[r] = true;
@@ -1863,6 +2130,10 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
         key.append((const char *)&d_ws, sizeof d_ws);
         key.append((const char *)&ws_bytes, sizeof ws_bytes);
         for (int i = 0; i < pa::LANE_CHOICE_COUNT; ++i) key.append((const char *)&ctx->lanes[i], 4);
+        {
+            std::lock_guard<std::mutex> lk(ctx->tune_mu);
+            key.append((const char *)&ctx->tune_gen, sizeof ctx->tune_gen);
+        }
         hipGraphExec_t exec = nullptr;
         for (auto &g : ctx->graph_cache)
             if (g.key == key) exec = g.exec;
