@@ -335,10 +335,12 @@ struct pa_ctx {
     std::deque<GraphCache> graph_cache;
 };
 
-// Pinned host memory of at least `bytes` for the batch's uploads (the
-// caller holds batch_mu, and the previous batch has synchronised its stream).
-static uint8_t *ctx_staging(pa_ctx *c, size_t bytes) {
+// Pinned host memory of at least `bytes` for the batch's copies (the caller
+// holds batch_mu; a batch synchronises its stream before it returns).
+static uint8_t *ctx_staging(pa_ctx *c, size_t bytes, hipStream_t s) {
     if (bytes > c->staging_bytes) {
+        // copies from the old buffer may still be in flight on the stream
+        if (hipStreamSynchronize(s) != hipSuccess) return nullptr;
         if (c->staging) (void)hipHostFree(c->staging);
         c->staging = nullptr;
         c->staging_bytes = 0;
@@ -1134,8 +1136,10 @@ namespace {
 // With `wait`, returns once the uploads and launches are done; otherwise the
 // caller synchronises the stream before freeing the run (its plan holds the
 // uploaded host tables).
+// With `w_stage` (pinned host memory of at least 8 |W| bytes, untouched until
+// the stream has drained) the weight tables go up from there asynchronously.
 pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes, void *stream,
-                    bool initial, pa_run_state **out, bool wait = true) {
+                    bool initial, pa_run_state **out, bool wait = true, uint8_t *w_stage = nullptr) {
     if (!ctx || !out) return fail(PA_ERR_INVALID, "null context or output");
     pa_run_state *r = new (std::nothrow) pa_run_state;
     if (!r) return fail(PA_ERR_NOMEM, "out of host memory");
@@ -1196,10 +1200,15 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
         delete r;
         return e;
     };
-    if (!p.W.empty() &&
-        (st = hip_check(r, hipMemcpyAsync(r->ws + p.off_W, p.W.data(), 8 * p.W.size(),
-                                          hipMemcpyHostToDevice, s), "upload W"))) {
-        return drop(st);
+    if (!p.W.empty()) {
+        const void *src = p.W.data();
+        if (w_stage) {
+            std::memcpy(w_stage, p.W.data(), 8 * p.W.size());
+            src = w_stage;
+        }
+        if ((st = hip_check(r, hipMemcpyAsync(r->ws + p.off_W, src, 8 * p.W.size(), hipMemcpyHostToDevice, s),
+                            "upload W")))
+            return drop(st);
     }
     const size_t hist_words = (size_t)p.nbins * (p.hist_all ? p.desc.K : 1);
     const size_t mhist_words = p.mag ? (size_t)(p.N + 1) * (p.hist_all ? p.desc.K : 1) : 0;
@@ -1221,8 +1230,14 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
     r->mbF0 = (p.desc.init == PA_INIT_GROUND)
                   ? std::log((double)p.desc.q) + 2.0 * (double)p.N * p.beta[0]
                   : (double)p.N * std::log((double)p.desc.q);
-    if ((st = hip_check(r, hipMemcpyAsync(r->ws + p.off_mbF, &r->mbF0, 8, hipMemcpyHostToDevice, s), "upload"))) {
-        return drop(st);
+    {
+        // -beta_0 F_0 as two 32-bit fills (no host copy)
+        uint64_t bits;
+        std::memcpy(&bits, &r->mbF0, 8);
+        uint32_t *dst = r->at<uint32_t>(p.off_mbF);
+        if ((st = hip_check(r, pa::launch_fill_u32(dst, 1, (uint32_t)bits, s), "fill")) ||
+            (st = hip_check(r, pa::launch_fill_u32(dst + 1, 1, (uint32_t)(bits >> 32), s), "fill")))
+            return drop(st);
     }
     const uint32_t mode = p.desc.init == PA_INIT_GROUND ? pa::SWEEP_INIT_GROUND : pa::SWEEP_INIT_RANDOM;
     pa::SweepArgs a = sweep_args(r, 0, mode, nullptr, nullptr, r->at<uint8_t>(p.off_pop[0]), 0);
@@ -1244,6 +1259,8 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
 }
 
 }  // namespace
+
+static pa_status finish_run(pa_run_state *r, pa_result *out, const uint8_t *blk_in);
 
 extern "C" {
 
@@ -1363,15 +1380,29 @@ pa_status pa_run_read_slots(pa_run_state *r, int previous, const uint32_t *slots
 }
 
 pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
+    return finish_run(r, out, nullptr);
+}
+
+}  // extern "C"
+
+// pa_run_finish, with the run's per-step block already read (blk_in, by a
+// batch that reads every run's block in one round) or not (null).
+static pa_status finish_run(pa_run_state *r, pa_result *out, const uint8_t *blk_in) {
     if (!r) return fail(PA_ERR_INVALID, "null run");
-    pa_status st = hip_check(r, hipStreamSynchronize(r->stream), "sync");
+    pa_status st = blk_in ? PA_OK : hip_check(r, hipStreamSynchronize(r->stream), "sync");
     const Plan &p = r->plan;
     const uint32_t K = p.desc.K;
     if (!st && out) {
         // the per-step block in one copy
-        std::vector<uint8_t> blk(p.steps_bytes);
-        st = hip_check(r, hipMemcpy(blk.data(), r->ws + p.off_steps, p.steps_bytes, hipMemcpyDeviceToHost), "read");
-        auto field = [&](size_t off) { return blk.data() + (off - p.off_steps); };
+        std::vector<uint8_t> own;
+        const uint8_t *blk = blk_in;
+        if (!blk) {
+            own.resize(p.steps_bytes);
+            st = hip_check(r, hipMemcpy(own.data(), r->ws + p.off_steps, p.steps_bytes, hipMemcpyDeviceToHost),
+                           "read");
+            blk = own.data();
+        }
+        auto field = [&](size_t off) { return blk + (off - p.off_steps); };
         std::vector<uint64_t> count(K);
         if (!st) std::memcpy(count.data(), field(p.off_count), 8 * (size_t)K);
         for (uint32_t i = r->first_step; !st && i <= r->step; ++i)
@@ -1446,12 +1477,10 @@ pa_status pa_run_finish(pa_run_state *r, pa_result *out) {
     return st;
 }
 
-
 // ---------------------------------------------------------------------------
 // Checkpoints: a run's population at a step, with -beta F of that step and the
 // run description, in the binary format documented in pa.h.
 // ---------------------------------------------------------------------------
-}  // extern "C"
 
 namespace {
 
@@ -2013,7 +2042,7 @@ pa_status run_team_launch(pa_ctx *ctx, uint32_t cls, std::vector<pa_run_state *>
     if (steps_bytes + runs_bytes + counter_bytes > dtab_bytes)
         return fail(PA_ERR_DEVICE, "team record table overflow");
     uint32_t *barriers = reinterpret_cast<uint32_t *>(dtab + steps_bytes + runs_bytes);
-    uint8_t *stage = ctx_staging(ctx, steps_bytes + runs_bytes);
+    uint8_t *stage = ctx_staging(ctx, steps_bytes + runs_bytes, s);
     if (!stage) return fail(PA_ERR_DEVICE, "cannot allocate pinned staging memory");
     std::memcpy(stage, recs.data(), recs.size() * sizeof(pa::TeamStep));
     std::memcpy(stage + steps_bytes, truns.data(), n * sizeof(pa::TeamRun));
@@ -2076,11 +2105,18 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
     };
     ctx->abort_requested = 0;
     ctx->team_runs = ctx->team_launches = 0;
-    for (uint32_t r = 0; r < n; ++r) {
+    // the runs' weight tables go up from pinned memory, with one wait for all
+    size_t w_total = 0;
+    for (const Plan &p : b.plans) w_total += align256(8 * p.W.size());
+    uint8_t *w_stage = ctx_staging(ctx, w_total, s);
+    if (!w_stage) return fail(PA_ERR_DEVICE, "cannot allocate pinned staging memory");
+    for (uint32_t r = 0, w_off = 0; r < n; ++r) {
         st = begin_run(ctx, &descs[r], ws + b.run_off[r], align256(b.plans[r].total), stream, true, &runs[r],
-                       /*wait=*/false);
+                       /*wait=*/false, w_stage + w_off);
         if (st) return cleanup(fail(st, "run " + std::to_string(r) + ": " + g_last_error));
+        w_off += (uint32_t)align256(8 * b.plans[r].W.size());
     }
+    if ((st = hip_check(nullptr, hipStreamSynchronize(s), "sync"))) return cleanup(st);
     // Team launches first, one per sweep class, for the runs that qualify;
     // they finish those runs.
     std::vector<bool> finished(n, false);
@@ -2114,7 +2150,7 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
     if (cursor > b.desc_bytes) return cleanup(fail(PA_ERR_DEVICE, "descriptor table overflow"));
     uint8_t *dtab = ws + b.desc_off;
     if (cursor) {
-        uint8_t *stage = ctx_staging(ctx, cursor);
+        uint8_t *stage = ctx_staging(ctx, cursor, s);
         if (!stage) return cleanup(fail(PA_ERR_DEVICE, "cannot allocate pinned staging memory"));
         std::memcpy(stage, blob.data(), cursor);
         if ((st = hip_check(nullptr, hipMemcpyAsync(dtab, stage, cursor, hipMemcpyHostToDevice, s),
@@ -2167,10 +2203,24 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
             if ((st = launch_step(L, dtab, s))) return cleanup(st);
         }
     }
+    // every run's per-step block in one round of copies into pinned memory
+    std::vector<size_t> blk_off(n);
+    size_t blk_total = 0;
+    for (uint32_t r = 0; r < n; ++r) {
+        blk_off[r] = blk_total;
+        blk_total += align256(runs[r]->plan.steps_bytes);
+    }
+    uint8_t *blk = ctx_staging(ctx, blk_total, s);
+    if (!blk) return cleanup(fail(PA_ERR_DEVICE, "cannot allocate pinned staging memory"));
+    for (uint32_t r = 0; r < n && outs; ++r)
+        if ((st = hip_check(nullptr, hipMemcpyAsync(blk + blk_off[r], runs[r]->ws + runs[r]->plan.off_steps,
+                                                   runs[r]->plan.steps_bytes, hipMemcpyDeviceToHost, s),
+                            "read results")))
+            return cleanup(st);
     if ((st = hip_check(nullptr, hipStreamSynchronize(s), "sync"))) return cleanup(st);
     pa_status first = PA_OK;
     for (uint32_t r = 0; r < n; ++r) {
-        pa_status sr = pa_run_finish(runs[r], outs ? &outs[r] : nullptr);
+        pa_status sr = finish_run(runs[r], outs ? &outs[r] : nullptr, outs ? blk + blk_off[r] : nullptr);
         runs[r] = nullptr;
         if (sr && !first) first = sr;
     }

@@ -2332,7 +2332,7 @@ void *team_kernel(uint32_t cls) {
     const bool qs = (cls & 2u) != 0;
 #define PA_TEAM(LV, GV) \
     if (L == LV && G == GV) return qs ? (void *)k_team<LV, GV, true, false> : (void *)k_team<LV, GV, false, false>;
-    PA_TEAM(8, 16) PA_TEAM(16, 64) PA_TEAM(32, 256) PA_TEAM(64, 512)
+    PA_TEAM(8, 16) PA_TEAM(8, 8) PA_TEAM(16, 64) PA_TEAM(16, 32) PA_TEAM(32, 256) PA_TEAM(32, 128) PA_TEAM(64, 512)
 #undef PA_TEAM
     return nullptr;
 }
