@@ -320,6 +320,9 @@ def main():
                          "to beta = 1.6 and THETA sweeps per step (Poisson, seed 2, per-step "
                          "histograms), for profiling")
     ap.add_argument("--profile-reps", type=int, default=1, help="repetitions of --profile-run")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="only the batch of 20 runs of 8x8, q=8, R=1000, 200 steps: segmented, "
+                         "then in team launches, twice each, for profiling")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -343,11 +346,22 @@ def main():
     pa.lib()
     # the profiling modes sweep with the default shapes, the others with the
     # package's tuned shapes (as any Context does)
-    ctx = pa.Context(0, tune_cache=not (args.profile_run or args.profile_steps))
+    ctx = pa.Context(0, tune_cache=not (args.profile_run or args.profile_steps or args.profile_batch))
     if args.issue_probe:
         print(json.dumps(issue_ceiling(ctx, pa.LIB_PATH)), flush=True)
         return
 
+    if args.profile_batch:
+        from paper_1704_01888_amd import workloads
+        descs = [pa.Desc(**r) for r in workloads.small_runs(20)]
+        ws = torch.empty(pa.pa_plan_batch(descs), dtype=torch.uint8, device="cuda:0")
+        for mode in (pa.BATCH_SEGMENTED, pa.BATCH_TEAM):
+            ctx.set_batch_mode(mode)
+            for _ in range(2):
+                pa.pa_run_batch(ctx, descs, workspace=ws)
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled_batch": "20 runs of 8x8, q=8, R=1000, 200 steps", "team": ctx.batch_info()}))
+        return
     if args.profile_run:
         L, R, K, theta = (int(x) for x in args.profile_run.split(":"))
         w = dict(L=L, q=10, R=R, K=K, beta_max=1.6, theta=theta, seed=2)
