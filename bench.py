@@ -183,9 +183,10 @@ def whole_runs(pa, torch, ctx, w, reps=3):
 
 
 def batched_vs_plain(pa, torch, ctx, runs, reps=1):
-    """The same runs as separate pa_run calls and as one pa_run_batch:
-    segmented launches (the default), team launches for the runs that
-    qualify, and the segmented step sequence replayed as a HIP graph."""
+    """The same runs as separate pa_run calls and as one pa_run_batch: the
+    automatic mode (the default), segmented launches only, team launches for
+    every run that qualifies, and the segmented step sequence replayed as a
+    HIP graph."""
     descs = [pa.Desc(**r) for r in runs]
     att = sum(float(r["theta"]) * r["L"] ** 2 * float(np.sum(pa.pa_plan_tables(d)[1][1:]))
               for r, d in zip(runs, descs))
@@ -209,13 +210,19 @@ def batched_vs_plain(pa, torch, ctx, runs, reps=1):
         return float(np.median(ts))
 
     t_plain = timed(lambda: [pa.pa_run(ctx, d, workspace=ws_p) for d in descs])
-    t_batch = timed(lambda: pa.pa_run_batch(ctx, descs, workspace=ws_b))
-    ctx.set_batch_mode(pa.BATCH_TEAM)
-    pa.pa_run_batch(ctx, descs, workspace=ws_b)
-    torch.cuda.synchronize()
-    t_team = timed(lambda: pa.pa_run_batch(ctx, descs, workspace=ws_b))
-    team_runs, team_launches = ctx.batch_info()
-    ctx.set_batch_mode(pa.BATCH_SEGMENTED)
+    t_batch = timed(lambda: pa.pa_run_batch(ctx, descs, workspace=ws_b))     # automatic mode
+    auto_team = ctx.batch_info()
+
+    def in_mode(mode):
+        ctx.set_batch_mode(mode)
+        pa.pa_run_batch(ctx, descs, workspace=ws_b)
+        torch.cuda.synchronize()
+        t = timed(lambda: pa.pa_run_batch(ctx, descs, workspace=ws_b))
+        return t, ctx.batch_info()
+
+    t_seg, _ = in_mode(pa.BATCH_SEGMENTED)
+    t_team, (team_runs, team_launches) = in_mode(pa.BATCH_TEAM)
+    ctx.set_batch_mode(pa.BATCH_AUTO)
     ctx.set_graphs(True)
     pa.pa_run_batch(ctx, descs, workspace=ws_b)        # capture
     torch.cuda.synchronize()
@@ -225,10 +232,12 @@ def batched_vs_plain(pa, torch, ctx, runs, reps=1):
     return {"runs": len(runs), "attempts": att,
             "plain_attempts_per_ns": att / t_plain / 1e9, "plain_ms": t_plain * 1e3,
             "batched_attempts_per_ns": att / t_batch / 1e9, "batched_ms": t_batch * 1e3,
+            "batched_team_runs": auto_team[0],
+            "segmented_attempts_per_ns": att / t_seg / 1e9, "segmented_ms": t_seg * 1e3,
             "team_attempts_per_ns": att / t_team / 1e9, "team_ms": t_team * 1e3,
             "team_runs": team_runs, "team_launches": team_launches,
             "graph_attempts_per_ns": att / t_graph / 1e9, "graph_ms": t_graph * 1e3,
-            "speedup": t_plain / min(t_batch, t_team, t_graph)}
+            "speedup": t_plain / min(t_batch, t_seg, t_team, t_graph)}
 
 
 def serving(pa, torch, ctx, n_requests, capacity_attempts_per_ns, rho=0.8,
@@ -322,7 +331,7 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=1, help="repetitions of --profile-run")
     ap.add_argument("--profile-batch", action="store_true",
                     help="only the batch of 20 runs of 8x8, q=8, R=1000, 200 steps: segmented, "
-                         "then in team launches, twice each, for profiling")
+                         "in team launches, then in the automatic mode, twice each, for profiling")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -355,7 +364,7 @@ def main():
         from paper_1704_01888_amd import workloads
         descs = [pa.Desc(**r) for r in workloads.small_runs(20)]
         ws = torch.empty(pa.pa_plan_batch(descs), dtype=torch.uint8, device="cuda:0")
-        for mode in (pa.BATCH_SEGMENTED, pa.BATCH_TEAM):
+        for mode in (pa.BATCH_SEGMENTED, pa.BATCH_TEAM, pa.BATCH_AUTO):
             ctx.set_batch_mode(mode)
             for _ in range(2):
                 pa.pa_run_batch(ctx, descs, workspace=ws)

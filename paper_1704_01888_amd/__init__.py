@@ -40,7 +40,7 @@ EXPORTS = [
 STATIC_SCRATCH_BYTES = 64 << 20
 PROBE_KINDS = ("xor", "bitop3", "mad64", "perm", "sad", "xad", "mulhi", "cmpsel", "mix")
 PA_ERR_BUSY, PA_ERR_CANCELLED, PA_ERR_TIMEOUT = -6, -7, -8
-BATCH_TEAM, BATCH_SEGMENTED = 0, 1
+BATCH_TEAM, BATCH_SEGMENTED, BATCH_AUTO = 0, 1, 2
 
 
 class PAError(RuntimeError):
@@ -357,7 +357,7 @@ class Context:
         _check(lib().pa_ctx_set_graphs(self.handle, 1 if on else 0))
 
     def set_batch_mode(self, mode: int):
-        """BATCH_SEGMENTED (default) or BATCH_TEAM for later pa_run_batch calls."""
+        """BATCH_AUTO (default), BATCH_SEGMENTED or BATCH_TEAM for later pa_run_batch calls."""
         _check(lib().pa_ctx_set_batch_mode(self.handle, int(mode)))
 
     def batch_info(self):
@@ -583,8 +583,7 @@ def pa_plan_batch(descs) -> int:
 
 def pa_run_batch(ctx: Context, descs, workspace=None):
     """Several independent runs advanced together; returns one result dict per run."""
-    ws_bytes = pa_plan_batch(descs)
-    ws = workspace if workspace is not None else _workspace(ws_bytes, ctx.device)
+    ws = workspace if workspace is not None else _workspace(pa_plan_batch(descs), ctx.device)
     outs, ress = [], (Result * len(descs))()
     for i, d in enumerate(descs):
         o, r = _alloc_result(d, pa_plan(d))

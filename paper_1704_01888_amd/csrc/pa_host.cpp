@@ -315,7 +315,7 @@ struct pa_ctx {
     std::shared_ptr<Server> server;
     std::mutex serve_mu;
     int graphs;          // batched runs replay a captured HIP graph
-    int batch_mode;      // PA_BATCH_SEGMENTED (default) or PA_BATCH_TEAM
+    int batch_mode;      // PA_BATCH_AUTO (default), PA_BATCH_SEGMENTED or PA_BATCH_TEAM
     uint32_t *team_abort;   // pinned host word read by the team launches' barrier waits
     std::atomic<int> abort_requested;
     uint32_t team_runs, team_launches;   // of the last pa_run_batch
@@ -376,6 +376,7 @@ struct pa_run_state {
     uint64_t R_cur, R_prev;
     uint64_t r_dirty[2];  // extent of nonzero copy counts in each parity buffer
     uint32_t G, wpb;     // sweep shape: lanes per replica, waves per workgroup
+    bool shape_default;  // neither a lane count of the context nor a tuned entry chose it
     double mbF0;
     uint32_t first_step;  // step of the initial or loaded population
     uint64_t R_first;
@@ -741,7 +742,7 @@ pa_status pa_ctx_create(int device, pa_ctx **out) {
     c->profiling = 0;
     for (auto &x : c->lanes) x = 0;
     c->graphs = 0;
-    c->batch_mode = PA_BATCH_SEGMENTED;
+    c->batch_mode = PA_BATCH_AUTO;
     c->team_abort = static_cast<uint32_t *>(abort_word);
     c->abort_requested = 0;
     c->team_runs = c->team_launches = 0;
@@ -786,7 +787,8 @@ pa_status pa_ctx_set_graphs(pa_ctx *ctx, int enable) {
 }
 
 pa_status pa_ctx_set_batch_mode(pa_ctx *ctx, int mode) {
-    if (!ctx || (mode != PA_BATCH_TEAM && mode != PA_BATCH_SEGMENTED)) return fail(PA_ERR_INVALID, "bad batch mode");
+    if (!ctx || (mode != PA_BATCH_TEAM && mode != PA_BATCH_SEGMENTED && mode != PA_BATCH_AUTO))
+        return fail(PA_ERR_INVALID, "bad batch mode");
     ctx->batch_mode = mode;
     return PA_OK;
 }
@@ -1139,11 +1141,17 @@ namespace {
 // With `w_stage` (pinned host memory of at least 8 |W| bytes, untouched until
 // the stream has drained) the weight tables go up from there asynchronously.
 pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes, void *stream,
-                    bool initial, pa_run_state **out, bool wait = true, uint8_t *w_stage = nullptr) {
+                    bool initial, pa_run_state **out, bool wait = true, uint8_t *w_stage = nullptr,
+                    const Plan *plan = nullptr) {
     if (!ctx || !out) return fail(PA_ERR_INVALID, "null context or output");
     pa_run_state *r = new (std::nothrow) pa_run_state;
     if (!r) return fail(PA_ERR_NOMEM, "out of host memory");
-    pa_status st = build_plan(desc, r->plan);
+    pa_status st = PA_OK;
+    if (plan) {
+        r->plan = *plan;                     // built already (a batch's layout)
+        r->plan.desc.beta = r->plan.beta.data();
+    } else
+        st = build_plan(desc, r->plan);
     if (st) { delete r; return st; }
     const Plan &p = r->plan;
     if (!d_ws || ws_bytes < p.total || ((uintptr_t)d_ws & 255u)) {
@@ -1167,6 +1175,7 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
         // a lane count set on the context, else the tuned shape of this
         // class, else the default
         pa::sweep_shape(p.desc.L, ctx_lanes(ctx, p.desc.L), &r->G, &r->wpb);
+        r->shape_default = ctx_lanes(ctx, p.desc.L) == 0;
         uint32_t tG = 0, tw = 0;
         if (ctx->tune_try_G) {
             tG = ctx->tune_try_G;
@@ -1182,6 +1191,7 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
         if (tG && pa::sweep_lds_bytes(p.N, tG, tw, p.mag ? p.desc.q : 0u) <= pa::max_lds_per_block(ctx->device)) {
             r->G = tG;
             r->wpb = tw;
+            r->shape_default = false;
         }
     }
     if (!p.tiled && pa::sweep_lds_bytes(p.N, r->G, r->wpb, p.mag ? p.desc.q : 0u) >
@@ -2112,7 +2122,7 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
     if (!w_stage) return fail(PA_ERR_DEVICE, "cannot allocate pinned staging memory");
     for (uint32_t r = 0, w_off = 0; r < n; ++r) {
         st = begin_run(ctx, &descs[r], ws + b.run_off[r], align256(b.plans[r].total), stream, true, &runs[r],
-                       /*wait=*/false, w_stage + w_off);
+                       /*wait=*/false, w_stage + w_off, &b.plans[r]);
         if (st) return cleanup(fail(st, "run " + std::to_string(r) + ": " + g_last_error));
         w_off += (uint32_t)align256(8 * b.plans[r].W.size());
     }
@@ -2120,10 +2130,21 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
     // Team launches first, one per sweep class, for the runs that qualify;
     // they finish those runs.
     std::vector<bool> finished(n, false);
-    if (ctx->batch_mode == PA_BATCH_TEAM && !ctx->graphs) {
+    if (ctx->batch_mode != PA_BATCH_SEGMENTED && !ctx->graphs) {
         std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>> by_class;   // (class, waves per group)
-        for (uint32_t r = 0; r < n; ++r)
-            if (const uint32_t cls = team_class(runs[r])) by_class[{cls, runs[r]->wpb}].push_back(r);
+        for (uint32_t r = 0; r < n; ++r) {
+            pa_run_state *rs = runs[r];
+            if (ctx->batch_mode == PA_BATCH_AUTO) {
+                // the team launch measured faster for 8x8 lattices only, and
+                // there with 8 lanes per replica (two pairs per lane)
+                if (rs->plan.desc.L != 8 || !team_class(rs)) continue;
+                if (rs->shape_default) {
+                    rs->G = 8;
+                    rs->wpb = 4;
+                }
+            }
+            if (const uint32_t cls = team_class(rs)) by_class[{cls, rs->wpb}].push_back(r);
+        }
         for (auto &kv : by_class) {
             std::vector<pa_run_state *> group;
             for (uint32_t r : kv.second) group.push_back(runs[r]);

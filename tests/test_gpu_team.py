@@ -4,8 +4,9 @@ separate pa_run calls, the segmented batch form and the oracle: every output
 bit-identical (FP64 estimators within 1e-12), for all four team classes, the
 three resampling modes, heating and ground-state starts, q above 128,
 populations of 1, 2 and 8192, one-step runs, and batches that mix team and
-segmented runs.  A batch stopped from another thread returns PA_ERR_CANCELLED
-and leaves the context usable."""
+segmented runs.  The automatic mode sends the 8x8 runs (with 8 lanes per
+replica) to team launches and the rest to segmented ones.  A batch stopped
+from another thread returns PA_ERR_CANCELLED and leaves the context usable."""
 import threading
 import time
 
@@ -103,6 +104,20 @@ def test_team_batch_repeats_and_reuses_a_workspace(ctx):
         again = pa.pa_run_batch(ctx, descs, workspace=ws)
         for a, b in zip(first, again):
             _same(a, b)
+
+
+def test_auto_mode_sends_8x8_runs_to_team_launches(ctx):
+    cases = [TEAM[0], TEAM[1], TEAM[5], TEAM[2], TEAM[6]] + SEGMENTED
+    descs = [pa.Desc(outputs=ALL, **c) for c in cases]
+    ctx.set_batch_mode(pa.BATCH_AUTO)
+    try:
+        got = pa.pa_run_batch(ctx, descs)
+        # the three 8x8 runs: q <= 128 and q > 128 are two classes
+        assert ctx.batch_info() == (3, 2)
+    finally:
+        ctx.set_batch_mode(pa.BATCH_TEAM)
+    for d, g in zip(descs, got):
+        _same(g, pa.pa_run(ctx, d))
 
 
 def test_abort_from_another_thread_cancels_and_the_context_stays_usable(ctx):
