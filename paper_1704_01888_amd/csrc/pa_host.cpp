@@ -2146,14 +2146,28 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
             if (const uint32_t cls = team_class(rs)) by_class[{cls, rs->wpb}].push_back(r);
         }
         for (auto &kv : by_class) {
-            std::vector<pa_run_state *> group;
-            for (uint32_t r : kv.second) group.push_back(runs[r]);
-            st = run_team_launch(ctx, kv.first.first, group, ws + b.team_off, b.team_bytes, s);
-            if (st == PA_ERR_UNSUPPORTED) continue;      // too large for one launch: segmented below
-            if (st) return cleanup(st);
-            for (uint32_t r : kv.second) finished[r] = true;
-            ctx->team_runs += (uint32_t)kv.second.size();
-            ++ctx->team_launches;
+            // a group too large for one launch is split in halves (launched one
+            // after the other); a single run that does not fit goes segmented
+            std::vector<std::vector<uint32_t>> pending{kv.second};
+            while (!pending.empty()) {
+                const std::vector<uint32_t> idx = pending.back();
+                pending.pop_back();
+                std::vector<pa_run_state *> group;
+                for (uint32_t r : idx) group.push_back(runs[r]);
+                st = run_team_launch(ctx, kv.first.first, group, ws + b.team_off, b.team_bytes, s);
+                if (st == PA_ERR_UNSUPPORTED) {
+                    if (idx.size() > 1) {
+                        const size_t h = idx.size() / 2;
+                        pending.emplace_back(idx.begin() + h, idx.end());
+                        pending.emplace_back(idx.begin(), idx.begin() + h);
+                    }
+                    continue;
+                }
+                if (st) return cleanup(st);
+                for (uint32_t r : idx) finished[r] = true;
+                ctx->team_runs += (uint32_t)idx.size();
+                ++ctx->team_launches;
+            }
         }
     }
     // Every global step's records for the other runs, built up front (all

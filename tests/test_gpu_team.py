@@ -120,6 +120,19 @@ def test_auto_mode_sends_8x8_runs_to_team_launches(ctx):
         _same(g, pa.pa_run(ctx, d))
 
 
+def test_more_runs_than_one_launch_holds_are_split_into_launches(ctx):
+    """300 runs of 8x8 need 600 resident workgroups as teams of two: the
+    group is split in halves until each launch fits."""
+    cases = [dict(L=8, q=8, R=100, beta=linear_betas(1.5, 5), theta=2, seed=500 + r, resample=r % 2)
+             for r in range(300)]
+    descs = [pa.Desc(outputs=pa.OUT_FINAL | pa.OUT_DIGEST, **c) for c in cases]
+    got = pa.pa_run_batch(ctx, descs)
+    runs_in_teams, launches = ctx.batch_info()
+    assert runs_in_teams == 300 and launches >= 3
+    for k in range(0, 300, 37):
+        _same(got[k], pa.pa_run(ctx, descs[k]))
+
+
 def test_abort_from_another_thread_cancels_and_the_context_stays_usable(ctx):
     long = [pa.Desc(L=16, q=8, R=1000, beta=linear_betas(1.5, 100000), theta=1, seed=40 + r,
                     resample=1) for r in range(2)]
