@@ -82,13 +82,20 @@ def test_team_batch_equals_separate_runs_segmented_batch_and_oracle(ctx):
         _same(g, want)
 
 
-def test_team_batch_of_the_small_run_workload(ctx):
-    """20 runs of 8x8, q = 8, R = 1000, 200 steps: one team launch, each run
-    equal to its pa_run and the first to the oracle."""
+@pytest.mark.parametrize("mode", ["team", "auto"])
+def test_team_batch_of_the_small_run_workload(ctx, mode):
+    """20 runs of 8x8, q = 8, R = 1000, 200 steps (the benchmark's small-run
+    batch, in team mode and in the default automatic mode, which sweeps them
+    with 8 lanes): one team launch, each run equal to its pa_run and the first
+    to the oracle."""
     runs = small_runs(20)
     descs = [pa.Desc(outputs=pa.OUT_HIST | pa.OUT_FINAL | pa.OUT_DIGEST, **r) for r in runs]
-    got = pa.pa_run_batch(ctx, descs)
-    assert ctx.batch_info() == (20, 1)
+    ctx.set_batch_mode(pa.BATCH_AUTO if mode == "auto" else pa.BATCH_TEAM)
+    try:
+        got = pa.pa_run_batch(ctx, descs)
+        assert ctx.batch_info() == (20, 1)
+    finally:
+        ctx.set_batch_mode(pa.BATCH_TEAM)
     for d, g in zip(descs, got):
         _same(g, pa.pa_run(ctx, d))
     _same(got[0], oracle.run(oracle.Desc(**runs[0]), hist=True, final=True, digest=True))
