@@ -1970,10 +1970,10 @@ pa_status run_team_launch(pa_ctx *ctx, uint32_t cls, std::vector<pa_run_state *>
         sub_lds = std::max(sub_lds, (pa::sweep_lds_bytes(p.N, r->G, r->wpb, p.mag ? p.desc.q : 0u) + 15) & ~size_t(15));
         r_max = std::max(r_max, p.R_cap);
         n_max = std::max(n_max, p.N);
-        // sweep workgroups beyond one claim of SUB blocks each would only
-        // repeat the resampling
+        // sweep workgroups beyond one block each would only repeat the
+        // resampling
         const uint64_t blocks = (p.R_cap + rpb - 1) / rpb;
-        useful[k] = (uint32_t)((blocks + SUB - 1) / SUB);
+        useful[k] = (uint32_t)blocks;
         // site updates (and the gather) of the run's remaining steps
         cost[k] = (double)p.N * (p.desc.theta + 1.0) * (double)p.R_cap * (double)(p.desc.K - 1 - r->step);
     }

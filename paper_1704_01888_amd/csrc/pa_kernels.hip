@@ -2100,21 +2100,27 @@ k_team(const TeamRun *runs, uint32_t n_runs, const TeamStep *steps, TeamCtl ctl)
             if (st.stats) team_stats(st.p, reinterpret_cast<uint32_t *>(work), scratch, lds_cap);
             continue;
         }
-        // Sweep blocks are taken SUB at a time from the step's counter, so
-        // that workgroups which run faster (alone on their compute unit, or
-        // first in its issue order) take more of them.  The next claim is
-        // in flight while the current blocks are swept.
+        // Sweep blocks are taken `unit` at a time from the step's counter,
+        // so that workgroups which run faster take more of them; `unit`
+        // (at most SUB, one per sweep group) spreads a step's blocks over
+        // all the team's sweep workgroups.  The next claim is in flight
+        // while the current blocks are swept.
         uint32_t *claim = tr.claims + s;
         const uint32_t nblocks = (uint32_t)((st.w.R_new + rpb - 1) / rpb);
+        const uint32_t nsw = tr.team - 1;
+        const uint32_t unit = min(SUB, max(1u, (nblocks + nsw - 1) / nsw));
         uint32_t next = 0;
-        if (threadIdx.x == 0) next = __hip_atomic_fetch_add(claim, SUB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) next = __hip_atomic_fetch_add(claim, unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         team_resample(st, ancL, ru, C, scratch, w == 1);
         if (threadIdx.x == 0) s_next = next;
         __syncthreads();
         uint32_t b = s_next;
         while (b < nblocks) {
-            if (threadIdx.x == 0) next = __hip_atomic_fetch_add(claim, SUB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sweep_body<LT, GT, QSMALL, T64, true>(st.w, b + sub, work + (size_t)sub * ctl.sub_lds, stid, BS,
+            if (threadIdx.x == 0) next = __hip_atomic_fetch_add(claim, unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // groups beyond the claim sweep no replica (they still meet the
+            // workgroup barriers of the classes that have them)
+            const uint32_t blk = sub < unit ? b + sub : nblocks;
+            sweep_body<LT, GT, QSMALL, T64, true>(st.w, blk, work + (size_t)sub * ctl.sub_lds, stid, BS,
                                                   ancL, 0u, (uint32_t)st.w.R_new);
             __syncthreads();                     // every group is done with its LDS and s_next
             if (threadIdx.x == 0) s_next = next;
