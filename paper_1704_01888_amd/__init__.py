@@ -284,7 +284,11 @@ class Context:
         _check(lib().pa_ctx_create(self.device, ctypes.byref(h)))
         self.handle = h
         if tune_cache and os.path.exists(tune_cache_path(self.device)):
-            self.tune_load(tune_cache_path(self.device))
+            try:
+                self.tune_load(tune_cache_path(self.device))
+            except PAError as e:          # a damaged cache leaves the default shapes
+                import warnings
+                warnings.warn(f"tuned shapes not loaded: {e}")
 
     def set_lanes(self, L: int, lanes: int):
         _check(lib().pa_ctx_set_lanes(self.handle, int(L), int(lanes)))
