@@ -210,8 +210,7 @@ def batched_vs_plain(pa, torch, ctx, runs, reps=1):
         return float(np.median(ts))
 
     t_plain = timed(lambda: [pa.pa_run(ctx, d, workspace=ws_p) for d in descs])
-    t_batch = timed(lambda: pa.pa_run_batch(ctx, descs, workspace=ws_b))     # automatic mode
-    auto_team = ctx.batch_info()
+    t_batch = timed(lambda: pa.pa_run_batch(ctx, descs, workspace=ws_b))     # segmented launches
 
     def in_mode(mode):
         ctx.set_batch_mode(mode)
@@ -220,9 +219,8 @@ def batched_vs_plain(pa, torch, ctx, runs, reps=1):
         t = timed(lambda: pa.pa_run_batch(ctx, descs, workspace=ws_b))
         return t, ctx.batch_info()
 
-    t_seg, _ = in_mode(pa.BATCH_SEGMENTED)
     t_team, (team_runs, team_launches) = in_mode(pa.BATCH_TEAM)
-    ctx.set_batch_mode(pa.BATCH_AUTO)
+    ctx.set_batch_mode(pa.BATCH_SEGMENTED)
     ctx.set_graphs(True)
     pa.pa_run_batch(ctx, descs, workspace=ws_b)        # capture
     torch.cuda.synchronize()
@@ -232,12 +230,10 @@ def batched_vs_plain(pa, torch, ctx, runs, reps=1):
     return {"runs": len(runs), "attempts": att,
             "plain_attempts_per_ns": att / t_plain / 1e9, "plain_ms": t_plain * 1e3,
             "batched_attempts_per_ns": att / t_batch / 1e9, "batched_ms": t_batch * 1e3,
-            "batched_team_runs": auto_team[0],
-            "segmented_attempts_per_ns": att / t_seg / 1e9, "segmented_ms": t_seg * 1e3,
             "team_attempts_per_ns": att / t_team / 1e9, "team_ms": t_team * 1e3,
             "team_runs": team_runs, "team_launches": team_launches,
             "graph_attempts_per_ns": att / t_graph / 1e9, "graph_ms": t_graph * 1e3,
-            "speedup": t_plain / min(t_batch, t_seg, t_team, t_graph)}
+            "speedup": t_plain / min(t_batch, t_team, t_graph)}
 
 
 def serving(pa, torch, ctx, n_requests, capacity_attempts_per_ns, rho=0.8,
@@ -364,7 +360,7 @@ def main():
         from paper_1704_01888_amd import workloads
         descs = [pa.Desc(**r) for r in workloads.small_runs(20)]
         ws = torch.empty(pa.pa_plan_batch(descs), dtype=torch.uint8, device="cuda:0")
-        for mode in (pa.BATCH_SEGMENTED, pa.BATCH_TEAM, pa.BATCH_AUTO):
+        for mode in (pa.BATCH_SEGMENTED, pa.BATCH_TEAM):
             ctx.set_batch_mode(mode)
             for _ in range(2):
                 pa.pa_run_batch(ctx, descs, workspace=ws)

@@ -338,20 +338,18 @@ pa_status pa_plan_batch(const pa_run_desc *descs, uint32_t n, uint64_t *workspac
  * stream by events) and replays it for later calls with the same
  * descriptions, workspace and kernel shapes (up to 8 cached graphs). */
 pa_status pa_ctx_set_graphs(pa_ctx *ctx, int enable);
-/* Batch modes.  PA_BATCH_SEGMENTED: the launches above, one set per global
- * step.  PA_BATCH_TEAM: the runs whose every remaining step fits one
- * workgroup's sweep class, with populations up to 8192 replicas and no 64-bit
- * thresholds, go through all their steps in one cooperative launch per sweep
- * class and workgroup size -- each run a team of workgroups that meet at one
- * device-wide barrier per step: every sweeping workgroup redoes the resampling
- * of eq. (1) from the energies in its LDS and then claims blocks of replicas
- * to sweep; the statistics of Sec. 4 run in a workgroup of their own, one step
- * behind.  Other runs take the segmented launches (graphs on: all of them).
- * PA_BATCH_AUTO (the default): team launches for the 8x8 runs that qualify,
- * which sweep there with 8 lanes per replica unless a lane count or a tuned
- * shape was set, the segmented launches for the rest (the team launch measured
- * faster for 8x8 lattices only).  Results are identical in every mode. */
-enum { PA_BATCH_TEAM = 0, PA_BATCH_SEGMENTED = 1, PA_BATCH_AUTO = 2 };
+/* Batch modes.  PA_BATCH_SEGMENTED (the default): the launches above, one
+ * set per global step.  PA_BATCH_TEAM: the runs whose every remaining step fits
+ * one workgroup's sweep class, with populations up to 8192 replicas and no
+ * 64-bit thresholds, go through all their steps in one cooperative launch per
+ * sweep class and workgroup size -- each run a team of workgroups that meet
+ * at one device-wide barrier per step: every sweeping workgroup redoes the
+ * resampling of eq. (1) from the energies in its LDS and then claims blocks of
+ * replicas to sweep; the statistics of Sec. 4 run in a workgroup of their own,
+ * one step behind.  Other runs take the segmented launches (graphs on: all of
+ * them).  Results are identical in both modes; the segmented form measured as
+ * fast or faster on every batch tried. */
+enum { PA_BATCH_TEAM = 0, PA_BATCH_SEGMENTED = 1 };
 pa_status pa_ctx_set_batch_mode(pa_ctx *ctx, int mode);
 /* How the last pa_run_batch on ctx went: the runs it finished in team
  * launches and the number of those launches (either may be NULL). */

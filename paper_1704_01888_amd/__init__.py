@@ -40,7 +40,7 @@ EXPORTS = [
 STATIC_SCRATCH_BYTES = 64 << 20
 PROBE_KINDS = ("xor", "bitop3", "mad64", "perm", "sad", "xad", "mulhi", "cmpsel", "mix")
 PA_ERR_BUSY, PA_ERR_CANCELLED, PA_ERR_TIMEOUT = -6, -7, -8
-BATCH_TEAM, BATCH_SEGMENTED, BATCH_AUTO = 0, 1, 2
+BATCH_TEAM, BATCH_SEGMENTED = 0, 1
 
 
 class PAError(RuntimeError):
@@ -361,7 +361,7 @@ class Context:
         _check(lib().pa_ctx_set_graphs(self.handle, 1 if on else 0))
 
     def set_batch_mode(self, mode: int):
-        """BATCH_AUTO (default), BATCH_SEGMENTED or BATCH_TEAM for later pa_run_batch calls."""
+        """BATCH_SEGMENTED (default) or BATCH_TEAM for later pa_run_batch calls."""
         _check(lib().pa_ctx_set_batch_mode(self.handle, int(mode)))
 
     def batch_info(self):

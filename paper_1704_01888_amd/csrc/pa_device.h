@@ -32,6 +32,27 @@ struct SweepArgs {
     uint32_t waves_per_block;
 };
 
+// The resampling into step `step` of a population small enough for one
+// workgroup's LDS (Sec. 2 step 2, eq. (1)): the reference energy, the integer
+// weights and their scan, the draws, the copy numbers and their scan, the
+// slot map, all from the energies of step-1 -- the integer results of k_post's
+// weights, k_sample and k_countfill.
+struct SmallResample {
+    const int32_t *E_prev;    // [R_prev] energies of step-1
+    uint32_t *anc_out;        // [n_new] ancestors of the new slots
+    uint32_t *counts_out;     // [R_prev] copy numbers
+    uint64_t R_prev, n_new;
+    const uint64_t *W;        // integer weights of the step, zero from D on
+    uint32_t D;
+    uint64_t w_const;         // nonzero: every weight equals it (dbeta = 0)
+    uint32_t ref_max;         // E_ref = largest energy (dbeta < 0), else the smallest
+    uint32_t resample;        // 0: resampling off (slot k keeps replica k)
+    uint32_t step, key0, key1;
+};
+// Populations up to this size resample in one workgroup inside the post
+// launch of the step before (R_cap; 12 bytes of LDS per replica).
+constexpr uint64_t SMALL_RESAMPLE_MAX = 4096;
+
 struct PostArgs {
     // population statistics of step i, from the energies E
     uint32_t *hist;           // [2N+1] energy histogram of step i (output; also the
@@ -70,6 +91,10 @@ struct PostArgs {
     uint32_t bin_e, bin_m;    // levels per histogram bin (>= 1)
     uint64_t *fw_e;           // [K][8]: H, jl, jr, h(jl-1), h(jl), h(jr), h(jr+1), unused
     uint64_t *fw_m;           // [K][8], M~ histogram (needs mhist)
+    // a population of at most SMALL_RESAMPLE_MAX: one more workgroup does the
+    // whole resampling into step i+1 (rs) in place of the weight workgroups
+    uint32_t small;
+    SmallResample rs;
 };
 
 struct SampleArgs {
@@ -107,7 +132,7 @@ __host__ __device__ inline uint32_t scan_block(uint64_t n) {
 }
 // Workgroups of a post launch: statistics plus the weight blocks.
 __host__ __device__ inline uint32_t post_blocks(const PostArgs &a) {
-    return 1u + (a.do_weights ? (uint32_t)((a.R_i + a.wblock - 1) / a.wblock) : 0u);
+    return 1u + (a.do_weights ? (uint32_t)((a.R_i + a.wblock - 1) / a.wblock) : 0u) + (a.small ? 1u : 0u);
 }
 __host__ __device__ inline uint32_t countfill_blocks(const SlotmapArgs &m) {
     return (uint32_t)((m.R_prev + m.block - 1) / m.block);
@@ -175,17 +200,8 @@ struct TeamStep {
     SweepArgs w;              // sweeps of step i (each workgroup gathers from its own LDS
                               // ancestors and sweeps its own range of slots)
     PostArgs p;               // statistics of step i-1 (used when stats != 0)
-    const int32_t *E_prev;    // [R_prev] energies of step i-1
-    uint32_t *anc_out;        // [R_new] ancestors of the new slots
-    uint32_t *counts_out;     // [R_prev] copy numbers
-    uint64_t R_prev, n_new;
-    const uint64_t *W;        // integer weights of step i, zero from D on
-    uint32_t D;
-    uint64_t w_const;         // nonzero: every weight equals it (dbeta = 0)
-    uint32_t ref_max;         // E_ref = largest energy (dbeta < 0), else the smallest
-    uint32_t resample;        // 0: resampling off (slot k keeps replica k)
+    SmallResample r;          // the resampling into step i
     uint32_t stats;           // statistics of step i-1 due in this launch
-    uint32_t step, key0, key1;
 };
 struct TeamRun {
     uint32_t team0, team;     // first workgroup of the run's team, workgroups (>= 2)

@@ -142,8 +142,12 @@ struct Plan {
     size_t off_pop[2], off_E, off_C, off_r, off_anc, off_counts, off_hist, off_Esum,
         off_count, off_lnQ, off_mbF, off_Eref, off_W, off_mhist, off_Mt, off_Mtsum,
         off_fwe, off_fwm, off_bonds, off_cnt, off_pop_x, off_H, off_Hacc, off_digest, off_E2, off_Mt2, off_H2,
-        off_steps, steps_bytes, total;
+        off_steps, steps_bytes, off_anc2, off_counts2, total;
     bool tiled = false;   // replicas beyond one workgroup's LDS: tiled half-sweeps in HBM
+    // a population small enough to resample in one workgroup inside the post
+    // launch of the step before; its ancestors and copy numbers alternate
+    // between two buffers by step parity
+    bool small = false;
 };
 
 pa_status validate(const pa_run_desc *d) {
@@ -292,6 +296,9 @@ pa_status build_plan(const pa_run_desc *d, Plan &p) {
     p.off_E2 = o; o += p.tiled ? 0 : align256(4 * p.R_cap);
     p.off_Mt2 = o; o += (!p.tiled && p.mag) ? align256(4 * p.R_cap) : 0;
     p.off_H2 = o; o += (!p.tiled && p.digest) ? align256(8 * p.R_cap) : 0;
+    p.small = !p.tiled && p.desc.resample != PA_RESAMPLE_NONE && p.R_cap <= pa::SMALL_RESAMPLE_MAX;
+    p.off_anc2 = o; o += p.small ? align256(4 * p.R_cap) : 0;
+    p.off_counts2 = o; o += p.small ? align256(4 * p.R_cap) : 0;
     p.total = o;
     return PA_OK;
 }
@@ -315,7 +322,7 @@ struct pa_ctx {
     std::shared_ptr<Server> server;
     std::mutex serve_mu;
     int graphs;          // batched runs replay a captured HIP graph
-    int batch_mode;      // PA_BATCH_AUTO (default), PA_BATCH_SEGMENTED or PA_BATCH_TEAM
+    int batch_mode;      // PA_BATCH_SEGMENTED (default) or PA_BATCH_TEAM
     uint32_t *team_abort;   // pinned host word read by the team launches' barrier waits
     std::atomic<int> abort_requested;
     uint32_t team_runs, team_launches;   // of the last pa_run_batch
@@ -376,7 +383,6 @@ struct pa_run_state {
     uint64_t R_cur, R_prev;
     uint64_t r_dirty[2];  // extent of nonzero copy counts in each parity buffer
     uint32_t G, wpb;     // sweep shape: lanes per replica, waves per workgroup
-    bool shape_default;  // neither a lane count of the context nor a tuned entry chose it
     double mbF0;
     uint32_t first_step;  // step of the initial or loaded population
     uint64_t R_first;
@@ -440,8 +446,13 @@ uint32_t *mhist_of(pa_run_state *r, uint32_t i) {
     return r->at<uint32_t>(p.off_mhist) + slot * (p.N + 1);
 }
 
+uint32_t *anc_of(pa_run_state *r, uint32_t i);
+uint32_t *counts_of(pa_run_state *r, uint32_t i);
+pa::SmallResample small_resample_args(pa_run_state *r, uint32_t i);
+
 // Post-kernel arguments of step i (population size R_cur): statistics of step
-// i, ln Q_{i+1}, and the weights of the resampling to i+1.
+// i, ln Q_{i+1}, and the weights of the resampling to i+1 (for a small
+// population: the whole resampling to i+1).
 pa::PostArgs post_args(pa_run_state *r, uint32_t i) {
     const Plan &p = r->plan;
     pa::PostArgs s{};
@@ -479,6 +490,11 @@ pa::PostArgs post_args(pa_run_state *r, uint32_t i) {
     s.bin_m = p.bin_m;
     s.fw_e = p.widths ? r->at<uint64_t>(p.off_fwe) : nullptr;
     s.fw_m = (p.widths && p.mag) ? r->at<uint64_t>(p.off_fwm) : nullptr;
+    if (p.small && s.has_next) {      // the whole resampling into i+1 in one workgroup
+        s.do_weights = 0;
+        s.small = 1;
+        s.rs = small_resample_args(r, i + 1);
+    }
     return s;
 }
 
@@ -570,6 +586,38 @@ uint32_t *counts_buf(pa_run_state *r, uint32_t par) {
 // Records of the resampling into step i (draws from the R_prev replicas of
 // step i-1, R_new of them).  The draws count into the buffer of parity i,
 // which is zero; the count scan clears the other buffer for step i+1.
+// The ancestors and copy numbers of the resampling into step i.
+uint32_t *anc_of(pa_run_state *r, uint32_t i) {
+    const Plan &p = r->plan;
+    return r->at<uint32_t>(p.small && (i & 1u) ? p.off_anc2 : p.off_anc);
+}
+uint32_t *counts_of(pa_run_state *r, uint32_t i) {
+    const Plan &p = r->plan;
+    return r->at<uint32_t>(p.small && (i & 1u) ? p.off_counts2 : p.off_counts);
+}
+
+// The resampling into step i of a small population, done by the post launch
+// of step i-1 from its energies (r->R_cur = R_{i-1}).
+pa::SmallResample small_resample_args(pa_run_state *r, uint32_t i) {
+    const Plan &p = r->plan;
+    pa::SmallResample t{};
+    t.E_prev = r->at<int32_t>(p.off_E);
+    t.anc_out = anc_of(r, i);
+    t.counts_out = counts_of(r, i);
+    t.R_prev = r->R_cur;
+    t.n_new = p.R_sched[i];
+    const uint32_t tab = p.table_of_step[i];
+    t.W = r->at<uint64_t>(p.off_W) + p.W_off[tab];
+    t.D = p.D[tab];
+    t.w_const = p.abs_dbeta[tab] == 0.0 ? (1ull << p.Kb) : 0ull;
+    t.ref_max = p.dbeta[i] < 0.0 ? 1u : 0u;
+    t.resample = p.desc.resample != PA_RESAMPLE_NONE ? 1u : 0u;
+    t.step = i;
+    t.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
+    t.key1 = (uint32_t)(p.desc.seed >> 32);
+    return t;
+}
+
 void resample_args(pa_run_state *r, uint32_t i, uint64_t R_prev, uint64_t R_new, pa::SampleArgs &s,
                    pa::SlotmapArgs &m) {
     const Plan &p = r->plan;
@@ -600,7 +648,9 @@ pa_status do_step(pa_run_state *r) {
     const uint64_t R_prev = r->R_cur, R_new = p.R_sched[i];
     pa_status st;
     const uint32_t *anc = nullptr;
-    if (p.desc.resample != PA_RESAMPLE_NONE) {
+    if (p.small) {
+        anc = anc_of(r, i);              // written by the post launch of step i-1
+    } else if (p.desc.resample != PA_RESAMPLE_NONE) {
         // C (inclusive weight scan over the step i-1 population) was written
         // by the post kernel of step i-1.
         pa::SampleArgs s;
@@ -742,7 +792,7 @@ pa_status pa_ctx_create(int device, pa_ctx **out) {
     c->profiling = 0;
     for (auto &x : c->lanes) x = 0;
     c->graphs = 0;
-    c->batch_mode = PA_BATCH_AUTO;
+    c->batch_mode = PA_BATCH_SEGMENTED;
     c->team_abort = static_cast<uint32_t *>(abort_word);
     c->abort_requested = 0;
     c->team_runs = c->team_launches = 0;
@@ -787,8 +837,7 @@ pa_status pa_ctx_set_graphs(pa_ctx *ctx, int enable) {
 }
 
 pa_status pa_ctx_set_batch_mode(pa_ctx *ctx, int mode) {
-    if (!ctx || (mode != PA_BATCH_TEAM && mode != PA_BATCH_SEGMENTED && mode != PA_BATCH_AUTO))
-        return fail(PA_ERR_INVALID, "bad batch mode");
+    if (!ctx || (mode != PA_BATCH_TEAM && mode != PA_BATCH_SEGMENTED)) return fail(PA_ERR_INVALID, "bad batch mode");
     ctx->batch_mode = mode;
     return PA_OK;
 }
@@ -1175,7 +1224,6 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
         // a lane count set on the context, else the tuned shape of this
         // class, else the default
         pa::sweep_shape(p.desc.L, ctx_lanes(ctx, p.desc.L), &r->G, &r->wpb);
-        r->shape_default = ctx_lanes(ctx, p.desc.L) == 0;
         uint32_t tG = 0, tw = 0;
         if (ctx->tune_try_G) {
             tG = ctx->tune_try_G;
@@ -1191,7 +1239,6 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
         if (tG && pa::sweep_lds_bytes(p.N, tG, tw, p.mag ? p.desc.q : 0u) <= pa::max_lds_per_block(ctx->device)) {
             r->G = tG;
             r->wpb = tw;
-            r->shape_default = false;
         }
     }
     if (!p.tiled && pa::sweep_lds_bytes(p.N, r->G, r->wpb, p.mag ? p.desc.q : 0u) >
@@ -1308,8 +1355,8 @@ pa_status pa_run_read(pa_run_state *r, uint32_t *step, uint64_t *R_cur, uint64_t
     struct { void *dst; size_t off, bytes; } cp[4] = {
         {spins, p.off_pop[r->cur], (size_t)r->R_cur * p.N},
         {E, p.off_E, 4 * (size_t)r->R_cur},
-        {anc, p.off_anc, 4 * (size_t)r->R_cur},
-        {counts, p.off_counts, 4 * (size_t)r->R_prev},
+        {anc, (size_t)((uint8_t *)anc_of(r, r->step) - r->ws), 4 * (size_t)r->R_cur},
+        {counts, (size_t)((uint8_t *)counts_of(r, r->step) - r->ws), 4 * (size_t)r->R_prev},
     };
     for (auto &c : cp) {
         if (!c.dst) continue;
@@ -1477,7 +1524,7 @@ static pa_status finish_run(pa_run_state *r, pa_result *out, const uint8_t *blk_
                 if (r->step == 0 || p.desc.resample == PA_RESAMPLE_NONE) {
                     for (uint64_t k = 0; k < r->R_cur; ++k) out->last_anc[k] = (uint32_t)k;
                 } else {
-                    st = hip_check(r, hipMemcpy(out->last_anc, r->ws + p.off_anc, 4 * (size_t)r->R_cur, hipMemcpyDeviceToHost), "read");
+                    st = hip_check(r, hipMemcpy(out->last_anc, anc_of(r, r->step), 4 * (size_t)r->R_cur, hipMemcpyDeviceToHost), "read");
                 }
             }
         }
@@ -1707,7 +1754,9 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
         const uint64_t R_prev = r->R_cur, R_new = p.R_sched[g];
         const int prev_buf = r->cur, new_buf = 1 - r->cur;
         const uint32_t *anc = nullptr;
-        if (p.desc.resample != PA_RESAMPLE_NONE) {
+        if (p.small) {
+            anc = anc_of(r, g);                  // written by the post launch of step g-1
+        } else if (p.desc.resample != PA_RESAMPLE_NONE) {
             pa::SampleArgs a;
             pa::SlotmapArgs m;
             resample_args(r, g, R_prev, R_new, a, m);
@@ -1906,6 +1955,7 @@ pa::PostArgs team_post(pa_run_state *r, uint32_t i) {
     a.Mt = b.Mt;
     a.H = b.H;
     a.do_weights = 0;
+    a.small = 0;
     return a;
 }
 
@@ -1922,20 +1972,8 @@ void team_records(pa_run_state *r, std::vector<pa::TeamStep> &recs, pa::TeamRun 
         t.stats = i - 1 > i0 ? 1u : 0u;
         if (t.stats) t.p = team_post(r, i - 1);         // r->R_cur is R_{i-1} here
         const TeamBufs prev = team_bufs(r, i - 1), cur = team_bufs(r, i);
-        t.E_prev = prev.E;
-        t.R_prev = R_prev;
-        t.n_new = R_new;
-        t.resample = p.desc.resample != PA_RESAMPLE_NONE ? 1u : 0u;
-        const uint32_t tab = p.table_of_step[i];
-        t.W = r->at<uint64_t>(p.off_W) + p.W_off[tab];
-        t.D = p.D[tab];
-        t.w_const = p.abs_dbeta[tab] == 0.0 ? (1ull << p.Kb) : 0ull;
-        t.ref_max = p.dbeta[i] < 0.0 ? 1u : 0u;
-        t.anc_out = r->at<uint32_t>(p.off_anc);
-        t.counts_out = r->at<uint32_t>(p.off_counts);
-        t.step = i;
-        t.key0 = (uint32_t)(p.desc.seed & 0xffffffffu);
-        t.key1 = (uint32_t)(p.desc.seed >> 32);
+        t.r = small_resample_args(r, i);            // from the energies of step i-1
+        t.r.E_prev = prev.E;
         r->R_prev = R_prev;
         r->R_cur = R_new;
         t.w = sweep_args(r, i, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[r->cur]), nullptr,
@@ -2130,21 +2168,10 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
     // Team launches first, one per sweep class, for the runs that qualify;
     // they finish those runs.
     std::vector<bool> finished(n, false);
-    if (ctx->batch_mode != PA_BATCH_SEGMENTED && !ctx->graphs) {
+    if (ctx->batch_mode == PA_BATCH_TEAM && !ctx->graphs) {
         std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>> by_class;   // (class, waves per group)
-        for (uint32_t r = 0; r < n; ++r) {
-            pa_run_state *rs = runs[r];
-            if (ctx->batch_mode == PA_BATCH_AUTO) {
-                // the team launch measured faster for 8x8 lattices only, and
-                // there with 8 lanes per replica (two pairs per lane)
-                if (rs->plan.desc.L != 8 || !team_class(rs)) continue;
-                if (rs->shape_default) {
-                    rs->G = 8;
-                    rs->wpb = 4;
-                }
-            }
-            if (const uint32_t cls = team_class(rs)) by_class[{cls, rs->wpb}].push_back(r);
-        }
+        for (uint32_t r = 0; r < n; ++r)
+            if (const uint32_t cls = team_class(runs[r])) by_class[{cls, runs[r]->wpb}].push_back(r);
         for (auto &kv : by_class) {
             // a group too large for one launch is split in halves (launched one
             // after the other); a single run that does not fit goes segmented

@@ -1421,11 +1421,23 @@ __device__ __forceinline__ void post_weights(const PostArgs &a, uint32_t b, uint
     }
 }
 
+__device__ __forceinline__ void small_resample_body(const SmallResample &st, uint32_t *ancL, uint32_t *ru,
+                                                    uint64_t *C, uint64_t *scratch, bool write_out);
+
 __device__ __forceinline__ void post_block(const PostArgs &a, uint32_t b) {
     __shared__ __align__(16) uint32_t lds[POST_LDS_BINS];
     __shared__ uint64_t scratch[17];
-    if (b == 0) post_stats(a, lds, scratch);
-    else post_weights(a, b - 1, lds, scratch);
+    if (b == 0) {
+        post_stats(a, lds, scratch);
+    } else if (a.small) {
+        // the whole resampling into step i+1 (R_prev <= SMALL_RESAMPLE_MAX:
+        // counts and cumulative weights take 12 bytes per replica of LDS)
+        uint64_t *C = reinterpret_cast<uint64_t *>(lds + ((a.rs.R_prev + 3u) & ~uint64_t(3)));
+        // (inlined: the record stays in the kernel arguments)
+        small_resample_body(a.rs, nullptr, lds, C, scratch, true);
+    } else {
+        post_weights(a, b - 1, lds, scratch);
+    }
 }
 
 __global__ void __launch_bounds__(WG_THREADS) k_post(PostArgs a) { post_block(a, blockIdx.x); }
@@ -1958,17 +1970,17 @@ __device__ bool team_barrier(uint32_t *ctr, uint32_t target, const TeamCtl &ctl,
     return *s_ok != 0;
 }
 
-// The resampling into step `st.step` (Sec. 2 step 2, eq. (1)) in LDS: the
-// ancestor of every new slot in ancL[0 .. n_new).  Work areas: E and then the
-// copy numbers in ru[R_prev], the cumulative weights and then the offsets in
-// C[R_prev].  With `write_out` the ancestors also go to st.anc_out and the
-// copy numbers to st.counts_out.
-__device__ __attribute__((noinline)) void team_resample(const TeamStep &st, uint32_t *ancL, uint32_t *ru, uint64_t *C,
-                                                        uint64_t *scratch, bool write_out) {
+// The resampling into step `st.step` (Sec. 2 step 2, eq. (1)) in one
+// workgroup's LDS: the ancestor of every new slot in ancL[0 .. n_new) (if
+// ancL is given).  Work areas: E and then the copy numbers in ru[R_prev], the
+// cumulative weights and then the offsets in C[R_prev].  With `write_out` the
+// ancestors also go to st.anc_out and the copy numbers to st.counts_out.
+__device__ __forceinline__ void small_resample_body(const SmallResample &st, uint32_t *ancL, uint32_t *ru,
+                                                    uint64_t *C, uint64_t *scratch, bool write_out) {
     const uint32_t tid = threadIdx.x, n = (uint32_t)st.R_prev;
     if (!st.resample) {
         for (uint32_t k = tid; k < (uint32_t)st.n_new; k += blockDim.x) {
-            ancL[k] = k;
+            if (ancL) ancL[k] = k;
             if (write_out) st.anc_out[k] = k;
         }
         __syncthreads();
@@ -2048,13 +2060,21 @@ __device__ __attribute__((noinline)) void team_resample(const TeamStep &st, uint
     // the copies of ancestor j fill slots o_j .. o_j + r_j - 1
     for (uint32_t j = tid; j < n; j += blockDim.x) {
         const uint32_t r = ru[j], b = o[j];
-        for (uint32_t k = b; k < b + r; ++k) ancL[k] = j;
+        if (ancL)
+            for (uint32_t k = b; k < b + r; ++k) ancL[k] = j;
         if (write_out) {
             st.counts_out[j] = r;
             for (uint32_t k = b; k < b + r; ++k) st.anc_out[k] = j;
         }
     }
     __syncthreads();
+}
+
+// The same, called (not inlined) from the team kernel so that its registers do
+// not add to the sweep's.
+__device__ __attribute__((noinline)) void small_resample(const SmallResample &st, uint32_t *ancL, uint32_t *ru,
+                                                         uint64_t *C, uint64_t *scratch, bool write_out) {
+    small_resample_body(st, ancL, ru, C, scratch, write_out);
 }
 
 // The statistics of a step, called (not inlined) from the team kernel so that
@@ -2111,7 +2131,7 @@ k_team(const TeamRun *runs, uint32_t n_runs, const TeamStep *steps, TeamCtl ctl)
         const uint32_t unit = min(SUB, max(1u, (nblocks + nsw - 1) / nsw));
         uint32_t next = 0;
         if (threadIdx.x == 0) next = __hip_atomic_fetch_add(claim, unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        team_resample(st, ancL, ru, C, scratch, w == 1);
+        small_resample(st.r, ancL, ru, C, scratch, w == 1);
         if (threadIdx.x == 0) s_next = next;
         __syncthreads();
         uint32_t b = s_next;

@@ -4,8 +4,7 @@ separate pa_run calls, the segmented batch form and the oracle: every output
 bit-identical (FP64 estimators within 1e-12), for all four team classes, the
 three resampling modes, heating and ground-state starts, q above 128,
 populations of 1, 2 and 8192, one-step runs, and batches that mix team and
-segmented runs.  The automatic mode sends the 8x8 runs (with 8 lanes per
-replica) to team launches and the rest to segmented ones.  A batch stopped
+segmented runs.  Segmented launches are the default mode.  A batch stopped
 from another thread returns PA_ERR_CANCELLED and leaves the context usable."""
 import threading
 import time
@@ -82,20 +81,20 @@ def test_team_batch_equals_separate_runs_segmented_batch_and_oracle(ctx):
         _same(g, want)
 
 
-@pytest.mark.parametrize("mode", ["team", "auto"])
-def test_team_batch_of_the_small_run_workload(ctx, mode):
+@pytest.mark.parametrize("lanes", [16, 8])
+def test_team_batch_of_the_small_run_workload(ctx, lanes):
     """20 runs of 8x8, q = 8, R = 1000, 200 steps (the benchmark's small-run
-    batch, in team mode and in the default automatic mode, which sweeps them
-    with 8 lanes): one team launch, each run equal to its pa_run and the first
-    to the oracle."""
+    batch) swept with 16 and with 8 lanes per replica: one team launch, each
+    run equal to its pa_run and the first to the oracle."""
     runs = small_runs(20)
     descs = [pa.Desc(outputs=pa.OUT_HIST | pa.OUT_FINAL | pa.OUT_DIGEST, **r) for r in runs]
-    ctx.set_batch_mode(pa.BATCH_AUTO if mode == "auto" else pa.BATCH_TEAM)
+    before = ctx.tune_get(8, 8, 1000)
+    ctx.tune_set(8, 0, 0, lanes, 4)
     try:
         got = pa.pa_run_batch(ctx, descs)
         assert ctx.batch_info() == (20, 1)
     finally:
-        ctx.set_batch_mode(pa.BATCH_TEAM)
+        ctx.tune_set(8, 0, 0, before["lanes"], before["waves_per_block"])
     for d, g in zip(descs, got):
         _same(g, pa.pa_run(ctx, d))
     _same(got[0], oracle.run(oracle.Desc(**runs[0]), hist=True, final=True, digest=True))
@@ -113,18 +112,16 @@ def test_team_batch_repeats_and_reuses_a_workspace(ctx):
             _same(a, b)
 
 
-def test_auto_mode_sends_8x8_runs_to_team_launches(ctx):
-    cases = [TEAM[0], TEAM[1], TEAM[5], TEAM[2], TEAM[6]] + SEGMENTED
-    descs = [pa.Desc(outputs=ALL, **c) for c in cases]
-    ctx.set_batch_mode(pa.BATCH_AUTO)
+def test_a_new_context_batches_in_segmented_launches():
+    descs = [pa.Desc(outputs=pa.OUT_FINAL | pa.OUT_DIGEST, **c) for c in (TEAM[0], TEAM[2], SEGMENTED[1])]
+    c = pa.Context(0)
     try:
-        got = pa.pa_run_batch(ctx, descs)
-        # the three 8x8 runs: q <= 128 and q > 128 are two classes
-        assert ctx.batch_info() == (3, 2)
+        got = pa.pa_run_batch(c, descs)
+        assert c.batch_info() == (0, 0)
+        for d, g in zip(descs, got):
+            _same(g, pa.pa_run(c, d))
     finally:
-        ctx.set_batch_mode(pa.BATCH_TEAM)
-    for d, g in zip(descs, got):
-        _same(g, pa.pa_run(ctx, d))
+        c.close()
 
 
 def test_more_runs_than_one_launch_holds_are_split_into_launches(ctx):

@@ -116,6 +116,6 @@ def test_one_class_with_two_tuned_workgroup_sizes_in_a_batch(ctx, mode):
         if mode == "team":
             assert ctx.batch_info() == (3, 2)        # one launch per workgroup size
     finally:
-        ctx.set_batch_mode(pa.BATCH_AUTO)
+        ctx.set_batch_mode(pa.BATCH_SEGMENTED)
     for d, g in zip(descs, got):
         _same(g, pa.pa_run(ctx, d))
