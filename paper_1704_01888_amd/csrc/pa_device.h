@@ -172,6 +172,22 @@ hipError_t launch_post(const PostArgs &a, hipStream_t s);
 hipError_t launch_resample(const SampleArgs &a, const SlotmapArgs &m, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 
+// One launch of many small fills and copies (a batch's start: zeroed
+// histograms, counts and sums, weight tables; its end: the per-step result
+// blocks gathered for one read-back).  Record r writes words [0, words) of
+// dst: src[i] where src is set, else value; it owns workgroups
+// start[r] .. start[r+1]-1, each PREP_CHUNK words.
+struct PrepRec {
+    uint32_t *dst;
+    const uint32_t *src;
+    uint64_t words;
+    uint32_t value;
+    uint32_t pad;
+};
+constexpr uint64_t PREP_CHUNK = 4096;
+hipError_t launch_prep_batch(const PrepRec *recs, const uint32_t *start, uint32_t n, uint32_t blocks,
+                             hipStream_t s);
+
 // Batched forms: several runs per launch.  Sweep launches group runs of one
 // kernel class (sweep_class); `start` [n+1] gives each run's first workgroup.
 uint32_t sweep_class(uint32_t L, uint32_t q, bool t64, uint32_t G);

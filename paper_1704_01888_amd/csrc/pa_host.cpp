@@ -174,7 +174,12 @@ pa_status validate(const pa_run_desc *d) {
     return PA_OK;
 }
 
-pa_status build_plan(const pa_run_desc *d, Plan &p) {
+pa_status plan_layout(const pa_run_desc *d, Plan &p);
+
+// `like`, if set, is the plan of a run with the same L, K and beta schedule
+// (bit for bit): its thresholds and weight tables, which depend on nothing
+// else (the weights also on K_b), are copied rather than recomputed.
+pa_status build_plan(const pa_run_desc *d, Plan &p, const Plan *like = nullptr) {
     pa_status st = validate(d);
     if (st) return st;
     p.desc = *d;
@@ -208,6 +213,27 @@ pa_status build_plan(const pa_run_desc *d, Plan &p) {
     while ((1ull << lg) < cap) ++lg;
     p.Kb = 63u - lg;
 
+    if (like) {
+        p.T = like->T;
+        p.dbeta = like->dbeta;
+        p.table_of_step = like->table_of_step;
+        p.n_tables = like->n_tables;
+        p.abs_dbeta = like->abs_dbeta;
+        if (like->Kb == p.Kb) {
+            p.W = like->W;
+            p.W_off = like->W_off;
+            p.D = like->D;
+        } else {
+            p.W.clear();
+            p.W_off.assign(p.n_tables, 0);
+            p.D.assign(p.n_tables, 0);
+            for (uint32_t t = 0; t < p.n_tables; ++t) {
+                p.W_off[t] = p.W.size();
+                p.D[t] = p.abs_dbeta[t] == 0.0 ? 0u : weight_prefix(p.abs_dbeta[t], p.Kb, p.N, p.W);
+            }
+        }
+        return plan_layout(d, p);
+    }
     // Metropolis thresholds floor(2^32 exp(-beta_i dE)), dE = 1..4.
     p.T.assign((size_t)K * 4, 0);
     for (uint32_t i = 0; i < K; ++i)
@@ -249,8 +275,12 @@ pa_status build_plan(const pa_run_desc *d, Plan &p) {
         // dbeta = 0: every weight is 2^Kb, no table
         p.D[t] = abs_list[t] == 0.0 ? 0u : weight_prefix(abs_list[t], p.Kb, p.N, p.W);
     }
+    return plan_layout(d, p);
+}
 
-    // Workspace layout.
+// The workspace layout of plan p (tables built) for description d.
+pa_status plan_layout(const pa_run_desc *d, Plan &p) {
+    const uint32_t K = d->K;
     p.hist_all = (d->outputs & PA_OUT_HIST) != 0;
     p.mag = (d->outputs & PA_OUT_MAG) != 0;
     p.widths = (d->outputs & PA_OUT_WIDTHS) != 0;
@@ -1182,15 +1212,40 @@ pa_status pa_issue_probe(pa_ctx *ctx, uint32_t kind, void *d_out, uint64_t out_b
 
 namespace {
 
-// pa_run_begin, optionally without the initial population (a run that loads
-// a population right after, from a checkpoint).
-// With `wait`, returns once the uploads and launches are done; otherwise the
-// caller synchronises the stream before freeing the run (its plan holds the
-// uploaded host tables).
-// With `w_stage` (pinned host memory of at least 8 |W| bytes, untouched until
-// the stream has drained) the weight tables go up from there asynchronously.
+// The buffers a run starts from, as fills: zeroed histograms, copy counts and
+// ln Q sums, the tiled sweeps' accumulators, and -beta_0 F_0 (r->mbF0) as two
+// 32-bit words.
+struct Fill { uint32_t *dst; uint64_t words; uint32_t value; };
+
+std::vector<Fill> start_fills(pa_run_state *r) {
+    const Plan &p = r->plan;
+    std::vector<Fill> f;
+    const size_t hist_words = (size_t)p.nbins * (p.hist_all ? p.desc.K : 1);
+    const size_t mhist_words = p.mag ? (size_t)(p.N + 1) * (p.hist_all ? p.desc.K : 1) : 0;
+    f.push_back({r->at<uint32_t>(p.off_hist), hist_words, 0u});
+    if (mhist_words) f.push_back({r->at<uint32_t>(p.off_mhist), mhist_words, 0u});
+    f.push_back({r->at<uint32_t>(p.off_r), 2 * counts_stride(p.R_cap), 0u});
+    f.push_back({r->at<uint32_t>(p.off_lnQ), 2 * (size_t)p.desc.K, 0u});
+    if (p.tiled) f.push_back({r->at<uint32_t>(p.off_bonds), p.R_cap, 0u});
+    if (p.tiled && p.mag) f.push_back({r->at<uint32_t>(p.off_cnt), p.R_cap * p.desc.q, 0u});
+    if (p.tiled && p.digest) f.push_back({r->at<uint32_t>(p.off_Hacc), 2 * p.R_cap, 0u});
+    uint64_t bits;
+    std::memcpy(&bits, &r->mbF0, 8);
+    f.push_back({r->at<uint32_t>(p.off_mbF), 1, (uint32_t)bits});
+    f.push_back({r->at<uint32_t>(p.off_mbF) + 1, 1, (uint32_t)(bits >> 32)});
+    return f;
+}
+
+// pa_run_begin: a run's host state in workspace d_ws and, unless `deferred`,
+// its start on the stream: the weight tables, the fills of start_fills and (if
+// `initial`; not for a run that loads a population right after, from a
+// checkpoint) the initial population with its statistics.  With `wait`,
+// returns once the uploads and launches are done; otherwise the caller
+// synchronises the stream before freeing the run (its plan holds the uploaded
+// host tables).  A deferred run leaves the start to the caller (a batch does
+// it for all its runs in a few launches).
 pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes, void *stream,
-                    bool initial, pa_run_state **out, bool wait = true, uint8_t *w_stage = nullptr,
+                    bool initial, pa_run_state **out, bool wait = true, bool deferred = false,
                     const Plan *plan = nullptr) {
     if (!ctx || !out) return fail(PA_ERR_INVALID, "null context or output");
     pa_run_state *r = new (std::nothrow) pa_run_state;
@@ -1247,6 +1302,15 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
         return fail(PA_ERR_UNSUPPORTED, "lattice does not fit the LDS of one workgroup on this device");
     }
     if ((st = hip_check(r, hipSetDevice(ctx->device), "hipSetDevice"))) { delete r; return st; }
+    // ln Z at beta_0: N ln q (Z = q^N at beta = 0, Sec. 6) or, for ground
+    // states, ln q + 2N beta_0 (eq. (7)-(8), E_0 = -2N).
+    r->mbF0 = (p.desc.init == PA_INIT_GROUND)
+                  ? std::log((double)p.desc.q) + 2.0 * (double)p.N * p.beta[0]
+                  : (double)p.N * std::log((double)p.desc.q);
+    if (deferred) {
+        *out = r;
+        return PA_OK;
+    }
 
     // Tables and initial state.
     hipStream_t s = r->stream;
@@ -1257,45 +1321,12 @@ pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t w
         delete r;
         return e;
     };
-    if (!p.W.empty()) {
-        const void *src = p.W.data();
-        if (w_stage) {
-            std::memcpy(w_stage, p.W.data(), 8 * p.W.size());
-            src = w_stage;
-        }
-        if ((st = hip_check(r, hipMemcpyAsync(r->ws + p.off_W, src, 8 * p.W.size(), hipMemcpyHostToDevice, s),
-                            "upload W")))
-            return drop(st);
-    }
-    const size_t hist_words = (size_t)p.nbins * (p.hist_all ? p.desc.K : 1);
-    const size_t mhist_words = p.mag ? (size_t)(p.N + 1) * (p.hist_all ? p.desc.K : 1) : 0;
-    if ((st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_hist), hist_words, 0u, s), "fill")) ||
-        (mhist_words &&
-         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_mhist), mhist_words, 0u, s), "fill"))) ||
-        (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_r), 2 * counts_stride(p.R_cap), 0u, s), "fill")) ||
-        (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_lnQ), 2 * (size_t)p.desc.K, 0u, s), "fill")) ||
-        (p.tiled &&
-         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_bonds), p.R_cap, 0u, s), "fill"))) ||
-        (p.tiled && p.mag &&
-         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_cnt), p.R_cap * p.desc.q, 0u, s), "fill"))) ||
-        (p.tiled && p.digest &&
-         (st = hip_check(r, pa::launch_fill_u32(r->at<uint32_t>(p.off_Hacc), 2 * p.R_cap, 0u, s), "fill")))) {
+    if (!p.W.empty() &&
+        (st = hip_check(r, hipMemcpyAsync(r->ws + p.off_W, p.W.data(), 8 * p.W.size(), hipMemcpyHostToDevice, s),
+                        "upload W")))
         return drop(st);
-    }
-    // ln Z at beta_0: N ln q (Z = q^N at beta = 0, Sec. 6) or, for ground
-    // states, ln q + 2N beta_0 (eq. (7)-(8), E_0 = -2N).
-    r->mbF0 = (p.desc.init == PA_INIT_GROUND)
-                  ? std::log((double)p.desc.q) + 2.0 * (double)p.N * p.beta[0]
-                  : (double)p.N * std::log((double)p.desc.q);
-    {
-        // -beta_0 F_0 as two 32-bit fills (no host copy)
-        uint64_t bits;
-        std::memcpy(&bits, &r->mbF0, 8);
-        uint32_t *dst = r->at<uint32_t>(p.off_mbF);
-        if ((st = hip_check(r, pa::launch_fill_u32(dst, 1, (uint32_t)bits, s), "fill")) ||
-            (st = hip_check(r, pa::launch_fill_u32(dst + 1, 1, (uint32_t)(bits >> 32), s), "fill")))
-            return drop(st);
-    }
+    for (const Fill &f : start_fills(r))
+        if ((st = hip_check(r, pa::launch_fill_u32(f.dst, f.words, f.value, s), "fill"))) return drop(st);
     const uint32_t mode = p.desc.init == PA_INIT_GROUND ? pa::SWEEP_INIT_GROUND : pa::SWEEP_INIT_RANDOM;
     pa::SweepArgs a = sweep_args(r, 0, mode, nullptr, nullptr, r->at<uint8_t>(p.off_pop[0]), 0);
     const pa::TiledArgs ta = tiled_args(r, 0, nullptr, nullptr, r->at<uint8_t>(p.off_pop[0]));
@@ -1731,14 +1762,16 @@ struct StepLaunch {
     uint32_t n_res, sample_blocks, slot_blocks, n_post, post_blocks;
     struct Group { uint32_t cls, first, count, blocks, threads; size_t lds; };
     std::vector<Group> groups;
-    struct Tiled { pa::TiledArgs a; uint32_t theta; uint8_t *x; };
+    struct Tiled { pa::TiledArgs a; uint32_t theta; uint8_t *x; bool init; };
     std::vector<Tiled> tiled;   // large lattices, launched one by one
 };
 
 // Advance the host state of every run in `active` (each with step < K-1) by one
-// step and write the step's descriptor records at blob + cursor.
+// step and write the step's descriptor records at blob + cursor.  With `init`,
+// the records of step 0 instead (runs begun deferred): the initial population
+// of each run and its statistics.
 StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uint8_t> &blob,
-                      size_t &cursor) {
+                      size_t &cursor, bool init = false) {
     const size_t n = active.size();
     StepLaunch L{};
     std::vector<pa::SampleArgs> sa;
@@ -1748,8 +1781,30 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
     struct SW { uint32_t cls, blocks, threads; size_t lds; pa::SweepArgs a; };
     std::vector<SW> sw;
     uint32_t sblocks = 0, mblocks = 0;
+    auto add_sweep = [&](pa_run_state *r, const pa::SweepArgs &a) {
+        const Plan &p = r->plan;
+        const uint64_t per_block = pa::replicas_per_block(r->G, r->wpb);
+        SW e;
+        e.cls = pa::sweep_class(p.desc.L, p.desc.q, a.T[3] == 0, r->G);
+        e.blocks = (uint32_t)((r->R_cur + per_block - 1) / per_block);
+        e.threads = 64u * r->wpb;
+        e.lds = pa::sweep_lds_bytes(p.N, r->G, r->wpb, p.mag ? p.desc.q : 0u);
+        e.a = a;
+        sw.push_back(e);
+    };
     for (pa_run_state *r : active) {
         const Plan &p = r->plan;
+        if (init) {
+            uint8_t *pop0 = r->at<uint8_t>(p.off_pop[0]);
+            if (p.tiled)
+                L.tiled.push_back({tiled_args(r, 0, nullptr, nullptr, pop0), 0u, nullptr, true});
+            else
+                add_sweep(r, sweep_args(r, 0, p.desc.init == PA_INIT_GROUND ? pa::SWEEP_INIT_GROUND
+                                                                            : pa::SWEEP_INIT_RANDOM,
+                                        nullptr, nullptr, pop0, 0));
+            po.push_back(post_args(r, 0));
+            continue;
+        }
         const uint32_t g = r->step + 1;
         const uint64_t R_prev = r->R_cur, R_new = p.R_sched[g];
         const int prev_buf = r->cur, new_buf = 1 - r->cur;
@@ -1773,22 +1828,14 @@ StepLaunch build_step(const std::vector<pa_run_state *> &active, std::vector<uin
         if (p.tiled) {
             L.tiled.push_back({tiled_args(r, g, r->at<uint8_t>(p.off_pop[prev_buf]), anc,
                                           r->at<uint8_t>(p.off_pop[new_buf])),
-                               p.desc.theta, r->at<uint8_t>(p.off_pop_x)});
+                               p.desc.theta, r->at<uint8_t>(p.off_pop_x), false});
             r->cur = new_buf;
             r->step = g;
             po.push_back(post_args(r, g));
             continue;
         }
-        pa::SweepArgs a = sweep_args(r, g, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[prev_buf]), anc,
-                                     r->at<uint8_t>(p.off_pop[new_buf]), p.desc.theta);
-        const uint64_t per_block = pa::replicas_per_block(r->G, r->wpb);
-        SW e;
-        e.cls = pa::sweep_class(p.desc.L, p.desc.q, a.T[3] == 0, r->G);
-        e.blocks = (uint32_t)((R_new + per_block - 1) / per_block);
-        e.threads = 64u * r->wpb;
-        e.lds = pa::sweep_lds_bytes(p.N, r->G, r->wpb, p.mag ? p.desc.q : 0u);
-        e.a = a;
-        sw.push_back(e);
+        add_sweep(r, sweep_args(r, g, pa::SWEEP_UPDATE, r->at<uint8_t>(p.off_pop[prev_buf]), anc,
+                                r->at<uint8_t>(p.off_pop[new_buf]), p.desc.theta));
         r->cur = new_buf;
         r->step = g;
         po.push_back(post_args(r, g));
@@ -1868,8 +1915,15 @@ pa_status launch_step(const StepLaunch &L, const uint8_t *dtab, hipStream_t s) {
             return st;
         run_index += G.count;
     }
-    for (const auto &t : L.tiled)
-        if ((st = hip_check(nullptr, launch_tiled_sweeps(t.a, t.theta, t.x, s), "tiled sweeps"))) return st;
+    for (const auto &t : L.tiled) {
+        if (t.init) {
+            if ((st = hip_check(nullptr, pa::launch_tiled_init(t.a, s), "tiled init")) ||
+                (st = hip_check(nullptr, pa::launch_tiled_measure(t.a, s), "tiled init")))
+                return st;
+        } else if ((st = hip_check(nullptr, launch_tiled_sweeps(t.a, t.theta, t.x, s), "tiled sweeps"))) {
+            return st;
+        }
+    }
     return hip_check(nullptr, pa::launch_post_batch(reinterpret_cast<const pa::PostArgs *>(dtab + L.post_off),
                                                     reinterpret_cast<const uint32_t *>(dtab + L.post_start_off),
                                                     L.n_post, L.post_blocks, s),
@@ -1879,9 +1933,52 @@ pa_status launch_step(const StepLaunch &L, const uint8_t *dtab, hipStream_t s) {
 struct BatchLayout {
     std::vector<Plan> plans;
     std::vector<size_t> run_off;
-    size_t desc_off = 0, desc_bytes = 0, team_off = 0, team_bytes = 0, total = 0;
+    size_t desc_off = 0, desc_bytes = 0, out_off = 0, team_off = 0, team_bytes = 0, total = 0;
     uint32_t max_K = 0;
 };
+
+// A k_prep_batch launch whose records sit in the descriptor table.
+struct PrepLaunch {
+    size_t rec_off = 0, start_off = 0;
+    uint32_t n = 0, blocks = 0;
+};
+
+// Write the records (none of zero words) and their workgroup starts at blob + cursor.
+PrepLaunch pack_prep(const std::vector<pa::PrepRec> &recs, std::vector<uint8_t> &blob, size_t &cursor) {
+    PrepLaunch P;
+    std::vector<uint32_t> start;
+    for (const auto &e : recs) {
+        start.push_back(P.blocks);
+        P.blocks += (uint32_t)((e.words + pa::PREP_CHUNK - 1) / pa::PREP_CHUNK);
+    }
+    start.push_back(P.blocks);
+    P.n = (uint32_t)recs.size();
+    P.rec_off = cursor;
+    P.start_off = P.rec_off + align256(recs.size() * sizeof(pa::PrepRec));
+    cursor = P.start_off + align256(start.size() * 4);
+    if (blob.size() < cursor) blob.resize(cursor, 0);
+    std::memcpy(blob.data() + P.rec_off, recs.data(), recs.size() * sizeof(pa::PrepRec));
+    std::memcpy(blob.data() + P.start_off, start.data(), start.size() * 4);
+    return P;
+}
+
+pa_status launch_prep(const PrepLaunch &P, const uint8_t *dtab, hipStream_t s) {
+    return hip_check(nullptr,
+                     pa::launch_prep_batch(reinterpret_cast<const pa::PrepRec *>(dtab + P.rec_off),
+                                           reinterpret_cast<const uint32_t *>(dtab + P.start_off), P.n, P.blocks, s),
+                     "batched fills");
+}
+
+// Descriptor bytes of a batch's start and end: the weight tables, up to ten
+// fill and copy records per run (start_fills and the table), the records of
+// step 0, and one gather record per run.
+size_t prep_bytes(const std::vector<Plan> &plans) {
+    const size_t n = plans.size();
+    size_t w = 0;
+    for (const Plan &p : plans) w += align256(8 * p.W.size());
+    return w + align256(10 * n * sizeof(pa::PrepRec)) + align256((10 * n + 1) * 4) + step_desc_bytes(n) +
+           align256(n * sizeof(pa::PrepRec)) + align256((n + 1) * 4);
+}
 
 // Device bytes of the team launches' records for runs with these plans: one
 // TeamStep per step after the first, one TeamRun, a 256-byte barrier counter
@@ -1900,16 +1997,30 @@ pa_status batch_layout(const pa_run_desc *descs, uint32_t n, BatchLayout &b) {
     b.plans.resize(n);
     b.run_off.resize(n);
     size_t o = 0;
+    // runs with one (L, K, beta schedule) share their tables
+    std::unordered_map<std::string, uint32_t> first_of;
     for (uint32_t r = 0; r < n; ++r) {
-        pa_status st = build_plan(&descs[r], b.plans[r]);
+        const Plan *like = nullptr;
+        if (descs[r].beta && descs[r].K) {
+            std::string key((const char *)descs[r].beta, 8 * (size_t)descs[r].K);
+            key.append((const char *)&descs[r].L, sizeof descs[r].L);
+            auto it = first_of.find(key);
+            if (it != first_of.end()) like = &b.plans[it->second];
+            else first_of.emplace(std::move(key), r);
+        }
+        pa_status st = build_plan(&descs[r], b.plans[r], like);
         if (st) return fail(st, "run " + std::to_string(r) + ": " + g_last_error);
         b.run_off[r] = o;
         o += align256(b.plans[r].total);
         b.max_K = std::max(b.max_K, descs[r].K);
     }
     b.desc_off = o;
-    b.desc_bytes = step_desc_bytes(n) * (b.max_K > 1 ? b.max_K - 1 : 1);
-    b.team_off = align256(o + b.desc_bytes);
+    b.desc_bytes = prep_bytes(b.plans) + step_desc_bytes(n) * (b.max_K > 1 ? b.max_K - 1 : 1);
+    // every run's per-step block, gathered for one read-back
+    b.out_off = align256(o + b.desc_bytes);
+    size_t out_bytes = 0;
+    for (const Plan &p : b.plans) out_bytes += align256(p.steps_bytes);
+    b.team_off = align256(b.out_off + out_bytes);
     b.team_bytes = team_record_bytes(b.plans);
     b.total = b.team_off + b.team_bytes;
     return PA_OK;
@@ -2153,22 +2264,72 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
     };
     ctx->abort_requested = 0;
     ctx->team_runs = ctx->team_launches = 0;
-    // the runs' weight tables go up from pinned memory, with one wait for all
-    size_t w_total = 0;
-    for (const Plan &p : b.plans) w_total += align256(8 * p.W.size());
-    uint8_t *w_stage = ctx_staging(ctx, w_total, s);
-    if (!w_stage) return fail(PA_ERR_DEVICE, "cannot allocate pinned staging memory");
-    for (uint32_t r = 0, w_off = 0; r < n; ++r) {
+    for (uint32_t r = 0; r < n; ++r) {
         st = begin_run(ctx, &descs[r], ws + b.run_off[r], align256(b.plans[r].total), stream, true, &runs[r],
-                       /*wait=*/false, w_stage + w_off, &b.plans[r]);
+                       /*wait=*/false, /*deferred=*/true, &b.plans[r]);
         if (st) return cleanup(fail(st, "run " + std::to_string(r) + ": " + g_last_error));
-        w_off += (uint32_t)align256(8 * b.plans[r].W.size());
     }
-    if ((st = hip_check(nullptr, hipStreamSynchronize(s), "sync"))) return cleanup(st);
-    // Team launches first, one per sweep class, for the runs that qualify;
-    // they finish those runs.
+    uint8_t *dtab = ws + b.desc_off;
+    std::vector<uint8_t> blob;
+    size_t cursor = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = cursor;
+        cursor += align256(bytes);
+        if (blob.size() < cursor) blob.resize(cursor, 0);
+        return at;
+    };
+    // The runs' start in three launches: the weight tables (copied from the
+    // descriptor table) and the fills of every run, then the initial
+    // populations and their statistics (step 0) of all runs.
+    std::vector<pa::PrepRec> recs;
+    for (pa_run_state *r : runs) {
+        const Plan &p = r->plan;
+        if (!p.W.empty()) {
+            const size_t at = take(8 * p.W.size());
+            std::memcpy(blob.data() + at, p.W.data(), 8 * p.W.size());
+            recs.push_back({r->at<uint32_t>(p.off_W), reinterpret_cast<const uint32_t *>(dtab + at),
+                            2 * (uint64_t)p.W.size(), 0u, 0u});
+        }
+        for (const Fill &f : start_fills(r))
+            if (f.words) recs.push_back({f.dst, nullptr, f.words, f.value, 0u});
+    }
+    const PrepLaunch prep = pack_prep(recs, blob, cursor);
+    const StepLaunch init = build_step(runs, blob, cursor, /*init=*/true);
+    // and its end: every run's per-step block gathered in one launch, read
+    // back in one copy
+    std::vector<size_t> blk_off(n);
+    size_t blk_total = 0;
+    recs.clear();
+    for (uint32_t r = 0; r < n; ++r) {
+        blk_off[r] = blk_total;
+        const Plan &p = runs[r]->plan;
+        recs.push_back({reinterpret_cast<uint32_t *>(ws + b.out_off + blk_total),
+                        reinterpret_cast<const uint32_t *>(runs[r]->ws + p.off_steps), p.steps_bytes / 4, 0u, 0u});
+        blk_total += align256(p.steps_bytes);
+    }
+    const PrepLaunch gather = pack_prep(recs, blob, cursor);
+
+    // The descriptor table goes up from pinned memory that mirrors it (each
+    // part at its own offset, so that the host can write the next part while
+    // the last one is still being copied); the results come back behind it.
+    const size_t stage_bytes = align256(b.desc_bytes) + blk_total;
+    auto upload = [&](size_t from) -> pa_status {
+        if (cursor > b.desc_bytes) return fail(PA_ERR_DEVICE, "descriptor table overflow");
+        if (cursor == from) return PA_OK;
+        uint8_t *stage = ctx_staging(ctx, stage_bytes, s);
+        if (!stage) return fail(PA_ERR_DEVICE, "cannot allocate pinned staging memory");
+        std::memcpy(stage + from, blob.data() + from, cursor - from);
+        return hip_check(nullptr, hipMemcpyAsync(dtab + from, stage + from, cursor - from, hipMemcpyHostToDevice, s),
+                         "upload descriptors");
+    };
+    if ((st = upload(0)) || (st = launch_prep(prep, dtab, s)) || (st = launch_step(init, dtab, s)))
+        return cleanup(st);
+    const bool team = ctx->batch_mode == PA_BATCH_TEAM && !ctx->graphs;
     std::vector<bool> finished(n, false);
-    if (ctx->batch_mode == PA_BATCH_TEAM && !ctx->graphs) {
+    if (team) {
+        // Team launches, one per sweep class, for the runs that qualify; they
+        // finish those runs.  (The wait: the staging memory is reused.)
+        if ((st = hip_check(nullptr, hipStreamSynchronize(s), "sync"))) return cleanup(st);
         std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>> by_class;   // (class, waves per group)
         for (uint32_t r = 0; r < n; ++r)
             if (const uint32_t cls = team_class(runs[r])) by_class[{cls, runs[r]->wpb}].push_back(r);
@@ -2197,29 +2358,26 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
             }
         }
     }
-    // Every global step's records for the other runs, built up front (all
-    // sizes are in the plans).
-    std::vector<uint8_t> blob;
+    // The global steps of the runs left: records built on the host from the
+    // plans, global step g advancing every run with g < K.
     std::vector<StepLaunch> steps;
-    size_t cursor = 0;
-    for (uint32_t g = 1; g < b.max_K; ++g) {
-        std::vector<pa_run_state *> active;
-        for (uint32_t r = 0; r < n; ++r)
-            if (!finished[r] && g < runs[r]->plan.desc.K) active.push_back(runs[r]);
-        if (active.empty()) break;
-        steps.push_back(build_step(active, blob, cursor));
-    }
-    if (cursor > b.desc_bytes) return cleanup(fail(PA_ERR_DEVICE, "descriptor table overflow"));
-    uint8_t *dtab = ws + b.desc_off;
-    if (cursor) {
-        uint8_t *stage = ctx_staging(ctx, cursor, s);
-        if (!stage) return cleanup(fail(PA_ERR_DEVICE, "cannot allocate pinned staging memory"));
-        std::memcpy(stage, blob.data(), cursor);
-        if ((st = hip_check(nullptr, hipMemcpyAsync(dtab, stage, cursor, hipMemcpyHostToDevice, s),
-                            "upload descriptors")))
-            return cleanup(st);
-    }
+    uint32_t next_g = 1;
+    auto build_steps = [&](uint32_t count) {
+        for (const uint32_t end = std::min(b.max_K, next_g + count); next_g < end; ++next_g) {
+            std::vector<pa_run_state *> active;
+            for (uint32_t r = 0; r < n; ++r)
+                if (!finished[r] && next_g < runs[r]->plan.desc.K) active.push_back(runs[r]);
+            if (active.empty()) {
+                next_g = b.max_K;
+                break;
+            }
+            steps.push_back(build_step(active, blob, cursor));
+        }
+    };
     if (ctx->graphs) {
+        const size_t from = cursor;
+        build_steps(b.max_K);
+        if ((st = upload(from))) return cleanup(st);
         // Replay (capturing first if needed) the step sequence as one graph on
         // the context's stream, ordered after everything on the caller's stream.
         std::string key((const char *)descs, sizeof(pa_run_desc) * n);
@@ -2260,25 +2418,28 @@ extern "C" pa_status pa_run_batch(pa_ctx *ctx, const pa_run_desc *descs, uint32_
             (st = hip_check(nullptr, hipStreamWaitEvent(s, ctx->ev_out, 0), "wait")))
             return cleanup(st);
     } else {
-        for (const StepLaunch &L : steps) {
-            if (ctx->abort_requested) return cleanup(fail(PA_ERR_CANCELLED, "batch aborted"));
-            if ((st = launch_step(L, dtab, s))) return cleanup(st);
+        // in growing chunks of steps: the device starts on the first steps
+        // while the host builds the next
+        for (uint32_t chunk = 4; next_g < b.max_K; chunk = std::min(2 * chunk, 64u)) {
+            const size_t from = cursor, first = steps.size();
+            build_steps(chunk);
+            if ((st = upload(from))) return cleanup(st);
+            for (size_t k = first; k < steps.size(); ++k) {
+                if (ctx->abort_requested) return cleanup(fail(PA_ERR_CANCELLED, "batch aborted"));
+                if ((st = launch_step(steps[k], dtab, s))) return cleanup(st);
+            }
         }
     }
-    // every run's per-step block in one round of copies into pinned memory
-    std::vector<size_t> blk_off(n);
-    size_t blk_total = 0;
-    for (uint32_t r = 0; r < n; ++r) {
-        blk_off[r] = blk_total;
-        blk_total += align256(runs[r]->plan.steps_bytes);
-    }
-    uint8_t *blk = ctx_staging(ctx, blk_total, s);
-    if (!blk) return cleanup(fail(PA_ERR_DEVICE, "cannot allocate pinned staging memory"));
-    for (uint32_t r = 0; r < n && outs; ++r)
-        if ((st = hip_check(nullptr, hipMemcpyAsync(blk + blk_off[r], runs[r]->ws + runs[r]->plan.off_steps,
-                                                   runs[r]->plan.steps_bytes, hipMemcpyDeviceToHost, s),
+    uint8_t *blk = nullptr;
+    if (outs) {
+        blk = ctx_staging(ctx, stage_bytes, s);
+        if (!blk) return cleanup(fail(PA_ERR_DEVICE, "cannot allocate pinned staging memory"));
+        blk += align256(b.desc_bytes);
+        if ((st = launch_prep(gather, dtab, s)) ||
+            (st = hip_check(nullptr, hipMemcpyAsync(blk, ws + b.out_off, blk_total, hipMemcpyDeviceToHost, s),
                             "read results")))
             return cleanup(st);
+    }
     if ((st = hip_check(nullptr, hipStreamSynchronize(s), "sync"))) return cleanup(st);
     pa_status first = PA_OK;
     for (uint32_t r = 0; r < n; ++r) {

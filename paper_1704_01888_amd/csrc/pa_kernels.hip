@@ -1620,6 +1620,19 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
         p[i] = v;
 }
 
+// Fills and copies of many small buffers in one launch: the workgroup takes
+// chunk blockIdx.x - start[r] of record r.
+__global__ void __launch_bounds__(256) k_prep_batch(const PrepRec *recs, const uint32_t *start, uint32_t n) {
+    const uint32_t r = segment_of(start, n, blockIdx.x);
+    const PrepRec e = recs[r];
+    const uint64_t lo = (uint64_t)(blockIdx.x - start[r]) * PREP_CHUNK;
+    const uint64_t hi = min(e.words, lo + PREP_CHUNK);
+    if (e.src)
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) e.dst[i] = e.src[i];
+    else
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) e.dst[i] = e.value;
+}
+
 // ---------------------------------------------------------------------------
 // Lattices beyond one workgroup's LDS.  A replica stays in HBM as L rows of L
 // bytes.  A launch runs a few half-sweeps over (replica, tile of `rows` rows):
@@ -2462,6 +2475,13 @@ hipError_t launch_tiled_measure(const TiledArgs &a, hipStream_t s) {
     const size_t lds = (size_t)(a.rows + 2) * a.L + 4 * 256;
     hipLaunchKernelGGL(k_tiled_measure, dim3((uint32_t)blocks), dim3(256), lds, s, a);
     hipLaunchKernelGGL(k_tiled_finalize, dim3((a.R + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_batch(const PrepRec *recs, const uint32_t *start, uint32_t n, uint32_t blocks,
+                             hipStream_t s) {
+    if (n == 0 || blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prep_batch, dim3(blocks), dim3(256), 0, s, recs, start, n);
     return hipGetLastError();
 }
 
