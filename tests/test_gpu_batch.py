@@ -78,3 +78,17 @@ def test_graph_replays_equal_eager(ctx):
             torch.cuda.synchronize()
     finally:
         ctx.set_graphs(False)
+
+
+def test_runs_sharing_a_schedule_with_different_weight_scales(ctx):
+    """Runs of one (L, beta schedule) share the plan's tables in a batch; the
+    weights depend on the population cap too (K_b), so runs of different R
+    must still match their separate runs, and the first the oracle."""
+    beta = linear_betas(1.5, 12)
+    cfg = [dict(L=16, q=8, R=R, beta=beta, theta=2, seed=200 + k, resample=m)
+           for k, (R, m) in enumerate([(1000, 1), (3000, 1), (1000, 0), (5000, 2), (9000, 0), (1000, 1)])]
+    descs = [pa.Desc(outputs=pa.OUT_HIST | pa.OUT_FINAL | pa.OUT_DIGEST, **c) for c in cfg]
+    got = pa.pa_run_batch(ctx, descs)
+    for d, g in zip(descs, got):
+        _same(g, pa.pa_run(ctx, d))
+    _same(got[1], oracle.run(oracle.Desc(**cfg[1]), hist=True, final=True, digest=True))
