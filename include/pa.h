@@ -329,9 +329,13 @@ pa_status pa_resume(pa_ctx *ctx, const char *path, void *d_ws, uint64_t ws_bytes
 
 /* Batched runs: n independent PA runs (any mix of L, q, R, K, theta, seeds,
  * resampling and init modes) advanced together, one set of segmented launches
- * per global step g for every run with K > g.  Results are identical to n
+ * per global step g for every run with K > g.  The runs start together (one
+ * launch of fills and weight-table copies, one initial sweep launch per kernel
+ * class, one launch of step-0 statistics) and their per-step results come back
+ * through one gathering launch and one copy.  Results are identical to n
  * separate pa_run calls.  pa_plan_batch gives the workspace size (the runs'
- * workspaces plus the per-step descriptor tables); outs[n] as in pa_run. */
+ * workspaces, the descriptor tables of the start, the steps and the read-back,
+ * and the gathering area); outs[n] as in pa_run. */
 pa_status pa_plan_batch(const pa_run_desc *descs, uint32_t n, uint64_t *workspace_bytes);
 /* With graphs enabled, pa_run_batch records its per-step launch sequence once
  * as a HIP graph (on a stream of the context, ordered after the caller's
