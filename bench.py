@@ -184,9 +184,8 @@ def whole_runs(pa, torch, ctx, w, reps=3):
 
 def batched_vs_plain(pa, torch, ctx, runs, reps=1):
     """The same runs as separate pa_run calls and as one pa_run_batch: the
-    automatic mode (the default), segmented launches only, team launches for
-    every run that qualifies, and the segmented step sequence replayed as a
-    HIP graph."""
+    segmented launches (the default), team launches for every run that
+    qualifies, and the segmented step sequence replayed as a HIP graph."""
     descs = [pa.Desc(**r) for r in runs]
     att = sum(float(r["theta"]) * r["L"] ** 2 * float(np.sum(pa.pa_plan_tables(d)[1][1:]))
               for r, d in zip(runs, descs))
@@ -327,7 +326,7 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=1, help="repetitions of --profile-run")
     ap.add_argument("--profile-batch", action="store_true",
                     help="only the batch of 20 runs of 8x8, q=8, R=1000, 200 steps: segmented, "
-                         "in team launches, then in the automatic mode, twice each, for profiling")
+                         "then in team launches, twice each, for profiling")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
