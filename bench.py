@@ -56,8 +56,8 @@ ALG_OPS_PER_ATTEMPT = 40
 # algorithmic (gather + store).
 SWEEP_TRAFFIC_BYTES = (2.0 * 1603274 + 3200009) * 1024
 
-CFG3 = dict(L=128, q=10, R=200000, K=501, beta_max=1.6, theta=20, seed=4)
-CFG1 = dict(L=32, q=10, R=20000, K=401, beta_max=1.6, theta=10, seed=2)
+RUN_128 = dict(L=128, q=10, R=200000, K=501, beta_max=1.6, theta=20, seed=4)
+RUN_32 = dict(L=32, q=10, R=20000, K=401, beta_max=1.6, theta=10, seed=2)
 
 SWEEP_SYMBOL = "_ZN2pa12_GLOBAL__N_17k_sweepILj128ELj512ELb1ELb0EEEvNS_9SweepArgsE"
 
@@ -97,7 +97,7 @@ def probe_class(op: str) -> str:
 
 def sweep_mix(lib_path: str, symbol: str = SWEEP_SYMBOL, attempts_per_iter: int = 32):
     """Vector instructions per attempt of the sweep's theta loop, by probe
-    kind, read from the AMD assembly of this build's gfx950 code object.  At
+    kind, read from the AMD assembly of the built library's gfx950 code object.  At
     L = 128 with 512 lanes a lane updates 8 pairs per half-sweep, so one
     iteration of the theta loop (both colours, fully unrolled) is 32 attempts
     per lane."""
@@ -285,7 +285,7 @@ def cpu_baseline(replicas: int):
     """The oracle on the host cores: the headline workload with its population
     cut to `replicas`, initial population and first temperature step."""
     import oracle
-    w = CFG3
+    w = RUN_128
     n = w["K"] - 1
     beta = np.array([w["beta_max"] * i / n for i in range(n + 1)])[:2]
     od = oracle.Desc(w["L"], w["q"], replicas, beta, w["theta"], w["seed"],
@@ -381,7 +381,7 @@ def main():
         print(json.dumps({"profiled_run": w, "reps": args.profile_reps, "attempts_per_ns": att / dt / 1e9}))
         return
 
-    desc = linear_desc(pa, CFG3)
+    desc = linear_desc(pa, RUN_128)
     N = desc.N
     R_sched = pa.pa_plan_tables(desc)[1]
     if args.profile_steps:
@@ -462,7 +462,7 @@ def main():
         "roofline": roofline,
     }
     print("32x32 whole runs", file=sys.stderr, flush=True)
-    result["whole_runs_32x32_q10_R20000"] = whole_runs(pa, torch, ctx, CFG1)
+    result["whole_runs_32x32_q10_R20000"] = whole_runs(pa, torch, ctx, RUN_32)
     if not args.no_batched:
         from paper_1704_01888_amd import workloads
         print("batched lines", file=sys.stderr, flush=True)

@@ -25,7 +25,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_headline_workload_is_the_128x128_q10_poisson_run():
-    d = bench.linear_desc(pa, bench.CFG3)
+    d = bench.linear_desc(pa, bench.RUN_128)
     assert (d.L, d.q, d.R, d.theta, d.seed) == (128, 10, 200000, 20, 4)
     assert d.resample == pa.RESAMPLE_POISSON
     # 500 equal steps from beta = 0 to 1.6
@@ -59,7 +59,7 @@ def test_probe_classes_cover_the_sweep_instruction_kinds():
 
 
 def test_sweep_mix_reads_the_built_kernel():
-    """The theta loop of the 128x128 sweep kernel, read from this build's code
+    """The theta loop of the 128x128 sweep kernel, read from the built library's code
     object: about 31 vector instructions per attempt, 9 of them multiply-adds
     (Philox and the proposal)."""
     if not os.path.exists("/opt/rocm/llvm/bin/llvm-objdump"):

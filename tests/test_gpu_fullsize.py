@@ -112,8 +112,8 @@ def test_32x32_q10_R20000_every_step(ctx):
     _compare_whole(got, want)
 
 
-CFG3 = dict(L=128, q=10, R=200000, beta=workloads.linear_betas(1.6, 500), theta=20, seed=4,
-            resample=0)
+RUN_128 = dict(L=128, q=10, R=200000, beta=workloads.linear_betas(1.6, 500), theta=20, seed=4,
+               resample=0)
 
 
 @pytest.mark.timeout(600)
@@ -123,13 +123,13 @@ def test_128x128_q10_R200000_first_steps_whole(ctx):
     attempts), every spin, against the oracle stepping from its own initial
     population."""
     _note("128x128 q=10 R=200000 theta=20 seed=4: steps 0 and 1 whole")
-    d = pa.Desc(outputs=pa.OUT_HIST | pa.OUT_DIGEST, **CFG3)
+    d = pa.Desc(outputs=pa.OUT_HIST | pa.OUT_DIGEST, **RUN_128)
     run = pa.Run(ctx, d)
     run.advance(1)
     got = run.finish()
-    kw2 = dict(CFG3, beta=CFG3["beta"][:2])
+    kw2 = dict(RUN_128, beta=RUN_128["beta"][:2])
     # the truncated schedule has the same weight precision (R_cap rounds to 2^18)
-    assert oracle.plan(oracle.Desc(**kw2))[2] == oracle.plan(oracle.Desc(**CFG3))[2]
+    assert oracle.plan(oracle.Desc(**kw2))[2] == oracle.plan(oracle.Desc(**RUN_128))[2]
     want = oracle.run(oracle.Desc(**kw2), hist=True, digest=True)
     _compare_whole(got, want, steps=2, final=False)
 
@@ -139,8 +139,8 @@ def test_128x128_q10_R200000_last_step_sampled(ctx):
     """The same run's last step (499 -> 500, beta 1.5968 -> 1.6), reached on the
     device: all 2e5 ancestors and copy numbers, and 256 re-swept replicas."""
     _note("128x128 q=10 R=200000 theta=20 seed=4: step 500 sampled")
-    d = pa.Desc(**CFG3)
-    od = oracle.Desc(**CFG3)
+    d = pa.Desc(**RUN_128)
+    od = oracle.Desc(**RUN_128)
     _, _, Kb = oracle.plan(od)
     run = pa.Run(ctx, d)
     run.advance(d.K - 2)
