@@ -399,7 +399,15 @@ def _stream_ptr():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _alloc_result(desc: Desc, info: PlanInfo):
+def _final_plan(desc: Desc):
+    """The plan when the result needs its final population size, else None
+    (planning builds the run's tables: tens of microseconds per run)."""
+    return pa_plan(desc) if desc.outputs & OUT_FINAL else None
+
+
+def _alloc_result(desc: Desc, info):
+    """Result arrays and the pa_result pointing at them; `info` (a plan) is
+    needed for the final population's buffers only (OUT_FINAL)."""
     K, N = desc.K, desc.N
     out = {
         "R_i": np.zeros(K, np.uint64), "E_sum": np.zeros(K, np.int64),
@@ -445,7 +453,7 @@ def _alloc_result(desc: Desc, info: PlanInfo):
 
 def pa_run(ctx: Context, desc: Desc, workspace=None):
     """Whole run on the current torch stream; returns a dict of numpy arrays."""
-    info = pa_plan(desc)
+    info = pa_plan(desc) if workspace is None else _final_plan(desc)
     ws = workspace if workspace is not None else _workspace(info.workspace_bytes, ctx.device)
     out, res = _alloc_result(desc, info)
     _check(lib().pa_run(ctx.handle, ctypes.byref(desc.c()), ctypes.c_void_p(ws.data_ptr()),
@@ -456,7 +464,7 @@ def pa_run(ctx: Context, desc: Desc, workspace=None):
 def pa_run_static(ctx: Context, desc: Desc):
     """Whole run in the library's fixed device workspace (pa_run_static: no
     device allocation by the call); returns a dict of numpy arrays."""
-    out, res = _alloc_result(desc, pa_plan(desc))
+    out, res = _alloc_result(desc, _final_plan(desc))
     _check(lib().pa_run_static(ctx.handle, ctypes.byref(desc.c()), _stream_ptr(), ctypes.byref(res)))
     return out
 
@@ -590,7 +598,7 @@ def pa_run_batch(ctx: Context, descs, workspace=None):
     ws = workspace if workspace is not None else _workspace(pa_plan_batch(descs), ctx.device)
     outs, ress = [], (Result * len(descs))()
     for i, d in enumerate(descs):
-        o, r = _alloc_result(d, pa_plan(d))
+        o, r = _alloc_result(d, _final_plan(d))
         outs.append(o)
         ress[i] = r
     arr = _desc_array(descs)
@@ -611,7 +619,7 @@ class Server:
         self.running = True
 
     def submit(self, desc: Desc) -> int:
-        out, res = _alloc_result(desc, pa_plan(desc))
+        out, res = _alloc_result(desc, _final_plan(desc))
         t = ctypes.c_uint64(0)
         _check(lib().pa_serve_submit(self.ctx.handle, ctypes.byref(desc.c()), ctypes.byref(res),
                                      ctypes.byref(t)))
@@ -639,7 +647,7 @@ class Server:
     def resume(self, path) -> int:
         """Submit a request continuing a checkpoint file (pa_serve_resume)."""
         desc, _, _ = checkpoint_info(path)
-        out, res = _alloc_result(desc, pa_plan(desc))
+        out, res = _alloc_result(desc, _final_plan(desc))
         t = ctypes.c_uint64(0)
         _check(lib().pa_serve_resume(self.ctx.handle, os.fsencode(str(path)), ctypes.byref(res),
                                      ctypes.byref(t)))
