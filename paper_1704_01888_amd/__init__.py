@@ -405,49 +405,47 @@ def _final_plan(desc: Desc):
     return pa_plan(desc) if desc.outputs & OUT_FINAL else None
 
 
+_ITEMSIZE = {np.uint8: 1, np.int32: 4, np.uint32: 4, np.int64: 8, np.uint64: 8, np.float64: 8}
+
+
 def _alloc_result(desc: Desc, info):
     """Result arrays and the pa_result pointing at them; `info` (a plan) is
-    needed for the final population's buffers only (OUT_FINAL)."""
-    K, N = desc.K, desc.N
-    out = {
-        "R_i": np.zeros(K, np.uint64), "E_sum": np.zeros(K, np.int64),
-        "E_mean": np.zeros(K), "lnQ": np.zeros(K), "minus_beta_F": np.zeros(K),
-    }
-    res = Result()
-    for k in ("R_i", "E_sum", "E_mean", "lnQ", "minus_beta_F"):
-        setattr(res, k, _ptr(out[k]))
-    if desc.outputs & OUT_HIST:
-        out["hist"] = np.zeros((K, 2 * N + 1), np.uint32)
-        res.hist = _ptr(out["hist"])
-    if desc.outputs & OUT_MAG:
-        out["Mt_sum"] = np.zeros(K, np.int64)
-        out["M_mean"] = np.zeros(K)
-        res.Mt_sum = _ptr(out["Mt_sum"])
-        res.M_mean = _ptr(out["M_mean"])
-        if desc.outputs & OUT_HIST:
-            out["mhist"] = np.zeros((K, N + 1), np.uint32)
-            res.mhist = _ptr(out["mhist"])
-    if desc.outputs & OUT_WIDTHS:
-        out["width_e"] = np.zeros(K)
-        res.width_e = _ptr(out["width_e"])
-        if desc.outputs & OUT_MAG:
-            out["width_m"] = np.zeros(K)
-            res.width_m = _ptr(out["width_m"])
-    if desc.outputs & OUT_DIGEST:
-        out["digest"] = np.zeros(K, np.uint64)
-        res.digest = _ptr(out["digest"])
-    if desc.outputs & OUT_FINAL:
+    needed for the final population's buffers only (OUT_FINAL).  The arrays
+    are views of one zeroed buffer (one address lookup per result)."""
+    K, N, o = desc.K, desc.N, desc.outputs
+    fields = [("R_i", (K,), np.uint64), ("E_sum", (K,), np.int64), ("E_mean", (K,), np.float64),
+              ("lnQ", (K,), np.float64), ("minus_beta_F", (K,), np.float64)]
+    if o & OUT_HIST:
+        fields.append(("hist", (K, 2 * N + 1), np.uint32))
+    if o & OUT_MAG:
+        fields += [("Mt_sum", (K,), np.int64), ("M_mean", (K,), np.float64)]
+        if o & OUT_HIST:
+            fields.append(("mhist", (K, N + 1), np.uint32))
+    if o & OUT_WIDTHS:
+        fields.append(("width_e", (K,), np.float64))
+        if o & OUT_MAG:
+            fields.append(("width_m", (K,), np.float64))
+    if o & OUT_DIGEST:
+        fields.append(("digest", (K,), np.uint64))
+    if o & OUT_FINAL:
         RF = int(info.R_final)
-        out["final_spins"] = np.zeros((RF, N), np.uint8)
-        out["final_E"] = np.zeros(RF, np.int32)
-        out["last_anc"] = np.zeros(RF, np.uint32)
-        res.final_spins = _ptr(out["final_spins"])
-        res.final_E = _ptr(out["final_E"])
-        res.last_anc = _ptr(out["last_anc"])
-    out["kernel_ms"] = np.zeros(len(KERNEL_NAMES))
-    out["kernel_launches"] = np.zeros(len(KERNEL_NAMES), np.uint64)
-    res.kernel_ms = _ptr(out["kernel_ms"])
-    res.kernel_launches = _ptr(out["kernel_launches"])
+        fields += [("final_spins", (RF, N), np.uint8), ("final_E", (RF,), np.int32),
+                   ("last_anc", (RF,), np.uint32)]
+    fields += [("kernel_ms", (len(KERNEL_NAMES),), np.float64),
+               ("kernel_launches", (len(KERNEL_NAMES),), np.uint64)]
+    spans, total = [], 0
+    for name, shape, dt in fields:
+        count = shape[0] * shape[1] if len(shape) == 2 else shape[0]
+        nbytes = count * _ITEMSIZE[dt]
+        spans.append((name, shape, dt, total, nbytes))
+        total += (nbytes + 7) & ~7
+    buf = np.zeros(max(total, 8), np.uint8)
+    base = buf.ctypes.data
+    out, res = {}, Result()
+    for name, shape, dt, off, nbytes in spans:
+        v = buf[off:off + nbytes].view(dt)
+        out[name] = v if len(shape) == 1 else v.reshape(shape)
+        setattr(res, name, base + off)
     return out, res
 
 
