@@ -1246,13 +1246,13 @@ std::vector<Fill> start_fills(pa_run_state *r) {
 // it for all its runs in a few launches).
 pa_status begin_run(pa_ctx *ctx, const pa_run_desc *desc, void *d_ws, uint64_t ws_bytes, void *stream,
                     bool initial, pa_run_state **out, bool wait = true, bool deferred = false,
-                    const Plan *plan = nullptr) {
+                    Plan *plan = nullptr) {
     if (!ctx || !out) return fail(PA_ERR_INVALID, "null context or output");
     pa_run_state *r = new (std::nothrow) pa_run_state;
     if (!r) return fail(PA_ERR_NOMEM, "out of host memory");
     pa_status st = PA_OK;
     if (plan) {
-        r->plan = *plan;                     // built already (a batch's layout)
+        r->plan = std::move(*plan);          // built already (a batch's layout, which gives it up)
         r->plan.desc.beta = r->plan.beta.data();
     } else
         st = build_plan(desc, r->plan);
