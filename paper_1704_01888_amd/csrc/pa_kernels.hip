@@ -689,14 +689,20 @@ __global__ void __launch_bounds__(1024) k_sweep(SweepArgs a) {
     sweep_body<LT, GT, QSMALL, T64>(a, blockIdx.x, smem, threadIdx.x, blockDim.x, a.anc, 0u, a.R_new);
 }
 
-// Index of the segment holding `block`: start[r] <= block < start[r + 1].
+// Index of the segment holding `block`: the last r < n with start[r] <= block
+// (start is non-decreasing from start[0] = 0, so segments without workgroups
+// are skipped).  Each wave counts the starts not after `block`, 64 per round
+// of vector loads, instead of following a chain of dependent loads through a
+// binary search; every thread of the workgroup must call it.
 __device__ __forceinline__ uint32_t segment_of(const uint32_t *start, uint32_t n, uint32_t block) {
-    uint32_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= block) lo = mid; else hi = mid - 1;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t count = 0;
+    for (uint32_t i0 = 0; i0 < n; i0 += 64u) {
+        const uint32_t i = i0 + lane;
+        const bool before = i < n && start[i] <= block;
+        count += (uint32_t)__popcll(__ballot(before));
     }
-    return __builtin_amdgcn_readfirstlane(lo);
+    return __builtin_amdgcn_readfirstlane(count - 1u);
 }
 
 // Batched form: the workgroups of several runs' sweep launches (same lattice
