@@ -130,7 +130,8 @@ __host__ __device__ inline uint32_t scan_block(uint64_t n) {
     const uint64_t rows = (n + row * max_blocks - 1) / (row * max_blocks);
     return (uint32_t)(row * (rows ? rows : 1));
 }
-// Workgroups of a post launch: statistics plus the weight blocks.
+// Workgroups of a post launch: statistics, the weight blocks, and the
+// resampling workgroup of a small population.
 __host__ __device__ inline uint32_t post_blocks(const PostArgs &a) {
     return 1u + (a.do_weights ? (uint32_t)((a.R_i + a.wblock - 1) / a.wblock) : 0u) + (a.small ? 1u : 0u);
 }
