@@ -92,3 +92,20 @@ def test_runs_sharing_a_schedule_with_different_weight_scales(ctx):
     for d, g in zip(descs, got):
         _same(g, pa.pa_run(ctx, d))
     _same(got[1], oracle.run(oracle.Desc(**cfg[1]), hist=True, final=True, digest=True))
+
+
+def test_populations_just_above_the_small_population_limit(ctx):
+    """Populations of 4097 to 8192 replicas (above the one-workgroup
+    resampling of the post launch, so through the sampling and count-scan
+    launches) in pa_run and pa_run_batch equal the oracle."""
+    cfg = [dict(L=16, q=8, R=4500, beta=linear_betas(1.5, 10), theta=2, seed=210, resample=1),
+           dict(L=16, q=10, R=7000, beta=linear_betas(1.6, 10), theta=2, seed=211, resample=0),
+           dict(L=8, q=8, R=8192, beta=linear_betas(1.5, 12), theta=3, seed=212, resample=1)]
+    descs = [pa.Desc(outputs=pa.OUT_HIST | pa.OUT_FINAL | pa.OUT_DIGEST, **c) for c in cfg]
+    for d in descs:
+        assert 4096 < pa.pa_plan(d).R_cap <= 8192
+    got = pa.pa_run_batch(ctx, descs)
+    for c, d, g in zip(cfg, descs, got):
+        want = oracle.run(oracle.Desc(**c), hist=True, final=True, digest=True)
+        _same(pa.pa_run(ctx, d), want)
+        _same(g, want)
